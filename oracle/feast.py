@@ -1,0 +1,139 @@
+"""The FEAST iteration on a band Hermitian matrix (test infrastructure).
+
+Follows the FEAST algorithm as the paper states it (Section 2.2, Algorithm
+alg:FEAST): while the eigen-residual is above the tolerance, apply the
+rational filter Q = r(A) X by the shifted solves, project with Rayleigh-Ritz
+A_q = Q^H A Q, solve A_q W = W Lambda, and set X = Q W.  The slice count m is
+known exactly from two inertias and every slice is checked against it
+(Section 3.2 "Validation and Other Details").
+
+Readings of points the paper leaves open:
+* stop test: the number of Ritz pairs with eigenvalue in [lo, hi) and
+  residual ||B x - lambda x||_2 / ||B||_1 <= tol (||x||_2 = 1) equals the
+  inertia count m; at most ``max_iter`` iterations.  Ritz pairs inside the
+  slice whose residual stays large are spurious (mixtures of eigenvectors
+  outside the slice that the unconverged edge of the search subspace
+  produces) and are not reported; the exact count is what tells them apart;
+* orthonormalisation (the mass matrix of the standard problem is I):
+  Q is replaced by Q V s^{-1/2} from the eigen-decomposition Q^H Q = V s V^H,
+  dropping directions with s_k <= 1e-14 max(s);
+* for complex Hermitian B the filter is
+  Q = sum_j [w_j (z_j I - B)^{-1} Y + conj(w_j) (z_j I - B)^{-H} Y];
+  for real symmetric B with real Y it is Q = sum_j 2 Re[w_j (z_j I - B)^{-1} Y].
+
+The small dense Hermitian eigenproblems use ``numpy.linalg.eigh`` as a
+library step.
+
+Pinned by: for diagonal B, Q = diag(r(d_i)) Y exactly; for small B,
+Q = V r(Lambda) V^H Y from the oracle's own dense Jacobi; the converged
+eigenvalues against dense eigenvalues of B; counts against inertia; the
+invariants of a full-spectrum run (sum lambda = tr B,
+sum lambda^2 = ||B||_F^2); orthonormality (tests).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .band import band_matmul, norm1
+from .bandlu import lu_solve, lu_solve_h, shifted_band_lu
+from .inertia import count_in
+from .quadrature import contour
+
+
+def factor_nodes(ab: np.ndarray, z) -> list:
+    """One band LU per integration node (equation eq:feast_L2)."""
+    return [shifted_band_lu(ab, zj) for zj in z]
+
+
+def filter_apply(ab: np.ndarray, factors, w, Y: np.ndarray) -> np.ndarray:
+    """Q = r(B) Y by the shifted solves, summed over the nodes in order."""
+    if np.iscomplexobj(ab):
+        Q = np.zeros(Y.shape, dtype=np.complex128)
+        for F, wj in zip(factors, w):
+            Q += wj * lu_solve(F, Y)
+            Q += np.conj(wj) * lu_solve_h(F, Y)
+        return Q
+    Q = np.zeros(Y.shape, dtype=np.float64)
+    for F, wj in zip(factors, w):
+        Q += 2.0 * np.real(wj * lu_solve(F, Y))
+    return Q
+
+
+def orthonormalise(Q: np.ndarray, drop: float = 1e-14):
+    """Q V s^{-1/2} over the kept directions of Q^H Q = V s V^H."""
+    G = Q.conj().T @ Q
+    G = 0.5 * (G + G.conj().T)
+    s, V = np.linalg.eigh(G)
+    keep = s > drop * s.max() if s.max() > 0 else np.zeros(len(s), bool)
+    return (Q @ V[:, keep]) / np.sqrt(s[keep]), int(keep.sum())
+
+
+def rayleigh_ritz(ab: np.ndarray, Q: np.ndarray):
+    """Ritz values (ascending) and vectors of B on span(Q)."""
+    Qo, k = orthonormalise(Q)
+    Aq = Qo.conj().T @ band_matmul(ab, Qo)
+    Aq = 0.5 * (Aq + Aq.conj().T)
+    lam, W = np.linalg.eigh(Aq)
+    X = Qo @ W
+    return lam, X, k
+
+
+def eig_residuals(ab: np.ndarray, X: np.ndarray, lam: np.ndarray, nrm: float) -> np.ndarray:
+    """||B x_k - lambda_k x_k||_2 / (||B||_1 ||x_k||_2) per pair."""
+    R = band_matmul(ab, X) - X * lam[None, :]
+    return np.linalg.norm(R, axis=0) / (nrm * np.linalg.norm(X, axis=0))
+
+
+def orthogonality(X: np.ndarray) -> float:
+    """Orth = ||X^H X - I||_max / n (Section 4, the metric used for Table
+    tab:orthogonality)."""
+    G = X.conj().T @ X
+    return float(np.abs(G - np.eye(G.shape[0])).max() / X.shape[0])
+
+
+@dataclass
+class SliceResult:
+    lo: float
+    hi: float
+    m: int                      # exact count from inertia
+    lam: np.ndarray             # in-slice Ritz values, ascending
+    X: np.ndarray               # in-slice Ritz vectors
+    res: np.ndarray             # their residuals
+    iters: int
+    info: int                   # 0 ok, 1 not converged, 2 count mismatch
+    history: list = field(default_factory=list)
+    Y_next: np.ndarray | None = None   # all Ritz vectors (warm start)
+
+
+def feast_slice(ab: np.ndarray, lo: float, hi: float, Y: np.ndarray,
+                n_nodes: int = 8, tol: float = 1e-10, max_iter: int = 20,
+                m_expected: int | None = None) -> SliceResult:
+    """Eigenpairs of B in [lo, hi) by FEAST from the start block Y (n x m0)."""
+    nrm = norm1(ab)
+    m = count_in(ab, lo, hi) if m_expected is None else m_expected
+    z, w = contour(lo, hi, n_nodes)
+    factors = factor_nodes(ab, z)
+    Y = np.array(Y, dtype=np.complex128 if np.iscomplexobj(ab) else np.float64, copy=True)
+    m0 = Y.shape[1]
+    hist = []
+    info = 1
+    it = 0
+    for it in range(1, max_iter + 1):
+        Q = filter_apply(ab, factors, w, Y)
+        lam, X, k = rayleigh_ritz(ab, Q)
+        res = eig_residuals(ab, X, lam, nrm)
+        inside = (lam >= lo) & (lam < hi)
+        good = inside & (res <= tol)
+        hist.append((int(inside.sum()), int(good.sum())))
+        if k < m0:
+            X = np.concatenate([X, Y[:, : m0 - k]], axis=1)
+        Y = X
+        if good.sum() == m:
+            info = 0
+            break
+    else:
+        info = 2 if good.sum() > m or inside.sum() < m else 1
+    return SliceResult(lo, hi, m, lam[good], X[:, : len(lam)][:, good], res[good],
+                       it, info, hist, Y)
