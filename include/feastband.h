@@ -1,0 +1,183 @@
+/*
+ * feastband.h -- C ABI of the MI355X banded FEAST spectrum-slicing library.
+ *
+ * The library computes eigenpairs of a band Hermitian (or real symmetric)
+ * matrix B slice by slice with FEAST: contour-integral filtering by shifted
+ * band solves, orthonormalisation and Rayleigh-Ritz, with slices placed and
+ * checked by Sylvester inertia (the spectrum-slicing stage of PDESHEP,
+ * Section 3 of the paper, with Algorithm alg:FEAST of Section 2.2).
+ *
+ * Conventions for every entry point
+ *  - Arrays are column-major and 0-based.  "dev" marks a device pointer
+ *    (memory of the current HIP device), "host" a host pointer.
+ *  - stream is a hipStream_t (NULL = the null stream).  Work is queued on
+ *    it; entry points that return host results synchronise it.
+ *  - Workspace: the caller owns all memory.  Calling with work == NULL is a
+ *    query: the required size in bytes is written to *lwork, nothing is
+ *    launched and 0 is returned.  Otherwise *lwork must be at least that
+ *    size and work must be 256-byte aligned device memory.
+ *  - Return value: 0 on success; -k when argument k (1-based) is invalid,
+ *    with nothing launched; -1000 - e for a HIP error e; FB_ERR_* codes
+ *    below for other failures; a positive value where an entry point says so.
+ *  - Inputs are never modified unless documented as in/out.
+ *  - Calls that overlap on one device must use distinct workspaces.
+ */
+#ifndef FEASTBAND_H
+#define FEASTBAND_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FB_REAL64 1     /* real symmetric, double */
+#define FB_COMPLEX128 2 /* complex Hermitian, interleaved (re, im) doubles */
+
+#define FB_ERR_SINGULAR (-2001)   /* an exactly zero pivot in a shifted LU */
+#define FB_ERR_NOT_BUILT (-2002)  /* no kernel for this device */
+#define FB_ERR_CERTIFY (-2003)    /* a slice boundary could not be certified */
+#define FB_ERR_NOMEM (-2004)      /* workspace or HBM budget below one unit of work */
+#define FB_ERR_NONFINITE (-2005)  /* NaN or Inf in an input block */
+#define FB_ERR_INTERNAL (-2006)
+
+/* A band Hermitian matrix in LAPACK lower band storage (the compact band form
+ * the paper keeps on every process, Section 3 "Proposed algorithm"):
+ * ab[(i-j) + j*ldab] = B(i, j) for 0 <= i-j <= b, ab dev, dtype FB_REAL64
+ * (double) or FB_COMPLEX128 (two doubles).  Imaginary parts of the diagonal
+ * are ignored.  Requires 0 <= b < n, ldab >= b+1. */
+typedef struct {
+  int64_t n;
+  int32_t b;
+  int32_t dtype;
+  int64_t ldab;
+  const void* ab;
+} fb_band;
+
+/* Sylvester inertia of B - shift_k I for every shift (Section 3.1 "Spectrum
+ * Partition": the LDL^H factorisation of A - s I counts the eigenvalues below
+ * s; Section 3.2 uses two such counts to check every slice).  Computed by a
+ * band LDL^H without pivoting in FP64, one factorisation per shift, all
+ * shifts in one batched launch.  A pivot of magnitude below
+ * eps^2 * ||B||_1 is counted in n_zero and replaced by its negative bound.
+ * shifts: host, nshift doubles.  n_neg/n_zero/n_pos: host, nshift int32
+ * each (n_zero and n_pos may be NULL).  Synchronises the stream. */
+int band_inertia(const fb_band* B, int32_t nshift, const double* shifts,
+                 int32_t* n_neg, int32_t* n_zero, int32_t* n_pos,
+                 void* work, size_t* lwork, void* stream);
+
+/* Options of the shifted band solves. */
+typedef struct {
+  int32_t precision; /* 0: complex128 LU and solves (plain FP64).
+                        1: complex64 LU and solves with FP32 accumulation,
+                           refined in FP64 (residual from the FP64 band) */
+  double ir_tol;     /* precision 1: stop refining a column once
+                        ||y - A x||_2 / ||y||_2 <= ir_tol */
+  int32_t ir_max;    /* precision 1: at most this many correction passes */
+  int32_t tile;      /* right-hand-side columns per work item; 0 = default */
+} fb_solve_opts;
+
+/* Batched shifted band solves, the building block of the FEAST filter
+ * (Section 2.2, equation eq:feast_L2: one factorisation of (z_j I - B) per
+ * integration node, then solves with many right-hand sides).
+ * For every system s: factor A_s = z_s I - B by band LU with partial
+ * pivoting, then X[s] = A_s^{-1} Y[s] and, if XH[s] != NULL,
+ * XH[s] = A_s^{-H} Y[s].
+ *  z      host, 2*nsys doubles: (re, im) of each shift
+ *  m      host, nsys: columns of system s (0 allowed)
+ *  Y      host array of nsys dev pointers to complex128 n x m[s] blocks,
+ *         leading dimension ldy[s] >= n (systems may share a block)
+ *  X, XH  host arrays of nsys dev pointers to complex128 outputs,
+ *         leading dimension ldx[s] >= n; XH itself or XH[s] may be NULL
+ *  resid  host, nsys or NULL: max over the columns of system s (N and H)
+ *         of ||y - A x||_2 / ||y||_2 after the call, computed in FP64
+ *  passes host, nsys or NULL: refinement passes used (precision 1)
+ * Returns FB_ERR_SINGULAR if a pivot is exactly zero.  Precision 1 returns
+ * the number of systems whose residual stayed above ir_tol after ir_max
+ * passes (0 when all converged). */
+int band_shifted_solve(const fb_band* B, int32_t nsys, const double* z,
+                       const int32_t* m, const void* const* Y,
+                       const int64_t* ldy, void* const* X, void* const* XH,
+                       const int64_t* ldx, double* resid, int32_t* passes,
+                       const fb_solve_opts* o, void* work, size_t* lwork,
+                       void* stream);
+
+/* FEAST options. */
+typedef struct {
+  int32_t n_nodes;     /* Gauss-Legendre nodes on the upper half circle (8) */
+  double tol;          /* eigen-residual ||Bx - lx||_2/||B||_1 target (1e-10) */
+  int32_t max_iter;    /* FEAST iterations (20) */
+  int32_t precision;   /* as fb_solve_opts.precision */
+  double ir_tol;       /* as fb_solve_opts.ir_tol (1e-12) */
+  int32_t ir_max;      /* as fb_solve_opts.ir_max (4) */
+  int32_t batched;     /* 0: one launch sequence per slice; 1: all slices of
+                          a sweep in shared batched launches */
+  double hbm_budget;   /* bytes of workspace the call may use, 0 = all of
+                          *lwork (systems are admitted in waves under it) */
+} fb_feast_opts;
+
+/* FEAST on the slices [lo_i, hi_i) of B (Algorithm alg:FEAST, Section 2.2,
+ * with the slice validation of Section 3.2):
+ *   repeat: Q = sum_j [w_j (z_j I - B)^{-1} Y + conj(w_j)(z_j I - B)^{-H} Y]
+ *           (real B: Q = sum_j 2 Re[w_j (z_j I - B)^{-1} Y]),
+ *           orthonormalise Q, A_q = Q^H B Q, A_q W = W Lambda, X = Q W,
+ *   until the number of Ritz pairs in [lo_i, hi_i) with
+ *   ||B x - l x||_2 / ||B||_1 <= tol equals the exact count m_i; Y <- X.
+ *  lo, hi      host, nslice doubles, lo_i < hi_i
+ *  m0          host, nslice: subspace sizes (columns of Y[i]), m0_i >= 1
+ *  m_expected  host, nslice or NULL: exact counts; NULL = computed here by
+ *              band_inertia at lo_i and hi_i
+ *  Y           host array of dev pointers, in/out: on entry the start block
+ *              (n x m0_i, dtype of B), on exit all Ritz vectors, the
+ *              converged in-slice pairs first in ascending order
+ *  ldy         host, nslice: leading dimensions (>= n)
+ *  evals,resid host arrays of dev pointers to m0_i doubles: Ritz values and
+ *              eigen-residuals in the order of the columns of Y
+ *  m_found, iters, info  host, nslice each.  info: 0 ok, 1 not converged in
+ *              max_iter, 2 count mismatch (m0 too small or a missed
+ *              eigenvalue: rerun with a larger m0), 4 rank-deficient
+ *              filtered block (a truncated basis was used), 5 m0 < m
+ * Returns 0, or the number of slices with info in {1, 2, 5}. */
+int feast_band_slice(const fb_band* B, int32_t nslice, const double* lo,
+                     const double* hi, const int32_t* m0,
+                     const int32_t* m_expected, void* const* Y,
+                     const int64_t* ldy, double* const* evals,
+                     double* const* resid, int32_t* m_found, int32_t* iters,
+                     int32_t* info, const fb_feast_opts* o, void* work,
+                     size_t* lwork, void* stream);
+
+#define FB_PLAN_EQUAL_WIDTH 0 /* Approach-2 of Section 3.1: equal widths */
+#define FB_PLAN_EQUAL_COUNT 1 /* Approach-1 of Section 3.1: equal counts */
+
+typedef struct {
+  int32_t mode;       /* FB_PLAN_* */
+  int32_t K;          /* number of slices */
+  double lo, hi;      /* interval; NaN = the Gershgorin bound */
+  double count_tol;   /* equal count: accept |n_-(s) - target| <= floor(tol*total/K) */
+  double cert_delta;  /* boundaries keep eigenvalues farther than cert_delta*||B||_1 */
+  int32_t max_rounds; /* bisection rounds */
+} fb_plan_opts;
+
+/* Slice placement by exact inertia (Section 3.1 "Spectrum Partition",
+ * Approach-1 and Approach-2; slice counts m_i = n_-(s_i) - n_-(s_{i-1}) as in
+ * Section 3.2).  Every boundary is certified: n_-(s - d) = n_-(s + d) with
+ * d = cert_delta * ||B||_1, else it is moved to the first certified point of
+ * s + 2 d k, k = 1, -1, 2, -2, ...  Equal count bisects all open boundaries
+ * together, one batched inertia launch per round.
+ *  bounds host, K+1 doubles; counts host, K; n_inertia host (may be NULL):
+ *  number of shifts factorised.  Synchronises the stream. */
+int slice_plan(const fb_band* B, const fb_plan_opts* o, double* bounds,
+               int32_t* counts, int32_t* n_inertia, void* work, size_t* lwork,
+               void* stream);
+
+const char* fb_strerror(int code);
+
+/* Device properties used by the library (for reports): compute units and
+ * the device name, written to name (cap bytes). */
+int fb_device_info(int32_t* cus, char* name, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEASTBAND_H */

@@ -1,0 +1,152 @@
+"""Python binding of the banded FEAST library.
+
+Argument marshalling only: every step runs in the HIP kernels behind the C
+ABI of include/feastband.h.  PyTorch supplies device memory and streams.
+
+Conventions: a band matrix is given as its compact lower band ``ab`` of
+shape (b+1, n) with ``ab[d, j] = B[j+d, j]`` (numpy or torch); it is moved to
+the device in the LAPACK column-major layout the ABI takes.  Blocks of
+vectors are (n, m) tensors in column-major storage (``colmajor``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+
+def _stream_handle(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def colmajor(n: int, m: int, dtype=torch.complex128, device="cuda") -> torch.Tensor:
+    """Uninitialised (n, m) tensor stored column by column (leading dim n)."""
+    return torch.empty((m, n), dtype=dtype, device=device).t()
+
+
+def to_colmajor(a, device="cuda", dtype=None) -> torch.Tensor:
+    t = torch.as_tensor(np.asarray(a)) if not isinstance(a, torch.Tensor) else a
+    if dtype is not None:
+        t = t.to(dtype)
+    out = colmajor(t.shape[0], t.shape[1], t.dtype, device)
+    out.copy_(t)
+    return out
+
+
+@dataclass
+class DeviceBand:
+    """A band Hermitian matrix resident on the device (LAPACK lower layout)."""
+    n: int
+    b: int
+    complex_: bool
+    data: torch.Tensor   # (n, b+1), row j = column j of the LAPACK array
+
+    @classmethod
+    def from_band(cls, ab, device="cuda") -> "DeviceBand":
+        ab = np.asarray(ab)
+        b1, n = ab.shape
+        cplx = np.iscomplexobj(ab)
+        host = np.ascontiguousarray(ab.T.astype(np.complex128 if cplx else np.float64))
+        data = torch.from_numpy(host).to(device)
+        return cls(n, b1 - 1, cplx, data)
+
+    def struct(self) -> N.fb_band:
+        return N.fb_band(self.n, self.b, N.FB_COMPLEX128 if self.complex_ else N.FB_REAL64,
+                         self.b + 1, C.c_void_p(self.data.data_ptr()))
+
+
+def _as_band(B) -> DeviceBand:
+    return B if isinstance(B, DeviceBand) else DeviceBand.from_band(B)
+
+
+def _workspace(call, lw: C.c_size_t, device) -> torch.Tensor:
+    return torch.empty(max(int(lw.value), 256), dtype=torch.uint8, device=device)
+
+
+def band_inertia(B, shifts, stream=None):
+    """(n_neg, n_zero, n_pos) of B - s I for each shift (numpy int32 arrays)."""
+    B = _as_band(B)
+    sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.float64).ravel())
+    k = len(sh)
+    neg = np.zeros(k, np.int32)
+    zero = np.zeros(k, np.int32)
+    pos = np.zeros(k, np.int32)
+    bs = B.struct()
+    lw = C.c_size_t(0)
+    L = N.lib()
+    pd = sh.ctypes.data_as(N.PD)
+    pn, pz, pp = (a.ctypes.data_as(N.PI32) for a in (neg, zero, pos))
+    N.check("band_inertia", L.band_inertia(C.byref(bs), k, pd, pn, pz, pp, None, C.byref(lw),
+                                           C.c_void_p(_stream_handle(stream))))
+    ws = _workspace(None, lw, B.data.device)
+    lw2 = C.c_size_t(ws.numel())
+    N.check("band_inertia", L.band_inertia(C.byref(bs), k, pd, pn, pz, pp,
+                                           C.c_void_p(ws.data_ptr()), C.byref(lw2),
+                                           C.c_void_p(_stream_handle(stream))))
+    return neg, zero, pos
+
+
+@dataclass
+class SolveResult:
+    X: list
+    XH: list
+    resid: np.ndarray
+    passes: np.ndarray
+    status: int
+
+
+def band_shifted_solve(B, z, Y, want_h=True, precision=0, ir_tol=1e-10, ir_max=4,
+                       resid=True, X=None, XH=None, stream=None) -> SolveResult:
+    """Solve (z_s I - B) X_s = Y_s (and the conjugate-transposed systems).
+
+    ``z``: sequence of complex shifts; ``Y``: one (n, m_s) complex128
+    column-major device tensor per shift (the same tensor may be shared).
+    """
+    B = _as_band(B)
+    z = np.asarray(z, dtype=np.complex128).ravel()
+    ns = len(z)
+    if len(Y) != ns:
+        raise ValueError("one right-hand-side block per shift")
+    zz = np.ascontiguousarray(np.stack([z.real, z.imag], axis=1).ravel())
+    m = np.array([y.shape[1] for y in Y], np.int32)
+    for y in Y:
+        if y.dtype != torch.complex128 or y.stride(0) != 1:
+            raise ValueError("Y blocks must be complex128 column-major")
+    if X is None:
+        X = [colmajor(B.n, int(mm), device=B.data.device) for mm in m]
+    if want_h and XH is None:
+        XH = [colmajor(B.n, int(mm), device=B.data.device) for mm in m]
+    ldy = np.array([y.stride(1) if y.shape[1] > 1 else B.n for y in Y], np.int64)
+    ldx = np.array([x.stride(1) if x.shape[1] > 1 else B.n for x in X], np.int64)
+    Yp = (C.c_void_p * ns)(*[y.data_ptr() for y in Y])
+    Xp = (C.c_void_p * ns)(*[x.data_ptr() for x in X])
+    XHp = (C.c_void_p * ns)(*[x.data_ptr() for x in XH]) if want_h else None
+    res = np.zeros(ns, np.float64)
+    passes = np.zeros(ns, np.int32)
+    o = N.fb_solve_opts(precision, ir_tol, ir_max, 0)
+    bs = B.struct()
+    L = N.lib()
+    sh = C.c_void_p(_stream_handle(stream))
+    args = (C.byref(bs), ns, zz.ctypes.data_as(N.PD), m.ctypes.data_as(N.PI32), Yp,
+            ldy.ctypes.data_as(N.PI64), Xp, XHp, ldx.ctypes.data_as(N.PI64),
+            res.ctypes.data_as(N.PD) if resid else None, passes.ctypes.data_as(N.PI32),
+            C.byref(o))
+    lw = C.c_size_t(0)
+    N.check("band_shifted_solve", L.band_shifted_solve(*args, None, C.byref(lw), sh))
+    ws = _workspace(None, lw, B.data.device)
+    lw2 = C.c_size_t(ws.numel())
+    rc = L.band_shifted_solve(*args, C.c_void_p(ws.data_ptr()), C.byref(lw2), sh)
+    N.check("band_shifted_solve", rc, allow_positive=True)
+    return SolveResult(X, XH if want_h else None, res, passes, rc)
+
+
+def device_info():
+    cus = C.c_int32(0)
+    name = C.create_string_buffer(64)
+    N.check("fb_device_info", N.lib().fb_device_info(C.byref(cus), name, 64))
+    return int(cus.value), name.value.decode()

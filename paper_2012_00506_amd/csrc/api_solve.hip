@@ -1,0 +1,320 @@
+// C ABI: band_inertia, band_shifted_solve, fb_strerror, fb_device_info.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "solve_job.h"
+
+namespace fb {
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return cus;
+}
+
+int check_band(const fb_band* B) {
+  if (!B) return -1;
+  if (B->n < 1 || B->b < 0 || B->b >= B->n) return -1;
+  if (B->dtype != FB_REAL64 && B->dtype != FB_COMPLEX128) return -1;
+  if (B->ldab < B->b + 1 || B->ab == nullptr) return -1;
+  if (B->b > 128) return -1;  // block kernels are sized for b <= 128
+  return 0;
+}
+
+// Factor nsys shifted systems (precision R) into the arena.
+template <typename R>
+struct FactorBufs {
+  cx<R>* mats = nullptr;
+  int16_t* perm = nullptr;
+  int32_t* info = nullptr;
+  cx<R>* scratch = nullptr;
+  c128* z = nullptr;
+};
+
+template <typename R>
+void carve_factors(Arena& ar, const Band& bd, int nsys, FactorBufs<R>& f) {
+  int K = (int)((bd.n + bd.b - 1) / bd.b);
+  size_t bb = (size_t)bd.b * bd.b;
+  f.mats = ar.take<cx<R>>((size_t)nsys * K * 5 * bb);
+  f.perm = ar.take<int16_t>((size_t)nsys * K * 2 * bd.b);
+  f.info = ar.take<int32_t>(nsys);
+  size_t sc = lu_window_scratch<R>(bd.b, nsys);
+  f.scratch = sc ? ar.take<cx<R>>(sc / sizeof(cx<R>)) : nullptr;
+  f.z = ar.take<c128>(nsys);
+}
+
+template <typename R>
+int factor_systems(const Band& bd, int nsys, const double* z_host, FactorBufs<R>& f,
+                   hipStream_t st) {
+  FB_HIP(hipMemcpyAsync(f.z, z_host, sizeof(c128) * nsys, hipMemcpyHostToDevice, st));
+  FB_TRY(launch_lu_impl<R>(bd, nsys, f.z, f.mats, f.perm, f.info, f.scratch, st));
+  std::vector<int32_t> info(nsys);
+  FB_HIP(hipMemcpyAsync(info.data(), f.info, sizeof(int32_t) * nsys, hipMemcpyDeviceToHost, st));
+  FB_HIP(hipStreamSynchronize(st));
+  for (int s = 0; s < nsys; ++s)
+    if (info[s] != 0) return FB_ERR_SINGULAR;
+  return 0;
+}
+
+
+}  // namespace fb
+
+using namespace fb;
+
+extern "C" const char* fb_strerror(int code) {
+  switch (code) {
+    case 0: return "success";
+    case FB_ERR_SINGULAR: return "a shifted system has an exactly zero pivot";
+    case FB_ERR_NOT_BUILT: return "no kernel for this device";
+    case FB_ERR_CERTIFY: return "a slice boundary could not be certified";
+    case FB_ERR_NOMEM: return "workspace too small";
+    case FB_ERR_NONFINITE: return "NaN or Inf in an input block";
+    case FB_ERR_INTERNAL: return "internal error";
+    default: break;
+  }
+  if (code <= -1000 && code > -2000) return hipGetErrorString((hipError_t)(-1000 - code));
+  if (code < 0 && code > -100) return "invalid argument";
+  if (code > 0) return "some slices or systems did not converge";
+  return "unknown error";
+}
+
+extern "C" int fb_device_info(int32_t* cus, char* name, int32_t cap) {
+  int dev = 0;
+  FB_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t p;
+  FB_HIP(hipGetDeviceProperties(&p, dev));
+  if (cus) *cus = p.multiProcessorCount;
+  if (name && cap > 0) {
+    strncpy(name, p.gcnArchName, (size_t)cap - 1);
+    name[cap - 1] = 0;
+  }
+  return 0;
+}
+
+extern "C" int band_inertia(const fb_band* B, int32_t nshift, const double* shifts,
+                            int32_t* n_neg, int32_t* n_zero, int32_t* n_pos, void* work,
+                            size_t* lwork, void* stream) {
+  if (check_band(B)) return -1;
+  if (nshift < 0) return -2;
+  if (nshift > 0 && !shifts) return -3;
+  if (nshift > 0 && !n_neg) return -4;
+  if (!lwork) return -8;
+  hipStream_t st = (hipStream_t)stream;
+  Arena ar;
+  ar.base = (char*)work;
+  ar.cap = *lwork;
+  Band bd;
+  FB_TRY(ingest_band(B, bd, ar, st));
+  double* sh = ar.take<double>(std::max(nshift, 1));
+  int32_t* cnt = ar.take<int32_t>(3 * (size_t)std::max(nshift, 1));
+  size_t scb = inertia_scratch_bytes(bd, nshift);
+  void* scratch = scb ? (void*)ar.take<char>(scb) : nullptr;
+  if (work == nullptr) {
+    *lwork = ar.used;
+    return 0;
+  }
+  if (!ar.fits()) return FB_ERR_NOMEM;
+  if (nshift == 0) return 0;
+  for (int i = 0; i < nshift; ++i)
+    if (!isfinite(shifts[i])) return -3;
+  FB_HIP(hipMemcpyAsync(sh, shifts, sizeof(double) * nshift, hipMemcpyHostToDevice, st));
+  FB_TRY(launch_inertia(bd, nshift, sh, cnt, scratch, st));
+  std::vector<int32_t> h(3 * (size_t)nshift);
+  FB_HIP(hipMemcpyAsync(h.data(), cnt, sizeof(int32_t) * 3 * nshift, hipMemcpyDeviceToHost, st));
+  FB_HIP(hipStreamSynchronize(st));
+  for (int i = 0; i < nshift; ++i) {
+    n_neg[i] = h[3 * i];
+    if (n_zero) n_zero[i] = h[3 * i + 1];
+    if (n_pos) n_pos[i] = h[3 * i + 2];
+  }
+  return 0;
+}
+
+namespace fb {
+
+// Largest number of tiles refined together (bounds the residual buffers).
+static size_t ir_wave_jobs(int64_t n, int tile) {
+  const size_t cap = (size_t)8 << 30;
+  size_t per = (size_t)n * tile * sizeof(c128);
+  size_t w = cap / per;
+  return std::max<size_t>(w, 64);
+}
+
+template <typename R>
+int shifted_solve_impl(const fb_band* B, int nsys, const double* z, const int32_t* m,
+                       const void* const* Y, const int64_t* ldy, void* const* X,
+                       void* const* XH, const int64_t* ldx, double* resid, int32_t* passes,
+                       const fb_solve_opts* o, void* work, size_t* lwork, hipStream_t st) {
+  const bool ir = (o->precision == 1);
+  Arena ar;
+  ar.base = (char*)work;
+  ar.cap = *lwork;
+  Band bd;
+  FB_TRY(ingest_band(B, bd, ar, st));
+  FactorBufs<R> f;
+  carve_factors<R>(ar, bd, nsys, f);
+
+  // jobs: every (system, direction, tile)
+  const int kTile = solve_tile<R>(bd.b);
+  std::vector<SolveJob> jobs;
+  for (int s = 0; s < nsys; ++s)
+    for (int dir = 0; dir < 2; ++dir) {
+      c128* out = (c128*)(dir == 0 ? X[s] : (XH ? XH[s] : nullptr));
+      if (!out) continue;
+      for (int c0 = 0; c0 < m[s]; c0 += kTile) {
+        SolveJob jb{};
+        jb.sys = s;
+        jb.dir = dir;
+        jb.col0 = c0;
+        jb.ncol = std::min(kTile, m[s] - c0);
+        jb.in = (const c128*)Y[s];
+        jb.mid = out;
+        jb.out = out;
+        jb.ldin = ldy[s];
+        jb.ldmid = ldx[s];
+        jb.ldout = ldx[s];
+        jb.add = 0;
+        jobs.push_back(jb);
+      }
+    }
+  const int njobs = (int)jobs.size();
+  SolveJob* jobs_dev = ar.take<SolveJob>(std::max(njobs, 1));
+  const bool need_res = ir || resid != nullptr;
+  size_t wave = need_res ? std::min<size_t>(ir_wave_jobs(bd.n, kTile), std::max(njobs, 1)) : 0;
+  ResJob* rjobs_dev = need_res ? ar.take<ResJob>(wave) : nullptr;
+  SolveJob* cjobs_dev = ir ? ar.take<SolveJob>(wave) : nullptr;
+  c128* rbuf = need_res ? ar.take<c128>(wave * (size_t)bd.n * kTile) : nullptr;
+  double* part = need_res ? ar.take<double>(residual_part_doubles(bd.n, (int)wave)) : nullptr;
+  double* ratio = need_res ? ar.take<double>(wave) : nullptr;
+  if (work == nullptr) {
+    *lwork = ar.used;
+    return 0;
+  }
+  if (!ar.fits()) return FB_ERR_NOMEM;
+
+  FB_TRY(factor_systems<R>(bd, nsys, z, f, st));
+  if (njobs == 0) return 0;
+  FB_HIP(hipMemcpyAsync(jobs_dev, jobs.data(), sizeof(SolveJob) * njobs, hipMemcpyHostToDevice, st));
+  FB_TRY(launch_solve_jobs<R>(f.mats, f.perm, bd.n, bd.b, njobs, jobs_dev, st));
+
+  std::vector<double> sys_res(nsys, 0.0);
+  std::vector<int32_t> sys_pass(nsys, 0);
+  int unconverged = 0;
+  if (need_res) {
+    std::vector<ResJob> rj;
+    std::vector<SolveJob> cj;
+    std::vector<double> rat;
+    for (size_t w0 = 0; w0 < (size_t)njobs; w0 += wave) {
+      size_t nw = std::min(wave, (size_t)njobs - w0);
+      // residual jobs of this wave, r into the wave buffer
+      rj.assign(nw, ResJob{});
+      std::vector<int> active(nw, 1);
+      for (size_t i = 0; i < nw; ++i) {
+        const SolveJob& jb = jobs[w0 + i];
+        ResJob& r = rj[i];
+        r.x = jb.out;
+        r.y = jb.in;
+        r.r = rbuf + i * (size_t)bd.n * kTile - (int64_t)jb.col0 * bd.n;
+        r.ldx = jb.ldout;
+        r.ldy = jb.ldin;
+        r.ldr = bd.n;
+        r.col0 = jb.col0;
+        r.ncol = jb.ncol;
+        r.dir = jb.dir;
+        r.z = mk(z[2 * jb.sys], z[2 * jb.sys + 1]);
+      }
+      int maxpass = ir ? o->ir_max : 0;
+      for (int pass = 0;; ++pass) {
+        // residual of the active tiles
+        std::vector<ResJob> ra;
+        std::vector<size_t> ai;
+        for (size_t i = 0; i < nw; ++i)
+          if (active[i]) {
+            ra.push_back(rj[i]);
+            ai.push_back(i);
+          }
+        if (ra.empty()) break;
+        FB_HIP(hipMemcpyAsync(rjobs_dev, ra.data(), sizeof(ResJob) * ra.size(),
+                              hipMemcpyHostToDevice, st));
+        FB_TRY(launch_residual_jobs(bd, (int)ra.size(), rjobs_dev, part, ratio, st));
+        rat.resize(ra.size());
+        FB_HIP(hipMemcpyAsync(rat.data(), ratio, sizeof(double) * ra.size(),
+                              hipMemcpyDeviceToHost, st));
+        FB_HIP(hipStreamSynchronize(st));
+        cj.clear();
+        for (size_t a = 0; a < ai.size(); ++a) {
+          size_t i = ai[a];
+          const SolveJob& jb = jobs[w0 + i];
+          bool ok = ir ? (rat[a] <= o->ir_tol) : true;
+          if (ok || pass >= maxpass) {
+            active[i] = 0;
+            double q = rat[a];
+            if (!(q <= sys_res[jb.sys])) sys_res[jb.sys] = q;
+            if (ir && !ok) ++unconverged;
+            continue;
+          }
+          SolveJob c = jb;
+          c.in = rj[i].r;
+          c.mid = rj[i].r;
+          c.ldin = bd.n;
+          c.ldmid = bd.n;
+          c.add = 1;
+          cj.push_back(c);
+          sys_pass[jb.sys] = std::max(sys_pass[jb.sys], pass + 1);
+        }
+        if (cj.empty()) break;
+        FB_HIP(hipMemcpyAsync(cjobs_dev, cj.data(), sizeof(SolveJob) * cj.size(),
+                              hipMemcpyHostToDevice, st));
+        FB_TRY(launch_solve_jobs<R>(f.mats, f.perm, bd.n, bd.b, (int)cj.size(), cjobs_dev, st));
+      }
+    }
+  } else {
+    FB_HIP(hipStreamSynchronize(st));
+  }
+  if (resid)
+    for (int s = 0; s < nsys; ++s) resid[s] = sys_res[s];
+  if (passes)
+    for (int s = 0; s < nsys; ++s) passes[s] = sys_pass[s];
+  if (unconverged) {
+    int ns = 0;
+    for (int s = 0; s < nsys; ++s) ns += (ir && sys_res[s] > o->ir_tol) ? 1 : 0;
+    return ns;
+  }
+  return 0;
+}
+
+}  // namespace fb
+
+extern "C" int band_shifted_solve(const fb_band* B, int32_t nsys, const double* z,
+                                  const int32_t* m, const void* const* Y, const int64_t* ldy,
+                                  void* const* X, void* const* XH, const int64_t* ldx,
+                                  double* resid, int32_t* passes, const fb_solve_opts* o,
+                                  void* work, size_t* lwork, void* stream) {
+  if (check_band(B)) return -1;
+  if (nsys < 0) return -2;
+  if (nsys > 0 && !z) return -3;
+  if (nsys > 0 && !m) return -4;
+  if (nsys > 0 && (!Y || !ldy)) return -5;
+  if (nsys > 0 && !X) return -7;
+  if (nsys > 0 && !ldx) return -9;
+  if (!o) return -12;
+  if (!lwork) return -14;
+  if (o->precision != 0 && o->precision != 1) return -12;
+  if (o->precision == 1 && (!(o->ir_tol > 0) || o->ir_max < 0)) return -12;
+  for (int s = 0; s < nsys; ++s) {
+    if (m[s] < 0) return -4;
+    if (!isfinite(z[2 * s]) || !isfinite(z[2 * s + 1])) return -3;
+    if (m[s] > 0 && (!Y[s] || ldy[s] < B->n)) return -5;
+    if (m[s] > 0 && (!X[s] || ldx[s] < B->n)) return -7;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (o->precision == 1)
+    return shifted_solve_impl<float>(B, nsys, z, m, Y, ldy, X, XH, ldx, resid, passes, o, work,
+                                     lwork, st);
+  return shifted_solve_impl<double>(B, nsys, z, m, Y, ldy, X, XH, ldx, resid, passes, o, work,
+                                    lwork, st);
+}

@@ -1,0 +1,128 @@
+// Band ingest: LAPACK lower band (real or complex) -> diagonal-major complex128
+// copy, plus ||B||_1 and the Gershgorin interval.
+#include "fb_internal.h"
+
+namespace fb {
+
+// One thread per stored element in the caller's (column-major) order, so the
+// reads are coalesced; writes go to row d of the diagonal-major copy.
+__global__ void k_band_ingest(const double* __restrict__ ab, int64_t ldab, int cplx,
+                              int64_t n, int b, int bsrc, c128* __restrict__ Bd) {
+  int64_t total = (int64_t)(b + 1) * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t j = e / (b + 1);
+    int d = (int)(e - j * (b + 1));
+    c128 v = mk(0.0, 0.0);
+    if (j + d < n && d <= bsrc) {
+      if (cplx) {
+        v = mk(ab[2 * (d + j * ldab)], ab[2 * (d + j * ldab) + 1]);
+      } else {
+        v = mk(ab[d + j * ldab], 0.0);
+      }
+      if (d == 0) v.y = 0.0;  // the diagonal of a Hermitian matrix is real
+    }
+    Bd[(int64_t)d * n + j] = v;
+  }
+}
+
+// Column sums of |B| over the full Hermitian matrix: column j holds the
+// lower entries B(j+d, j) and the upper ones conj(B(j, j-d)).
+// Per block: max colsum, min(a_jj - R_j), max(a_jj + R_j).
+__global__ void k_band_colstats(const c128* __restrict__ Bd, int64_t n, int b,
+                                double* __restrict__ part) {
+  __shared__ double s0[256], s1[256], s2[256];
+  double mx = 0.0, lo = 1e308, hi = -1e308;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    double r = 0.0;
+    for (int d = 1; d <= b; ++d) {
+      if (j + d < n) r += sqrt(cabs2(Bd[(int64_t)d * n + j]));
+      if (j - d >= 0) r += sqrt(cabs2(Bd[(int64_t)d * n + j - d]));
+    }
+    double a = Bd[j].x;
+    mx = fmax(mx, r + fabs(a));
+    lo = fmin(lo, a - r);
+    hi = fmax(hi, a + r);
+  }
+  int t = threadIdx.x;
+  s0[t] = mx;
+  s1[t] = lo;
+  s2[t] = hi;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      s0[t] = fmax(s0[t], s0[t + s]);
+      s1[t] = fmin(s1[t], s1[t + s]);
+      s2[t] = fmax(s2[t], s2[t + s]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    part[3 * blockIdx.x + 0] = s0[0];
+    part[3 * blockIdx.x + 1] = s1[0];
+    part[3 * blockIdx.x + 2] = s2[0];
+  }
+}
+
+__global__ void k_band_colstats_final(const double* __restrict__ part, int nb,
+                                      double* __restrict__ out) {
+  __shared__ double s0[256], s1[256], s2[256];
+  int t = threadIdx.x;
+  double mx = 0.0, lo = 1e308, hi = -1e308;
+  for (int i = t; i < nb; i += blockDim.x) {
+    mx = fmax(mx, part[3 * i]);
+    lo = fmin(lo, part[3 * i + 1]);
+    hi = fmax(hi, part[3 * i + 2]);
+  }
+  s0[t] = mx;
+  s1[t] = lo;
+  s2[t] = hi;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      s0[t] = fmax(s0[t], s0[t + s]);
+      s1[t] = fmin(s1[t], s1[t + s]);
+      s2[t] = fmax(s2[t], s2[t + s]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    out[0] = s0[0];
+    out[1] = s1[0];
+    out[2] = s2[0];
+  }
+}
+
+static const int kStatBlocks = 256;
+
+int ingest_band(const fb_band* B, Band& out, Arena& ar, hipStream_t st) {
+  // a diagonal matrix is handled as a band of width 1 with a zero sub-diagonal
+  out.n = B->n;
+  out.b = B->b > 0 ? B->b : 1;
+  out.cplx = B->dtype == FB_COMPLEX128;
+  out.Bd = ar.take<c128>((size_t)(out.b + 1) * B->n);
+  out.stats = ar.take<double>(3);
+  double* part = ar.take<double>(3 * kStatBlocks);
+  if (ar.base == nullptr) return 0;
+  if (!ar.fits()) return FB_ERR_NOMEM;
+  int64_t total = (int64_t)(out.b + 1) * B->n;
+  int grid = (int)((total + 255) / 256);
+  if (grid > 65535 * 4) grid = 65535 * 4;
+  k_band_ingest<<<grid, 256, 0, st>>>((const double*)B->ab, B->ldab, out.cplx ? 1 : 0,
+                                      B->n, out.b, B->b, out.Bd);
+  FB_HIP(hipGetLastError());
+  k_band_colstats<<<kStatBlocks, 256, 0, st>>>(out.Bd, B->n, out.b, part);
+  FB_HIP(hipGetLastError());
+  k_band_colstats_final<<<1, 256, 0, st>>>(part, kStatBlocks, out.stats);
+  FB_HIP(hipGetLastError());
+  return 0;
+}
+
+int band_stats_host(const Band& bd, double* out3, hipStream_t st) {
+  FB_HIP(hipMemcpyAsync(out3, bd.stats, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  FB_HIP(hipStreamSynchronize(st));
+  return 0;
+}
+
+}  // namespace fb

@@ -1,0 +1,132 @@
+// Internal declarations of the banded FEAST library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/feastband.h"
+
+namespace fb {
+
+// ------------------------------------------------------------------ complex
+template <typename T>
+struct cx {
+  T x, y;
+};
+using c64 = cx<float>;
+using c128 = cx<double>;
+
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> mk(T a, T b) {
+  cx<T> r;
+  r.x = a;
+  r.y = b;
+  return r;
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) {
+  return mk(a.x + b.x, a.y + b.y);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) {
+  return mk(a.x - b.x, a.y - b.y);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) {
+  return mk(s * a.x, s * a.y);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cconj(cx<T> a) {
+  return mk(a.x, -a.y);
+}
+template <typename T>
+__host__ __device__ __forceinline__ T cabs2(cx<T> a) {
+  return a.x * a.x + a.y * a.y;
+}
+// acc += a * b
+template <typename T>
+__host__ __device__ __forceinline__ void cmac(cx<T>& acc, cx<T> a, cx<T> b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+// acc += conj(a) * b
+template <typename T>
+__host__ __device__ __forceinline__ void cmacc(cx<T>& acc, cx<T> a, cx<T> b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(-a.y, b.x, acc.y);
+}
+// 1 / a
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cinv(cx<T> a) {
+  T d = a.x * a.x + a.y * a.y;
+  return mk(a.x / d, -a.y / d);
+}
+template <typename To, typename Ti>
+__host__ __device__ __forceinline__ cx<To> ccast(cx<Ti> a) {
+  return mk((To)a.x, (To)a.y);
+}
+
+// ------------------------------------------------------------------ errors
+#define FB_HIP(expr)                                  \
+  do {                                                \
+    hipError_t _e = (expr);                           \
+    if (_e != hipSuccess) return -1000 - (int)_e;     \
+  } while (0)
+
+#define FB_TRY(expr)          \
+  do {                        \
+    int _r = (expr);          \
+    if (_r != 0) return _r;   \
+  } while (0)
+
+// ------------------------------------------------------------------ workspace
+// Bump allocator over the caller's workspace.  In query mode (base == NULL)
+// it only accumulates the size.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+  template <typename T>
+  T* take(size_t count) {
+    size_t off = (used + 255) & ~(size_t)255;
+    used = off + count * sizeof(T);
+    if (base == nullptr) return nullptr;
+    return reinterpret_cast<T*>(base + off);
+  }
+  bool fits() const { return base == nullptr || used <= cap; }
+};
+
+// ------------------------------------------------------------------ band
+// Internal copy of B: diagonal-major, Bd[d*n + j] = B(j+d, j) (complex128,
+// zero beyond the matrix), with the norms and Gershgorin bounds.
+struct Band {
+  int64_t n;
+  int b;
+  bool cplx;
+  c128* Bd;      // dev, (b+1) * n
+  double* stats; // dev, 3: ||B||_1, g_lo, g_hi
+};
+
+// Kernels launched from the host side (defined in the .hip files).
+int ingest_band(const fb_band* B, Band& out, Arena& ar, hipStream_t st);
+int band_stats_host(const Band& bd, double* out3, hipStream_t st);
+
+// inertia for nshift shifts (dev shifts array), counts dev int32 x3
+int launch_inertia(const Band& bd, int nshift, const double* shifts_dev,
+                   int32_t* cnt_dev, void* scratch, hipStream_t st);
+size_t inertia_scratch_bytes(const Band& bd, int nshift);
+
+int device_cus();
+
+}  // namespace fb

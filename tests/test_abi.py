@@ -1,0 +1,109 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, rejects invalid arguments before launching anything, and
+answers workspace queries."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "feastband.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b(\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2012_00506_amd import _native as N
+    return N.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert "band_inertia" in names and "feast_band_slice" in names and "slice_plan" in names
+    for name in names:
+        assert hasattr(L, name), f"{name} declared in feastband.h but not exported"
+
+
+def test_python_signatures_cover_header():
+    from paper_2012_00506_amd import _native as N
+    for name in declared_functions():
+        assert name in N.SIGNATURES, name
+
+
+def _band(n=10, b=2, dtype=2, ldab=None, ptr=1):
+    from paper_2012_00506_amd import _native as N
+    return N.fb_band(n, b, dtype, ldab if ldab is not None else b + 1, C.c_void_p(ptr))
+
+
+@pytest.mark.parametrize("kw", [dict(n=0), dict(b=-1), dict(b=10), dict(dtype=3), dict(ldab=2),
+                                dict(ptr=0), dict(n=400, b=129)])
+def test_invalid_band_rejected(L, kw):
+    from paper_2012_00506_amd import _native as N
+    bs = _band(**kw)
+    lw = C.c_size_t(0)
+    sh = (C.c_double * 1)(0.0)
+    neg = (C.c_int32 * 1)()
+    assert L.band_inertia(C.byref(bs), 1, sh, neg, None, None, None, C.byref(lw), None) == -1
+
+
+def test_inertia_argument_errors_and_query(L):
+    bs = _band()
+    lw = C.c_size_t(0)
+    sh = (C.c_double * 2)(0.0, 1.0)
+    neg = (C.c_int32 * 2)()
+    assert L.band_inertia(C.byref(bs), -1, sh, neg, None, None, None, C.byref(lw), None) == -2
+    assert L.band_inertia(C.byref(bs), 2, None, neg, None, None, None, C.byref(lw), None) == -3
+    assert L.band_inertia(C.byref(bs), 2, sh, None, None, None, None, C.byref(lw), None) == -4
+    assert L.band_inertia(C.byref(bs), 2, sh, neg, None, None, None, None, None) == -8
+    assert L.band_inertia(C.byref(bs), 2, sh, neg, None, None, None, C.byref(lw), None) == 0
+    assert lw.value >= (2 + 1) * 10 * 16
+
+
+def test_shifted_solve_argument_errors_and_query(L):
+    from paper_2012_00506_amd import _native as N
+    n = 100
+    bs = _band(n=n, b=4)
+    z = (C.c_double * 4)(0.1, 0.2, 0.3, 0.4)
+    m = (C.c_int32 * 2)(5, 7)
+    Y = (C.c_void_p * 2)(1, 1)
+    X = (C.c_void_p * 2)(2, 3)
+    ld = (C.c_int64 * 2)(n, n)
+    o = N.fb_solve_opts(0, 1e-10, 4, 0)
+    lw = C.c_size_t(0)
+    args = [C.byref(bs), 2, z, m, Y, ld, X, None, ld, None, None, C.byref(o), None, C.byref(lw),
+            None]
+    assert L.band_shifted_solve(*args) == 0 and lw.value > 0
+    bad = list(args)
+    bad[1] = -1
+    assert L.band_shifted_solve(*bad) == -2
+    bad = list(args)
+    bad[3] = (C.c_int32 * 2)(-1, 3)
+    assert L.band_shifted_solve(*bad) == -4
+    bad = list(args)
+    bad[5] = (C.c_int64 * 2)(n - 1, n)
+    assert L.band_shifted_solve(*bad) == -5
+    bad = list(args)
+    bad[11] = C.byref(N.fb_solve_opts(2, 1e-10, 4, 0))
+    assert L.band_shifted_solve(*bad) == -12
+    bad = list(args)
+    bad[2] = (C.c_double * 4)(float("nan"), 0, 0, 0)
+    assert L.band_shifted_solve(*bad) == -3
+    # the refined path needs residual buffers: a larger workspace
+    lw1 = C.c_size_t(0)
+    args1 = list(args)
+    args1[11] = C.byref(N.fb_solve_opts(1, 1e-10, 4, 0))
+    args1[13] = C.byref(lw1)
+    assert L.band_shifted_solve(*args1) == 0 and lw1.value > lw.value
+
+
+def test_strerror(L):
+    assert b"pivot" in L.fb_strerror(-2001)
+    assert L.fb_strerror(0) == b"success"
+    assert b"invalid" in L.fb_strerror(-3)
