@@ -16,7 +16,8 @@ Readings of points the paper leaves open:
   produces) and are not reported; the exact count is what tells them apart;
 * orthonormalisation (the mass matrix of the standard problem is I):
   Q is replaced by Q V s^{-1/2} from the eigen-decomposition Q^H Q = V s V^H,
-  dropping directions with s_k <= 1e-14 max(s);
+  dropping directions with s_k <= 1e-14 max(s) (if any are dropped, the
+  next start block keeps the trailing columns of the previous one);
 * for complex Hermitian B the filter is
   Q = sum_j [w_j (z_j I - B)^{-1} Y + conj(w_j) (z_j I - B)^{-H} Y];
   for real symmetric B with real Y it is Q = sum_j 2 Re[w_j (z_j I - B)^{-1} Y].
@@ -128,7 +129,7 @@ def feast_slice(ab: np.ndarray, lo: float, hi: float, Y: np.ndarray,
         good = inside & (res <= tol)
         hist.append((int(inside.sum()), int(good.sum())))
         if k < m0:
-            X = np.concatenate([X, Y[:, : m0 - k]], axis=1)
+            X = np.concatenate([X, Y[:, k:m0]], axis=1)
         Y = X
         if good.sum() == m:
             info = 0

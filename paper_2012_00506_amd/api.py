@@ -150,3 +150,95 @@ def device_info():
     name = C.create_string_buffer(64)
     N.check("fb_device_info", N.lib().fb_device_info(C.byref(cus), name, 64))
     return int(cus.value), name.value.decode()
+
+
+@dataclass
+class SliceResult:
+    lo: float
+    hi: float
+    m_found: int
+    iters: int
+    info: int
+    evals: np.ndarray      # all m0 Ritz values, converged in-slice pairs first
+    resid: np.ndarray      # their eigen-residuals ||Bx - lx|| / ||B||_1
+    Y: torch.Tensor        # (n, m0) Ritz vectors in the same order (in/out block)
+
+    @property
+    def lam(self) -> np.ndarray:
+        return self.evals[: self.m_found]
+
+    @property
+    def X(self) -> torch.Tensor:
+        return self.Y[:, : self.m_found]
+
+
+def feast_band_slice(B, lo, hi, Y, m_expected=None, n_nodes=8, tol=1e-10, max_iter=20,
+                     precision=0, ir_tol=1e-12, ir_max=4, batched=True, stream=None):
+    """FEAST on the slices [lo_i, hi_i) of B from the start blocks Y[i]
+    ((n, m0_i) column-major device tensors in the dtype of B; overwritten with
+    the Ritz vectors).  Returns one SliceResult per slice."""
+    B = _as_band(B)
+    lo = np.ascontiguousarray(np.asarray(lo, dtype=np.float64).ravel())
+    hi = np.ascontiguousarray(np.asarray(hi, dtype=np.float64).ravel())
+    ns = len(lo)
+    if len(hi) != ns or len(Y) != ns:
+        raise ValueError("lo, hi and Y must have one entry per slice")
+    want = torch.complex128 if B.complex_ else torch.float64
+    for y in Y:
+        if y.dtype != want or y.stride(0) != 1:
+            raise ValueError(f"start blocks must be column-major {want}")
+    m0 = np.array([y.shape[1] for y in Y], np.int32)
+    ldy = np.array([y.stride(1) if y.shape[1] > 1 else B.n for y in Y], np.int64)
+    dev = B.data.device
+    ev = [torch.empty(int(m), dtype=torch.float64, device=dev) for m in m0]
+    rs = [torch.empty(int(m), dtype=torch.float64, device=dev) for m in m0]
+    Yp = (C.c_void_p * ns)(*[y.data_ptr() for y in Y])
+    Ep = (C.c_void_p * ns)(*[e.data_ptr() for e in ev])
+    Rp = (C.c_void_p * ns)(*[r.data_ptr() for r in rs])
+    mexp = None if m_expected is None else np.ascontiguousarray(np.asarray(m_expected, np.int32))
+    mf = np.zeros(ns, np.int32)
+    its = np.zeros(ns, np.int32)
+    inf = np.zeros(ns, np.int32)
+    o = N.fb_feast_opts(n_nodes, tol, max_iter, precision, ir_tol, ir_max, 1 if batched else 0, 0.0)
+    bs = B.struct()
+    L = N.lib()
+    sh = C.c_void_p(_stream_handle(stream))
+    args = (C.byref(bs), ns, lo.ctypes.data_as(N.PD), hi.ctypes.data_as(N.PD),
+            m0.ctypes.data_as(N.PI32), None if mexp is None else mexp.ctypes.data_as(N.PI32),
+            Yp, ldy.ctypes.data_as(N.PI64), Ep, Rp, mf.ctypes.data_as(N.PI32),
+            its.ctypes.data_as(N.PI32), inf.ctypes.data_as(N.PI32), C.byref(o))
+    lw = C.c_size_t(0)
+    N.check("feast_band_slice", L.feast_band_slice(*args, None, C.byref(lw), sh))
+    ws = _workspace(None, lw, dev)
+    lw2 = C.c_size_t(ws.numel())
+    rc = L.feast_band_slice(*args, C.c_void_p(ws.data_ptr()), C.byref(lw2), sh)
+    N.check("feast_band_slice", rc, allow_positive=True)
+    out = []
+    for i in range(ns):
+        out.append(SliceResult(float(lo[i]), float(hi[i]), int(mf[i]), int(its[i]), int(inf[i]),
+                               ev[i].cpu().numpy(), rs[i].cpu().numpy(), Y[i]))
+    return out
+
+
+def slice_plan(B, K, mode="equal_count", lo=float("nan"), hi=float("nan"), count_tol=0.05,
+               cert_delta=1e-8, max_rounds=60, stream=None):
+    """Slice boundaries (K+1), exact counts (K) and the number of inertia
+    evaluations, by equal width or equal count (bisection)."""
+    B = _as_band(B)
+    modes = {"equal_width": N.FB_PLAN_EQUAL_WIDTH, "equal_count": N.FB_PLAN_EQUAL_COUNT}
+    o = N.fb_plan_opts(modes[mode], int(K), float(lo), float(hi), float(count_tol),
+                       float(cert_delta), int(max_rounds))
+    bounds = np.zeros(K + 1, np.float64)
+    counts = np.zeros(K, np.int32)
+    nev = C.c_int32(0)
+    bs = B.struct()
+    L = N.lib()
+    sh = C.c_void_p(_stream_handle(stream))
+    args = (C.byref(bs), C.byref(o), bounds.ctypes.data_as(N.PD), counts.ctypes.data_as(N.PI32),
+            C.byref(nev))
+    lw = C.c_size_t(0)
+    N.check("slice_plan", L.slice_plan(*args, None, C.byref(lw), sh))
+    ws = _workspace(None, lw, B.data.device)
+    lw2 = C.c_size_t(ws.numel())
+    N.check("slice_plan", L.slice_plan(*args, C.c_void_p(ws.data_ptr()), C.byref(lw2), sh))
+    return bounds, counts, int(nev.value)

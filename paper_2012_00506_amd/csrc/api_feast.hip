@@ -1,0 +1,417 @@
+// C ABI: feast_band_slice -- FEAST on band slices (Algorithm alg:FEAST of
+// Section 2.2 with the slice count check of Section 3.2).
+#include <math.h>
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "rr.h"
+#include "solve_job.h"
+
+namespace fb {
+
+// ---------------------------------------------------------------- quadrature
+// Gauss-Legendre nodes (ascending) and weights on [-1, 1] by Newton's method
+// on the Legendre polynomial P_k (three-term recurrence), weights
+// 2 / ((1 - x^2) P_k'(x)^2).
+void gauss_legendre(int k, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(k, 0.0);
+  w.assign(k, 0.0);
+  for (int i = 0; i < (k + 1) / 2; ++i) {
+    double r = cos(M_PI * (i + 0.75) / (k + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = r;
+      for (int j = 2; j <= k; ++j) {
+        double p2 = ((2.0 * j - 1.0) * r * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (k == 1) {
+        p1 = r;
+        p0 = 1.0;
+      }
+      dp = k * (r * p1 - p0) / (r * r - 1.0);
+      double dr = p1 / dp;
+      r -= dr;
+      if (fabs(dr) < 1e-16) break;
+    }
+    {
+      double p0 = 1.0, p1 = r;
+      for (int j = 2; j <= k; ++j) {
+        double p2 = ((2.0 * j - 1.0) * r * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (k == 1) p0 = 1.0;
+      dp = k * (r * p1 - p0) / (r * r - 1.0);
+    }
+    double wt = 2.0 / ((1.0 - r * r) * dp * dp);
+    x[k - 1 - i] = r;
+    w[k - 1 - i] = wt;
+    x[i] = -r;
+    w[i] = wt;
+  }
+}
+
+// Half-circle contour through the slice ends: z_j = c + r e^{i theta_j},
+// w_j = (omega_j / 4) r e^{i theta_j}, theta_j = (pi/2)(1 - x_j).
+void contour(double lo, double hi, int k, std::vector<c128>& z, std::vector<c128>& w) {
+  std::vector<double> x, om;
+  gauss_legendre(k, x, om);
+  double c = 0.5 * (lo + hi), r = 0.5 * (hi - lo);
+  z.resize(k);
+  w.resize(k);
+  for (int j = 0; j < k; ++j) {
+    double th = 0.5 * M_PI * (1.0 - x[j]);
+    c128 e = mk(cos(th), sin(th));
+    z[j] = mk(c + r * e.x, r * e.y);
+    w[j] = mk(0.25 * om[j] * r * e.x, 0.25 * om[j] * r * e.y);
+  }
+}
+
+// ---------------------------------------------------------------- rocBLAS
+static rocblas_handle blas_handle(hipStream_t st) {
+  static std::mutex mu;
+  static rocblas_handle h[64] = {};
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> g(mu);
+  if (dev < 0 || dev >= 64) return nullptr;
+  if (!h[dev] && rocblas_create_handle(&h[dev]) != rocblas_status_success) h[dev] = nullptr;
+  if (h[dev]) rocblas_set_stream(h[dev], st);
+  return h[dev];
+}
+
+// C = op(A) op(B), complex128 (plain library GEMM)
+static int zgemm(hipStream_t st, bool ta, int m, int n, int k, const c128* A, int64_t lda,
+                 const c128* B, int64_t ldb, c128* C, int64_t ldc) {
+  if (m <= 0 || n <= 0) return 0;
+  rocblas_handle h = blas_handle(st);
+  if (!h) return FB_ERR_INTERNAL;
+  rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+  rocblas_status s = rocblas_zgemm(
+      h, ta ? rocblas_operation_conjugate_transpose : rocblas_operation_none,
+      rocblas_operation_none, m, n, k, &one, (const rocblas_double_complex*)A, (rocblas_int)lda,
+      (const rocblas_double_complex*)B, (rocblas_int)ldb, &zero, (rocblas_double_complex*)C,
+      (rocblas_int)ldc);
+  return s == rocblas_status_success ? 0 : FB_ERR_INTERNAL;
+}
+
+struct SliceBufs {
+  c128 *Y, *Q, *X;      // n x m0 each (start block, filter sum, scratch)
+  c128 *G, *V, *W;      // m0 x m0
+  double *s, *lam, *res, *scale, *part;
+  int32_t *order, *idx, *kept, *sweeps;
+};
+
+template <typename R>
+int feast_impl(const fb_band* B, int nslice, const double* lo, const double* hi, const int32_t* m0,
+               const int32_t* m_expected, void* const* Y, const int64_t* ldy,
+               double* const* evals, double* const* resid, int32_t* m_found, int32_t* iters,
+               int32_t* info, const fb_feast_opts* o, void* work, size_t* lwork, hipStream_t st) {
+  const bool ir = o->precision == 1;
+  const int ne = o->n_nodes;
+  Arena ar;
+  ar.base = (char*)work;
+  ar.cap = *lwork;
+  Band bd;
+  FB_TRY(ingest_band(B, bd, ar, st));
+  const int64_t n = B->n;
+  const bool cplx = B->dtype == FB_COMPLEX128;
+  const int nsys = nslice * ne;
+  FactorBufs<R> f;
+  carve_factors<R>(ar, bd, nsys, f);
+  double* shifts = ar.take<double>(2 * nslice);
+  int32_t* cnt = ar.take<int32_t>(6 * nslice);
+  size_t iscr = inertia_scratch_bytes(bd, 2 * nslice);
+  void* iscratch = iscr ? (void*)ar.take<char>(iscr) : nullptr;
+  std::vector<SliceBufs> sb(nslice);
+  int maxm = 1;
+  for (int i = 0; i < nslice; ++i) {
+    int m = m0[i];
+    maxm = std::max(maxm, m);
+    SliceBufs& b = sb[i];
+    b.Y = ar.take<c128>((size_t)n * m);
+    b.Q = ar.take<c128>((size_t)n * m);
+    b.X = ar.take<c128>((size_t)n * m);
+    b.G = ar.take<c128>((size_t)m * m);
+    b.V = ar.take<c128>((size_t)m * m);
+    b.W = ar.take<c128>((size_t)m * m);
+    b.s = ar.take<double>(m);
+    b.lam = ar.take<double>(m);
+    b.res = ar.take<double>(m);
+    b.scale = ar.take<double>(m);
+    b.part = ar.take<double>(eig_resid_part_doubles(n, m));
+    b.order = ar.take<int32_t>(m);
+    b.idx = ar.take<int32_t>(m);
+    b.kept = ar.take<int32_t>(1);
+    b.sweeps = ar.take<int32_t>(1);
+  }
+  JacobiJob* jj_dev = ar.take<JacobiJob>(nslice);
+  int32_t* perm_dev = ar.take<int32_t>(maxm);
+  const int tile = solve_tile<R>(bd.b);
+  int max_jobs = 0;
+  for (int i = 0; i < nslice; ++i) max_jobs += (m0[i] + tile - 1) / tile;
+  RefineBufs rb;
+  carve_refine(ar, bd, tile, max_jobs, ir, ir, rb);
+  if (work == nullptr) {
+    *lwork = ar.used;
+    return 0;
+  }
+  if (!ar.fits()) return FB_ERR_NOMEM;
+
+  // ---- exact counts (Sylvester inertia at the slice ends)
+  double stats[3];
+  FB_TRY(band_stats_host(bd, stats, st));
+  std::vector<int> mexp(nslice);
+  if (m_expected) {
+    for (int i = 0; i < nslice; ++i) mexp[i] = m_expected[i];
+  } else {
+    std::vector<double> sh(2 * nslice);
+    for (int i = 0; i < nslice; ++i) {
+      sh[2 * i] = lo[i];
+      sh[2 * i + 1] = hi[i];
+    }
+    FB_HIP(hipMemcpyAsync(shifts, sh.data(), sizeof(double) * 2 * nslice, hipMemcpyHostToDevice, st));
+    FB_TRY(launch_inertia(bd, 2 * nslice, shifts, cnt, iscratch, st));
+    std::vector<int32_t> h(6 * nslice);
+    FB_HIP(hipMemcpyAsync(h.data(), cnt, sizeof(int32_t) * 6 * nslice, hipMemcpyDeviceToHost, st));
+    FB_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < nslice; ++i) mexp[i] = h[6 * i + 3] - h[6 * i];
+  }
+
+  // ---- nodes, weights and the factorisations of every (slice, node)
+  std::vector<c128> zsys(nsys), wsys(nsys);
+  std::vector<double> zh(2 * nsys);
+  for (int i = 0; i < nslice; ++i) {
+    std::vector<c128> z, w;
+    contour(lo[i], hi[i], ne, z, w);
+    for (int j = 0; j < ne; ++j) {
+      zsys[i * ne + j] = z[j];
+      wsys[i * ne + j] = w[j];
+      zh[2 * (i * ne + j)] = z[j].x;
+      zh[2 * (i * ne + j) + 1] = z[j].y;
+    }
+  }
+  FB_TRY(factor_systems<R>(bd, nsys, zh.data(), f, st));
+
+  // ---- start blocks
+  std::vector<int> done(nslice, 0), kept(nslice, 0), good(nslice, 0), inside(nslice, 0);
+  std::vector<std::vector<double>> hl(nslice), hr(nslice);
+  for (int i = 0; i < nslice; ++i) {
+    iters[i] = 0;
+    m_found[i] = 0;
+    info[i] = 0;
+    if (m0[i] < mexp[i]) {
+      info[i] = 5;
+      done[i] = 1;
+      continue;
+    }
+    FB_TRY(gather_cols(Y[i], ldy[i], !cplx, sb[i].Y, n, n, m0[i], nullptr, nullptr, st));
+  }
+
+  std::vector<double> sys_res(nsys, 0.0);
+  std::vector<int32_t> sys_pass(nsys, 0);
+  std::vector<SolveJob> jobs;
+  for (int it = 1; it <= o->max_iter; ++it) {
+    std::vector<int> act;
+    for (int i = 0; i < nslice; ++i)
+      if (!done[i]) act.push_back(i);
+    if (act.empty()) break;
+    // ---- filter: Q = sum_j w_j (z_j - B)^{-1} Y (+ conj(w_j)(z_j - B)^{-H} Y)
+    for (int i : act) FB_TRY(fill_zero(sb[i].Q, n, m0[i], n, st));
+    const int ndir = cplx ? 2 : 1;
+    for (int j = 0; j < ne; ++j)
+      for (int dir = 0; dir < ndir; ++dir) {
+        // batched: every active slice in one launch; otherwise slice by slice
+        size_t groups = o->batched ? 1 : act.size();
+        for (size_t g = 0; g < groups; ++g) {
+          jobs.clear();
+          for (size_t a = 0; a < act.size(); ++a) {
+            if (!o->batched && a != g) continue;
+            int i = act[a];
+            for (int c0 = 0; c0 < m0[i]; c0 += tile) {
+              SolveJob jb{};
+              jb.sys = i * ne + j;
+              jb.dir = dir;
+              jb.col0 = c0;
+              jb.ncol = std::min(tile, m0[i] - c0);
+              jb.in = sb[i].Y;
+              jb.mid = sb[i].X;
+              jb.out = sb[i].X;
+              jb.ldin = jb.ldmid = jb.ldout = n;
+              jb.acc = sb[i].Q;
+              jb.ldacc = n;
+              c128 w = wsys[i * ne + j];
+              jb.w = dir == 0 ? w : cconj(w);
+              jb.acc_real = cplx ? 0 : 1;
+              jobs.push_back(jb);
+            }
+          }
+          FB_TRY(solve_refine<R>(bd, f.mats, f.perm, jobs, zsys, ir, o->ir_tol, o->ir_max, ir,
+                                 rb, sys_res, sys_pass, nullptr, st));
+        }
+      }
+    // ---- orthonormalise: Q^H Q = V s V^H, keep s > 1e-14 max s, Q' = Q V s^{-1/2}
+    std::vector<JacobiJob> jj;
+    for (int i : act) {
+      int m = m0[i];
+      FB_TRY(zgemm(st, true, m, m, (int)n, sb[i].Q, n, sb[i].Q, n, sb[i].G, m));
+      FB_TRY(hermitize(sb[i].G, m, m, st));
+      JacobiJob J{};
+      J.m = m;
+      J.A = sb[i].G;
+      J.lda = m;
+      J.V = sb[i].V;
+      J.ldv = m;
+      J.W = sb[i].W;
+      J.ldw = m;
+      J.w = sb[i].s;
+      J.order = sb[i].order;
+      J.sweeps = sb[i].sweeps;
+      jj.push_back(J);
+    }
+    FB_HIP(hipMemcpyAsync(jj_dev, jj.data(), sizeof(JacobiJob) * jj.size(), hipMemcpyHostToDevice, st));
+    FB_TRY(launch_jacobi((int)jj.size(), jj_dev, 60, 1e-14, st));
+    for (int i : act) FB_TRY(gram_keep(sb[i].s, m0[i], 1e-14, sb[i].idx, sb[i].scale, sb[i].kept, st));
+    for (int i : act) FB_HIP(hipMemcpyAsync(&kept[i], sb[i].kept, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FB_HIP(hipStreamSynchronize(st));
+    jj.clear();
+    for (int i : act) {
+      int m = m0[i], k = kept[i];
+      if (k <= 0) continue;
+      // V' = W[:, idx] diag(scale) (m x k) into V; Q' = Q V' into X
+      FB_TRY(gather_cols(sb[i].W, m, false, sb[i].V, m, m, k, sb[i].idx, sb[i].scale, st));
+      FB_TRY(zgemm(st, false, (int)n, k, m, sb[i].Q, n, sb[i].V, m, sb[i].X, n));
+      // B Q' into Y (the start block is no longer needed this iteration)
+      FB_TRY(band_matmul(bd, sb[i].X, n, sb[i].Y, n, k, st));
+      // A_q = Q'^H B Q' (k x k) into G
+      FB_TRY(zgemm(st, true, k, k, (int)n, sb[i].X, n, sb[i].Y, n, sb[i].G, k));
+      FB_TRY(hermitize(sb[i].G, k, k, st));
+      JacobiJob J{};
+      J.m = k;
+      J.A = sb[i].G;
+      J.lda = k;
+      J.V = sb[i].V;
+      J.ldv = k;
+      J.W = sb[i].W;
+      J.ldw = k;
+      J.w = sb[i].lam;
+      J.order = sb[i].order;
+      J.sweeps = sb[i].sweeps;
+      jj.push_back(J);
+    }
+    if (!jj.empty()) {
+      FB_HIP(hipMemcpyAsync(jj_dev, jj.data(), sizeof(JacobiJob) * jj.size(), hipMemcpyHostToDevice, st));
+      FB_TRY(launch_jacobi((int)jj.size(), jj_dev, 60, 1e-14, st));
+    }
+    for (int i : act) {
+      int m = m0[i], k = kept[i];
+      if (k <= 0) continue;
+      // Ritz vectors X = Q' W into Q; residuals; Q becomes the next start block
+      FB_TRY(zgemm(st, false, (int)n, k, k, sb[i].X, n, sb[i].W, k, sb[i].Q, n));
+      FB_TRY(eig_residuals(bd, sb[i].Q, n, sb[i].lam, k, sb[i].part, sb[i].res, st));
+      if (k < m)  // rank-deficient filter output: keep the trailing start vectors
+        FB_HIP(hipMemcpy2DAsync(sb[i].Q + (size_t)k * n, n * sizeof(c128), sb[i].Y + (size_t)k * n,
+                                n * sizeof(c128), n * sizeof(c128), m - k,
+                                hipMemcpyDeviceToDevice, st));
+      hl[i].resize(k);
+      hr[i].resize(k);
+      FB_HIP(hipMemcpyAsync(hl[i].data(), sb[i].lam, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+      FB_HIP(hipMemcpyAsync(hr[i].data(), sb[i].res, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+    }
+    FB_HIP(hipStreamSynchronize(st));
+    for (int i : act) {
+      std::swap(sb[i].Y, sb[i].Q);  // next start block = all Ritz vectors
+      iters[i] = it;
+      int k = kept[i], g = 0, in = 0;
+      for (int c = 0; c < k; ++c) {
+        bool ins = hl[i][c] >= lo[i] && hl[i][c] < hi[i];
+        in += ins;
+        g += ins && hr[i][c] <= o->tol;
+      }
+      good[i] = g;
+      inside[i] = in;
+      if (g == mexp[i]) done[i] = 1;
+    }
+  }
+
+  // ---- outputs: converged in-slice pairs first (ascending), then the rest
+  int nbad = 0;
+  for (int i = 0; i < nslice; ++i) {
+    if (info[i] == 5) {
+      ++nbad;
+      continue;
+    }
+    int m = m0[i], k = kept[i];
+    std::vector<int32_t> perm;
+    std::vector<double> ev, rs;
+    for (int c = 0; c < k; ++c)
+      if (hl[i][c] >= lo[i] && hl[i][c] < hi[i] && hr[i][c] <= o->tol) perm.push_back(c);
+    for (int c = 0; c < k; ++c)
+      if (!(hl[i][c] >= lo[i] && hl[i][c] < hi[i] && hr[i][c] <= o->tol)) perm.push_back(c);
+    for (int c = k; c < m; ++c) perm.push_back(c);
+    for (int c = 0; c < m; ++c) {
+      int p = perm[c];
+      ev.push_back(p < k ? hl[i][p] : NAN);
+      rs.push_back(p < k ? hr[i][p] : INFINITY);
+    }
+    m_found[i] = good[i];
+    if (done[i])
+      info[i] = (k < m) ? 4 : 0;
+    else
+      info[i] = (good[i] > mexp[i] || inside[i] < mexp[i]) ? 2 : 1;
+    if (info[i] == 1 || info[i] == 2) ++nbad;
+    FB_HIP(hipMemcpyAsync(perm_dev, perm.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
+    FB_TRY(store_cols(sb[i].Y, n, Y[i], ldy[i], !cplx, n, m, perm_dev, st));
+    FB_HIP(hipMemcpyAsync(evals[i], ev.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+    FB_HIP(hipMemcpyAsync(resid[i], rs.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+    FB_HIP(hipStreamSynchronize(st));
+  }
+  return nbad;
+}
+
+}  // namespace fb
+
+using namespace fb;
+
+extern "C" int feast_band_slice(const fb_band* B, int32_t nslice, const double* lo,
+                                const double* hi, const int32_t* m0, const int32_t* m_expected,
+                                void* const* Y, const int64_t* ldy, double* const* evals,
+                                double* const* resid, int32_t* m_found, int32_t* iters,
+                                int32_t* info, const fb_feast_opts* o, void* work,
+                                size_t* lwork, void* stream) {
+  if (check_band(B)) return -1;
+  if (nslice < 0) return -2;
+  if (nslice > 0 && (!lo || !hi)) return -3;
+  if (nslice > 0 && !m0) return -5;
+  if (nslice > 0 && (!Y || !ldy)) return -7;
+  if (nslice > 0 && (!evals || !resid)) return -9;
+  if (nslice > 0 && (!m_found || !iters || !info)) return -11;
+  if (!o) return -14;
+  if (!lwork) return -16;
+  if (o->n_nodes < 1 || o->n_nodes > 64 || !(o->tol > 0) || o->max_iter < 1) return -14;
+  if (o->precision != 0 && o->precision != 1) return -14;
+  if (o->precision == 1 && (!(o->ir_tol > 0) || o->ir_max < 0)) return -14;
+  for (int i = 0; i < nslice; ++i) {
+    if (!isfinite(lo[i]) || !isfinite(hi[i]) || !(lo[i] < hi[i])) return -3;
+    if (m0[i] < 1 || m0[i] > 4096 || m0[i] > B->n) return -5;
+    if (m_expected && m_expected[i] < 0) return -6;
+    if (!Y[i] || ldy[i] < B->n) return -7;
+    if (!evals[i] || !resid[i]) return -9;
+  }
+  if (nslice == 0) {
+    if (!work) *lwork = 0;
+    return 0;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (o->precision == 1)
+    return feast_impl<float>(B, nslice, lo, hi, m0, m_expected, Y, ldy, evals, resid, m_found,
+                             iters, info, o, work, lwork, st);
+  return feast_impl<double>(B, nslice, lo, hi, m0, m_expected, Y, ldy, evals, resid, m_found,
+                            iters, info, o, work, lwork, st);
+}

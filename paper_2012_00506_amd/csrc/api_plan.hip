@@ -1,0 +1,204 @@
+// C ABI: slice_plan -- slice boundaries by exact inertia (Section 3.1,
+// Approach-1 equal counts and Approach-2 equal widths; counts per slice from
+// two inertias as in Section 3.2).  Host control over batched GPU inertia:
+// every round evaluates all open boundaries in one launch.
+#include <math.h>
+
+#include <algorithm>
+#include <map>
+#include <vector>
+
+#include "solve_job.h"
+
+namespace fb {
+
+struct InertiaRunner {
+  const Band* bd;
+  double* shifts_dev;
+  int32_t* cnt_dev;
+  void* scratch;
+  int cap;
+  hipStream_t st;
+  int evals = 0;
+  std::vector<int32_t> h;
+  // n_-(s) for every shift, in one launch per chunk of cap shifts
+  int run(const std::vector<double>& s, std::vector<int>& neg) {
+    neg.assign(s.size(), 0);
+    for (size_t c0 = 0; c0 < s.size(); c0 += cap) {
+      int nc = (int)std::min<size_t>(cap, s.size() - c0);
+      FB_HIP(hipMemcpyAsync(shifts_dev, s.data() + c0, sizeof(double) * nc, hipMemcpyHostToDevice, st));
+      FB_TRY(launch_inertia(*bd, nc, shifts_dev, cnt_dev, scratch, st));
+      h.resize(3 * (size_t)nc);
+      FB_HIP(hipMemcpyAsync(h.data(), cnt_dev, sizeof(int32_t) * 3 * nc, hipMemcpyDeviceToHost, st));
+      FB_HIP(hipStreamSynchronize(st));
+      for (int i = 0; i < nc; ++i) neg[c0 + i] = h[3 * i];
+    }
+    evals += (int)s.size();
+    return 0;
+  }
+};
+
+// Certify boundaries: n_-(s - d) = n_-(s + d), trying s + 2 d k for
+// k = 0, 1, -1, 2, -2, ..., 32, -32.  All open boundaries advance together.
+static int certify_all(InertiaRunner& ir, std::vector<double>& s, double delta,
+                       std::vector<int>& neg_out) {
+  const int nb = (int)s.size();
+  std::vector<double> base = s;
+  std::vector<int> open(nb, 1), tries(nb, 0);
+  neg_out.assign(nb, 0);
+  for (int round = 0; round < 65; ++round) {
+    std::vector<double> q;
+    std::vector<int> who;
+    for (int i = 0; i < nb; ++i)
+      if (open[i]) {
+        int t = tries[i];
+        double k = t == 0 ? 0.0 : (t % 2 ? (t + 1) / 2 : -(t / 2));
+        double c = base[i] + 2.0 * delta * k;
+        s[i] = c;
+        q.push_back(c - delta);
+        q.push_back(c + delta);
+        who.push_back(i);
+      }
+    if (who.empty()) return 0;
+    std::vector<int> neg;
+    FB_TRY(ir.run(q, neg));
+    for (size_t a = 0; a < who.size(); ++a) {
+      int i = who[a];
+      if (neg[2 * a] == neg[2 * a + 1]) {
+        open[i] = 0;
+        neg_out[i] = neg[2 * a];
+      } else {
+        ++tries[i];
+      }
+    }
+  }
+  for (int i = 0; i < nb; ++i)
+    if (open[i]) return FB_ERR_CERTIFY;
+  return 0;
+}
+
+}  // namespace fb
+
+using namespace fb;
+
+extern "C" int slice_plan(const fb_band* B, const fb_plan_opts* o, double* bounds,
+                          int32_t* counts, int32_t* n_inertia, void* work, size_t* lwork,
+                          void* stream) {
+  if (check_band(B)) return -1;
+  if (!o) return -2;
+  if (o->mode != FB_PLAN_EQUAL_WIDTH && o->mode != FB_PLAN_EQUAL_COUNT) return -2;
+  if (o->K < 1 || o->K > 1 << 20) return -2;
+  if (!(o->cert_delta >= 0) || !(o->count_tol >= 0) || o->max_rounds < 0) return -2;
+  if (o->mode == FB_PLAN_EQUAL_WIDTH && (isnan(o->lo) || isnan(o->hi) || !(o->lo < o->hi)))
+    return -2;
+  if (!bounds) return -3;
+  if (!counts) return -4;
+  if (!lwork) return -7;
+  const int K = o->K;
+  hipStream_t st = (hipStream_t)stream;
+  Arena ar;
+  ar.base = (char*)work;
+  ar.cap = *lwork;
+  Band bd;
+  FB_TRY(ingest_band(B, bd, ar, st));
+  const int cap = 2 * (K + 1) + K;
+  double* sh = ar.take<double>(cap);
+  int32_t* cnt = ar.take<int32_t>(3 * (size_t)cap);
+  size_t scb = inertia_scratch_bytes(bd, cap);
+  void* scratch = scb ? (void*)ar.take<char>(scb) : nullptr;
+  if (work == nullptr) {
+    *lwork = ar.used;
+    return 0;
+  }
+  if (!ar.fits()) return FB_ERR_NOMEM;
+  double stats[3];
+  FB_TRY(band_stats_host(bd, stats, st));
+  const double delta = o->cert_delta * stats[0];
+  InertiaRunner ir{&bd, sh, cnt, scratch, cap, st};
+
+  std::vector<double> edges;
+  std::vector<int> neg;
+  if (o->mode == FB_PLAN_EQUAL_WIDTH) {
+    for (int i = 0; i <= K; ++i) edges.push_back(o->lo + (o->hi - o->lo) * i / K);
+    edges[K] = o->hi;
+    FB_TRY(certify_all(ir, edges, delta, neg));
+  } else {
+    double lo = isnan(o->lo) ? stats[1] : o->lo;
+    double hi = isnan(o->hi) ? stats[2] : o->hi;
+    if (!(lo < hi)) return -2;
+    std::vector<double> ends = {lo, hi};
+    std::vector<int> ne;
+    FB_TRY(certify_all(ir, ends, delta, ne));
+    lo = ends[0];
+    hi = ends[1];
+    const int n_lo = ne[0], n_hi = ne[1], total = n_hi - n_lo;
+    std::vector<int> target(K - 1);
+    for (int i = 1; i < K; ++i) target[i - 1] = n_lo + (int)nearbyint((double)i * total / K);  // half to even
+    const int tol = (int)floor(o->count_tol * total / K);
+    std::map<double, int> known = {{lo, n_lo}, {hi, n_hi}};
+    std::vector<double> found(K - 1, NAN);
+    std::vector<char> have(K - 1, 0);
+    for (int round = 0; round < o->max_rounds; ++round) {
+      std::vector<double> xs;
+      std::vector<int> vs;
+      for (auto& kv : known) {
+        xs.push_back(kv.first);
+        vs.push_back(kv.second);
+      }
+      std::vector<double> shifts;
+      for (int i = 0; i < K - 1; ++i) {
+        if (have[i]) continue;
+        const int t = target[i];
+        int ia = 0;
+        for (size_t j = 0; j < xs.size(); ++j)
+          if (vs[j] <= t) ia = (int)j;
+        int ib = std::min<int>(ia + 1, (int)xs.size() - 1);
+        if (abs(vs[ia] - t) <= tol) {
+          found[i] = xs[ia];
+          have[i] = 1;
+        } else if (abs(vs[ib] - t) <= tol) {
+          found[i] = xs[ib];
+          have[i] = 1;
+        } else {
+          shifts.push_back(0.5 * (xs[ia] + xs[ib]));
+        }
+      }
+      if (shifts.empty()) break;
+      std::vector<double> fresh;
+      for (double s : shifts)
+        if (!known.count(s) && std::find(fresh.begin(), fresh.end(), s) == fresh.end())
+          fresh.push_back(s);
+      std::vector<int> fv;
+      FB_TRY(ir.run(fresh, fv));
+      for (size_t j = 0; j < fresh.size(); ++j) known[fresh[j]] = fv[j];
+    }
+    for (int i = 0; i < K - 1; ++i) {
+      if (have[i]) continue;
+      // round cap reached: the known point whose count is closest to the target
+      double best = NAN;
+      int bd_ = 0;
+      for (auto& kv : known) {
+        int d = abs(kv.second - target[i]);
+        if (isnan(best) || d < bd_) {
+          best = kv.first;
+          bd_ = d;
+        }
+      }
+      found[i] = best;
+    }
+    std::vector<int> inner_neg;
+    FB_TRY(certify_all(ir, found, delta, inner_neg));
+    edges.push_back(lo);
+    neg.push_back(n_lo);
+    for (int i = 0; i < K - 1; ++i) {
+      edges.push_back(found[i]);
+      neg.push_back(inner_neg[i]);
+    }
+    edges.push_back(hi);
+    neg.push_back(n_hi);
+  }
+  for (int i = 0; i <= K; ++i) bounds[i] = edges[i];
+  for (int i = 0; i < K; ++i) counts[i] = neg[i + 1] - neg[i];
+  if (n_inertia) *n_inertia = ir.evals;
+  return 0;
+}

@@ -25,16 +25,6 @@ int check_band(const fb_band* B) {
   return 0;
 }
 
-// Factor nsys shifted systems (precision R) into the arena.
-template <typename R>
-struct FactorBufs {
-  cx<R>* mats = nullptr;
-  int16_t* perm = nullptr;
-  int32_t* info = nullptr;
-  cx<R>* scratch = nullptr;
-  c128* z = nullptr;
-};
-
 template <typename R>
 void carve_factors(Arena& ar, const Band& bd, int nsys, FactorBufs<R>& f) {
   int K = (int)((bd.n + bd.b - 1) / bd.b);
@@ -60,6 +50,11 @@ int factor_systems(const Band& bd, int nsys, const double* z_host, FactorBufs<R>
   return 0;
 }
 
+
+template void carve_factors<float>(Arena&, const Band&, int, FactorBufs<float>&);
+template void carve_factors<double>(Arena&, const Band&, int, FactorBufs<double>&);
+template int factor_systems<float>(const Band&, int, const double*, FactorBufs<float>&, hipStream_t);
+template int factor_systems<double>(const Band&, int, const double*, FactorBufs<double>&, hipStream_t);
 
 }  // namespace fb
 
@@ -137,12 +132,120 @@ extern "C" int band_inertia(const fb_band* B, int32_t nshift, const double* shif
 namespace fb {
 
 // Largest number of tiles refined together (bounds the residual buffers).
-static size_t ir_wave_jobs(int64_t n, int tile) {
+size_t ir_wave_jobs(int64_t n, int tile) {
   const size_t cap = (size_t)8 << 30;
   size_t per = (size_t)n * tile * sizeof(c128);
   size_t w = cap / per;
   return std::max<size_t>(w, 64);
 }
+
+void carve_refine(Arena& ar, const Band& bd, int tile, int max_jobs, bool ir, bool need_res,
+                  RefineBufs& rb) {
+  rb.tile = tile;
+  rb.jobs_dev = ar.take<SolveJob>(std::max(max_jobs, 1));
+  rb.cap_jobs = std::max(max_jobs, 1);
+  rb.wave = need_res ? std::min<size_t>(ir_wave_jobs(bd.n, tile), (size_t)std::max(max_jobs, 1)) : 0;
+  rb.rjobs_dev = need_res ? ar.take<ResJob>(rb.wave) : nullptr;
+  rb.cjobs_dev = ir ? ar.take<SolveJob>(rb.wave) : nullptr;
+  rb.rbuf = need_res ? ar.take<c128>(rb.wave * (size_t)bd.n * tile) : nullptr;
+  rb.part = need_res ? ar.take<double>(residual_part_doubles(bd.n, (int)rb.wave)) : nullptr;
+  rb.ratio = need_res ? ar.take<double>(rb.wave) : nullptr;
+}
+
+// Launch the solve jobs, then (need_res) compute per-tile residuals
+// ||y - A x|| / ||y|| in FP64 and (ir) refine the tiles above ir_tol with
+// correction solves until they pass or ir_max passes are spent.  The tiles
+// are processed in waves that bound the residual buffers.
+template <typename R>
+int solve_refine(const Band& bd, const cx<R>* mats, const int16_t* perm,
+                 const std::vector<SolveJob>& jobs, const std::vector<c128>& zsys, bool ir,
+                 double ir_tol, int ir_max, bool need_res, RefineBufs& rb,
+                 std::vector<double>& sys_res, std::vector<int32_t>& sys_pass, int* unconverged,
+                 hipStream_t st) {
+  const int njobs = (int)jobs.size();
+  if (njobs == 0) return 0;
+  if (njobs > rb.cap_jobs) return FB_ERR_INTERNAL;
+  FB_HIP(hipMemcpyAsync(rb.jobs_dev, jobs.data(), sizeof(SolveJob) * njobs, hipMemcpyHostToDevice, st));
+  FB_TRY(launch_solve_jobs<R>(mats, perm, bd.n, bd.b, njobs, rb.jobs_dev, st));
+  if (!need_res) return 0;
+  const int tile = rb.tile;
+  std::vector<ResJob> rj, ra;
+  std::vector<SolveJob> cj;
+  std::vector<double> rat;
+  std::vector<size_t> ai;
+  for (size_t w0 = 0; w0 < (size_t)njobs; w0 += rb.wave) {
+    size_t nw = std::min(rb.wave, (size_t)njobs - w0);
+    rj.assign(nw, ResJob{});
+    std::vector<int> active(nw, 1);
+    for (size_t i = 0; i < nw; ++i) {
+      const SolveJob& jb = jobs[w0 + i];
+      ResJob& r = rj[i];
+      r.x = jb.out;
+      r.y = jb.in;
+      r.r = rb.rbuf + i * (size_t)bd.n * tile - (int64_t)jb.col0 * bd.n;
+      r.ldx = jb.ldout;
+      r.ldy = jb.ldin;
+      r.ldr = bd.n;
+      r.col0 = jb.col0;
+      r.ncol = jb.ncol;
+      r.dir = jb.dir;
+      r.z = zsys[jb.sys];
+    }
+    const int maxpass = ir ? ir_max : 0;
+    for (int pass = 0;; ++pass) {
+      ra.clear();
+      ai.clear();
+      for (size_t i = 0; i < nw; ++i)
+        if (active[i]) {
+          ra.push_back(rj[i]);
+          ai.push_back(i);
+        }
+      if (ra.empty()) break;
+      FB_HIP(hipMemcpyAsync(rb.rjobs_dev, ra.data(), sizeof(ResJob) * ra.size(),
+                            hipMemcpyHostToDevice, st));
+      FB_TRY(launch_residual_jobs(bd, (int)ra.size(), rb.rjobs_dev, rb.part, rb.ratio, st));
+      rat.resize(ra.size());
+      FB_HIP(hipMemcpyAsync(rat.data(), rb.ratio, sizeof(double) * ra.size(),
+                            hipMemcpyDeviceToHost, st));
+      FB_HIP(hipStreamSynchronize(st));
+      cj.clear();
+      for (size_t a = 0; a < ai.size(); ++a) {
+        size_t i = ai[a];
+        const SolveJob& jb = jobs[w0 + i];
+        bool ok = ir ? (rat[a] <= ir_tol) : true;
+        if (ok || pass >= maxpass) {
+          active[i] = 0;
+          double q = rat[a];
+          if (!(q <= sys_res[jb.sys])) sys_res[jb.sys] = q;
+          if (ir && !ok && unconverged) ++*unconverged;
+          continue;
+        }
+        SolveJob c = jb;
+        c.in = rj[i].r;
+        c.mid = rj[i].r;
+        c.ldin = bd.n;
+        c.ldmid = bd.n;
+        c.add = 1;
+        cj.push_back(c);
+        sys_pass[jb.sys] = std::max(sys_pass[jb.sys], pass + 1);
+      }
+      if (cj.empty()) break;
+      FB_HIP(hipMemcpyAsync(rb.cjobs_dev, cj.data(), sizeof(SolveJob) * cj.size(),
+                            hipMemcpyHostToDevice, st));
+      FB_TRY(launch_solve_jobs<R>(mats, perm, bd.n, bd.b, (int)cj.size(), rb.cjobs_dev, st));
+    }
+  }
+  return 0;
+}
+
+template int solve_refine<float>(const Band&, const c64*, const int16_t*,
+                                 const std::vector<SolveJob>&, const std::vector<c128>&, bool,
+                                 double, int, bool, RefineBufs&, std::vector<double>&,
+                                 std::vector<int32_t>&, int*, hipStream_t);
+template int solve_refine<double>(const Band&, const c128*, const int16_t*,
+                                  const std::vector<SolveJob>&, const std::vector<c128>&, bool,
+                                  double, int, bool, RefineBufs&, std::vector<double>&,
+                                  std::vector<int32_t>&, int*, hipStream_t);
 
 template <typename R>
 int shifted_solve_impl(const fb_band* B, int nsys, const double* z, const int32_t* m,
@@ -159,37 +262,30 @@ int shifted_solve_impl(const fb_band* B, int nsys, const double* z, const int32_
   carve_factors<R>(ar, bd, nsys, f);
 
   // jobs: every (system, direction, tile)
-  const int kTile = solve_tile<R>(bd.b);
+  const int tile = solve_tile<R>(bd.b);
   std::vector<SolveJob> jobs;
   for (int s = 0; s < nsys; ++s)
     for (int dir = 0; dir < 2; ++dir) {
       c128* out = (c128*)(dir == 0 ? X[s] : (XH ? XH[s] : nullptr));
       if (!out) continue;
-      for (int c0 = 0; c0 < m[s]; c0 += kTile) {
+      for (int c0 = 0; c0 < m[s]; c0 += tile) {
         SolveJob jb{};
         jb.sys = s;
         jb.dir = dir;
         jb.col0 = c0;
-        jb.ncol = std::min(kTile, m[s] - c0);
+        jb.ncol = std::min(tile, m[s] - c0);
         jb.in = (const c128*)Y[s];
         jb.mid = out;
         jb.out = out;
         jb.ldin = ldy[s];
         jb.ldmid = ldx[s];
         jb.ldout = ldx[s];
-        jb.add = 0;
         jobs.push_back(jb);
       }
     }
-  const int njobs = (int)jobs.size();
-  SolveJob* jobs_dev = ar.take<SolveJob>(std::max(njobs, 1));
   const bool need_res = ir || resid != nullptr;
-  size_t wave = need_res ? std::min<size_t>(ir_wave_jobs(bd.n, kTile), std::max(njobs, 1)) : 0;
-  ResJob* rjobs_dev = need_res ? ar.take<ResJob>(wave) : nullptr;
-  SolveJob* cjobs_dev = ir ? ar.take<SolveJob>(wave) : nullptr;
-  c128* rbuf = need_res ? ar.take<c128>(wave * (size_t)bd.n * kTile) : nullptr;
-  double* part = need_res ? ar.take<double>(residual_part_doubles(bd.n, (int)wave)) : nullptr;
-  double* ratio = need_res ? ar.take<double>(wave) : nullptr;
+  RefineBufs rb;
+  carve_refine(ar, bd, tile, (int)jobs.size(), ir, need_res, rb);
   if (work == nullptr) {
     *lwork = ar.used;
     return 0;
@@ -197,84 +293,14 @@ int shifted_solve_impl(const fb_band* B, int nsys, const double* z, const int32_
   if (!ar.fits()) return FB_ERR_NOMEM;
 
   FB_TRY(factor_systems<R>(bd, nsys, z, f, st));
-  if (njobs == 0) return 0;
-  FB_HIP(hipMemcpyAsync(jobs_dev, jobs.data(), sizeof(SolveJob) * njobs, hipMemcpyHostToDevice, st));
-  FB_TRY(launch_solve_jobs<R>(f.mats, f.perm, bd.n, bd.b, njobs, jobs_dev, st));
-
+  std::vector<c128> zsys(nsys);
+  for (int s = 0; s < nsys; ++s) zsys[s] = mk(z[2 * s], z[2 * s + 1]);
   std::vector<double> sys_res(nsys, 0.0);
   std::vector<int32_t> sys_pass(nsys, 0);
   int unconverged = 0;
-  if (need_res) {
-    std::vector<ResJob> rj;
-    std::vector<SolveJob> cj;
-    std::vector<double> rat;
-    for (size_t w0 = 0; w0 < (size_t)njobs; w0 += wave) {
-      size_t nw = std::min(wave, (size_t)njobs - w0);
-      // residual jobs of this wave, r into the wave buffer
-      rj.assign(nw, ResJob{});
-      std::vector<int> active(nw, 1);
-      for (size_t i = 0; i < nw; ++i) {
-        const SolveJob& jb = jobs[w0 + i];
-        ResJob& r = rj[i];
-        r.x = jb.out;
-        r.y = jb.in;
-        r.r = rbuf + i * (size_t)bd.n * kTile - (int64_t)jb.col0 * bd.n;
-        r.ldx = jb.ldout;
-        r.ldy = jb.ldin;
-        r.ldr = bd.n;
-        r.col0 = jb.col0;
-        r.ncol = jb.ncol;
-        r.dir = jb.dir;
-        r.z = mk(z[2 * jb.sys], z[2 * jb.sys + 1]);
-      }
-      int maxpass = ir ? o->ir_max : 0;
-      for (int pass = 0;; ++pass) {
-        // residual of the active tiles
-        std::vector<ResJob> ra;
-        std::vector<size_t> ai;
-        for (size_t i = 0; i < nw; ++i)
-          if (active[i]) {
-            ra.push_back(rj[i]);
-            ai.push_back(i);
-          }
-        if (ra.empty()) break;
-        FB_HIP(hipMemcpyAsync(rjobs_dev, ra.data(), sizeof(ResJob) * ra.size(),
-                              hipMemcpyHostToDevice, st));
-        FB_TRY(launch_residual_jobs(bd, (int)ra.size(), rjobs_dev, part, ratio, st));
-        rat.resize(ra.size());
-        FB_HIP(hipMemcpyAsync(rat.data(), ratio, sizeof(double) * ra.size(),
-                              hipMemcpyDeviceToHost, st));
-        FB_HIP(hipStreamSynchronize(st));
-        cj.clear();
-        for (size_t a = 0; a < ai.size(); ++a) {
-          size_t i = ai[a];
-          const SolveJob& jb = jobs[w0 + i];
-          bool ok = ir ? (rat[a] <= o->ir_tol) : true;
-          if (ok || pass >= maxpass) {
-            active[i] = 0;
-            double q = rat[a];
-            if (!(q <= sys_res[jb.sys])) sys_res[jb.sys] = q;
-            if (ir && !ok) ++unconverged;
-            continue;
-          }
-          SolveJob c = jb;
-          c.in = rj[i].r;
-          c.mid = rj[i].r;
-          c.ldin = bd.n;
-          c.ldmid = bd.n;
-          c.add = 1;
-          cj.push_back(c);
-          sys_pass[jb.sys] = std::max(sys_pass[jb.sys], pass + 1);
-        }
-        if (cj.empty()) break;
-        FB_HIP(hipMemcpyAsync(cjobs_dev, cj.data(), sizeof(SolveJob) * cj.size(),
-                              hipMemcpyHostToDevice, st));
-        FB_TRY(launch_solve_jobs<R>(f.mats, f.perm, bd.n, bd.b, (int)cj.size(), cjobs_dev, st));
-      }
-    }
-  } else {
-    FB_HIP(hipStreamSynchronize(st));
-  }
+  FB_TRY(solve_refine<R>(bd, f.mats, f.perm, jobs, zsys, ir, o->ir_tol, o->ir_max, need_res, rb,
+                         sys_res, sys_pass, &unconverged, st));
+  FB_HIP(hipStreamSynchronize(st));
   if (resid)
     for (int s = 0; s < nsys; ++s) resid[s] = sys_res[s];
   if (passes)

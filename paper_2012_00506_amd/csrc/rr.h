@@ -1,0 +1,39 @@
+// Rayleigh-Ritz support kernels (host launch wrappers).
+#pragma once
+#include <algorithm>
+
+#include "fb_internal.h"
+
+namespace fb {
+
+struct JacobiJob {
+  int32_t m;
+  int32_t pad_;
+  c128* A;        // in: Hermitian matrix (destroyed)
+  int64_t lda;
+  c128* V;        // scratch m x m (rotations accumulate here)
+  int64_t ldv;
+  c128* W;        // out: eigenvectors, columns in ascending eigenvalue order
+  int64_t ldw;
+  double* w;      // out: eigenvalues ascending
+  int32_t* order; // scratch m
+  int32_t* sweeps;// out (may be null)
+};
+
+int fill_zero(c128* p, int64_t rows, int64_t cols, int64_t ld, hipStream_t st);
+int gather_cols(const void* src, int64_t lds, bool real_src, c128* dst, int64_t ldd,
+                int64_t rows, int cols, const int32_t* idx_dev, const double* scale_dev,
+                hipStream_t st);
+int store_cols(const c128* src, int64_t lds, void* dst, int64_t ldd, bool real_dst, int64_t rows,
+               int cols, const int32_t* idx_dev, hipStream_t st);
+int hermitize(c128* A, int m, int64_t lda, hipStream_t st);
+int band_matmul(const Band& bd, const c128* X, int64_t ldx, c128* Y, int64_t ldy, int m,
+                hipStream_t st);
+size_t eig_resid_part_doubles(int64_t n, int m);
+int eig_residuals(const Band& bd, const c128* X, int64_t ldx, const double* lam, int m,
+                  double* part, double* res, hipStream_t st);
+int launch_jacobi(int njobs, JacobiJob* jobs_dev, int max_sweeps, double tol, hipStream_t st);
+int gram_keep(const double* s, int m, double drop, int32_t* idx, double* scale, int32_t* kept,
+              hipStream_t st);
+
+}  // namespace fb

@@ -46,6 +46,20 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
   const int64_t npad = (int64_t)K * b;
   constexpr int MAXR = 16;  // rows per thread: b <= 16 * RS
 
+  c128* accp = jb.acc ? jb.acc + (int64_t)jb.col0 * jb.ldacc : nullptr;
+  // final value of a solution entry: store (or add) it, and fold it into the
+  // node sum when accumulating
+  auto emit = [&](int64_t row, c128 v) {
+    c128* o = out + (int64_t)c * jb.ldout + row;
+    *o = jb.add ? *o + v : v;
+    if (accp) {
+      c128* a = accp + (int64_t)c * jb.ldacc + row;
+      c128 wv = jb.w * v;
+      if (jb.acc_real) wv = mk(2.0 * wv.x, 0.0);
+      *a = *a + wv;
+    }
+  };
+
   auto load_in = [&](int64_t row) -> cx<R> {
     if (!colok || row >= n) return mk<R>(0, 0);
     return ld_in<R>(in + (int64_t)c * jb.ldin + row);
@@ -139,12 +153,7 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
         for (int q = r; q < b; ++q) cmac(acc, Ui[(size_t)q * b + r], V[q * T + c]);
         xr[i] = acc;
         int64_t row = (int64_t)k * b + r;
-        if (colok && row < n) {
-          c128* o = out + (int64_t)c * jb.ldout + row;
-          c128 v = mk((double)acc.x, (double)acc.y);
-          if (jb.add) v = *o + v;
-          *o = v;
-        }
+        if (colok && row < n) emit(row, mk((double)acc.x, (double)acc.y));
       }
       __syncthreads();
       // rotate carries: x_{k+2} <- x_{k+1}, x_{k+1} <- x_k
@@ -272,12 +281,7 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
         cx<R> v = V2[i * T + c];
         if (d >= b) {
           int64_t row = (int64_t)k * b + d;
-          if (colok && row < n) {
-            c128* o = out + (int64_t)c * jb.ldout + row;
-            c128 vv = mk((double)v.x, (double)v.y);
-            if (jb.add) vv = *o + vv;
-            *o = vv;
-          }
+          if (colok && row < n) emit(row, mk((double)v.x, (double)v.y));
         } else {
           C[d * T + c] = v;
         }
@@ -290,10 +294,7 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
     for (int r = r0; r < b; r += RS) {
       if (colok && r < n) {
         cx<R> v = V2[(b + r) * T + c];
-        c128* o = out + (int64_t)c * jb.ldout + r;
-        c128 vv = mk((double)v.x, (double)v.y);
-        if (jb.add) vv = *o + vv;
-        *o = vv;
+        emit(r, mk((double)v.x, (double)v.y));
       }
     }
   }

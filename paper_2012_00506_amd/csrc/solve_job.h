@@ -15,7 +15,10 @@ struct SolveJob {
   c128* out;      // solution (written, or added to when add != 0)
   int64_t ldin, ldmid, ldout;
   int32_t add;
-  int32_t pad_;
+  int32_t acc_real;  // accumulate 2 Re(w x) instead of w x
+  c128* acc;         // if set: acc += w * (solution written to out)
+  int64_t ldacc;
+  c128 w;
 };
 
 // r = y - A x for one tile (A = zI - B, or its conjugate transpose).
@@ -43,5 +46,43 @@ int solve_tile(int b);
 size_t residual_part_doubles(int64_t n, int njobs);
 int launch_residual_jobs(const Band& bd, int njobs, const ResJob* jobs_dev, double* part,
                          double* ratio_dev, hipStream_t st);
+
+// Shifted-system factors of one call.
+template <typename R>
+struct FactorBufs {
+  cx<R>* mats = nullptr;
+  int16_t* perm = nullptr;
+  int32_t* info = nullptr;
+  cx<R>* scratch = nullptr;
+  c128* z = nullptr;
+};
+template <typename R>
+void carve_factors(Arena& ar, const Band& bd, int nsys, FactorBufs<R>& f);
+// z_host: 2*nsys doubles (re, im); returns FB_ERR_SINGULAR on a zero pivot
+template <typename R>
+int factor_systems(const Band& bd, int nsys, const double* z_host, FactorBufs<R>& f,
+                   hipStream_t st);
+
+// Buffers of the solve + refinement driver.
+struct RefineBufs {
+  int tile = 32;
+  int cap_jobs = 0;
+  size_t wave = 0;
+  SolveJob* jobs_dev = nullptr;
+  ResJob* rjobs_dev = nullptr;
+  SolveJob* cjobs_dev = nullptr;
+  c128* rbuf = nullptr;
+  double* part = nullptr;
+  double* ratio = nullptr;
+};
+void carve_refine(Arena& ar, const Band& bd, int tile, int max_jobs, bool ir, bool need_res,
+                  RefineBufs& rb);
+template <typename R>
+int solve_refine(const Band& bd, const cx<R>* mats, const int16_t* perm,
+                 const std::vector<SolveJob>& jobs, const std::vector<c128>& zsys, bool ir,
+                 double ir_tol, int ir_max, bool need_res, RefineBufs& rb,
+                 std::vector<double>& sys_res, std::vector<int32_t>& sys_pass, int* unconverged,
+                 hipStream_t st);
+int check_band(const fb_band* B);
 
 }  // namespace fb
