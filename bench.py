@@ -1,0 +1,206 @@
+#!/usr/bin/env python
+"""Shifted band-solve throughput of the FEAST filter on one MI355X.
+
+A step is one filter sweep over the whole workload: for every slice and
+every Gauss-Legendre node, the band LU of z_j I - B, the solves with the
+slice's start block (A x = y and A^H x = y), FP64 refinement to
+||y - A x|| / ||y|| <= 1e-10 (complex64 path), and the weighted node sum
+Q_i = sum_j [w_j x_j + conj(w_j) xh_j].  One right-hand-side column is one
+column of one shifted system in one direction.
+
+Default workload: complex Hermitian band n=16384, b=64, 16 equal-width
+slices of [-50, 50] x 8 nodes = 128 shifted systems, m0_i =
+max(ceil(1.5 m_i), m_i + 10) columns per slice with m_i the exact inertia
+count.  The reported value is the complex64 + FP64-refinement path; the
+plain FP64 path is measured the same way and reported beside it.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA = 157.3e12   # MI355X dense FP32 matrix, flop/s
+PEAK_FP64 = 78.6e12         # MI355X FP64 (vector and matrix), flop/s
+PEAK_HBM = 8.0e12           # bytes/s
+METRIC = "shifted band-solve RHS-cols/s, FP32+refine vs FP64, at resid ≤1e-10"
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", default="cplx-n16384-b64")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 path")
+    p.add_argument("--cpu-cols", type=int, default=256, help="columns in the CPU sample")
+    return p.parse_args()
+
+
+def cpu_baseline(cfg, ab, m0_mean, ncols):
+    """The CPU oracle on a bounded sample: one shifted system of the workload,
+    its band LU and ncols N and H solves, timed on this host.  The per-system
+    throughput is scaled to the workload's columns per system
+    (2 * mean m0): t_sys = t_LU + 2 m0 t_col."""
+    from threadpoolctl import threadpool_limits
+    from oracle import bandlu, quadrature
+    import synth
+    lo, hi = cfg.slices[len(cfg.slices) // 2]
+    z, _ = quadrature.contour(lo, hi, 8)
+    Y = synth.rhs_block(cfg.n, ncols, cfg.seed, True)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        F = bandlu.shifted_band_lu(ab, z[0])
+        t1 = time.perf_counter()
+        bandlu.lu_solve(F, Y)
+        bandlu.lu_solve_h(F, Y)
+        t2 = time.perf_counter()
+    t_lu = t1 - t0
+    t_col = (t2 - t1) / (2 * ncols)
+    cols_sys = 2.0 * m0_mean
+    value = cols_sys / (t_lu + cols_sys * t_col)
+    return {"value": value, "unit": "RHS-cols/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one shifted system of the workload (n={cfg.n}, b={cfg.b}): oracle band LU "
+                       f"{t_lu:.2f} s + {ncols} N and {ncols} H column solves {t2 - t1:.2f} s on one "
+                       f"core; scaled to {cols_sys:.0f} columns per system")}
+
+
+def run_path(fb, F, Y, Q, steps, warmup, cols_per_step):
+    import torch
+    # verification pass (not timed): every column's FP64 residual <= 1e-10
+    F.with_resid = True
+    r = F(Y, Q)
+    torch.cuda.synchronize()
+    worst = float(np.max(r.resid))
+    passes = int(np.max(r.passes))
+    F.with_resid = False
+    for _ in range(warmup):
+        F(Y, Q)
+    torch.cuda.synchronize()
+    fb.profile_enable(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        F(Y, Q)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = fb.profile_read()
+    fb.profile_enable(False)
+    ms_step = 1e3 * wall / steps
+    return {"ms_per_step": ms_step, "value": cols_per_step / (ms_step / 1e3),
+            "max_resid": worst, "ir_passes": passes, "prof": prof,
+            "event_ms_per_step": ev0.elapsed_time(ev1) / steps}
+
+
+def roofline(prof, precision):
+    name, (L, ms, work) = max(prof.items(), key=lambda kv: kv[1][1])
+    if L == 0 or ms <= 0:
+        return None
+    achieved = work / (ms / 1e3)
+    if name == "solve":
+        peak = PEAK_FP32_MFMA if precision == 1 else PEAK_FP64
+        bound = "mfma"
+    elif name in ("resid", "bandmm", "inertia"):
+        peak, bound = PEAK_FP64, "alu"
+    else:
+        peak = PEAK_FP32_MFMA if precision == 1 else PEAK_FP64
+        bound = "mfma"
+    return {"kernel": name, "bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+            "launches": L, "avg_launch_ms": ms / L, "work_per_launch_flop": work / L}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path shards by slices; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+    import paper_2012_00506_amd as fb
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(3)
+    cfg = synth.CONFIGS[args.workload]
+    t_setup = time.perf_counter()
+    ab = cfg.matrix()
+    B = fb.DeviceBand.from_band(ab)
+    edges = [cfg.slices[0][0]] + [s[1] for s in cfg.slices]
+    neg, _, _ = fb.band_inertia(B, edges)
+    counts = np.diff(neg)
+    m0 = [max(math.ceil(1.5 * int(c)), int(c) + 10) for c in counts]
+    lo = [s[0] for s in cfg.slices]
+    hi = [s[1] for s in cfg.slices]
+    Y = [synth.rhs_block_device(cfg.n, m, cfg.seed * 1000 + i, cfg.complex_)
+         for i, m in enumerate(m0)]
+    Y = [y.contiguous().t().contiguous().t() if y.stride(0) != 1 else y for y in Y]
+    Q = [fb.colmajor(cfg.n, m, Y[0].dtype) for m in m0]
+    n_nodes = 8
+    ndir = 2 if cfg.complex_ else 1
+    cols_per_step = float(sum(m0) * n_nodes * ndir)
+    setup_s = time.perf_counter() - t_setup
+
+    res = {}
+    F32 = fb.FeastFilter(B, lo, hi, m0, n_nodes=n_nodes, precision=1, ir_tol=1e-10, ir_max=6)
+    res["fp32ir"] = run_path(fb, F32, Y, Q, args.steps, args.warmup, cols_per_step)
+    del F32
+    torch.cuda.empty_cache()
+    if not args.no_fp64:
+        F64 = fb.FeastFilter(B, lo, hi, m0, n_nodes=n_nodes, precision=0)
+        res["fp64"] = run_path(fb, F64, Y, Q, args.steps, args.warmup, cols_per_step)
+        del F64
+        torch.cuda.empty_cache()
+
+    main_ = res["fp32ir"]
+    out = {
+        "metric": METRIC,
+        "value": main_["value"],
+        "unit": "RHS-cols/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 LU+solves, f64 residual/refinement",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "n": cfg.n, "b": cfg.b, "complex": cfg.complex_,
+                   "slices": len(cfg.slices), "nodes": n_nodes, "systems": len(cfg.slices) * n_nodes,
+                   "m0": m0, "rhs_cols_per_step": cols_per_step, "ir_tol": 1e-10,
+                   "parallelism": "single GPU"},
+        "roofline": roofline(main_["prof"], 1),
+        "fp32ir": {k: v for k, v in main_.items() if k != "prof"},
+        "kernels_fp32ir": {k: {"launches": v[0], "ms": v[1], "flop": v[2]}
+                           for k, v in main_["prof"].items() if v[0]},
+        "setup_s": setup_s,
+    }
+    if "fp64" in res:
+        r64 = res["fp64"]
+        out["fp64"] = {k: v for k, v in r64.items() if k != "prof"}
+        out["fp64"]["roofline"] = roofline(r64["prof"], 0)
+        out["kernels_fp64"] = {k: {"launches": v[0], "ms": v[1], "flop": v[2]}
+                               for k, v in r64["prof"].items() if v[0]}
+        out["fp32ir_over_fp64"] = main_["value"] / r64["value"]
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg, ab, float(np.mean(m0)), args.cpu_cols)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

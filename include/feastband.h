@@ -171,6 +171,44 @@ int slice_plan(const fb_band* B, const fb_plan_opts* o, double* bounds,
                int32_t* counts, int32_t* n_inertia, void* work, size_t* lwork,
                void* stream);
 
+/* Filter application only (the shifted solves of one FEAST iteration,
+ * Section 2.2, eq:feast_L2 and the quadrature sum Q = sum_j w_j Q^(j)):
+ * factor z_j I - B for every node of every slice, solve with Y[i]
+ * (N and, for complex B, H), refine (precision 1) and accumulate
+ *   Q[i] = sum_j [w_j (z_j I - B)^{-1} Y[i] + conj(w_j) (z_j I - B)^{-H} Y[i]]
+ * (real B: Q[i] = sum_j 2 Re[w_j (z_j I - B)^{-1} Y[i]]), nodes in order.
+ *  Y, Q   host arrays of dev pointers, n x m[i] in the dtype of B, leading
+ *         dimensions ldy[i], ldq[i] >= n (Y is not modified)
+ *  resid  host, nslice or NULL: max over nodes, directions and columns of
+ *         ||y - A x||_2 / ||y||_2 in FP64 (extra residual pass for precision 0)
+ *  passes host, nslice or NULL: most refinement passes of any tile
+ * o->max_iter, o->tol and o->hbm_budget are ignored.  Returns 0, or for
+ * precision 1 the number of slices with a tile above ir_tol after ir_max. */
+int feast_filter(const fb_band* B, int32_t nslice, const double* lo, const double* hi,
+                 const int32_t* m, const void* const* Y, const int64_t* ldy,
+                 void* const* Q, const int64_t* ldq, double* resid, int32_t* passes,
+                 const fb_feast_opts* o, void* work, size_t* lwork, void* stream);
+
+/* Launch timing, a tracing aid.  While enabled, every launch of the classes
+ * below is bracketed by HIP events on its own stream.  fb_profile_enable
+ * resets the counters; fb_profile_read waits for the recorded events and
+ * returns, for one class, the number of launches, their summed duration in
+ * milliseconds and their summed algorithmic work (flops; for FB_PROF_SOLVE
+ * 24 n b per right-hand-side column, for FB_PROF_RESID 8 (2b+1) n per
+ * column, for FB_PROF_LU 16 n b^2 per system, for FB_PROF_INERTIA 4 n b^2
+ * per shift). */
+#define FB_PROF_LU 0
+#define FB_PROF_INVERT 1
+#define FB_PROF_SOLVE 2
+#define FB_PROF_RESID 3
+#define FB_PROF_INERTIA 4
+#define FB_PROF_JACOBI 5
+#define FB_PROF_GEMM 6
+#define FB_PROF_BANDMM 7
+#define FB_PROF_NCLASS 8
+int fb_profile_enable(int32_t on);
+int fb_profile_read(int32_t cls, int64_t* launches, double* ms, double* work);
+
 const char* fb_strerror(int code);
 
 /* Device properties used by the library (for reports): compute units and

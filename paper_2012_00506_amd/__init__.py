@@ -5,9 +5,10 @@ The compute path is the HIP library ``libfeastband.so`` (C ABI in
 ``include/feastband.h``); this package is its Python binding.  Importing the
 binding raises if the library has not been built: there is no CPU fallback.
 """
-from .api import (DeviceBand, SliceResult, SolveResult, band_inertia, band_shifted_solve,
-                  colmajor, feast_band_slice, slice_plan,
-                  device_info, to_colmajor)
+from .api import (DeviceBand, FeastFilter, FilterResult, SliceResult, SolveResult, band_inertia,
+                  band_shifted_solve, colmajor, device_info, feast_band_slice, feast_filter,
+                  profile_enable, profile_read, slice_plan, to_colmajor)
 
-__all__ = ["DeviceBand", "SliceResult", "feast_band_slice", "slice_plan", "SolveResult", "band_inertia", "band_shifted_solve", "colmajor",
-           "device_info", "to_colmajor"]
+__all__ = ["DeviceBand", "FeastFilter", "FilterResult", "SliceResult", "SolveResult",
+           "band_inertia", "band_shifted_solve", "colmajor", "device_info", "feast_band_slice",
+           "feast_filter", "profile_enable", "profile_read", "slice_plan", "to_colmajor"]

@@ -11,6 +11,7 @@ FB_REAL64 = 1
 FB_COMPLEX128 = 2
 FB_PLAN_EQUAL_WIDTH = 0
 FB_PLAN_EQUAL_COUNT = 1
+PROF_CLASSES = ["lu", "invert", "solve", "resid", "inertia", "jacobi", "gemm", "bandmm"]
 
 
 class fb_band(C.Structure):
@@ -52,6 +53,10 @@ SIGNATURES = {
                                    PI32, C.POINTER(fb_feast_opts), P, PSZ, P]),
     "slice_plan": (C.c_int, [C.POINTER(fb_band), C.POINTER(fb_plan_opts), PD, PI32, PI32, P,
                              PSZ, P]),
+    "feast_filter": (C.c_int, [C.POINTER(fb_band), C.c_int32, PD, PD, PI32, C.POINTER(P), PI64,
+                               C.POINTER(P), PI64, PD, PI32, C.POINTER(fb_feast_opts), P, PSZ, P]),
+    "fb_profile_enable": (C.c_int, [C.c_int32]),
+    "fb_profile_read": (C.c_int, [C.c_int32, PI64, PD, PD]),
     "fb_strerror": (C.c_char_p, [C.c_int]),
     "fb_device_info": (C.c_int, [PI32, C.c_char_p, C.c_int32]),
 }

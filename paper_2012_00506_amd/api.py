@@ -242,3 +242,85 @@ def slice_plan(B, K, mode="equal_count", lo=float("nan"), hi=float("nan"), count
     lw2 = C.c_size_t(ws.numel())
     N.check("slice_plan", L.slice_plan(*args, C.c_void_p(ws.data_ptr()), C.byref(lw2), sh))
     return bounds, counts, int(nev.value)
+
+
+@dataclass
+class FilterResult:
+    Q: list
+    resid: np.ndarray | None
+    passes: np.ndarray
+    status: int
+
+
+class FeastFilter:
+    """Reusable filter application Q_i = r(B) Y_i over a fixed set of slices
+    (workspace allocated once; each call factors and solves everything)."""
+
+    def __init__(self, B, lo, hi, m, n_nodes=8, precision=0, ir_tol=1e-10, ir_max=4,
+                 batched=True, with_resid=False, device="cuda"):
+        self.B = _as_band(B)
+        self.lo = np.ascontiguousarray(np.asarray(lo, np.float64).ravel())
+        self.hi = np.ascontiguousarray(np.asarray(hi, np.float64).ravel())
+        self.m = np.ascontiguousarray(np.asarray(m, np.int32).ravel())
+        self.ns = len(self.lo)
+        self.o = N.fb_feast_opts(n_nodes, 1e-10, 1, precision, ir_tol, ir_max,
+                                 1 if batched else 0, 0.0)
+        self.with_resid = with_resid
+        self.bs = self.B.struct()
+        self.resid = np.zeros(self.ns, np.float64)
+        self.passes = np.zeros(self.ns, np.int32)
+        self._ws = None
+
+    def _args(self, Y, Q):
+        ldy = np.array([y.stride(1) if y.shape[1] > 1 else self.B.n for y in Y], np.int64)
+        ldq = np.array([q.stride(1) if q.shape[1] > 1 else self.B.n for q in Q], np.int64)
+        self._keep = (ldy, ldq)
+        Yp = (C.c_void_p * self.ns)(*[y.data_ptr() for y in Y])
+        Qp = (C.c_void_p * self.ns)(*[q.data_ptr() for q in Q])
+        self._keep2 = (Yp, Qp)
+        return (C.byref(self.bs), self.ns, self.lo.ctypes.data_as(N.PD),
+                self.hi.ctypes.data_as(N.PD), self.m.ctypes.data_as(N.PI32), Yp,
+                ldy.ctypes.data_as(N.PI64), Qp, ldq.ctypes.data_as(N.PI64),
+                self.resid.ctypes.data_as(N.PD) if self.with_resid else None,
+                self.passes.ctypes.data_as(N.PI32), C.byref(self.o))
+
+    def workspace_bytes(self, Y, Q) -> int:
+        lw = C.c_size_t(0)
+        N.check("feast_filter", N.lib().feast_filter(*self._args(Y, Q), None, C.byref(lw), None))
+        return int(lw.value)
+
+    def __call__(self, Y, Q, stream=None) -> FilterResult:
+        if self._ws is None:
+            self._ws = torch.empty(max(self.workspace_bytes(Y, Q), 256), dtype=torch.uint8,
+                                   device=self.B.data.device)
+        lw = C.c_size_t(self._ws.numel())
+        rc = N.lib().feast_filter(*self._args(Y, Q), C.c_void_p(self._ws.data_ptr()),
+                                  C.byref(lw), C.c_void_p(_stream_handle(stream)))
+        N.check("feast_filter", rc, allow_positive=True)
+        return FilterResult(Q, self.resid.copy() if self.with_resid else None,
+                            self.passes.copy(), rc)
+
+
+def feast_filter(B, lo, hi, Y, Q=None, **kw) -> FilterResult:
+    """One-shot filter application (see FeastFilter)."""
+    B = _as_band(B)
+    m = [y.shape[1] for y in Y]
+    if Q is None:
+        Q = [colmajor(B.n, mm, Y[0].dtype, B.data.device) for mm in m]
+    return FeastFilter(B, lo, hi, m, **kw)(Y, Q)
+
+
+def profile_enable(on: bool = True):
+    N.check("fb_profile_enable", N.lib().fb_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """{class: (launches, total ms, total algorithmic flops)} since enable."""
+    out = {}
+    for i, name in enumerate(N.PROF_CLASSES):
+        L = C.c_int64(0)
+        ms = C.c_double(0)
+        w = C.c_double(0)
+        N.check("fb_profile_read", N.lib().fb_profile_read(i, C.byref(L), C.byref(ms), C.byref(w)))
+        out[name] = (int(L.value), float(ms.value), float(w.value))
+    return out

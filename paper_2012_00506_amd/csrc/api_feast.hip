@@ -10,6 +10,7 @@
 
 #include "rr.h"
 #include "solve_job.h"
+#include "prof.h"
 
 namespace fb {
 
@@ -92,6 +93,7 @@ static int zgemm(hipStream_t st, bool ta, int m, int n, int k, const c128* A, in
   if (m <= 0 || n <= 0) return 0;
   rocblas_handle h = blas_handle(st);
   if (!h) return FB_ERR_INTERNAL;
+  ProfScope ps(FB_PROF_GEMM, st, 8.0 * (double)m * n * k);
   rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
   rocblas_status s = rocblas_zgemm(
       h, ta ? rocblas_operation_conjugate_transpose : rocblas_operation_none,
@@ -107,6 +109,56 @@ struct SliceBufs {
   double *s, *lam, *res, *scale, *part;
   int32_t *order, *idx, *kept, *sweeps;
 };
+
+// Q_i = sum_j w_ij (z_ij - B)^{-1} Y_i (+ conj(w_ij) (z_ij - B)^{-H} Y_i) for
+// the slices in act: nodes in order, each (node, direction) one batched
+// launch over all slices (batched) or one launch per slice; the solution of
+// each tile is folded into Q_i by the solve epilogue.
+template <typename R>
+int filter_apply(const Band& bd, const FactorBufs<R>& f, int ne, const std::vector<int>& act,
+                 const int32_t* m, c128* const* Yc, const int64_t* ldyc, c128* const* Qc,
+                 const int64_t* ldqc, c128* const* Xs, const std::vector<c128>& zsys,
+                 const std::vector<c128>& wsys, bool cplx, bool batched, bool ir, double ir_tol,
+                 int ir_max, bool need_res, RefineBufs& rb, std::vector<double>& sys_res,
+                 std::vector<int32_t>& sys_pass, int* unconverged, hipStream_t st) {
+  const int64_t n = bd.n;
+  const int tile = rb.tile;
+  for (int i : act) FB_TRY(fill_zero(Qc[i], n, m[i], ldqc[i], st));
+  const int ndir = cplx ? 2 : 1;
+  std::vector<SolveJob> jobs;
+  for (int j = 0; j < ne; ++j)
+    for (int dir = 0; dir < ndir; ++dir) {
+      size_t groups = batched ? 1 : act.size();
+      for (size_t g = 0; g < groups; ++g) {
+        jobs.clear();
+        for (size_t a = 0; a < act.size(); ++a) {
+          if (!batched && a != g) continue;
+          int i = act[a];
+          for (int c0 = 0; c0 < m[i]; c0 += tile) {
+            SolveJob jb{};
+            jb.sys = i * ne + j;
+            jb.dir = dir;
+            jb.col0 = c0;
+            jb.ncol = std::min(tile, m[i] - c0);
+            jb.in = Yc[i];
+            jb.ldin = ldyc[i];
+            jb.mid = Xs[i];
+            jb.out = Xs[i];
+            jb.ldmid = jb.ldout = n;
+            jb.acc = Qc[i];
+            jb.ldacc = ldqc[i];
+            c128 w = wsys[i * ne + j];
+            jb.w = dir == 0 ? w : cconj(w);
+            jb.acc_real = cplx ? 0 : 1;
+            jobs.push_back(jb);
+          }
+        }
+        FB_TRY(solve_refine<R>(bd, f.mats, f.perm, jobs, zsys, ir, ir_tol, ir_max, need_res, rb,
+                               sys_res, sys_pass, unconverged, st));
+      }
+    }
+  return 0;
+}
 
 template <typename R>
 int feast_impl(const fb_band* B, int nslice, const double* lo, const double* hi, const int32_t* m0,
@@ -223,39 +275,18 @@ int feast_impl(const fb_band* B, int nslice, const double* lo, const double* hi,
       if (!done[i]) act.push_back(i);
     if (act.empty()) break;
     // ---- filter: Q = sum_j w_j (z_j - B)^{-1} Y (+ conj(w_j)(z_j - B)^{-H} Y)
-    for (int i : act) FB_TRY(fill_zero(sb[i].Q, n, m0[i], n, st));
-    const int ndir = cplx ? 2 : 1;
-    for (int j = 0; j < ne; ++j)
-      for (int dir = 0; dir < ndir; ++dir) {
-        // batched: every active slice in one launch; otherwise slice by slice
-        size_t groups = o->batched ? 1 : act.size();
-        for (size_t g = 0; g < groups; ++g) {
-          jobs.clear();
-          for (size_t a = 0; a < act.size(); ++a) {
-            if (!o->batched && a != g) continue;
-            int i = act[a];
-            for (int c0 = 0; c0 < m0[i]; c0 += tile) {
-              SolveJob jb{};
-              jb.sys = i * ne + j;
-              jb.dir = dir;
-              jb.col0 = c0;
-              jb.ncol = std::min(tile, m0[i] - c0);
-              jb.in = sb[i].Y;
-              jb.mid = sb[i].X;
-              jb.out = sb[i].X;
-              jb.ldin = jb.ldmid = jb.ldout = n;
-              jb.acc = sb[i].Q;
-              jb.ldacc = n;
-              c128 w = wsys[i * ne + j];
-              jb.w = dir == 0 ? w : cconj(w);
-              jb.acc_real = cplx ? 0 : 1;
-              jobs.push_back(jb);
-            }
-          }
-          FB_TRY(solve_refine<R>(bd, f.mats, f.perm, jobs, zsys, ir, o->ir_tol, o->ir_max, ir,
-                                 rb, sys_res, sys_pass, nullptr, st));
-        }
+    {
+      std::vector<c128*> Yc(nslice), Qc(nslice), Xs(nslice);
+      std::vector<int64_t> lds(nslice, n);
+      for (int i = 0; i < nslice; ++i) {
+        Yc[i] = sb[i].Y;
+        Qc[i] = sb[i].Q;
+        Xs[i] = sb[i].X;
       }
+      FB_TRY(filter_apply<R>(bd, f, ne, act, m0, Yc.data(), lds.data(), Qc.data(), lds.data(),
+                             Xs.data(), zsys, wsys, cplx, o->batched != 0, ir, o->ir_tol,
+                             o->ir_max, ir, rb, sys_res, sys_pass, nullptr, st));
+    }
     // ---- orthonormalise: Q^H Q = V s V^H, keep s > 1e-14 max s, Q' = Q V s^{-1/2}
     std::vector<JacobiJob> jj;
     for (int i : act) {
@@ -414,4 +445,127 @@ extern "C" int feast_band_slice(const fb_band* B, int32_t nslice, const double* 
                              iters, info, o, work, lwork, st);
   return feast_impl<double>(B, nslice, lo, hi, m0, m_expected, Y, ldy, evals, resid, m_found,
                             iters, info, o, work, lwork, st);
+}
+
+namespace fb {
+
+template <typename R>
+int filter_impl(const fb_band* B, int nslice, const double* lo, const double* hi, const int32_t* m,
+                const void* const* Y, const int64_t* ldy, void* const* Q, const int64_t* ldq,
+                double* resid, int32_t* passes, const fb_feast_opts* o, void* work,
+                size_t* lwork, hipStream_t st) {
+  const bool ir = o->precision == 1;
+  const bool need_res = ir || resid != nullptr;
+  const int ne = o->n_nodes;
+  Arena ar;
+  ar.base = (char*)work;
+  ar.cap = *lwork;
+  Band bd;
+  FB_TRY(ingest_band(B, bd, ar, st));
+  const int64_t n = B->n;
+  const bool cplx = B->dtype == FB_COMPLEX128;
+  const int nsys = nslice * ne;
+  FactorBufs<R> f;
+  carve_factors<R>(ar, bd, nsys, f);
+  std::vector<c128*> Yc(nslice), Qc(nslice), Xs(nslice);
+  std::vector<int64_t> ldyc(nslice), ldqc(nslice);
+  for (int i = 0; i < nslice; ++i) {
+    Xs[i] = ar.take<c128>((size_t)n * std::max(m[i], 1));
+    if (cplx) {
+      Yc[i] = (c128*)Y[i];
+      Qc[i] = (c128*)Q[i];
+      ldyc[i] = ldy[i];
+      ldqc[i] = ldq[i];
+    } else {  // real B: complex working copies of Y and Q
+      Yc[i] = ar.take<c128>((size_t)n * std::max(m[i], 1));
+      Qc[i] = ar.take<c128>((size_t)n * std::max(m[i], 1));
+      ldyc[i] = ldqc[i] = n;
+    }
+  }
+  const int tile = solve_tile<R>(bd.b);
+  int max_jobs = 0;
+  for (int i = 0; i < nslice; ++i) max_jobs += (m[i] + tile - 1) / tile;
+  RefineBufs rb;
+  carve_refine(ar, bd, tile, max_jobs, ir, need_res, rb);
+  if (work == nullptr) {
+    *lwork = ar.used;
+    return 0;
+  }
+  if (!ar.fits()) return FB_ERR_NOMEM;
+  std::vector<c128> zsys(nsys), wsys(nsys);
+  std::vector<double> zh(2 * nsys);
+  for (int i = 0; i < nslice; ++i) {
+    std::vector<c128> z, w;
+    contour(lo[i], hi[i], ne, z, w);
+    for (int j = 0; j < ne; ++j) {
+      zsys[i * ne + j] = z[j];
+      wsys[i * ne + j] = w[j];
+      zh[2 * (i * ne + j)] = z[j].x;
+      zh[2 * (i * ne + j) + 1] = z[j].y;
+    }
+  }
+  FB_TRY(factor_systems<R>(bd, nsys, zh.data(), f, st));
+  std::vector<int> act;
+  for (int i = 0; i < nslice; ++i) {
+    if (m[i] <= 0) continue;
+    act.push_back(i);
+    if (!cplx) FB_TRY(gather_cols(Y[i], ldy[i], true, Yc[i], n, n, m[i], nullptr, nullptr, st));
+  }
+  std::vector<double> sys_res(nsys, 0.0);
+  std::vector<int32_t> sys_pass(nsys, 0);
+  int unconverged = 0;
+  FB_TRY(filter_apply<R>(bd, f, ne, act, m, Yc.data(), ldyc.data(), Qc.data(), ldqc.data(),
+                         Xs.data(), zsys, wsys, cplx, o->batched != 0, ir, o->ir_tol, o->ir_max,
+                         need_res, rb, sys_res, sys_pass, &unconverged, st));
+  if (!cplx)
+    for (int i : act) FB_TRY(store_cols(Qc[i], n, Q[i], ldq[i], true, n, m[i], nullptr, st));
+  FB_HIP(hipStreamSynchronize(st));
+  int nbad = 0;
+  for (int i = 0; i < nslice; ++i) {
+    double r = 0.0;
+    int p = 0;
+    for (int j = 0; j < ne; ++j) {
+      r = std::max(r, sys_res[i * ne + j]);
+      p = std::max(p, sys_pass[i * ne + j]);
+    }
+    if (resid) resid[i] = r;
+    if (passes) passes[i] = p;
+    if (ir && !(r <= o->ir_tol) && m[i] > 0) ++nbad;
+  }
+  return nbad;
+}
+
+}  // namespace fb
+
+extern "C" int feast_filter(const fb_band* B, int32_t nslice, const double* lo, const double* hi,
+                            const int32_t* m, const void* const* Y, const int64_t* ldy,
+                            void* const* Q, const int64_t* ldq, double* resid, int32_t* passes,
+                            const fb_feast_opts* o, void* work, size_t* lwork, void* stream) {
+  if (check_band(B)) return -1;
+  if (nslice < 0) return -2;
+  if (nslice > 0 && (!lo || !hi)) return -3;
+  if (nslice > 0 && !m) return -5;
+  if (nslice > 0 && (!Y || !ldy)) return -6;
+  if (nslice > 0 && (!Q || !ldq)) return -8;
+  if (!o) return -12;
+  if (!lwork) return -14;
+  if (o->n_nodes < 1 || o->n_nodes > 64) return -12;
+  if (o->precision != 0 && o->precision != 1) return -12;
+  if (o->precision == 1 && (!(o->ir_tol > 0) || o->ir_max < 0)) return -12;
+  for (int i = 0; i < nslice; ++i) {
+    if (!isfinite(lo[i]) || !isfinite(hi[i]) || !(lo[i] < hi[i])) return -3;
+    if (m[i] < 0) return -5;
+    if (m[i] > 0 && (!Y[i] || ldy[i] < B->n)) return -6;
+    if (m[i] > 0 && (!Q[i] || ldq[i] < B->n)) return -8;
+  }
+  if (nslice == 0) {
+    if (!work) *lwork = 0;
+    return 0;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (o->precision == 1)
+    return filter_impl<float>(B, nslice, lo, hi, m, Y, ldy, Q, ldq, resid, passes, o, work, lwork,
+                              st);
+  return filter_impl<double>(B, nslice, lo, hi, m, Y, ldy, Q, ldq, resid, passes, o, work, lwork,
+                             st);
 }

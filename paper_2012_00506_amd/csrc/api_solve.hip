@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "solve_job.h"
+#include "prof.h"
 
 namespace fb {
 
@@ -166,7 +167,10 @@ int solve_refine(const Band& bd, const cx<R>* mats, const int16_t* perm,
   if (njobs == 0) return 0;
   if (njobs > rb.cap_jobs) return FB_ERR_INTERNAL;
   FB_HIP(hipMemcpyAsync(rb.jobs_dev, jobs.data(), sizeof(SolveJob) * njobs, hipMemcpyHostToDevice, st));
-  FB_TRY(launch_solve_jobs<R>(mats, perm, bd.n, bd.b, njobs, rb.jobs_dev, st));
+  double cols = 0;
+  for (const SolveJob& jb : jobs) cols += jb.ncol;
+  FB_TRY(launch_solve_jobs<R>(mats, perm, bd.n, bd.b, njobs, rb.jobs_dev,
+                              solve_flops(bd.n, bd.b, cols), st));
   if (!need_res) return 0;
   const int tile = rb.tile;
   std::vector<ResJob> rj, ra;
@@ -203,7 +207,10 @@ int solve_refine(const Band& bd, const cx<R>* mats, const int16_t* perm,
       if (ra.empty()) break;
       FB_HIP(hipMemcpyAsync(rb.rjobs_dev, ra.data(), sizeof(ResJob) * ra.size(),
                             hipMemcpyHostToDevice, st));
-      FB_TRY(launch_residual_jobs(bd, (int)ra.size(), rb.rjobs_dev, rb.part, rb.ratio, st));
+      double rcols = 0;
+      for (const ResJob& r : ra) rcols += r.ncol;
+      FB_TRY(launch_residual_jobs(bd, (int)ra.size(), rb.rjobs_dev, rb.part, rb.ratio,
+                                  resid_flops(bd.n, bd.b, rcols), st));
       rat.resize(ra.size());
       FB_HIP(hipMemcpyAsync(rat.data(), rb.ratio, sizeof(double) * ra.size(),
                             hipMemcpyDeviceToHost, st));
@@ -232,7 +239,10 @@ int solve_refine(const Band& bd, const cx<R>* mats, const int16_t* perm,
       if (cj.empty()) break;
       FB_HIP(hipMemcpyAsync(rb.cjobs_dev, cj.data(), sizeof(SolveJob) * cj.size(),
                             hipMemcpyHostToDevice, st));
-      FB_TRY(launch_solve_jobs<R>(mats, perm, bd.n, bd.b, (int)cj.size(), rb.cjobs_dev, st));
+      double ccols = 0;
+      for (const SolveJob& c : cj) ccols += c.ncol;
+      FB_TRY(launch_solve_jobs<R>(mats, perm, bd.n, bd.b, (int)cj.size(), rb.cjobs_dev,
+                                  solve_flops(bd.n, bd.b, ccols), st));
     }
   }
   return 0;

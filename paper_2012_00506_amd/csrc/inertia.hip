@@ -10,6 +10,7 @@
 // written by step k, and a single barrier per step suffices.  The window sits in LDS when it fits and
 // in a per-shift global scratch area otherwise.
 #include "fb_internal.h"
+#include "prof.h"
 
 namespace fb {
 
@@ -105,9 +106,11 @@ int launch_inertia(const Band& bd, int nshift, const double* shifts_dev, int32_t
   bool lds = inertia_lds(bd.b);
   size_t smem = lds ? (size_t)(bd.b + 2) * (bd.b + 2) * sizeof(c128) : 0;
   if (lds) {
-    FB_HIP(hipFuncSetAttribute((const void*)k_band_ldlh_inertia,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget));
+    (void)hipFuncSetAttribute((const void*)k_band_ldlh_inertia,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
+    (void)hipGetLastError();
   }
+  ProfScope ps(FB_PROF_INERTIA, st, 4.0 * (double)bd.n * bd.b * bd.b * nshift);
   k_band_ldlh_inertia<<<nshift, kInertiaThreads, smem, st>>>(
       bd.Bd, bd.n, bd.b, shifts_dev, bd.stats, cnt_dev, (c128*)scratch, lds ? 1 : 0);
   FB_HIP(hipGetLastError());

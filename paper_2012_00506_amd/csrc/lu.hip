@@ -20,6 +20,7 @@
 // A second kernel replaces Lh11 and U(k,k) by their inverses, so that the
 // solves are chains of dense b x b products.
 #include "solve_job.h"
+#include "prof.h"
 
 namespace fb {
 
@@ -314,8 +315,11 @@ int launch_lu_impl(const Band& bd, int nsys, const c128* z_dev, cx<R>* mats, int
   (void)hipFuncSetAttribute((const void*)k_band_lu<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)kLdsBudget);
   (void)hipGetLastError();
-  k_band_lu<R><<<nsys, kLuThreads, smem, st>>>(bd.Bd, bd.n, b, K, z_dev, o, scratch, lds ? 1 : 0);
-  FB_HIP(hipGetLastError());
+  {
+    ProfScope ps(FB_PROF_LU, st, 16.0 * (double)bd.n * b * b * nsys);
+    k_band_lu<R><<<nsys, kLuThreads, smem, st>>>(bd.Bd, bd.n, b, K, z_dev, o, scratch, lds ? 1 : 0);
+    FB_HIP(hipGetLastError());
+  }
   size_t full = sizeof(cx<R>) * ((size_t)b * b + b);
   bool ilds = full <= kLdsBudget;
   size_t ismem = ilds ? full : sizeof(cx<R>) * (size_t)b;
@@ -323,6 +327,7 @@ int launch_lu_impl(const Band& bd, int nsys, const c128* z_dev, cx<R>* mats, int
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
   (void)hipGetLastError();
   int nblk = nsys * K;
+  ProfScope ps(FB_PROF_INVERT, st, 8.0 * 2.0 * nblk * b * b * b / 3.0);
   k_block_invert<R><<<2 * nblk, 256, ismem, st>>>(mats, b, nblk, ilds ? 1 : 0);
   FB_HIP(hipGetLastError());
   return 0;

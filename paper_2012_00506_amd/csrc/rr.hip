@@ -2,6 +2,7 @@
 // column gathers, and a cyclic Jacobi eigensolver for the reduced Hermitian
 // problems A_q W = W Lambda (Section 2.2, "The FEAST Algorithm").
 #include "rr.h"
+#include "prof.h"
 
 namespace fb {
 
@@ -126,6 +127,7 @@ k_band_matmul(const c128* __restrict__ Bd, int64_t n, int b, const c128* __restr
 int band_matmul(const Band& bd, const c128* X, int64_t ldx, c128* Y, int64_t ldy, int m,
                 hipStream_t st) {
   if (m <= 0) return 0;
+  ProfScope ps(FB_PROF_BANDMM, st, 8.0 * (2.0 * bd.b + 1.0) * bd.n * m);
   for (int c0 = 0; c0 < m; c0 += 65535) {
     int mc = std::min(65535, m - c0);
     dim3 grid((unsigned)((bd.n + kBmRows - 1) / kBmRows), (unsigned)mc);
@@ -367,6 +369,7 @@ k_jacobi(JacobiJob* __restrict__ jobs, int max_sweeps, double tol) {
 
 int launch_jacobi(int njobs, JacobiJob* jobs_dev, int max_sweeps, double tol, hipStream_t st) {
   if (njobs <= 0) return 0;
+  ProfScope ps(FB_PROF_JACOBI, st, 0.0);
   k_jacobi<<<njobs, kJacThreads, 0, st>>>(jobs_dev, max_sweeps, tol);
   FB_HIP(hipGetLastError());
   return 0;

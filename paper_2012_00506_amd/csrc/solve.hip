@@ -13,6 +13,7 @@
 // arithmetic is in R (float: complex64 path, double: complex128 path).
 #include "fb_internal.h"
 #include "solve_job.h"
+#include "prof.h"
 
 namespace fb {
 
@@ -309,7 +310,8 @@ int solve_tile(int b) {
 
 template <typename R, int T>
 static int launch_solve_t(const cx<R>* mats, const int16_t* perm, int64_t n, int b, int njobs,
-                          const SolveJob* jobs_dev, hipStream_t st) {
+                          const SolveJob* jobs_dev, double work, hipStream_t st) {
+  ProfScope ps(FB_PROF_SOLVE, st, work);
   const int K = (int)((n + b - 1) / b);
   if (b > 16 * (kSolveThreads / T)) return FB_ERR_INTERNAL;
   size_t smem = (size_t)4 * b * T * sizeof(cx<R>);
@@ -326,19 +328,20 @@ static int launch_solve_t(const cx<R>* mats, const int16_t* perm, int64_t n, int
 
 template <typename R>
 int launch_solve_jobs(const cx<R>* mats, const int16_t* perm, int64_t n, int b, int njobs,
-                      const SolveJob* jobs_dev, hipStream_t st) {
+                      const SolveJob* jobs_dev, double work, hipStream_t st) {
   if (njobs <= 0) return 0;
-  if (solve_tile<R>(b) == 32) return launch_solve_t<R, 32>(mats, perm, n, b, njobs, jobs_dev, st);
-  return launch_solve_t<R, 16>(mats, perm, n, b, njobs, jobs_dev, st);
+  if (solve_tile<R>(b) == 32)
+    return launch_solve_t<R, 32>(mats, perm, n, b, njobs, jobs_dev, work, st);
+  return launch_solve_t<R, 16>(mats, perm, n, b, njobs, jobs_dev, work, st);
 }
 
 template int solve_tile<float>(int);
 template int solve_tile<double>(int);
 
 template int launch_solve_jobs<float>(const c64*, const int16_t*, int64_t, int, int,
-                                      const SolveJob*, hipStream_t);
+                                      const SolveJob*, double, hipStream_t);
 template int launch_solve_jobs<double>(const c128*, const int16_t*, int64_t, int, int,
-                                       const SolveJob*, hipStream_t);
+                                       const SolveJob*, double, hipStream_t);
 
 // ---------------------------------------------------------------- residual
 // r = y - (zz x - B x) in FP64 with zz = z (N) or conj(z) (H), for the
@@ -425,8 +428,9 @@ size_t residual_part_doubles(int64_t n, int njobs) {
 }
 
 int launch_residual_jobs(const Band& bd, int njobs, const ResJob* jobs_dev, double* part,
-                         double* ratio_dev, hipStream_t st) {
+                         double* ratio_dev, double work, hipStream_t st) {
   if (njobs <= 0) return 0;
+  ProfScope ps(FB_PROF_RESID, st, work);
   int nchunk = (int)((bd.n + kResChunk - 1) / kResChunk);
   for (int j0 = 0; j0 < njobs; j0 += 65535) {
     int nj = njobs - j0 < 65535 ? njobs - j0 : 65535;

@@ -33,7 +33,7 @@ struct ResJob {
 
 template <typename R>
 int launch_solve_jobs(const cx<R>* mats, const int16_t* perm, int64_t n, int b, int njobs,
-                      const SolveJob* jobs_dev, hipStream_t st);
+                      const SolveJob* jobs_dev, double work, hipStream_t st);
 template <typename R>
 int launch_lu_impl(const Band& bd, int nsys, const c128* z_dev, cx<R>* mats, int16_t* perm,
                    int32_t* info, cx<R>* scratch, hipStream_t st);
@@ -45,7 +45,13 @@ int solve_tile(int b);
 
 size_t residual_part_doubles(int64_t n, int njobs);
 int launch_residual_jobs(const Band& bd, int njobs, const ResJob* jobs_dev, double* part,
-                         double* ratio_dev, hipStream_t st);
+                         double* ratio_dev, double work, hipStream_t st);
+// algorithmic flops: solve 24 n b per column (L: n b, U: 2 n b complex MACs),
+// FP64 residual 8 (2b+1) n per column
+inline double solve_flops(int64_t n, int b, double cols) { return 24.0 * (double)n * b * cols; }
+inline double resid_flops(int64_t n, int b, double cols) {
+  return 8.0 * (2.0 * b + 1.0) * (double)n * cols;
+}
 
 // Shifted-system factors of one call.
 template <typename R>

@@ -169,3 +169,21 @@ CONFIGS = {
         "cplx-n65536-b128", 65536, 128, True, 5, -50.0, 50.0, (),
         "complex Hermitian band n=65536 b=128, lowest 25600 eigenvalues in 64 slices"),
 }
+
+
+def rhs_block_device(n: int, m: int, seed: int, complex_: bool, device="cuda"):
+    """A seeded N(0,1) start block generated on the device with torch's
+    Philox generator (real, or (N + iN)/sqrt(2) complex), column-major (n, m).
+    Used where the block is too large to draw on the host; values differ from
+    ``rhs_block`` for the same seed."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed + 100)
+    if complex_:
+        re = torch.randn((m, n), generator=g, device=device, dtype=torch.float64)
+        im = torch.randn((m, n), generator=g, device=device, dtype=torch.float64)
+        out = torch.complex(re, im) / math.sqrt(2.0)
+        del re, im
+    else:
+        out = torch.randn((m, n), generator=g, device=device, dtype=torch.float64)
+    return out.t()
