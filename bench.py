@@ -155,6 +155,12 @@ def main():
     cols_per_step = float(sum(m0) * n_nodes * ndir)
     setup_s = time.perf_counter() - t_setup
 
+    # tune the block-solve kernel for both precisions on this shape (not timed)
+    tuned = {}
+    for prec in (1, 0):
+        v, ms = fb.autotune(B, prec, nsys=len(m0), m=int(max(m0)))
+        tuned["c64" if prec else "c128"] = {"variant": v, "ms": ms}
+
     res = {}
     F32 = fb.FeastFilter(B, lo, hi, m0, n_nodes=n_nodes, precision=1, ir_tol=1e-10, ir_max=6)
     res["fp32ir"] = run_path(fb, F32, Y, Q, args.steps, args.warmup, cols_per_step)
@@ -164,6 +170,11 @@ def main():
         F64 = fb.FeastFilter(B, lo, hi, m0, n_nodes=n_nodes, precision=0)
         res["fp64"] = run_path(fb, F64, Y, Q, args.steps, args.warmup, cols_per_step)
         del F64
+        torch.cuda.empty_cache()
+        # the plain FP64 path: one launch sequence per slice, no batching
+        F64p = fb.FeastFilter(B, lo, hi, m0, n_nodes=n_nodes, precision=0, batched=False)
+        res["fp64_plain"] = run_path(fb, F64p, Y, Q, 1, 0, cols_per_step)
+        del F64p
         torch.cuda.empty_cache()
 
     main_ = res["fp32ir"]
@@ -197,6 +208,10 @@ def main():
         out["kernels_fp64"] = {k: {"launches": v[0], "ms": v[1], "flop": v[2]}
                                for k, v in r64["prof"].items() if v[0]}
         out["fp32ir_over_fp64"] = main_["value"] / r64["value"]
+        rp = res["fp64_plain"]
+        out["fp64_plain"] = {k: v for k, v in rp.items() if k != "prof"}
+        out["fp32ir_over_fp64_plain"] = main_["value"] / rp["value"]
+    out["solve_variants"] = tuned
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, ab, float(np.mean(m0)), args.cpu_cols)
     print(json.dumps(out), flush=True)

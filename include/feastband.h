@@ -209,6 +209,20 @@ int feast_filter(const fb_band* B, int32_t nslice, const double* lo, const doubl
 int fb_profile_enable(int32_t on);
 int fb_profile_read(int32_t cls, int64_t* launches, double* ms, double* work);
 
+/* Autotuner of the block-solve kernel (the tile width of right-hand sides per
+ * work item and whether factor fragments are prefetched a product ahead):
+ * factors nsys shifted systems of B in the given precision (0: complex128,
+ * 1: complex64), times every variant that fits in LDS on the N and H solves
+ * of m right-hand sides each with HIP events, and keeps the fastest for this
+ * precision and block size for the rest of the process.  When cache_path is
+ * not NULL the choice is appended to it as one JSON line.  chosen/ms (host,
+ * may be NULL) receive the variant and its time per sweep. */
+int fb_autotune(const fb_band* B, int32_t precision, int32_t nsys, int32_t m,
+                const char* cache_path, int32_t* chosen, double* ms, void* work,
+                size_t* lwork, void* stream);
+/* Load choices written by fb_autotune; returns how many were read, or -1. */
+int fb_tune_load(const char* cache_path);
+
 const char* fb_strerror(int code);
 
 /* Device properties used by the library (for reports): compute units and

@@ -57,6 +57,9 @@ SIGNATURES = {
                                C.POINTER(P), PI64, PD, PI32, C.POINTER(fb_feast_opts), P, PSZ, P]),
     "fb_profile_enable": (C.c_int, [C.c_int32]),
     "fb_profile_read": (C.c_int, [C.c_int32, PI64, PD, PD]),
+    "fb_autotune": (C.c_int, [C.POINTER(fb_band), C.c_int32, C.c_int32, C.c_int32, C.c_char_p,
+                              PI32, PD, P, PSZ, P]),
+    "fb_tune_load": (C.c_int, [C.c_char_p]),
     "fb_strerror": (C.c_char_p, [C.c_int]),
     "fb_device_info": (C.c_int, [PI32, C.c_char_p, C.c_int32]),
 }

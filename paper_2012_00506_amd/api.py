@@ -324,3 +324,27 @@ def profile_read() -> dict:
         N.check("fb_profile_read", N.lib().fb_profile_read(i, C.byref(L), C.byref(ms), C.byref(w)))
         out[name] = (int(L.value), float(ms.value), float(w.value))
     return out
+
+
+def autotune(B, precision, nsys=8, m=256, cache_path=None, stream=None):
+    """Time the block-solve variants on B's shape and keep the fastest for
+    this precision for the rest of the process.  Returns (variant, ms)."""
+    B = _as_band(B)
+    bs = B.struct()
+    L = N.lib()
+    ch = C.c_int32(-1)
+    ms = C.c_double(0)
+    path = cache_path.encode() if cache_path else None
+    sh = C.c_void_p(_stream_handle(stream))
+    lw = C.c_size_t(0)
+    N.check("fb_autotune", L.fb_autotune(C.byref(bs), precision, nsys, m, path, C.byref(ch),
+                                         C.byref(ms), None, C.byref(lw), sh))
+    ws = _workspace(None, lw, B.data.device)
+    lw2 = C.c_size_t(ws.numel())
+    N.check("fb_autotune", L.fb_autotune(C.byref(bs), precision, nsys, m, path, C.byref(ch),
+                                         C.byref(ms), C.c_void_p(ws.data_ptr()), C.byref(lw2), sh))
+    return int(ch.value), float(ms.value)
+
+
+def tune_load(cache_path) -> int:
+    return int(N.lib().fb_tune_load(cache_path.encode()))

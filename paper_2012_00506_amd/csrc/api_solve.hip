@@ -28,10 +28,11 @@ int check_band(const fb_band* B) {
 
 template <typename R>
 void carve_factors(Arena& ar, const Band& bd, int nsys, FactorBufs<R>& f) {
-  int K = (int)((bd.n + bd.b - 1) / bd.b);
-  size_t bb = (size_t)bd.b * bd.b;
+  const int nb = block_size(bd.b);
+  int K = (int)((bd.n + nb - 1) / nb);
+  size_t bb = (size_t)nb * nb;
   f.mats = ar.take<cx<R>>((size_t)nsys * K * 5 * bb);
-  f.perm = ar.take<int16_t>((size_t)nsys * K * 2 * bd.b);
+  f.perm = ar.take<int16_t>((size_t)nsys * K * 2 * nb);
   f.info = ar.take<int32_t>(nsys);
   size_t sc = lu_window_scratch<R>(bd.b, nsys);
   f.scratch = sc ? ar.take<cx<R>>(sc / sizeof(cx<R>)) : nullptr;

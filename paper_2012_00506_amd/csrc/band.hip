@@ -1,5 +1,7 @@
 // Band ingest: LAPACK lower band (real or complex) -> diagonal-major complex128
 // copy, plus ||B||_1 and the Gershgorin interval.
+#include <algorithm>
+
 #include "fb_internal.h"
 
 namespace fb {
@@ -94,6 +96,33 @@ __global__ void k_band_colstats_final(const double* __restrict__ part, int nb,
   }
 }
 
+// Dense nb x nb blocks of the block-tridiagonal form of B (zero outside the
+// band and beyond n).
+__global__ void k_band_blocks(const c128* __restrict__ Bd, int64_t n, int b, int nb, int K,
+                              c128* __restrict__ Bblk) {
+  const int64_t total = (int64_t)K * 3 * nb * nb;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t blk = e / ((int64_t)nb * nb);
+    int rem = (int)(e - blk * nb * nb);
+    int c = rem / nb, r = rem % nb;
+    int k = (int)(blk / 3), sft = (int)(blk % 3) - 1;
+    int64_t i = (int64_t)k * nb + r, j = (int64_t)(k + sft) * nb + c;
+    c128 v = mk(0.0, 0.0);
+    if (j >= 0 && i < n && j < n) {
+      int64_t d = i - j;
+      if (d >= 0 && d <= b) {
+        v = Bd[d * n + j];
+        if (d == 0) v.y = 0.0;
+      } else if (d < 0 && -d <= b) {
+        c128 u = Bd[(-d) * n + i];
+        v = mk(u.x, -u.y);
+      }
+    }
+    Bblk[e] = v;
+  }
+}
+
 static const int kStatBlocks = 256;
 
 int ingest_band(const fb_band* B, Band& out, Arena& ar, hipStream_t st) {
@@ -103,6 +132,9 @@ int ingest_band(const fb_band* B, Band& out, Arena& ar, hipStream_t st) {
   out.cplx = B->dtype == FB_COMPLEX128;
   out.Bd = ar.take<c128>((size_t)(out.b + 1) * B->n);
   out.stats = ar.take<double>(3);
+  out.nb = (out.b + 15) / 16 * 16;
+  out.K = (int)((out.n + out.nb - 1) / out.nb);
+  out.Bblk = ar.take<c128>((size_t)out.K * 3 * out.nb * out.nb);
   double* part = ar.take<double>(3 * kStatBlocks);
   if (ar.base == nullptr) return 0;
   if (!ar.fits()) return FB_ERR_NOMEM;
@@ -116,6 +148,12 @@ int ingest_band(const fb_band* B, Band& out, Arena& ar, hipStream_t st) {
   FB_HIP(hipGetLastError());
   k_band_colstats_final<<<1, 256, 0, st>>>(part, kStatBlocks, out.stats);
   FB_HIP(hipGetLastError());
+  {
+    int64_t tb = (int64_t)out.K * 3 * out.nb * out.nb;
+    int g = (int)std::min<int64_t>((tb + 255) / 256, 65536);
+    k_band_blocks<<<g, 256, 0, st>>>(out.Bd, out.n, out.b, out.nb, out.K, out.Bblk);
+    FB_HIP(hipGetLastError());
+  }
   return 0;
 }
 

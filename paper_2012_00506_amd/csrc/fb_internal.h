@@ -116,6 +116,11 @@ struct Band {
   bool cplx;
   c128* Bd;      // dev, (b+1) * n
   double* stats; // dev, 3: ||B||_1, g_lo, g_hi
+  // block-tridiagonal copy with nb x nb blocks (nb = b rounded up to 16):
+  // Bblk[(k*3 + s) * nb*nb], s = 0: B(k,k-1), 1: B(k,k), 2: B(k,k+1), column-major
+  c128* Bblk;
+  int nb;
+  int K;
 };
 
 // Kernels launched from the host side (defined in the .hip files).

@@ -50,8 +50,10 @@ k_band_ldlh_inertia(const c128* __restrict__ Bd, int64_t n, int b,
   __syncthreads();
 
   int neg = 0, zero = 0;
+  int ks = 0;  // k mod M; offsets below M need at most one wrap
+  auto slot = [&](int off) { int v = ks + off; return v >= M ? v - M : v; };
   for (int64_t k = 0; k < n; ++k) {
-    double dk = W[(k % M) * M + (k % M)].x;
+    double dk = W[ks * M + ks].x;
     if (fabs(dk) < pivmin) {
       ++zero;
       dk = -pivmin;
@@ -60,14 +62,13 @@ k_band_ldlh_inertia(const c128* __restrict__ Bd, int64_t n, int b,
     }
     const int m = (int)((n - 1 - k) < b ? (n - 1 - k) : b);
     const double rdk = 1.0 / dk;
-    const int ks = (int)(k % M);
     // rank-one update of the trailing triangle: for k < c <= i <= k+m
     // A(i, c) -= A(i, k) conj(A(c, k)) / d_k
     for (int idx = t; idx < m * m; idx += blockDim.x) {
       int ii = idx / m + 1;  // i - k
-      int jc = idx % m + 1;  // c - k
+      int jc = idx - (ii - 1) * m + 1;  // c - k
       if (jc > ii) continue;
-      int is = (int)((k + ii) % M), cs = (int)((k + jc) % M);
+      int is = slot(ii), cs = slot(jc);
       c128 aik = W[ks * M + is];
       c128 ack = W[ks * M + cs];
       c128 upd = W[cs * M + is];
@@ -79,12 +80,14 @@ k_band_ldlh_inertia(const c128* __restrict__ Bd, int64_t n, int b,
     // entering row i = k+b+1 (columns k+1 .. k+b+1), used from step k+1 on
     int64_t inew = k + b + 1;
     if (inew < n) {
+      const int rs = slot(b + 1);
       for (int jc = t; jc <= b; jc += blockDim.x) {
         int64_t c = inew - b + jc;  // columns inew-b .. inew
-        W[(int)(c % M) * M + (int)(inew % M)] = band_entry(Bd, n, inew, c, sigma);
+        W[slot(1 + jc) * M + rs] = band_entry(Bd, n, inew, c, sigma);
       }
     }
     __syncthreads();
+    ks = slot(1);
   }
   if (t == 0) {
     counts[3 * s + 0] = neg;

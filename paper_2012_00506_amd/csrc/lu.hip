@@ -59,31 +59,31 @@ __device__ __forceinline__ cx<R> shifted_entry(const c128* __restrict__ Bd, int6
 
 template <typename R>
 __global__ void __launch_bounds__(kLuThreads)
-k_band_lu(const c128* __restrict__ Bd, int64_t n, int b, int K,
+k_band_lu(const c128* __restrict__ Bd, int64_t n, int b, int nb, int K,
           const c128* __restrict__ zs, FactorOut<R> out, cx<R>* __restrict__ gwin,
           int use_lds) {
   extern __shared__ char lds_raw[];
   const int MR = b + 2, MC = 2 * b + 2;
   const int s = blockIdx.x;
   const int t = threadIdx.x;
-  const int64_t npad = (int64_t)K * b;
+  const int64_t npad = (int64_t)K * nb;
   const c128 z = zs[s];
 
-  // LDS: phys[MR] int, idx[2][2b] int, lvec[b] cx<R>, piv info, then window
+  // LDS: phys[MR] int, idx[2][2nb] int, piv info, lvec[b+1] cx<R>, then window
   int* phys = reinterpret_cast<int*>(lds_raw);
   int* idx = phys + MR;                   // two perm buffers (block parity)
-  int* pivp = idx + 4 * b;                // [0] = pivot row of this step
-  cx<R>* lvec = reinterpret_cast<cx<R>*>(lds_raw + ((sizeof(int) * (MR + 4 * b + 4) + 15) & ~15));
+  int* pivp = idx + 4 * nb;               // [0] = pivot row of this step
+  cx<R>* lvec = reinterpret_cast<cx<R>*>(lds_raw + ((sizeof(int) * (MR + 4 * nb + 4) + 15) & ~15));
   cx<R>* W = use_lds ? lvec + b + 1 : gwin + (size_t)s * MR * MC;
 
-  cx<R>* mats = out.mats + (size_t)s * K * 5 * b * b;
-  int16_t* permg = out.perm + (size_t)s * K * 2 * b;
-  const size_t bb = (size_t)b * b;
+  cx<R>* mats = out.mats + (size_t)s * K * 5 * nb * nb;
+  int16_t* permg = out.perm + (size_t)s * K * 2 * nb;
+  const size_t bb = (size_t)nb * nb;
 
   // --- init: zero window, load rows 0..b, identity tables, zero block 0 Lh
   for (int e = t; e < MR * MC; e += blockDim.x) W[e] = mk<R>(0, 0);
   for (int e = t; e < MR; e += blockDim.x) phys[e] = e;
-  for (int e = t; e < 2 * b; e += blockDim.x) idx[e] = e;
+  for (int e = t; e < 2 * nb; e += blockDim.x) idx[e] = e;
   for (size_t e = t; e < 2 * bb; e += blockDim.x) mats[e] = mk<R>(0, 0);  // Lh11, Lh21 of block 0
   if (t == 0) out.info[s] = 0;
   __syncthreads();
@@ -98,24 +98,26 @@ k_band_lu(const c128* __restrict__ Bd, int64_t n, int b, int K,
   __syncthreads();
 
   int first_zero = 0;
+  // running slots: row j sits in slot jr = j mod MR, column j in jcs = j mod MC;
+  // an offset below MR (MC) needs at most one wrap
+  int jr = 0, jcs = 0, k = 0, jj = 0;
+  auto rslot = [&](int off) { int v = jr + off; return v >= MR ? v - MR : v; };
+  auto cslot = [&](int off) { int v = jcs + off; return v >= MC ? v - MC : v; };
   for (int64_t j = 0; j < npad; ++j) {
-    const int k = (int)(j / b);
-    const int jj = (int)(j - (int64_t)k * b);
     const int par = k & 1;
-    int* idxk = idx + par * 2 * b;
+    int* idxk = idx + par * 2 * nb;
     const int64_t last = (j + b < npad - 1) ? j + b : npad - 1;
     const int nr = (int)(last - j);               // rows below the pivot
     const int64_t cend = (j + 2 * b < npad - 1) ? j + 2 * b : npad - 1;
     const int nc = (int)(cend - j);               // columns right of the pivot
-    const int jc = (int)(j % MC);
+    const int jc = jcs;
 
     // ---- phase A (wave 0): pivot search, interchange, multipliers
     if (t < 64) {
       R best = (R)-1;
       int bi = 0x7fffffff;
       for (int r = t; r <= nr; r += 64) {
-        int64_t i = j + r;
-        cx<R> a = W[(size_t)phys[i % MR] * MC + jc];
+        cx<R> a = W[(size_t)phys[rslot(r)] * MC + jc];
         R v = cabs2(a);
         if (v > best) {  // rows scanned in increasing order per lane
           best = v;
@@ -130,31 +132,29 @@ k_band_lu(const c128* __restrict__ Bd, int64_t n, int b, int K,
           bi = oi;
         }
       }
-      const int64_t p = j + bi;
-      const int sj = (int)(j % MR), sp = (int)(p % MR);
+      const int sj = jr, sp = rslot(bi);
       const int physj_old = phys[sj], physp_old = phys[sp];
-      // physical row of logical row i after the interchange
-      const int prow_j = physp_old;
-      cx<R> piv = W[(size_t)prow_j * MC + jc];
+      // physical row of logical row j + r after the interchange
+      cx<R> piv = W[(size_t)physp_old * MC + jc];
       cx<R> rp = cabs2(piv) > (R)0 ? cinv(piv) : mk<R>(0, 0);
       for (int r = t + 1; r <= nr; r += 64) {
-        int64_t i = j + r;
-        int pr = (i == p) ? physj_old : phys[i % MR];
+        int pr = (r == bi) ? physj_old : phys[rslot(r)];
         cx<R> l = W[(size_t)pr * MC + jc] * rp;
         lvec[r - 1] = l;
-        int64_t wr = i - (int64_t)k * b;  // window row of the block
-        if (wr < b)
-          mats[((size_t)k * 5 + 0) * bb + (size_t)jj * b + wr] = l;
+        int wr = jj + r;  // window row of the block
+        if (wr < nb)
+          mats[((size_t)k * 5 + 0) * bb + (size_t)jj * nb + wr] = l;
         else
-          mats[((size_t)k * 5 + 1) * bb + (size_t)jj * b + (wr - b)] = l;
+          mats[((size_t)k * 5 + 1) * bb + (size_t)jj * nb + (wr - nb)] = l;
       }
       if (t == 0) {
         phys[sj] = physp_old;
         phys[sp] = physj_old;
+        int pw0 = jj + bi;
         int a = idxk[jj];
-        idxk[jj] = idxk[p - (int64_t)k * b];
-        idxk[p - (int64_t)k * b] = a;
-        pivp[0] = (int)(p - (int64_t)k * b);
+        idxk[jj] = idxk[pw0];
+        idxk[pw0] = a;
+        pivp[0] = pw0;
         if (!(cabs2(piv) > (R)0) && first_zero == 0) first_zero = (int)(j + 1);
       }
     }
@@ -162,23 +162,23 @@ k_band_lu(const c128* __restrict__ Bd, int64_t n, int b, int K,
 
     // ---- phase B (all): U row, multiplier interchange, update, entering row
     const int pw = pivp[0];
-    const int prj = phys[j % MR];
+    const int prj = phys[jr];
     {
-      // U row j: columns kb .. kb+3b-1 of blocks U(k,k), U(k,k+1), U(k,k+2)
-      for (int e = t; e < 3 * b; e += blockDim.x) {
-        int64_t c = (int64_t)k * b + e;
+      // U row j: columns k nb .. k nb+3nb-1 of blocks U(k,k), U(k,k+1), U(k,k+2)
+      for (int e = t; e < 3 * nb; e += blockDim.x) {
+        int co = e - jj;  // column offset from j
         cx<R> v = mk<R>(0, 0);
-        if (c >= j && c <= cend) v = W[(size_t)prj * MC + (int)(c % MC)];
-        int which = 2 + e / b;
-        mats[((size_t)k * 5 + which) * bb + (size_t)(e % b) * b + jj] = v;
+        if (co >= 0 && co <= nc) v = W[(size_t)prj * MC + cslot(co)];
+        int which = 2 + e / nb;
+        mats[((size_t)k * 5 + which) * bb + (size_t)(e % nb) * nb + jj] = v;
       }
       // keep Lh in the form P A = Lh U: earlier multipliers follow the rows
       if (pw != jj) {
         for (int c = t; c < jj; c += blockDim.x) {
-          size_t a0 = (jj < b) ? ((size_t)k * 5 + 0) * bb + (size_t)c * b + jj
-                               : ((size_t)k * 5 + 1) * bb + (size_t)c * b + (jj - b);
-          size_t a1 = (pw < b) ? ((size_t)k * 5 + 0) * bb + (size_t)c * b + pw
-                               : ((size_t)k * 5 + 1) * bb + (size_t)c * b + (pw - b);
+          size_t a0 = (jj < nb) ? ((size_t)k * 5 + 0) * bb + (size_t)c * nb + jj
+                                : ((size_t)k * 5 + 1) * bb + (size_t)c * nb + (jj - nb);
+          size_t a1 = (pw < nb) ? ((size_t)k * 5 + 0) * bb + (size_t)c * nb + pw
+                                : ((size_t)k * 5 + 1) * bb + (size_t)c * nb + (pw - nb);
           cx<R> va = mats[a0];
           mats[a0] = mats[a1];
           mats[a1] = va;
@@ -186,10 +186,9 @@ k_band_lu(const c128* __restrict__ Bd, int64_t n, int b, int K,
       }
       // rank-one update of rows j+1..last, columns j+1..cend
       for (int e = t; e < nr * nc; e += blockDim.x) {
-        int ro = e / nc, co = e % nc;
-        int64_t i = j + 1 + ro, c = j + 1 + co;
-        int cs = (int)(c % MC);
-        size_t a = (size_t)phys[i % MR] * MC + cs;
+        int ro = e / nc, co = e - ro * nc;
+        int cs = cslot(co + 1);
+        size_t a = (size_t)phys[rslot(ro + 1)] * MC + cs;
         cx<R> u = W[(size_t)prj * MC + cs];
         cx<R> l = lvec[ro];
         cx<R> v = W[a];
@@ -199,28 +198,25 @@ k_band_lu(const c128* __restrict__ Bd, int64_t n, int b, int K,
       }
       // column j+2b+1 enters: zero it in rows j+1..j+b (out of their band)
       {
-        int cs = (int)((j + 2 * b + 1) % MC);
-        for (int r = t; r < b; r += blockDim.x) {
-          int64_t i = j + 1 + r;
-          W[(size_t)phys[i % MR] * MC + cs] = mk<R>(0, 0);
-        }
+        int cs = cslot(2 * b + 1);
+        for (int r = t; r < b; r += blockDim.x) W[(size_t)phys[rslot(r + 1)] * MC + cs] = mk<R>(0, 0);
       }
       // row j+b+1 enters (columns j+1 .. j+2b+1)
       int64_t inew = j + b + 1;
       if (inew < npad) {
-        int pr = phys[inew % MR];
+        int pr = phys[rslot(b + 1)];
         for (int e = t; e <= 2 * b; e += blockDim.x) {
           int64_t c = j + 1 + e;
           cx<R> v = mk<R>(0, 0);
           if (c < npad) v = shifted_entry<R>(Bd, n, b, inew, c, z);
-          W[(size_t)pr * MC + (int)(c % MC)] = v;
+          W[(size_t)pr * MC + cslot(1 + e)] = v;
         }
       }
-      if (jj == b - 1) {
+      if (jj == nb - 1) {
         // block k complete: publish its permutation, prepare block k+1
-        for (int e = t; e < 2 * b; e += blockDim.x) {
-          permg[(size_t)k * 2 * b + e] = (int16_t)idxk[e];
-          idx[(par ^ 1) * 2 * b + e] = e;
+        for (int e = t; e < 2 * nb; e += blockDim.x) {
+          permg[(size_t)k * 2 * nb + e] = (int16_t)idxk[e];
+          idx[(par ^ 1) * 2 * nb + e] = e;
         }
         if (k + 1 < K)
           for (size_t e = t; e < 2 * bb; e += blockDim.x)
@@ -228,6 +224,12 @@ k_band_lu(const c128* __restrict__ Bd, int64_t n, int b, int K,
       }
     }
     __syncthreads();
+    jr = rslot(1);
+    jcs = cslot(1);
+    if (++jj == nb) {
+      jj = 0;
+      ++k;
+    }
   }
   if (t == 0 && first_zero) out.info[s] = first_zero;
 }
@@ -288,14 +290,14 @@ k_block_invert(cx<R>* __restrict__ mats, int b, int nblk, int use_lds) {
 }
 
 template <typename R>
-static size_t lu_lds_bytes(int b) {
-  size_t head = (sizeof(int) * (size_t)((b + 2) + 4 * b + 4) + 15) & ~(size_t)15;
-  return head + sizeof(cx<R>) * ((size_t)b + 1 + (size_t)(b + 2) * (2 * b + 2));
+static size_t lu_lds_head_bytes(int b) {
+  const int nb = block_size(b);
+  size_t head = (sizeof(int) * (size_t)((b + 2) + 4 * nb + 4) + 15) & ~(size_t)15;
+  return head + sizeof(cx<R>) * ((size_t)b + 1);
 }
 template <typename R>
-static size_t lu_lds_head_bytes(int b) {
-  size_t head = (sizeof(int) * (size_t)((b + 2) + 4 * b + 4) + 15) & ~(size_t)15;
-  return head + sizeof(cx<R>) * ((size_t)b + 1);
+static size_t lu_lds_bytes(int b) {
+  return lu_lds_head_bytes<R>(b) + sizeof(cx<R>) * (size_t)(b + 2) * (2 * b + 2);
 }
 
 template <typename R>
@@ -308,7 +310,8 @@ template <typename R>
 int launch_lu_impl(const Band& bd, int nsys, const c128* z_dev, cx<R>* mats, int16_t* perm,
                    int32_t* info, cx<R>* scratch, hipStream_t st) {
   const int b = bd.b;
-  const int K = (int)((bd.n + b - 1) / b);
+  const int nb = block_size(b);
+  const int K = (int)((bd.n + nb - 1) / nb);
   FactorOut<R> o{mats, perm, info};
   bool lds = lu_lds_bytes<R>(b) <= kLdsBudget;
   size_t smem = lds ? lu_lds_bytes<R>(b) : lu_lds_head_bytes<R>(b);
@@ -317,18 +320,19 @@ int launch_lu_impl(const Band& bd, int nsys, const c128* z_dev, cx<R>* mats, int
   (void)hipGetLastError();
   {
     ProfScope ps(FB_PROF_LU, st, 16.0 * (double)bd.n * b * b * nsys);
-    k_band_lu<R><<<nsys, kLuThreads, smem, st>>>(bd.Bd, bd.n, b, K, z_dev, o, scratch, lds ? 1 : 0);
+    k_band_lu<R><<<nsys, kLuThreads, smem, st>>>(bd.Bd, bd.n, b, nb, K, z_dev, o, scratch,
+                                                  lds ? 1 : 0);
     FB_HIP(hipGetLastError());
   }
-  size_t full = sizeof(cx<R>) * ((size_t)b * b + b);
+  size_t full = sizeof(cx<R>) * ((size_t)nb * nb + nb);
   bool ilds = full <= kLdsBudget;
-  size_t ismem = ilds ? full : sizeof(cx<R>) * (size_t)b;
+  size_t ismem = ilds ? full : sizeof(cx<R>) * (size_t)nb;
   (void)hipFuncSetAttribute((const void*)k_block_invert<R>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
   (void)hipGetLastError();
   int nblk = nsys * K;
-  ProfScope ps(FB_PROF_INVERT, st, 8.0 * 2.0 * nblk * b * b * b / 3.0);
-  k_block_invert<R><<<2 * nblk, 256, ismem, st>>>(mats, b, nblk, ilds ? 1 : 0);
+  ProfScope ps(FB_PROF_INVERT, st, 8.0 * 2.0 * nblk * (double)nb * nb * nb / 3.0);
+  k_block_invert<R><<<2 * nblk, 256, ismem, st>>>(mats, nb, nblk, ilds ? 1 : 0);
   FB_HIP(hipGetLastError());
   return 0;
 }

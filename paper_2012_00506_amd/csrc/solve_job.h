@@ -31,6 +31,9 @@ struct ResJob {
   c128 z;
 };
 
+// Block size of the factor blocks: the band rounded up to the 16-row MFMA tile.
+inline int block_size(int b) { return (b + 15) / 16 * 16; }
+
 template <typename R>
 int launch_solve_jobs(const cx<R>* mats, const int16_t* perm, int64_t n, int b, int njobs,
                       const SolveJob* jobs_dev, double work, hipStream_t st);

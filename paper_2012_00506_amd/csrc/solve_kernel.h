@@ -1,0 +1,443 @@
+// MFMA block-solve kernel templates (instantiated per precision in
+// solve_f32.hip and solve_f64.hip).
+#pragma once
+#include "fb_internal.h"
+#include "prof.h"
+#include "solve_job.h"
+
+namespace fb {
+
+// ---------------------------------------------------------------- MFMA helpers
+// One wave computes a 16-row block of a complex product C (16 x T) +=
+// A (16 x K rows of an NB x NB block) * B (K x T, in LDS), as real
+// 16x16x4 MFMAs: Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br.  Lane l feeds
+// A[l % 16][k + l / 16] and B[k + l / 16][l % 16].  Register r of lane l
+// holds C[row][l % 16] with row = 4 (l / 16) + r for the f32 instruction and
+// row = l / 16 + 4 r for the f64 one (both checked on gfx950).
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+
+template <typename R>
+struct MF;
+template <>
+struct MF<float> {
+  using V = mf_f4;
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+  static __device__ __forceinline__ V mma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct MF<double> {
+  using V = mf_d4;
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+  static __device__ __forceinline__ V mma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename R, int NC>
+struct Acc {
+  typename MF<R>::V re[NC], im[NC];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        re[c][r] = (R)0;
+        im[c][r] = (R)0;
+      }
+  }
+};
+
+// A fragments of one wave for one block product: register s holds
+// op(A)[16 w + lane % 16][4 s + lane / 16] (complex), op(A) = A or A^H.
+template <typename R, int NB>
+struct Frag {
+  cx<R> a[NB / 4];
+};
+
+template <typename R, int NB, bool CONJT>
+__device__ __forceinline__ void frag_load(Frag<R, NB>& f, const cx<R>* __restrict__ A, int w,
+                                          int lane, int k0, int k1) {
+  const int i = 16 * w + (lane & 15), kq = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < NB / 4; ++s) {
+    const int kk = 4 * s;
+    if (kk < k0 || kk >= k1) continue;
+    const int k = kk + kq;
+    f.a[s] = CONJT ? A[(size_t)i * NB + k] : A[(size_t)k * NB + i];
+  }
+}
+
+// acc += op(A) * B over k in [k0, k1) (multiples of 4) from prefetched
+// fragments; NEG subtracts.  B row k is LDS row rmap[k] (or k when rmap is
+// null), row stride ldb elements, columns from cb0.
+template <typename R, int NB, int NC, bool CONJT, bool NEG>
+__device__ __forceinline__ void frag_mma(Acc<R, NC>& acc, const Frag<R, NB>& f, const cx<R>* Bl,
+                                         int ldb, const int* rmap, int cb0, int lane, int k0,
+                                         int k1) {
+  const int kq = lane >> 4;
+  const int j = lane & 15;
+#pragma unroll
+  for (int s = 0; s < NB / 4; ++s) {
+    const int kk = 4 * s;
+    if (kk < k0 || kk >= k1) continue;
+    const int k = kk + kq;
+    cx<R> a = f.a[s];
+    R ar = a.x, ai = CONJT ? -a.y : a.y;
+    if (NEG) {
+      ar = -ar;
+      ai = -ai;
+    }
+    const R nai = -ai;
+    const int br = rmap ? rmap[k] : k;
+    const cx<R>* bp = Bl + (size_t)br * ldb + cb0 + j;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      cx<R> bv = bp[16 * c];
+      acc.re[c] = MF<R>::mma(ar, bv.x, acc.re[c]);
+      acc.re[c] = MF<R>::mma(nai, bv.y, acc.re[c]);
+      acc.im[c] = MF<R>::mma(ar, bv.y, acc.im[c]);
+      acc.im[c] = MF<R>::mma(ai, bv.x, acc.im[c]);
+    }
+  }
+}
+
+template <typename R, int NB, int NC, bool CONJT, bool NEG>
+__device__ __forceinline__ void wave_prod(Acc<R, NC>& acc, const cx<R>* __restrict__ A,
+                                          const cx<R>* Bl, int ldb, const int* rmap, int w,
+                                          int cb0, int lane, int k0, int k1) {
+  Frag<R, NB> f;
+  frag_load<R, NB, CONJT>(f, A, w, lane, k0, k1);
+  frag_mma<R, NB, NC, CONJT, NEG>(acc, f, Bl, ldb, rmap, cb0, lane, k0, k1);
+}
+
+// accumulator <-> LDS rows (rows 16 w + MF<R>::row(lane, r), columns 16 c + lane%16)
+template <typename R, int NC>
+__device__ __forceinline__ void acc_to_lds(const Acc<R, NC>& acc, cx<R>* L, int ldb,
+                                           const int* rmap, int w, int cb0, int lane) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int row = 16 * w + MF<R>::row(lane, r);
+      int lr = rmap ? rmap[row] : row;
+      L[(size_t)lr * ldb + cb0 + 16 * c + (lane & 15)] = mk<R>(acc.re[c][r], acc.im[c][r]);
+    }
+}
+template <typename R, int NC>
+__device__ __forceinline__ void acc_from_lds(Acc<R, NC>& acc, const cx<R>* L, int ldb,
+                                             const int* rmap, int w, int cb0, int lane) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int row = 16 * w + MF<R>::row(lane, r);
+      int lr = rmap ? rmap[row] : row;
+      cx<R> v = L[(size_t)lr * ldb + cb0 + 16 * c + (lane & 15)];
+      acc.re[c][r] = v.x;
+      acc.im[c][r] = v.y;
+    }
+}
+
+static __device__ __forceinline__ int remap_job(int bid, int njobs) {
+  // consecutive jobs (one system's tiles) on one XCD: workgroups are dealt
+  // to the 8 XCDs round-robin, so XCD x runs the x-th contiguous range
+  const int per = (njobs + 7) / 8;
+  return (bid % 8) * per + bid / 8;
+}
+
+// ---------------------------------------------------------------- MFMA block solve
+// One workgroup per job with one wave per 16 x 16 output tile of a block
+// product ((NB/16) x (T/16) waves); LDS holds 4 NB x T blocks.
+template <typename R, int NB, int T, bool PREF>
+__global__ void __launch_bounds__(NB * 4 * (T / 16))
+k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, int64_t n,
+             int K, const SolveJob* __restrict__ jobs, int njobs) {
+  constexpr int NC = 1;
+  constexpr int NRW = NB / 16;
+  extern __shared__ char lds_raw[];
+  int* sp = reinterpret_cast<int*>(lds_raw);                        // 2 NB perm entries
+  cx<R>* S = reinterpret_cast<cx<R>*>(lds_raw + ((2 * NB * sizeof(int) + 15) & ~15));
+  const int job = remap_job(blockIdx.x, njobs);
+  if (job >= njobs) return;
+  const SolveJob jb = jobs[job];
+  const int t = threadIdx.x, lane = t & 63;
+  const int w = (t >> 6) % NRW, cb0 = 16 * ((t >> 6) / NRW);  // row block, column base
+  const int nthr = NB * 4 * (T / 16);
+  const size_t bb = (size_t)NB * NB;
+  const cx<R>* F = mats + (size_t)jb.sys * K * 5 * bb;
+  const int16_t* P = permg + (size_t)jb.sys * K * 2 * NB;
+  const c128* in = jb.in + (int64_t)jb.col0 * jb.ldin;
+  c128* mid = jb.mid + (int64_t)jb.col0 * jb.ldmid;
+  c128* out = jb.out + (int64_t)jb.col0 * jb.ldout;
+  c128* accp = jb.acc ? jb.acc + (int64_t)jb.col0 * jb.ldacc : nullptr;
+  const int ncol = jb.ncol;
+
+  auto emit = [&](int64_t row, int col, cx<R> v) {
+    if (row >= n || col >= ncol) return;
+    c128 x = mk((double)v.x, (double)v.y);
+    c128* o = out + (int64_t)col * jb.ldout + row;
+    *o = jb.add ? *o + x : x;
+    if (accp) {
+      c128* a = accp + (int64_t)col * jb.ldacc + row;
+      c128 wv = jb.w * x;
+      if (jb.acc_real) wv = mk(2.0 * wv.x, 0.0);
+      *a = *a + wv;
+    }
+  };
+  auto gload = [&](const c128* base, int64_t ld, int64_t row, int col) -> cx<R> {
+    if (row >= n || col >= ncol) return mk<R>(0, 0);
+    c128 v = base[(int64_t)col * ld + row];
+    return mk<R>((R)v.x, (R)v.y);
+  };
+  // accumulator <-> global rows k NB + (wave rows)
+  auto acc_from_g = [&](Acc<R, NC>& acc, const c128* base, int64_t ld, int64_t row0) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        cx<R> v = gload(base, ld, row0 + 16 * w + MF<R>::row(lane, r), cb0 + 16 * c + (lane & 15));
+        acc.re[c][r] = v.x;
+        acc.im[c][r] = v.y;
+      }
+  };
+  auto acc_to_g = [&](const Acc<R, NC>& acc, c128* base, int64_t ld, int64_t row0) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int64_t row = row0 + 16 * w + MF<R>::row(lane, r);
+        int col = cb0 + 16 * c + (lane & 15);
+        if (row < n && col < ncol)
+          base[(int64_t)col * ld + row] = mk((double)acc.re[c][r], (double)acc.im[c][r]);
+      }
+  };
+  auto acc_emit = [&](const Acc<R, NC>& acc, int64_t row0) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        emit(row0 + 16 * w + MF<R>::row(lane, r), cb0 + 16 * c + (lane & 15),
+             mk<R>(acc.re[c][r], acc.im[c][r]));
+  };
+  auto load_perm = [&](int k) {
+    for (int e = t; e < 2 * NB; e += nthr) sp[e] = P[(size_t)k * 2 * NB + e];
+  };
+  const int lo_tri = 16 * w + 16;  // k < lo_tri: lower triangle rows of this wave
+  const int up_tri = 16 * w;       // k >= up_tri: upper triangle
+  auto blk = [&](int k, int slot) { return F + ((size_t)k * 5 + slot) * bb; };
+  // initial accumulator values for the wave's rows of block k, prefetched
+  // into registers one step ahead
+  struct Pre {
+    cx<R> v[4];
+  };
+  auto pre_load = [&](Pre& p, const c128* base, int64_t ld, int k) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      p.v[r] = gload(base, ld, (int64_t)k * NB + 16 * w + MF<R>::row(lane, r), cb0 + (lane & 15));
+  };
+  auto pre_to_acc = [&](Acc<R, NC>& acc, const Pre& p) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      acc.re[0][r] = p.v[r].x;
+      acc.im[0][r] = p.v[r].y;
+    }
+  };
+  Acc<R, NC> acc;
+  Frag<R, NB> fa, fb, fc;
+  Pre pv;
+
+  if (jb.dir == 0) {
+    // ---------------------------------------------------------- N forward
+    cx<R>* W = S;                 // window, 2 NB x T
+    cx<R>* Yt = S + 2 * NB * T;   // y_top, NB x T
+    for (int e = t; e < 2 * NB * T; e += nthr) W[e] = gload(in, jb.ldin, e / T, e % T);
+    load_perm(0);
+    if (PREF) frag_load<R, NB, false>(fa, blk(0, 0), w, lane, 0, lo_tri);
+    __syncthreads();
+    for (int k = 0; k < K; ++k) {
+      if (PREF) frag_load<R, NB, false>(fb, blk(k, 1), w, lane, 0, NB);
+      if (!PREF) frag_load<R, NB, false>(fa, blk(k, 0), w, lane, 0, lo_tri);
+      acc.zero();
+      frag_mma<R, NB, NC, false, false>(acc, fa, W, T, sp, cb0, lane, 0, lo_tri);
+      acc_to_lds(acc, Yt, T, nullptr, w, cb0, lane);
+      acc_to_g(acc, mid, jb.ldmid, (int64_t)k * NB);
+      __syncthreads();
+      if (PREF && k + 1 < K) frag_load<R, NB, false>(fa, blk(k + 1, 0), w, lane, 0, lo_tri);
+      if (!PREF) frag_load<R, NB, false>(fb, blk(k, 1), w, lane, 0, NB);
+      acc_from_lds(acc, W, T, sp + NB, w, cb0, lane);
+      frag_mma<R, NB, NC, false, true>(acc, fb, Yt, T, nullptr, cb0, lane, 0, NB);
+      __syncthreads();
+      acc_to_lds(acc, W, T, nullptr, w, cb0, lane);
+      for (int e = t; e < NB * T; e += nthr)
+        W[NB * T + e] = gload(in, jb.ldin, (int64_t)(k + 2) * NB + e / T, e % T);
+      if (k + 1 < K) load_perm(k + 1);
+      __syncthreads();
+    }
+    // ---------------------------------------------------------- N backward
+    cx<R>* X1 = S;
+    cx<R>* X2 = S + NB * T;
+    cx<R>* V = S + 2 * NB * T;
+    for (int e = t; e < 2 * NB * T; e += nthr) S[e] = mk<R>(0, 0);
+    // fa = U(k,k+1), fb = U(k,k+2), fc = U(k,k)^{-1}, pv = y_k: prefetched
+    if (PREF) frag_load<R, NB, false>(fc, blk(K - 1, 2), w, lane, up_tri, NB);
+    pre_load(pv, mid, jb.ldmid, K - 1);
+    __syncthreads();
+    for (int k = K - 1; k >= 0; --k) {
+      if (!PREF && k + 1 < K) frag_load<R, NB, false>(fa, blk(k, 3), w, lane, 0, NB);
+      if (!PREF && k + 2 < K) frag_load<R, NB, false>(fb, blk(k, 4), w, lane, 0, lo_tri);
+      pre_to_acc(acc, pv);
+      if (k + 1 < K) frag_mma<R, NB, NC, false, true>(acc, fa, X1, T, nullptr, cb0, lane, 0, NB);
+      if (k + 2 < K) frag_mma<R, NB, NC, false, true>(acc, fb, X2, T, nullptr, cb0, lane, 0, lo_tri);
+      acc_to_lds(acc, V, T, nullptr, w, cb0, lane);
+      __syncthreads();
+      if (k > 0) {
+        if (PREF && k < K) frag_load<R, NB, false>(fa, blk(k - 1, 3), w, lane, 0, NB);
+        if (PREF && k + 1 < K) frag_load<R, NB, false>(fb, blk(k - 1, 4), w, lane, 0, lo_tri);
+        pre_load(pv, mid, jb.ldmid, k - 1);
+      }
+      if (!PREF) frag_load<R, NB, false>(fc, blk(k, 2), w, lane, up_tri, NB);
+      acc.zero();
+      frag_mma<R, NB, NC, false, false>(acc, fc, V, T, nullptr, cb0, lane, up_tri, NB);
+      if (PREF && k > 0) frag_load<R, NB, false>(fc, blk(k - 1, 2), w, lane, up_tri, NB);
+      acc_emit(acc, (int64_t)k * NB);
+      acc_to_lds(acc, X2, T, nullptr, w, cb0, lane);
+      __syncthreads();
+      cx<R>* tmp = X1;
+      X1 = X2;
+      X2 = tmp;
+    }
+  } else {
+    // ---------------------------------------------------------- H forward (U^H)
+    cx<R>* W1 = S;
+    cx<R>* W2 = S + NB * T;
+    cx<R>* V = S + 2 * NB * T;
+    for (int e = t; e < 2 * NB * T; e += nthr) S[e] = mk<R>(0, 0);
+    // fa = U(k-1,k)^H, fb = U(k-2,k)^H, fc = U(k,k)^{-H}, pv = y_k
+    if (PREF) frag_load<R, NB, true>(fc, blk(0, 2), w, lane, 0, lo_tri);
+    pre_load(pv, in, jb.ldin, 0);
+    __syncthreads();
+    for (int k = 0; k < K; ++k) {
+      if (!PREF && k >= 1) frag_load<R, NB, true>(fa, blk(k - 1, 3), w, lane, 0, NB);
+      if (!PREF && k >= 2) frag_load<R, NB, true>(fb, blk(k - 2, 4), w, lane, up_tri, NB);
+      pre_to_acc(acc, pv);
+      if (k >= 1) frag_mma<R, NB, NC, true, true>(acc, fa, W1, T, nullptr, cb0, lane, 0, NB);
+      if (k >= 2) frag_mma<R, NB, NC, true, true>(acc, fb, W2, T, nullptr, cb0, lane, up_tri, NB);
+      acc_to_lds(acc, V, T, nullptr, w, cb0, lane);
+      __syncthreads();
+      if (k + 1 < K) {
+        if (PREF) frag_load<R, NB, true>(fa, blk(k, 3), w, lane, 0, NB);
+        if (PREF && k >= 1) frag_load<R, NB, true>(fb, blk(k - 1, 4), w, lane, up_tri, NB);
+        pre_load(pv, in, jb.ldin, k + 1);
+      }
+      if (!PREF) frag_load<R, NB, true>(fc, blk(k, 2), w, lane, 0, lo_tri);
+      acc.zero();
+      frag_mma<R, NB, NC, true, false>(acc, fc, V, T, nullptr, cb0, lane, 0, lo_tri);
+      if (PREF && k + 1 < K) frag_load<R, NB, true>(fc, blk(k + 1, 2), w, lane, 0, lo_tri);
+      acc_to_g(acc, mid, jb.ldmid, (int64_t)k * NB);
+      acc_to_lds(acc, W2, T, nullptr, w, cb0, lane);
+      __syncthreads();
+      cx<R>* tmp = W1;
+      W1 = W2;
+      W2 = tmp;
+    }
+    // ---------------------------------------------------------- H backward (L^H)
+    cx<R>* Vt = S;               // top of the window after the L^H step
+    cx<R>* T1 = S + NB * T;
+    cx<R>* Cb = S + 2 * NB * T;  // carry: window bottom
+    cx<R>* Cn = S + 3 * NB * T;  // next carry
+    for (int e = t; e < NB * T; e += nthr) Cb[e] = mk<R>(0, 0);
+    load_perm(K - 1);
+    // fa = Lh21^H, fc = (Lh11^{-1})^H, pv = w_k
+    if (PREF) frag_load<R, NB, true>(fa, blk(K - 1, 1), w, lane, 0, NB);
+    if (PREF) frag_load<R, NB, true>(fc, blk(K - 1, 0), w, lane, up_tri, NB);
+    pre_load(pv, mid, jb.ldmid, K - 1);
+    __syncthreads();
+    for (int k = K - 1; k >= 0; --k) {
+      if (!PREF) frag_load<R, NB, true>(fa, blk(k, 1), w, lane, 0, NB);
+      pre_to_acc(acc, pv);
+      frag_mma<R, NB, NC, true, true>(acc, fa, Cb, T, nullptr, cb0, lane, 0, NB);
+      acc_to_lds(acc, T1, T, nullptr, w, cb0, lane);
+      __syncthreads();
+      if (k > 0) {
+        if (PREF) frag_load<R, NB, true>(fa, blk(k - 1, 1), w, lane, 0, NB);
+        pre_load(pv, mid, jb.ldmid, k - 1);
+      }
+      if (!PREF) frag_load<R, NB, true>(fc, blk(k, 0), w, lane, up_tri, NB);
+      acc.zero();
+      frag_mma<R, NB, NC, true, false>(acc, fc, T1, T, nullptr, cb0, lane, up_tri, NB);
+      if (PREF && k > 0) frag_load<R, NB, true>(fc, blk(k - 1, 0), w, lane, up_tri, NB);
+      acc_to_lds(acc, Vt, T, nullptr, w, cb0, lane);
+      __syncthreads();
+      // x_win = P^T [top ; carry]
+      for (int e = t; e < 2 * NB * T; e += nthr) {
+        int i = e / T, col = e % T;
+        cx<R> v = i < NB ? Vt[i * T + col] : Cb[(i - NB) * T + col];
+        int d = sp[i];
+        if (d >= NB)
+          emit((int64_t)k * NB + d, col, v);
+        else
+          Cn[d * T + col] = v;
+      }
+      __syncthreads();
+      cx<R>* tmp = Cb;
+      Cb = Cn;
+      Cn = tmp;
+      if (k > 0) load_perm(k - 1);
+      __syncthreads();
+    }
+    for (int e = t; e < NB * T; e += nthr) emit(e / T, e % T, Cb[e]);
+  }
+}
+
+
+template <typename R, int NB, int T, bool PREF>
+int launch_nb(const cx<R>* mats, const int16_t* perm, int64_t n, int njobs,
+              const SolveJob* jobs_dev, hipStream_t st) {
+  const int K = (int)((n + NB - 1) / NB);
+  size_t smem = ((2 * NB * sizeof(int) + 15) & ~(size_t)15) + (size_t)4 * NB * T * sizeof(cx<R>);
+  (void)hipFuncSetAttribute((const void*)k_band_solve<R, NB, T, PREF>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  (void)hipGetLastError();
+  for (int j0 = 0; j0 < njobs; j0 += 1 << 20) {
+    int nj = njobs - j0 < (1 << 20) ? njobs - j0 : (1 << 20);
+    int grid = 8 * ((nj + 7) / 8);
+    k_band_solve<R, NB, T, PREF><<<grid, NB * 4 * (T / 16), smem, st>>>(mats, perm, n, K,
+                                                                         jobs_dev + j0, nj);
+    FB_HIP(hipGetLastError());
+  }
+  return 0;
+}
+
+template <typename R, int T, bool PREF>
+int launch_t(const cx<R>* mats, const int16_t* perm, int64_t n, int nb, int njobs,
+             const SolveJob* jobs_dev, hipStream_t st) {
+  switch (nb) {
+    case 16: return launch_nb<R, 16, T, PREF>(mats, perm, n, njobs, jobs_dev, st);
+    case 32: return launch_nb<R, 32, T, PREF>(mats, perm, n, njobs, jobs_dev, st);
+    case 48: return launch_nb<R, 48, T, PREF>(mats, perm, n, njobs, jobs_dev, st);
+    case 64: return launch_nb<R, 64, T, PREF>(mats, perm, n, njobs, jobs_dev, st);
+    case 80: return launch_nb<R, 80, T, PREF>(mats, perm, n, njobs, jobs_dev, st);
+    case 96: return launch_nb<R, 96, T, PREF>(mats, perm, n, njobs, jobs_dev, st);
+    case 112: return launch_nb<R, 112, T, PREF>(mats, perm, n, njobs, jobs_dev, st);
+    case 128: return launch_nb<R, 128, T, PREF>(mats, perm, n, njobs, jobs_dev, st);
+    default: return FB_ERR_INTERNAL;
+  }
+}
+
+// every (tile width, prefetch) variant of one precision
+template <typename R>
+int launch_variant(int variant, const cx<R>* mats, const int16_t* perm, int64_t n, int nb,
+                   int njobs, const SolveJob* jobs_dev, hipStream_t st) {
+  switch (variant) {
+    case 0: return launch_t<R, 16, false>(mats, perm, n, nb, njobs, jobs_dev, st);
+    case 1: return launch_t<R, 16, true>(mats, perm, n, nb, njobs, jobs_dev, st);
+    case 2: return launch_t<R, 32, false>(mats, perm, n, nb, njobs, jobs_dev, st);
+    case 3: return launch_t<R, 32, true>(mats, perm, n, nb, njobs, jobs_dev, st);
+    default: return FB_ERR_INTERNAL;
+  }
+}
+
+}  // namespace fb

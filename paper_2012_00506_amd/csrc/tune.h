@@ -1,0 +1,16 @@
+// Solve-kernel variants and the autotuned choice per (precision, block size).
+#pragma once
+#include <stddef.h>
+
+namespace fb {
+
+// variant v: tile width (16 or 32 right-hand sides) and whether the factor
+// fragments of the next block product are prefetched into registers
+constexpr int kNumVariants = 4;
+inline int variant_tile(int v) { return v >= 2 ? 32 : 16; }
+inline bool variant_prefetch(int v) { return (v & 1) != 0; }
+bool variant_fits(size_t rsize, int nb, int v);
+int tuned_variant(size_t rsize, int nb);
+void set_tuned_variant(size_t rsize, int nb, int v);
+
+}  // namespace fb

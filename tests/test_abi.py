@@ -95,12 +95,17 @@ def test_shifted_solve_argument_errors_and_query(L):
     bad = list(args)
     bad[2] = (C.c_double * 4)(float("nan"), 0, 0, 0)
     assert L.band_shifted_solve(*bad) == -3
-    # the refined path needs residual buffers: a larger workspace
+    # residuals need their own buffers: asking for them grows the workspace
     lw1 = C.c_size_t(0)
     args1 = list(args)
-    args1[11] = C.byref(N.fb_solve_opts(1, 1e-10, 4, 0))
+    args1[9] = (C.c_double * 2)()
     args1[13] = C.byref(lw1)
     assert L.band_shifted_solve(*args1) == 0 and lw1.value > lw.value
+    lw2 = C.c_size_t(0)
+    args2 = list(args)
+    args2[11] = C.byref(N.fb_solve_opts(1, 1e-10, 4, 0))
+    args2[13] = C.byref(lw2)
+    assert L.band_shifted_solve(*args2) == 0 and lw2.value > 0
 
 
 def test_strerror(L):

@@ -164,3 +164,30 @@ def test_solve_cfg2_shape_sampled(fb):
         assert r.status == 0
         assert r.resid.max() <= (1e-13 if prec == 0 else 1e-12)
         _check_against_oracle(ab, zs, Yh, r, 1e-10, 1e-12, cols=np.array([0, 17, 39]))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_every_solve_variant_parity(fb, precision, tmp_path):
+    """Each block-solve variant the autotuner may pick gives oracle-parity
+    solutions (ragged n and tile tails; N and H)."""
+    n, b, m = 700, 64, 45
+    nb = 64
+    rsize = 4 if precision == 1 else 8
+    tol_x, tol_r = (1e-9, 1e-12) if precision else (1e-11, 1e-13)
+    for v in range(4):
+        lds = ((2 * nb * 4 + 15) // 16) * 16 + 4 * nb * (32 if v >= 2 else 16) * 2 * rsize
+        if lds > 160 * 1024:
+            continue
+        path = tmp_path / f"tune{v}.json"
+        path.write_text(f'{{"rsize": {rsize}, "nb": {nb}, "variant": {v}, "ms": 0}}\n')
+        assert fb.tune_load(str(path)) == 1
+        ab, z, Yh, r = _solve_case(fb, n, b, True, m, precision)
+        assert r.status == 0
+        _check_against_oracle(ab, z, Yh, r, tol_x, tol_r)
+
+
+def test_autotune_picks_a_variant(fb):
+    ab = synth.band_matrix(2000, 64, 9, True, -10, 10)
+    for prec in (0, 1):
+        v, ms = fb.autotune(ab, prec, nsys=4, m=64)
+        assert 0 <= v < 4 and ms > 0
