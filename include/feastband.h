@@ -149,14 +149,21 @@ int feast_band_slice(const fb_band* B, int32_t nslice, const double* lo,
 
 #define FB_PLAN_EQUAL_WIDTH 0 /* Approach-2 of Section 3.1: equal widths */
 #define FB_PLAN_EQUAL_COUNT 1 /* Approach-1 of Section 3.1: equal counts */
+#define FB_PLAN_LEARNED 2     /* equal counts, search guided by the planner network */
 
 typedef struct {
   int32_t mode;       /* FB_PLAN_* */
   int32_t K;          /* number of slices */
-  double lo, hi;      /* interval; NaN = the Gershgorin bound */
+  double lo, hi;      /* interval; NaN = the Gershgorin bound moved outward by
+                         4 cert_delta ||B||_1 + 1e-12 ||B||_1 (equal count and
+                         LEARNED; EQUAL_WIDTH needs both) */
   double count_tol;   /* equal count: accept |n_-(s) - target| <= floor(tol*total/K) */
   double cert_delta;  /* boundaries keep eigenvalues farther than cert_delta*||B||_1 */
   int32_t max_rounds; /* bisection rounds */
+  const void* planner;/* FB_PLAN_LEARNED: dev pointer to the network weights
+                         (fb_planner_bytes() bytes), or NULL for a uniform
+                         prior over [lo, hi] (interpolation search) */
+  uint64_t seed;      /* FB_PLAN_LEARNED: probe seed of the features */
 } fb_plan_opts;
 
 /* Slice placement by exact inertia (Section 3.1 "Spectrum Partition",
@@ -164,7 +171,12 @@ typedef struct {
  * Section 3.2).  Every boundary is certified: n_-(s - d) = n_-(s + d) with
  * d = cert_delta * ||B||_1, else it is moved to the first certified point of
  * s + 2 d k, k = 1, -1, 2, -2, ...  Equal count bisects all open boundaries
- * together, one batched inertia launch per round.
+ * together, one batched inertia launch per round.  LEARNED predicts the
+ * eigenvalue distribution from the band features (band_features) with the
+ * planner network and searches every boundary by inverting that prediction
+ * inside the current bracket, rescaled by the exact counts at its ends (a
+ * bracket that did not halve in two rounds is bisected); the final plan is
+ * certified and exact whatever the network predicts.
  *  bounds host, K+1 doubles; counts host, K; n_inertia host (may be NULL):
  *  number of shifts factorised.  Synchronises the stream. */
 int slice_plan(const fb_band* B, const fb_plan_opts* o, double* bounds,
@@ -222,6 +234,47 @@ int fb_autotune(const fb_band* B, int32_t precision, int32_t nsys, int32_t m,
                 size_t* lwork, void* stream);
 /* Load choices written by fb_autotune; returns how many were read, or -1. */
 int fb_tune_load(const char* cache_path);
+
+/* Stochastic Chebyshev moments of B, the density-of-states estimate the
+ * paper names as the matrix-vector alternative to inertia (Section 3.1):
+ * with Bh = (B - c I)/h, c = (g_lo + g_hi)/2, h = 1.01 (g_hi - g_lo)/2 from
+ * the Gershgorin bounds, mu[p*(K+1) + k] = v_p^T T_k(Bh) v_p / n for
+ * k = 0..K, the Rademacher probes being v_p(i) = 1 - 2 (SplitMix64(seed*2^40
+ * + p*2^32 + i) & 1), p = 0..P-1.  mu host, P*(K+1) doubles; gersh host (may
+ * be NULL), 3 doubles: g_lo, g_hi, ||B||_1.  Synchronises the stream. */
+int band_cheb_moments(const fb_band* B, int32_t K, int32_t P, uint64_t seed, double* mu,
+                      double* gersh, void* work, size_t* lwork, void* stream);
+
+/* The 80 planner features of B (host, doubles): Gershgorin bounds over
+ * ||B||_1, the mean and the spread over 20 probes of the Chebyshev moments
+ * mu_1..mu_16, the Jackson-damped Chebyshev estimate of the fraction of
+ * eigenvalues below 32 evenly spaced points of the Gershgorin interval, and
+ * 14 band statistics (size, bandwidth, type, diagonal moments, off-diagonal
+ * energy, norms).  Synchronises the stream. */
+int band_features(const fb_band* B, uint64_t seed, double* feat, void* work, size_t* lwork,
+                  void* stream);
+
+/* Bytes of the planner network's FP32 weights: W1 (80 x 256), b1 (256),
+ * W2 (256 x 256), b2 (256), W3 (256 x 64), b3 (64), row-major, packed. */
+size_t fb_planner_bytes(void);
+
+/* Network forward for a batch: x dev float [batch x 80] row-major, out dev
+ * float [batch x 64]; ReLU hidden layers; every product takes its operands
+ * rounded to BF16 and accumulates in FP32 (MFMA).  Workspace as above. */
+int planner_forward(const void* weights, int32_t batch, const float* x, float* out,
+                    void* work, size_t* lwork, void* stream);
+
+/* One training step of the network on a batch: forward, mean squared error
+ * against target (dev float [batch x 64]), backward (BF16 operands, FP32
+ * accumulation), then, unless grads is given, Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias-corrected with step t >= 1) on the FP32 weights with
+ * opt_state = [m | v] (dev, 2 fb_planner_bytes(), zero before step 1).
+ * grads (dev, fb_planner_bytes(), may be NULL): receives the gradients and
+ * no update is made.  loss (host, may be NULL): the batch loss; giving it
+ * synchronises the stream. */
+int planner_train_step(void* weights, void* opt_state, int32_t batch, const float* x,
+                       const float* target, float lr, int32_t t, float* loss, void* grads,
+                       void* work, size_t* lwork, void* stream);
 
 const char* fb_strerror(int code);
 

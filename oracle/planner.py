@@ -15,7 +15,11 @@ Readings:
   t_i = n_lo + round(i (n_hi - n_lo) / K); each interior boundary is bisected
   inside the tightest bracket known so far until |n_-(sigma) - t_i| <= tol_i,
   tol_i = floor(count_tol * (n_hi - n_lo) / K), one shift per open boundary
-  per round, at most ``max_rounds`` rounds.
+  per round, at most ``max_rounds`` rounds;
+* with no interval given the whole spectrum is partitioned: the Gershgorin
+  interval widened by 4 delta + 1e-12 ||B||_1 on each side, since a
+  Gershgorin bound can itself be an eigenvalue (diagonal B) and [lo, hi)
+  must hold every eigenvalue.
 
 Pinned by: exact counts against dense eigenvalues, and the invariants
 (boundaries increasing, counts sum to n_-(hi) - n_-(lo), every boundary
@@ -68,9 +72,11 @@ def plan_equal_count(ab, K: int, lo: float | None = None, hi: float | None = Non
     """Equal-count slices of [lo, hi) by batched bisection on inertia."""
     log: list = []
     g_lo, g_hi = gershgorin(ab)
-    lo = g_lo if lo is None or math.isnan(lo) else lo
-    hi = g_hi if hi is None or math.isnan(hi) else hi
-    delta = cert_delta * norm1(ab)
+    nrm = norm1(ab)
+    delta = cert_delta * nrm
+    pad = 4.0 * delta + 1e-12 * nrm
+    lo = g_lo - pad if lo is None or math.isnan(lo) else lo
+    hi = g_hi + pad if hi is None or math.isnan(hi) else hi
     lo, n_lo = certify(ab, lo, delta, log)
     hi, n_hi = certify(ab, hi, delta, log)
     total = n_hi - n_lo

@@ -11,6 +11,7 @@ FB_REAL64 = 1
 FB_COMPLEX128 = 2
 FB_PLAN_EQUAL_WIDTH = 0
 FB_PLAN_EQUAL_COUNT = 1
+FB_PLAN_LEARNED = 2
 PROF_CLASSES = ["lu", "invert", "solve", "resid", "inertia", "jacobi", "gemm", "bandmm"]
 
 
@@ -33,7 +34,7 @@ class fb_feast_opts(C.Structure):
 class fb_plan_opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("K", C.c_int32), ("lo", C.c_double), ("hi", C.c_double),
                 ("count_tol", C.c_double), ("cert_delta", C.c_double),
-                ("max_rounds", C.c_int32)]
+                ("max_rounds", C.c_int32), ("planner", C.c_void_p), ("seed", C.c_uint64)]
 
 
 P = C.c_void_p
@@ -60,6 +61,13 @@ SIGNATURES = {
     "fb_autotune": (C.c_int, [C.POINTER(fb_band), C.c_int32, C.c_int32, C.c_int32, C.c_char_p,
                               PI32, PD, P, PSZ, P]),
     "fb_tune_load": (C.c_int, [C.c_char_p]),
+    "band_cheb_moments": (C.c_int, [C.POINTER(fb_band), C.c_int32, C.c_int32, C.c_uint64, PD, PD,
+                                    P, PSZ, P]),
+    "band_features": (C.c_int, [C.POINTER(fb_band), C.c_uint64, PD, P, PSZ, P]),
+    "fb_planner_bytes": (C.c_size_t, []),
+    "planner_forward": (C.c_int, [P, C.c_int32, P, P, P, PSZ, P]),
+    "planner_train_step": (C.c_int, [P, P, C.c_int32, P, P, C.c_float, C.c_int32,
+                                     C.POINTER(C.c_float), P, P, PSZ, P]),
     "fb_strerror": (C.c_char_p, [C.c_int]),
     "fb_device_info": (C.c_int, [PI32, C.c_char_p, C.c_int32]),
 }

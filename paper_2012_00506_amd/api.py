@@ -221,13 +221,17 @@ def feast_band_slice(B, lo, hi, Y, m_expected=None, n_nodes=8, tol=1e-10, max_it
 
 
 def slice_plan(B, K, mode="equal_count", lo=float("nan"), hi=float("nan"), count_tol=0.05,
-               cert_delta=1e-8, max_rounds=60, stream=None):
+               cert_delta=1e-8, max_rounds=60, planner=None, seed=0, stream=None):
     """Slice boundaries (K+1), exact counts (K) and the number of inertia
-    evaluations, by equal width or equal count (bisection)."""
+    evaluations, by equal width, equal count (bisection) or equal count
+    searched with the planner network's predicted distribution (``planner``:
+    device weights tensor; None in "learned" mode = uniform prior)."""
     B = _as_band(B)
-    modes = {"equal_width": N.FB_PLAN_EQUAL_WIDTH, "equal_count": N.FB_PLAN_EQUAL_COUNT}
+    modes = {"equal_width": N.FB_PLAN_EQUAL_WIDTH, "equal_count": N.FB_PLAN_EQUAL_COUNT,
+             "learned": N.FB_PLAN_LEARNED}
+    wp = C.c_void_p(planner.data_ptr()) if planner is not None else None
     o = N.fb_plan_opts(modes[mode], int(K), float(lo), float(hi), float(count_tol),
-                       float(cert_delta), int(max_rounds))
+                       float(cert_delta), int(max_rounds), wp, int(seed))
     bounds = np.zeros(K + 1, np.float64)
     counts = np.zeros(K, np.int32)
     nev = C.c_int32(0)
@@ -348,3 +352,83 @@ def autotune(B, precision, nsys=8, m=256, cache_path=None, stream=None):
 
 def tune_load(cache_path) -> int:
     return int(N.lib().fb_tune_load(cache_path.encode()))
+
+
+def _query_run(name, call):
+    lw = C.c_size_t(0)
+    N.check(name, call(None, C.byref(lw)))
+    return lw
+
+
+def cheb_moments(B, K=16, P=20, seed=0, stream=None):
+    """(P, K+1) Chebyshev moments and (g_lo, g_hi, ||B||_1)."""
+    B = _as_band(B)
+    bs = B.struct()
+    mu = np.zeros(P * (K + 1))
+    g = np.zeros(3)
+    L = N.lib()
+    sh = C.c_void_p(_stream_handle(stream))
+    f = lambda w, lw: L.band_cheb_moments(C.byref(bs), K, P, seed, mu.ctypes.data_as(N.PD),
+                                          g.ctypes.data_as(N.PD), w, lw, sh)
+    lw = _query_run("band_cheb_moments", f)
+    ws = _workspace(None, lw, B.data.device)
+    lw2 = C.c_size_t(ws.numel())
+    N.check("band_cheb_moments", f(C.c_void_p(ws.data_ptr()), C.byref(lw2)))
+    return mu.reshape(P, K + 1), g
+
+
+def band_features(B, seed=0, stream=None) -> np.ndarray:
+    """The 80 planner features of B (float64)."""
+    B = _as_band(B)
+    bs = B.struct()
+    feat = np.zeros(80)
+    L = N.lib()
+    sh = C.c_void_p(_stream_handle(stream))
+    f = lambda w, lw: L.band_features(C.byref(bs), seed, feat.ctypes.data_as(N.PD), w, lw, sh)
+    lw = _query_run("band_features", f)
+    ws = _workspace(None, lw, B.data.device)
+    lw2 = C.c_size_t(ws.numel())
+    N.check("band_features", f(C.c_void_p(ws.data_ptr()), C.byref(lw2)))
+    return feat
+
+
+def planner_bytes() -> int:
+    return int(N.lib().fb_planner_bytes())
+
+
+def planner_forward(weights: torch.Tensor, x: torch.Tensor, stream=None) -> torch.Tensor:
+    """Network outputs (batch, 64) for features x (batch, 80) float32 on the device."""
+    x = x.contiguous().float()
+    out = torch.empty((x.shape[0], 64), dtype=torch.float32, device=x.device)
+    L = N.lib()
+    sh = C.c_void_p(_stream_handle(stream))
+    f = lambda w, lw: L.planner_forward(C.c_void_p(weights.data_ptr()), x.shape[0],
+                                        C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()),
+                                        w, lw, sh)
+    lw = _query_run("planner_forward", f)
+    ws = _workspace(None, lw, x.device)
+    lw2 = C.c_size_t(ws.numel())
+    N.check("planner_forward", f(C.c_void_p(ws.data_ptr()), C.byref(lw2)))
+    return out
+
+
+def planner_train_step(weights, opt_state, x, target, lr, t, grads=None, want_loss=True,
+                       stream=None):
+    """One Adam step (or gradients only when ``grads`` is given); returns the
+    batch loss (float) when want_loss."""
+    x = x.contiguous().float()
+    target = target.contiguous().float()
+    loss = C.c_float(0)
+    L = N.lib()
+    sh = C.c_void_p(_stream_handle(stream))
+    gp = C.c_void_p(grads.data_ptr()) if grads is not None else None
+    op = C.c_void_p(opt_state.data_ptr()) if opt_state is not None else None
+    f = lambda w, lw: L.planner_train_step(C.c_void_p(weights.data_ptr()), op, x.shape[0],
+                                           C.c_void_p(x.data_ptr()),
+                                           C.c_void_p(target.data_ptr()), float(lr), int(t),
+                                           C.byref(loss) if want_loss else None, gp, w, lw, sh)
+    lw = _query_run("planner_train_step", f)
+    ws = _workspace(None, lw, x.device)
+    lw2 = C.c_size_t(ws.numel())
+    N.check("planner_train_step", f(C.c_void_p(ws.data_ptr()), C.byref(lw2)))
+    return float(loss.value) if want_loss else None

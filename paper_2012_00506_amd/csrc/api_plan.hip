@@ -8,6 +8,7 @@
 #include <map>
 #include <vector>
 
+#include "planner.h"
 #include "solve_job.h"
 
 namespace fb {
@@ -86,7 +87,9 @@ extern "C" int slice_plan(const fb_band* B, const fb_plan_opts* o, double* bound
                           void* stream) {
   if (check_band(B)) return -1;
   if (!o) return -2;
-  if (o->mode != FB_PLAN_EQUAL_WIDTH && o->mode != FB_PLAN_EQUAL_COUNT) return -2;
+  if (o->mode != FB_PLAN_EQUAL_WIDTH && o->mode != FB_PLAN_EQUAL_COUNT &&
+      o->mode != FB_PLAN_LEARNED)
+    return -2;
   if (o->K < 1 || o->K > 1 << 20) return -2;
   if (!(o->cert_delta >= 0) || !(o->count_tol >= 0) || o->max_rounds < 0) return -2;
   if (o->mode == FB_PLAN_EQUAL_WIDTH && (isnan(o->lo) || isnan(o->hi) || !(o->lo < o->hi)))
@@ -106,6 +109,21 @@ extern "C" int slice_plan(const fb_band* B, const fb_plan_opts* o, double* bound
   int32_t* cnt = ar.take<int32_t>(3 * (size_t)cap);
   size_t scb = inertia_scratch_bytes(bd, cap);
   void* scratch = scb ? (void*)ar.take<char>(scb) : nullptr;
+  const bool learned = o->mode == FB_PLAN_LEARNED;
+  float *xin = nullptr, *yout = nullptr, *hid = nullptr;
+  Arena far;  // features scratch, carved after everything else
+  if (learned && o->planner) {
+    xin = ar.take<float>(kPlanFeatures);
+    yout = ar.take<float>(kPlanOutputs);
+    hid = ar.take<float>(kH1 + kH2);
+    far.base = nullptr;
+    std::vector<double> dummy(kPlanFeatures);
+    FB_TRY(band_features_dev(bd, o->seed, far, dummy.data(), st));  // size query
+    char* fbase = ar.take<char>(far.used + 256);
+    far.base = fbase;
+    far.cap = far.used + 256;
+    far.used = 0;
+  }
   if (work == nullptr) {
     *lwork = ar.used;
     return 0;
@@ -123,8 +141,11 @@ extern "C" int slice_plan(const fb_band* B, const fb_plan_opts* o, double* bound
     edges[K] = o->hi;
     FB_TRY(certify_all(ir, edges, delta, neg));
   } else {
-    double lo = isnan(o->lo) ? stats[1] : o->lo;
-    double hi = isnan(o->hi) ? stats[2] : o->hi;
+    // no interval: the whole spectrum, i.e. the Gershgorin interval widened
+    // so that a bound that is itself an eigenvalue stays inside [lo, hi)
+    const double pad = 4.0 * delta + 1e-12 * stats[0];
+    double lo = isnan(o->lo) ? stats[1] - pad : o->lo;
+    double hi = isnan(o->hi) ? stats[2] + pad : o->hi;
     if (!(lo < hi)) return -2;
     std::vector<double> ends = {lo, hi};
     std::vector<int> ne;
@@ -136,8 +157,58 @@ extern "C" int slice_plan(const fb_band* B, const fb_plan_opts* o, double* bound
     for (int i = 1; i < K; ++i) target[i - 1] = n_lo + (int)nearbyint((double)i * total / K);  // half to even
     const int tol = (int)floor(o->count_tol * total / K);
     std::map<double, int> known = {{lo, n_lo}, {hi, n_hi}};
+    // Predicted fraction of eigenvalues below x as a monotone piecewise-linear
+    // function through (px, py): the network's 64 outputs at the centres of
+    // the Gershgorin interval's 64 cells, clipped to [0, 1] and made
+    // non-decreasing; without a network, the uniform density on [lo, hi].
+    std::vector<double> px, py;
+    if (learned) {
+      px = {stats[1]};
+      py = {0.0};
+      if (o->planner && K > 1) {
+        std::vector<double> feat(kPlanFeatures);
+        FB_TRY(band_features_dev(bd, o->seed, far, feat.data(), st));
+        std::vector<float> xf(feat.begin(), feat.end());
+        FB_HIP(hipMemcpyAsync(xin, xf.data(), sizeof(float) * kPlanFeatures,
+                              hipMemcpyHostToDevice, st));
+        FB_TRY(net_forward((const float*)o->planner, 1, xin, yout, hid, hid + kH1, st));
+        std::vector<float> q(kPlanOutputs);
+        FB_HIP(hipMemcpyAsync(q.data(), yout, sizeof(float) * kPlanOutputs,
+                              hipMemcpyDeviceToHost, st));
+        FB_HIP(hipStreamSynchronize(st));
+        const double glo = stats[1], ghi = stats[2];
+        double run = 0.0;
+        for (int k = 0; k < kPlanOutputs; ++k) {
+          double v = std::min(1.0, std::max(0.0, (double)q[k]));  // NaN -> 0
+          run = std::max(run, v);
+          px.push_back(glo + (k + 0.5) * (ghi - glo) / kPlanOutputs);
+          py.push_back(run);
+        }
+        px.push_back(ghi);
+        py.push_back(1.0);
+      } else {
+        px = {lo, hi};
+        py = {(double)n_lo / bd.n, (double)n_hi / bd.n};
+      }
+    }
+    auto fhat = [&](double x) {
+      if (x <= px.front()) return py.front();
+      if (x >= px.back()) return py.back();
+      size_t j = std::upper_bound(px.begin(), px.end(), x) - px.begin();
+      double t = (x - px[j - 1]) / (px[j] - px[j - 1]);
+      return py[j - 1] + t * (py[j] - py[j - 1]);
+    };
+    auto finv = [&](double y) {  // smallest x with fhat(x) >= y
+      if (y <= py.front()) return px.front();
+      if (y >= py.back()) return px.back();
+      size_t j = std::lower_bound(py.begin(), py.end(), y) - py.begin();
+      if (py[j] <= py[j - 1]) return px[j];
+      return px[j - 1] + (px[j] - px[j - 1]) * (y - py[j - 1]) / (py[j] - py[j - 1]);
+    };
     std::vector<double> found(K - 1, NAN);
     std::vector<char> have(K - 1, 0);
+    // bracket widths one and two rounds ago
+    std::vector<double> w1(K - 1, INFINITY), w2(K - 1, INFINITY);
     for (int round = 0; round < o->max_rounds; ++round) {
       std::vector<double> xs;
       std::vector<int> vs;
@@ -160,7 +231,20 @@ extern "C" int slice_plan(const fb_band* B, const fb_plan_opts* o, double* bound
           found[i] = xs[ib];
           have[i] = 1;
         } else {
-          shifts.push_back(0.5 * (xs[ia] + xs[ib]));
+          const double xa = xs[ia], xb = xs[ib], w = xb - xa;
+          double s = 0.5 * (xa + xb);
+          if (learned && w <= 0.5 * w2[i]) {
+            // The exact counts at the bracket ends rescale the predicted
+            // distribution inside it; invert it at the target.  A bracket
+            // that did not halve over the last two rounds is bisected.
+            const double fa = fhat(xa), fb = fhat(xb);
+            const double frac = (double)(t - vs[ia]) / (double)(vs[ib] - vs[ia]);
+            double g = fb > fa ? finv(fa + frac * (fb - fa)) : xa + frac * w;
+            s = std::min(xb - 0.01 * w, std::max(xa + 0.01 * w, g));
+          }
+          w2[i] = w1[i];
+          w1[i] = w;
+          shifts.push_back(s);
         }
       }
       if (shifts.empty()) break;

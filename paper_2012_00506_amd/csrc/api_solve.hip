@@ -144,20 +144,24 @@ size_t ir_wave_jobs(int64_t n, int tile) {
 void carve_refine(Arena& ar, const Band& bd, int tile, int max_jobs, bool ir, bool need_res,
                   RefineBufs& rb) {
   rb.tile = tile;
+  rb.gcols = residual_cols(block_size(bd.b));  // >= tile (variant_fits)
   rb.jobs_dev = ar.take<SolveJob>(std::max(max_jobs, 1));
   rb.cap_jobs = std::max(max_jobs, 1);
-  rb.wave = need_res ? std::min<size_t>(ir_wave_jobs(bd.n, tile), (size_t)std::max(max_jobs, 1)) : 0;
+  rb.wave = need_res ? std::min<size_t>(ir_wave_jobs(bd.n, rb.gcols), (size_t)std::max(max_jobs, 1)) : 0;
   rb.rjobs_dev = need_res ? ar.take<ResJob>(rb.wave) : nullptr;
-  rb.cjobs_dev = ir ? ar.take<SolveJob>(rb.wave) : nullptr;
-  rb.rbuf = need_res ? ar.take<c128>(rb.wave * (size_t)bd.n * tile) : nullptr;
+  // every group of a wave can need corrections for all of its tiles
+  const size_t per_group = (size_t)(rb.gcols + tile - 1) / tile;
+  rb.cjobs_dev = ir ? ar.take<SolveJob>(rb.wave * per_group) : nullptr;
+  rb.rbuf = need_res ? ar.take<c128>(rb.wave * (size_t)bd.n * rb.gcols) : nullptr;
   rb.part = need_res ? ar.take<double>(residual_part_doubles(bd.n, (int)rb.wave)) : nullptr;
   rb.ratio = need_res ? ar.take<double>(rb.wave) : nullptr;
 }
 
-// Launch the solve jobs, then (need_res) compute per-tile residuals
-// ||y - A x|| / ||y|| in FP64 and (ir) refine the tiles above ir_tol with
-// correction solves until they pass or ir_max passes are spent.  The tiles
-// are processed in waves that bound the residual buffers.
+// Launch the solve jobs, then (need_res) compute the FP64 residual
+// ||y - A x|| / ||y|| per group of adjacent tiles (same system, direction and
+// blocks, up to gcols columns) and (ir) refine the groups above ir_tol with
+// correction solves of their tiles until they pass or ir_max passes are
+// spent.  Groups are processed in waves that bound the residual buffers.
 template <typename R>
 int solve_refine(const Band& bd, const cx<R>* mats, const int16_t* perm,
                  const std::vector<SolveJob>& jobs, const std::vector<c128>& zsys, bool ir,
@@ -173,37 +177,54 @@ int solve_refine(const Band& bd, const cx<R>* mats, const int16_t* perm,
   FB_TRY(launch_solve_jobs<R>(mats, perm, bd.n, bd.b, njobs, rb.jobs_dev,
                               solve_flops(bd.n, bd.b, cols), st));
   if (!need_res) return 0;
-  const int tile = rb.tile;
+  // groups [first, last] of consecutive jobs
+  std::vector<std::pair<int, int>> groups;
+  for (int i = 0; i < njobs; ++i) {
+    if (!groups.empty()) {
+      const SolveJob& f = jobs[groups.back().first];
+      const SolveJob& p = jobs[groups.back().second];
+      const SolveJob& c = jobs[i];
+      if (c.sys == p.sys && c.dir == p.dir && c.in == p.in && c.out == p.out &&
+          c.ldin == p.ldin && c.ldout == p.ldout && c.col0 == p.col0 + p.ncol &&
+          c.col0 + c.ncol - f.col0 <= rb.gcols) {
+        groups.back().second = i;
+        continue;
+      }
+    }
+    groups.push_back({i, i});
+  }
+  const int ng = (int)groups.size();
   std::vector<ResJob> rj, ra;
   std::vector<SolveJob> cj;
   std::vector<double> rat;
   std::vector<size_t> ai;
-  for (size_t w0 = 0; w0 < (size_t)njobs; w0 += rb.wave) {
-    size_t nw = std::min(rb.wave, (size_t)njobs - w0);
+  for (size_t w0 = 0; w0 < (size_t)ng; w0 += rb.wave) {
+    size_t nw = std::min(rb.wave, (size_t)ng - w0);
     rj.assign(nw, ResJob{});
     std::vector<int> active(nw, 1);
-    for (size_t i = 0; i < nw; ++i) {
-      const SolveJob& jb = jobs[w0 + i];
-      ResJob& r = rj[i];
-      r.x = jb.out;
-      r.y = jb.in;
-      r.r = rb.rbuf + i * (size_t)bd.n * tile - (int64_t)jb.col0 * bd.n;
-      r.ldx = jb.ldout;
-      r.ldy = jb.ldin;
+    for (size_t g = 0; g < nw; ++g) {
+      const SolveJob& f = jobs[groups[w0 + g].first];
+      const SolveJob& l = jobs[groups[w0 + g].second];
+      ResJob& r = rj[g];
+      r.x = f.out;
+      r.y = f.in;
+      r.r = rb.rbuf + g * (size_t)bd.n * rb.gcols - (int64_t)f.col0 * bd.n;
+      r.ldx = f.ldout;
+      r.ldy = f.ldin;
       r.ldr = bd.n;
-      r.col0 = jb.col0;
-      r.ncol = jb.ncol;
-      r.dir = jb.dir;
-      r.z = zsys[jb.sys];
+      r.col0 = f.col0;
+      r.ncol = l.col0 + l.ncol - f.col0;
+      r.dir = f.dir;
+      r.z = zsys[f.sys];
     }
     const int maxpass = ir ? ir_max : 0;
     for (int pass = 0;; ++pass) {
       ra.clear();
       ai.clear();
-      for (size_t i = 0; i < nw; ++i)
-        if (active[i]) {
-          ra.push_back(rj[i]);
-          ai.push_back(i);
+      for (size_t g = 0; g < nw; ++g)
+        if (active[g]) {
+          ra.push_back(rj[g]);
+          ai.push_back(g);
         }
       if (ra.empty()) break;
       FB_HIP(hipMemcpyAsync(rb.rjobs_dev, ra.data(), sizeof(ResJob) * ra.size(),
@@ -218,24 +239,26 @@ int solve_refine(const Band& bd, const cx<R>* mats, const int16_t* perm,
       FB_HIP(hipStreamSynchronize(st));
       cj.clear();
       for (size_t a = 0; a < ai.size(); ++a) {
-        size_t i = ai[a];
-        const SolveJob& jb = jobs[w0 + i];
+        size_t g = ai[a];
+        const int sys = jobs[groups[w0 + g].first].sys;
         bool ok = ir ? (rat[a] <= ir_tol) : true;
         if (ok || pass >= maxpass) {
-          active[i] = 0;
+          active[g] = 0;
           double q = rat[a];
-          if (!(q <= sys_res[jb.sys])) sys_res[jb.sys] = q;
+          if (!(q <= sys_res[sys])) sys_res[sys] = q;
           if (ir && !ok && unconverged) ++*unconverged;
           continue;
         }
-        SolveJob c = jb;
-        c.in = rj[i].r;
-        c.mid = rj[i].r;
-        c.ldin = bd.n;
-        c.ldmid = bd.n;
-        c.add = 1;
-        cj.push_back(c);
-        sys_pass[jb.sys] = std::max(sys_pass[jb.sys], pass + 1);
+        for (int i = groups[w0 + g].first; i <= groups[w0 + g].second; ++i) {
+          SolveJob c = jobs[i];
+          c.in = rj[g].r;
+          c.mid = rj[g].r;
+          c.ldin = bd.n;
+          c.ldmid = bd.n;
+          c.add = 1;
+          cj.push_back(c);
+        }
+        sys_pass[sys] = std::max(sys_pass[sys], pass + 1);
       }
       if (cj.empty()) break;
       FB_HIP(hipMemcpyAsync(rb.cjobs_dev, cj.data(), sizeof(SolveJob) * cj.size(),

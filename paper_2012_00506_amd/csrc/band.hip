@@ -129,6 +129,7 @@ int ingest_band(const fb_band* B, Band& out, Arena& ar, hipStream_t st) {
   // a diagonal matrix is handled as a band of width 1 with a zero sub-diagonal
   out.n = B->n;
   out.b = B->b > 0 ? B->b : 1;
+  out.b0 = B->b;
   out.cplx = B->dtype == FB_COMPLEX128;
   out.Bd = ar.take<c128>((size_t)(out.b + 1) * B->n);
   out.stats = ar.take<double>(3);

@@ -112,7 +112,8 @@ struct Arena {
 // zero beyond the matrix), with the norms and Gershgorin bounds.
 struct Band {
   int64_t n;
-  int b;
+  int b;         // bandwidth used by the kernels (>= 1)
+  int b0;        // declared bandwidth (may be 0)
   bool cplx;
   c128* Bd;      // dev, (b+1) * n
   double* stats; // dev, 3: ||B||_1, g_lo, g_hi

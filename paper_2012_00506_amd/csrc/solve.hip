@@ -47,33 +47,28 @@ template int solve_tile<float>(int);
 template int solve_tile<double>(int);
 
 // ---------------------------------------------------------------- residual
-// r = y - (zz x - B x) in FP64 for 16 columns of a job (zz = z for A x = y,
+// r = y - (zz x - B x) in FP64 for the columns of a job (zz = z for A x = y,
 // conj(z) for A^H x = y), with B in block-tridiagonal form:
 // (B x)_k = B(k,k-1) x_{k-1} + B(k,k) x_k + B(k,k+1) x_{k+1}, each an NB x NB
-// by NB x 16 product on f64 MFMA.  x blocks roll through three LDS slots.
-// Per (job, column): sum |r|^2 and sum |y|^2.
-template <int NB>
-__global__ void __launch_bounds__(NB * 4)
+// by NB x T product on f64 MFMA, one wave per 16 x 16 output tile.  x blocks
+// roll through three LDS slots.  Per (job, column): sum |r|^2 and sum |y|^2.
+template <int NB, int T>
+__global__ void __launch_bounds__(NB * 4 * (T / 16))
 k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* __restrict__ jobs,
                  int njobs, double* __restrict__ part) {
-  constexpr int T = 16, NC = 1;
+  constexpr int NC = 1, NRW = NB / 16, NW = NRW * (T / 16);
   extern __shared__ char lds_raw[];
   c128* X = reinterpret_cast<c128*>(lds_raw);              // 3 slots of NB x T
-  double* red = reinterpret_cast<double*>(X + 3 * NB * T);  // 2 x (NB/16) x 16
-  const int job = blockIdx.x >> 1, g = blockIdx.x & 1;
+  double* red = reinterpret_cast<double*>(X + 3 * NB * T);  // 2 x NW x 16
+  const int job = remap_job(blockIdx.x, njobs);
   if (job >= njobs) return;
   const ResJob jb = jobs[job];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, nthr = NB * 4;
-  const int c0 = jb.col0 + 16 * g;
-  const int nc = jb.ncol - 16 * g;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int w = wv % NRW, cb0 = 16 * (wv / NRW);
+  const int nthr = NB * 4 * (T / 16);
+  const int c0 = jb.col0;
+  const int nc = jb.ncol;
   const size_t bb = (size_t)NB * NB;
-  if (nc <= 0) {
-    for (int c = t; c < 16; c += nthr) {
-      part[((size_t)job * 32 + 16 * g + c) * 2] = 0.0;
-      part[((size_t)job * 32 + 16 * g + c) * 2 + 1] = 0.0;
-    }
-    return;
-  }
   const c128 zz = jb.dir ? mk(jb.z.x, -jb.z.y) : jb.z;
   auto xload = [&](int k, int slot) {
     for (int e = t; e < NB * T; e += nthr) {
@@ -86,7 +81,7 @@ k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* 
   for (int e = t; e < NB * T; e += nthr) X[2 * NB * T + e] = mk(0.0, 0.0);  // x_{-1}
   xload(0, 0);
   double rr = 0.0, yy = 0.0;
-  const int col = lane & 15;
+  const int col = cb0 + (lane & 15);
   Acc<double, NC> acc;
   for (int k = 0; k < K; ++k) {
     xload(k + 1, (k + 1) % 3);
@@ -105,12 +100,12 @@ k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* 
     }
     const c128* Bk = Bblk + (size_t)k * 3 * bb;
     if (k > 0)
-      wave_prod<double, NB, NC, false, false>(acc, Bk, X + ((k + 2) % 3) * NB * T, T, nullptr, w, 0,
-                                              lane, 16 * w, NB);
-    wave_prod<double, NB, NC, false, false>(acc, Bk + bb, Xk, T, nullptr, w, 0, lane, 0, NB);
+      wave_prod<double, NB, NC, false, false>(acc, Bk, X + ((k + 2) % 3) * NB * T, T, nullptr, w,
+                                              cb0, lane, 16 * w, NB);
+    wave_prod<double, NB, NC, false, false>(acc, Bk + bb, Xk, T, nullptr, w, cb0, lane, 0, NB);
     if (k + 1 < K)
       wave_prod<double, NB, NC, false, false>(acc, Bk + 2 * bb, X + ((k + 1) % 3) * NB * T, T,
-                                              nullptr, w, 0, lane, 0, 16 * w + 16);
+                                              nullptr, w, cb0, lane, 0, 16 * w + 16);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       int row = 16 * w + MF<double>::row(lane, r);
@@ -123,24 +118,25 @@ k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* 
     }
     __syncthreads();
   }
-  // column sums: lanes l, l+16, l+32, l+48 share a column; then across waves
+  // column sums: lanes l, l+16, l+32, l+48 share a column; then across row waves
   for (int off = 16; off < 64; off <<= 1) {
     rr += __shfl_xor(rr, off, 64);
     yy += __shfl_xor(yy, off, 64);
   }
   if (lane < 16) {
-    red[(0 * (NB / 16) + w) * 16 + lane] = rr;
-    red[(1 * (NB / 16) + w) * 16 + lane] = yy;
+    red[(0 * NW + wv) * 16 + lane] = rr;
+    red[(1 * NW + wv) * 16 + lane] = yy;
   }
   __syncthreads();
-  if (t < 16) {
+  if (t < T) {
+    const int cw = t / 16, l = t % 16;
     double sr = 0.0, sy = 0.0;
-    for (int q = 0; q < NB / 16; ++q) {
-      sr += red[(0 * (NB / 16) + q) * 16 + t];
-      sy += red[(1 * (NB / 16) + q) * 16 + t];
+    for (int q = 0; q < NRW; ++q) {
+      sr += red[(0 * NW + cw * NRW + q) * 16 + l];
+      sy += red[(1 * NW + cw * NRW + q) * 16 + l];
     }
-    part[((size_t)job * 32 + 16 * g + t) * 2] = sr;
-    part[((size_t)job * 32 + 16 * g + t) * 2 + 1] = sy;
+    part[((size_t)job * 32 + t) * 2] = sr;
+    part[((size_t)job * 32 + t) * 2 + 1] = sy;
   }
 }
 
@@ -164,21 +160,27 @@ size_t residual_part_doubles(int64_t n, int njobs) {
   return (size_t)njobs * 32 * 2;
 }
 
+// residual jobs carry up to 32 columns; blocks of 128 rows use 16-column
+// tiles (LDS), the others 32
 template <int NB>
 static int launch_res_nb(const Band& bd, int njobs, const ResJob* jobs_dev, double* part,
                          hipStream_t st) {
-  size_t smem = (size_t)3 * NB * 16 * sizeof(c128) + 2 * (NB / 16) * 16 * sizeof(double);
-  (void)hipFuncSetAttribute((const void*)k_shift_residual<NB>,
+  constexpr int T = NB <= 64 ? 32 : 16;
+  size_t smem = (size_t)3 * NB * T * sizeof(c128) + 2 * (NB / 16) * (T / 16) * 16 * sizeof(double);
+  (void)hipFuncSetAttribute((const void*)k_shift_residual<NB, T>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   (void)hipGetLastError();
   for (int j0 = 0; j0 < njobs; j0 += 1 << 20) {
     int nj = njobs - j0 < (1 << 20) ? njobs - j0 : (1 << 20);
-    k_shift_residual<NB><<<2 * nj, NB * 4, smem, st>>>(bd.Bblk, bd.n, bd.K, jobs_dev + j0, nj,
-                                                       part + (size_t)j0 * 64);
+    int grid = 8 * ((nj + 7) / 8);
+    k_shift_residual<NB, T><<<grid, NB * 4 * (T / 16), smem, st>>>(
+        bd.Bblk, bd.n, bd.K, jobs_dev + j0, nj, part + (size_t)j0 * 64);
     FB_HIP(hipGetLastError());
   }
   return 0;
 }
+
+int residual_cols(int nb) { return nb <= 64 ? 32 : 16; }
 
 int launch_residual_jobs(const Band& bd, int njobs, const ResJob* jobs_dev, double* part,
                          double* ratio_dev, double work, hipStream_t st) {

@@ -47,6 +47,8 @@ template <typename R>
 int solve_tile(int b);
 
 size_t residual_part_doubles(int64_t n, int njobs);
+// columns per residual job for block size nb
+int residual_cols(int nb);
 int launch_residual_jobs(const Band& bd, int njobs, const ResJob* jobs_dev, double* part,
                          double* ratio_dev, double work, hipStream_t st);
 // algorithmic flops: solve 24 n b per column (L: n b, U: 2 n b complex MACs),
@@ -75,6 +77,7 @@ int factor_systems(const Band& bd, int nsys, const double* z_host, FactorBufs<R>
 // Buffers of the solve + refinement driver.
 struct RefineBufs {
   int tile = 32;
+  int gcols = 32;  // columns per residual group
   int cap_jobs = 0;
   size_t wave = 0;
   SolveJob* jobs_dev = nullptr;

@@ -25,6 +25,8 @@ std::map<std::pair<int, int>, int>& table() {
 }  // namespace
 
 bool variant_fits(size_t rsize, int nb, int v) {
+  // a refinement residual group (residual_cols(nb) columns) must cover a tile
+  if (variant_tile(v) > residual_cols(nb)) return false;
   size_t lds = ((2 * (size_t)nb * sizeof(int) + 15) & ~(size_t)15) +
                (size_t)4 * nb * variant_tile(v) * 2 * rsize;
   return lds <= 160 * 1024;

@@ -94,17 +94,19 @@ def rhs_block(n: int, m: int, seed: int, complex_: bool, col0: int = 0) -> np.nd
     return rhs_columns(n, np.arange(col0, col0 + m), seed, complex_)
 
 
-def planner_matrix(i: int):
+def planner_matrix(i: int, scale: int = 1):
     """Training/validation matrix i of the planner set (seed 4000 + i).
 
-    n = 256 * U{16..128}, b = U{16..128} (clipped below n), real or complex
+    n = 256 * U{16..128} // scale (scale > 1 gives the same family at a
+    fraction of the size, for quick tests), b = U{16..128} (clipped below n),
+    real or complex
     with probability 1/2, diagonal drawn from one of three families:
     uniform U(-50, 50); a Gaussian mixture of 2..8 clusters; uniform with two
     gaps.  Off-diagonals N(0, 1/b) as in ``band_matrix``.
     Returns (ab, meta dict).
     """
     rng = np.random.default_rng(4000 + i)
-    n = 256 * int(rng.integers(16, 129))
+    n = 256 * int(rng.integers(16, 129)) // scale
     b = int(rng.integers(16, 129))
     b = min(b, n - 1)
     complex_ = bool(rng.integers(0, 2))

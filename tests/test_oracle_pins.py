@@ -310,3 +310,15 @@ def test_planner_certification_moves_boundary():
     edges, counts, _ = planner.plan_equal_width(ab, 3, 0.0, 9.0)
     assert np.all(np.min(np.abs(d[None, :] - edges[:, None]), axis=1) > 0)
     assert counts.sum() == int(((d >= edges[0]) & (d < edges[-1])).sum())
+
+
+def test_planner_whole_spectrum_when_gershgorin_is_tight():
+    # diagonal B: the Gershgorin bounds are eigenvalues (multiplicity 5); the
+    # default interval must still hold all of them
+    d = np.repeat(np.arange(-4.0, 4.0), 5)
+    ab = np.zeros((2, d.size))
+    ab[0] = d
+    edges, counts, _ = planner.plan_equal_count(ab, 4, count_tol=0.0)
+    assert counts.sum() == d.size
+    assert list(counts) == [10, 10, 10, 10]
+    assert np.all(np.min(np.abs(d[None, :] - edges[:, None]), axis=1) > 1e-8 * 4)
