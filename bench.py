@@ -45,7 +45,40 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 path")
     p.add_argument("--cpu-cols", type=int, default=256, help="columns in the CPU sample")
+    p.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                   help="after the timed region, run one plain device copy of MIB MiB "
+                        "(calibrates the HBM byte counters of a profiler run)")
     return p.parse_args()
+
+
+# Sources of the block-solve kernel: HBM byte counts recorded under profiles/
+# are reported as roofline traffic only while these files are unchanged.
+SOLVE_SOURCES = ["solve_kernel.h", "solve_f32.hip", "solve_f64.hip", "solve.hip", "solve_job.h",
+                 "fb_internal.h"]
+
+
+def solve_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in SOLVE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2012_00506_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(workload: str, precision: int):
+    """HBM bytes per launch of the block-solve kernel from the committed
+    counter summary of this workload, if taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", f"solve_{workload}_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    ent = rec.get("c64" if precision == 1 else "c128")
+    if not ent or rec.get("source_sha256") != solve_source_hash():
+        return None
+    return ent["hbm_bytes_per_launch"]
 
 
 def cpu_baseline(cfg, ab, m0_mean, ncols):
@@ -106,7 +139,7 @@ def run_path(fb, F, Y, Q, steps, warmup, cols_per_step):
             "event_ms_per_step": ev0.elapsed_time(ev1) / steps}
 
 
-def roofline(prof, precision):
+def roofline(prof, precision, workload):
     name, (L, ms, work) = max(prof.items(), key=lambda kv: kv[1][1])
     if L == 0 or ms <= 0:
         return None
@@ -120,7 +153,8 @@ def roofline(prof, precision):
         peak = PEAK_FP32_MFMA if precision == 1 else PEAK_FP64
         bound = "mfma"
     return {"kernel": name, "bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": recorded_traffic(workload, precision) if name == "solve" else None,
             "launches": L, "avg_launch_ms": ms / L, "work_per_launch_flop": work / L}
 
 
@@ -195,7 +229,7 @@ def main():
                    "slices": len(cfg.slices), "nodes": n_nodes, "systems": len(cfg.slices) * n_nodes,
                    "m0": m0, "rhs_cols_per_step": cols_per_step, "ir_tol": 1e-10,
                    "parallelism": "single GPU"},
-        "roofline": roofline(main_["prof"], 1),
+        "roofline": roofline(main_["prof"], 1, cfg.name),
         "fp32ir": {k: v for k, v in main_.items() if k != "prof"},
         "kernels_fp32ir": {k: {"launches": v[0], "ms": v[1], "flop": v[2]}
                            for k, v in main_["prof"].items() if v[0]},
@@ -204,7 +238,7 @@ def main():
     if "fp64" in res:
         r64 = res["fp64"]
         out["fp64"] = {k: v for k, v in r64.items() if k != "prof"}
-        out["fp64"]["roofline"] = roofline(r64["prof"], 0)
+        out["fp64"]["roofline"] = roofline(r64["prof"], 0, cfg.name)
         out["kernels_fp64"] = {k: {"launches": v[0], "ms": v[1], "flop": v[2]}
                                for k, v in r64["prof"].items() if v[0]}
         out["fp32ir_over_fp64"] = main_["value"] / r64["value"]
@@ -212,6 +246,15 @@ def main():
         out["fp64_plain"] = {k: v for k, v in rp.items() if k != "prof"}
         out["fp32ir_over_fp64_plain"] = main_["value"] / rp["value"]
     out["solve_variants"] = tuned
+    if args.calib_copy:
+        nel = args.calib_copy * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = {"read": nel * 4, "write": nel * 4}
+        del src, dst
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, ab, float(np.mean(m0)), args.cpu_cols)
     print(json.dumps(out), flush=True)
