@@ -113,8 +113,13 @@ typedef struct {
   int32_t ir_max;      /* as fb_solve_opts.ir_max (4) */
   int32_t batched;     /* 0: one launch sequence per slice; 1: all slices of
                           a sweep in shared batched launches */
-  double hbm_budget;   /* bytes of workspace the call may use, 0 = all of
-                          *lwork (systems are admitted in waves under it) */
+  double hbm_budget;   /* bytes of device memory the workspace may take,
+                          0 = half of the device's memory.  It sets how many
+                          (node, direction) pairs share one batched launch:
+                          each pair needs an n x m0 complex128 buffer per
+                          slice (batched = 0 uses one) */
+  int32_t pairs;       /* > 0: exactly this many pairs per batched launch
+                          (capped at 2 n_nodes), overriding hbm_budget */
 } fb_feast_opts;
 
 /* FEAST on the slices [lo_i, hi_i) of B (Algorithm alg:FEAST, Section 2.2,

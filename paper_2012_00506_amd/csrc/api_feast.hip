@@ -111,29 +111,43 @@ struct SliceBufs {
 };
 
 // Q_i = sum_j w_ij (z_ij - B)^{-1} Y_i (+ conj(w_ij) (z_ij - B)^{-H} Y_i) for
-// the slices in act: nodes in order, each (node, direction) one batched
-// launch over all slices (batched) or one launch per slice; the solution of
-// each tile is folded into Q_i by the solve epilogue.
+// the slices in act.  The (node, direction) pairs are taken in order, P of
+// them per batched launch over all slices (batched) or one pair of one slice
+// per launch (plain); each pair's solutions go to their own buffer
+// Xp[i * P + p] and are then added into Q_i in pair order, so the sum does
+// not depend on how the pairs were grouped.
 template <typename R>
 int filter_apply(const Band& bd, const FactorBufs<R>& f, int ne, const std::vector<int>& act,
                  const int32_t* m, c128* const* Yc, const int64_t* ldyc, c128* const* Qc,
-                 const int64_t* ldqc, c128* const* Xs, const std::vector<c128>& zsys,
-                 const std::vector<c128>& wsys, bool cplx, bool batched, bool ir, double ir_tol,
-                 int ir_max, bool need_res, RefineBufs& rb, std::vector<double>& sys_res,
-                 std::vector<int32_t>& sys_pass, int* unconverged, hipStream_t st) {
+                 const int64_t* ldqc, c128* const* Xp, int P, AccJob* acc_dev,
+                 const std::vector<c128>& zsys, const std::vector<c128>& wsys, bool cplx,
+                 bool batched, bool ir, double ir_tol, int ir_max, bool need_res, RefineBufs& rb,
+                 std::vector<double>& sys_res, std::vector<int32_t>& sys_pass, int* unconverged,
+                 hipStream_t st) {
   const int64_t n = bd.n;
   const int tile = rb.tile;
   for (int i : act) FB_TRY(fill_zero(Qc[i], n, m[i], ldqc[i], st));
   const int ndir = cplx ? 2 : 1;
-  std::vector<SolveJob> jobs;
+  std::vector<std::pair<int, int>> pairs;
   for (int j = 0; j < ne; ++j)
-    for (int dir = 0; dir < ndir; ++dir) {
-      size_t groups = batched ? 1 : act.size();
-      for (size_t g = 0; g < groups; ++g) {
-        jobs.clear();
+    for (int dir = 0; dir < ndir; ++dir) pairs.push_back({j, dir});
+  const int npair = (int)pairs.size();
+  const int chunk = batched ? std::max(1, std::min(P, npair)) : 1;
+  if (chunk > kMaxPairs) return FB_ERR_INTERNAL;
+  const size_t groups = batched ? 1 : act.size();
+  std::vector<SolveJob> jobs;
+  std::vector<AccJob> aj;
+  for (size_t g = 0; g < groups; ++g)
+    for (int p0 = 0; p0 < npair; p0 += chunk) {
+      const int np = std::min(chunk, npair - p0);
+      jobs.clear();
+      aj.clear();
+      int maxm = 0;
+      for (int p = 0; p < np; ++p) {
+        const int j = pairs[p0 + p].first, dir = pairs[p0 + p].second;
         for (size_t a = 0; a < act.size(); ++a) {
           if (!batched && a != g) continue;
-          int i = act[a];
+          const int i = act[a];
           for (int c0 = 0; c0 < m[i]; c0 += tile) {
             SolveJob jb{};
             jb.sys = i * ne + j;
@@ -142,22 +156,54 @@ int filter_apply(const Band& bd, const FactorBufs<R>& f, int ne, const std::vect
             jb.ncol = std::min(tile, m[i] - c0);
             jb.in = Yc[i];
             jb.ldin = ldyc[i];
-            jb.mid = Xs[i];
-            jb.out = Xs[i];
+            jb.mid = Xp[(size_t)i * P + p];
+            jb.out = Xp[(size_t)i * P + p];
             jb.ldmid = jb.ldout = n;
-            jb.acc = Qc[i];
-            jb.ldacc = ldqc[i];
-            c128 w = wsys[i * ne + j];
-            jb.w = dir == 0 ? w : cconj(w);
-            jb.acc_real = cplx ? 0 : 1;
             jobs.push_back(jb);
           }
         }
-        FB_TRY(solve_refine<R>(bd, f.mats, f.perm, jobs, zsys, ir, ir_tol, ir_max, need_res, rb,
-                               sys_res, sys_pass, unconverged, st));
       }
+      FB_TRY(solve_refine<R>(bd, f.mats, f.perm, jobs, zsys, ir, ir_tol, ir_max, need_res, rb,
+                             sys_res, sys_pass, unconverged, st));
+      for (size_t a = 0; a < act.size(); ++a) {
+        if (!batched && a != g) continue;
+        const int i = act[a];
+        AccJob J{};
+        J.Q = Qc[i];
+        J.ldq = ldqc[i];
+        J.ldx = n;
+        J.np = np;
+        J.m = m[i];
+        J.acc_real = cplx ? 0 : 1;
+        for (int p = 0; p < np; ++p) {
+          const int j = pairs[p0 + p].first, dir = pairs[p0 + p].second;
+          J.X[p] = Xp[(size_t)i * P + p];
+          const c128 w = wsys[i * ne + j];
+          J.w[p] = dir == 0 ? w : cconj(w);
+        }
+        maxm = std::max(maxm, m[i]);
+        aj.push_back(J);
+      }
+      FB_HIP(hipMemcpyAsync(acc_dev, aj.data(), sizeof(AccJob) * aj.size(), hipMemcpyHostToDevice, st));
+      FB_TRY(accumulate_pairs(acc_dev, (int)aj.size(), n, maxm, st));
     }
   return 0;
+}
+
+// Pairs per batched launch: as many (node, direction) pairs as the budget
+// leaves room for, each needing one n x m complex128 buffer per slice.
+static int pairs_per_launch(double budget, int fixed, bool batched, int npair, size_t base,
+                            size_t per_pair) {
+  if (!batched || npair <= 1) return 1;
+  if (fixed > 0) return std::min(fixed, std::min(npair, kMaxPairs));
+  if (!(budget > 0)) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) tot = 0;
+    budget = 0.5 * (double)tot;
+  }
+  const double room = budget - (double)base;
+  int p = per_pair ? (int)std::min<double>(npair, floor(room / (double)per_pair)) : npair;
+  return std::max(1, std::min(p, std::min(npair, kMaxPairs)));
 }
 
 template <typename R>
@@ -205,11 +251,26 @@ int feast_impl(const fb_band* B, int nslice, const double* lo, const double* hi,
   }
   JacobiJob* jj_dev = ar.take<JacobiJob>(nslice);
   int32_t* perm_dev = ar.take<int32_t>(maxm);
+  AccJob* acc_dev = ar.take<AccJob>(nslice);
   const int tile = solve_tile<R>(bd.b);
   int max_jobs = 0;
-  for (int i = 0; i < nslice; ++i) max_jobs += (m0[i] + tile - 1) / tile;
+  size_t cols = 0;
+  for (int i = 0; i < nslice; ++i) {
+    max_jobs += (m0[i] + tile - 1) / tile;
+    cols += m0[i];
+  }
+  const int npair = ne * (cplx ? 2 : 1);
+  const int P = pairs_per_launch(o->hbm_budget, o->pairs, o->batched != 0, npair,
+                                 ar.used + refine_bytes(bd, tile, max_jobs, ir, ir),
+                                 (size_t)n * cols * sizeof(c128));
+  // pair 0 uses the slice's X buffer, pairs 1.. P-1 a pool
+  std::vector<c128*> Xp((size_t)nslice * P);
+  for (int i = 0; i < nslice; ++i) {
+    Xp[(size_t)i * P] = sb[i].X;
+    for (int p = 1; p < P; ++p) Xp[(size_t)i * P + p] = ar.take<c128>((size_t)n * m0[i]);
+  }
   RefineBufs rb;
-  carve_refine(ar, bd, tile, max_jobs, ir, ir, rb);
+  carve_refine(ar, bd, tile, max_jobs * P, ir, ir, rb);
   if (work == nullptr) {
     *lwork = ar.used;
     return 0;
@@ -276,16 +337,15 @@ int feast_impl(const fb_band* B, int nslice, const double* lo, const double* hi,
     if (act.empty()) break;
     // ---- filter: Q = sum_j w_j (z_j - B)^{-1} Y (+ conj(w_j)(z_j - B)^{-H} Y)
     {
-      std::vector<c128*> Yc(nslice), Qc(nslice), Xs(nslice);
+      std::vector<c128*> Yc(nslice), Qc(nslice);
       std::vector<int64_t> lds(nslice, n);
       for (int i = 0; i < nslice; ++i) {
         Yc[i] = sb[i].Y;
         Qc[i] = sb[i].Q;
-        Xs[i] = sb[i].X;
       }
       FB_TRY(filter_apply<R>(bd, f, ne, act, m0, Yc.data(), lds.data(), Qc.data(), lds.data(),
-                             Xs.data(), zsys, wsys, cplx, o->batched != 0, ir, o->ir_tol,
-                             o->ir_max, ir, rb, sys_res, sys_pass, nullptr, st));
+                             Xp.data(), P, acc_dev, zsys, wsys, cplx, o->batched != 0, ir,
+                             o->ir_tol, o->ir_max, ir, rb, sys_res, sys_pass, nullptr, st));
     }
     // ---- orthonormalise: Q^H Q = V s V^H, keep s > 1e-14 max s, Q' = Q V s^{-1/2}
     std::vector<JacobiJob> jj;
@@ -467,10 +527,9 @@ int filter_impl(const fb_band* B, int nslice, const double* lo, const double* hi
   const int nsys = nslice * ne;
   FactorBufs<R> f;
   carve_factors<R>(ar, bd, nsys, f);
-  std::vector<c128*> Yc(nslice), Qc(nslice), Xs(nslice);
+  std::vector<c128*> Yc(nslice), Qc(nslice);
   std::vector<int64_t> ldyc(nslice), ldqc(nslice);
   for (int i = 0; i < nslice; ++i) {
-    Xs[i] = ar.take<c128>((size_t)n * std::max(m[i], 1));
     if (cplx) {
       Yc[i] = (c128*)Y[i];
       Qc[i] = (c128*)Q[i];
@@ -482,11 +541,23 @@ int filter_impl(const fb_band* B, int nslice, const double* lo, const double* hi
       ldyc[i] = ldqc[i] = n;
     }
   }
+  AccJob* acc_dev = ar.take<AccJob>(nslice);
   const int tile = solve_tile<R>(bd.b);
   int max_jobs = 0;
-  for (int i = 0; i < nslice; ++i) max_jobs += (m[i] + tile - 1) / tile;
+  size_t cols = 0;
+  for (int i = 0; i < nslice; ++i) {
+    max_jobs += (m[i] + tile - 1) / tile;
+    cols += std::max(m[i], 1);
+  }
+  const int npair = ne * (cplx ? 2 : 1);
+  const int P = pairs_per_launch(o->hbm_budget, o->pairs, o->batched != 0, npair,
+                                 ar.used + refine_bytes(bd, tile, max_jobs, ir, need_res),
+                                 (size_t)n * cols * sizeof(c128));
+  std::vector<c128*> Xp((size_t)nslice * P);
+  for (int i = 0; i < nslice; ++i)
+    for (int p = 0; p < P; ++p) Xp[(size_t)i * P + p] = ar.take<c128>((size_t)n * std::max(m[i], 1));
   RefineBufs rb;
-  carve_refine(ar, bd, tile, max_jobs, ir, need_res, rb);
+  carve_refine(ar, bd, tile, max_jobs * P, ir, need_res, rb);
   if (work == nullptr) {
     *lwork = ar.used;
     return 0;
@@ -515,8 +586,8 @@ int filter_impl(const fb_band* B, int nslice, const double* lo, const double* hi
   std::vector<int32_t> sys_pass(nsys, 0);
   int unconverged = 0;
   FB_TRY(filter_apply<R>(bd, f, ne, act, m, Yc.data(), ldyc.data(), Qc.data(), ldqc.data(),
-                         Xs.data(), zsys, wsys, cplx, o->batched != 0, ir, o->ir_tol, o->ir_max,
-                         need_res, rb, sys_res, sys_pass, &unconverged, st));
+                         Xp.data(), P, acc_dev, zsys, wsys, cplx, o->batched != 0, ir, o->ir_tol,
+                         o->ir_max, need_res, rb, sys_res, sys_pass, &unconverged, st));
   if (!cplx)
     for (int i : act) FB_TRY(store_cols(Qc[i], n, Q[i], ldq[i], true, n, m[i], nullptr, st));
   FB_HIP(hipStreamSynchronize(st));

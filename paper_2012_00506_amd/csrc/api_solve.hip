@@ -36,6 +36,7 @@ void carve_factors(Arena& ar, const Band& bd, int nsys, FactorBufs<R>& f) {
   f.info = ar.take<int32_t>(nsys);
   size_t sc = lu_window_scratch<R>(bd.b, nsys);
   f.scratch = sc ? ar.take<cx<R>>(sc / sizeof(cx<R>)) : nullptr;
+  f.lscr = ar.take<cx<R>>((size_t)nsys * 4 * bb);
   f.z = ar.take<c128>(nsys);
 }
 
@@ -43,7 +44,7 @@ template <typename R>
 int factor_systems(const Band& bd, int nsys, const double* z_host, FactorBufs<R>& f,
                    hipStream_t st) {
   FB_HIP(hipMemcpyAsync(f.z, z_host, sizeof(c128) * nsys, hipMemcpyHostToDevice, st));
-  FB_TRY(launch_lu_impl<R>(bd, nsys, f.z, f.mats, f.perm, f.info, f.scratch, st));
+  FB_TRY(launch_lu_impl<R>(bd, nsys, f.z, f.mats, f.perm, f.info, f.scratch, f.lscr, st));
   std::vector<int32_t> info(nsys);
   FB_HIP(hipMemcpyAsync(info.data(), f.info, sizeof(int32_t) * nsys, hipMemcpyDeviceToHost, st));
   FB_HIP(hipStreamSynchronize(st));
@@ -155,6 +156,13 @@ void carve_refine(Arena& ar, const Band& bd, int tile, int max_jobs, bool ir, bo
   rb.rbuf = need_res ? ar.take<c128>(rb.wave * (size_t)bd.n * rb.gcols) : nullptr;
   rb.part = need_res ? ar.take<double>(residual_part_doubles(bd.n, (int)rb.wave)) : nullptr;
   rb.ratio = need_res ? ar.take<double>(rb.wave) : nullptr;
+}
+
+size_t refine_bytes(const Band& bd, int tile, int max_jobs, bool ir, bool need_res) {
+  Arena q;
+  RefineBufs rb;
+  carve_refine(q, bd, tile, max_jobs, ir, need_res, rb);
+  return q.used;
 }
 
 // Launch the solve jobs, then (need_res) compute the FP64 residual

@@ -19,6 +19,7 @@ struct cx {
 using c64 = cx<float>;
 using c128 = cx<double>;
 
+
 template <typename T>
 __host__ __device__ __forceinline__ cx<T> mk(T a, T b) {
   cx<T> r;
@@ -26,6 +27,32 @@ __host__ __device__ __forceinline__ cx<T> mk(T a, T b) {
   r.y = b;
   return r;
 }
+// Loads and stores of global memory.  Pointers that reach a kernel through
+// job tables (or a runtime choice between LDS and global memory) are
+// otherwise accessed with flat instructions, which also count against the
+// LDS wait counter, so that every LDS wait waits for them too; going through
+// a pointer in the global address space gives global loads and stores.
+#define FB_GMEM __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) {
+  return *(const FB_GMEM T*)p;
+}
+template <typename T>
+__device__ __forceinline__ cx<T> gld(const cx<T>* p) {
+  const FB_GMEM T* q = (const FB_GMEM T*)p;
+  return mk(q[0], q[1]);
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* p, T v) {
+  *(FB_GMEM T*)p = v;
+}
+template <typename T>
+__device__ __forceinline__ void gst(cx<T>* p, cx<T> v) {
+  FB_GMEM T* q = (FB_GMEM T*)p;
+  q[0] = v.x;
+  q[1] = v.y;
+}
+
 template <typename T>
 __host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) {
   return mk(a.x + b.x, a.y + b.y);

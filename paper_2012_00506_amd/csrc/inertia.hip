@@ -25,14 +25,17 @@ __device__ __forceinline__ c128 band_entry(const c128* __restrict__ Bd, int64_t 
   return v;
 }
 
+template <bool USE_LDS>
 __global__ void __launch_bounds__(kInertiaThreads)
 k_band_ldlh_inertia(const c128* __restrict__ Bd, int64_t n, int b,
                     const double* __restrict__ shifts, const double* __restrict__ stats,
-                    int32_t* __restrict__ counts, c128* __restrict__ gwin, int use_lds) {
+                    int32_t* __restrict__ counts, c128* __restrict__ gwin) {
   extern __shared__ c128 lds_win[];
   const int M = b + 2;
   const int s = blockIdx.x;
-  c128* W = use_lds ? lds_win : gwin + (size_t)s * M * M;
+  // the LDS window is a compile-time choice, so that its accesses are LDS
+  // instructions rather than flat ones
+  c128* W = USE_LDS ? lds_win : gwin + (size_t)s * M * M;
   const double sigma = shifts[s];
   const double eps = 2.220446049250313e-16;
   const double pivmin = eps * eps * stats[0];
@@ -109,13 +112,17 @@ int launch_inertia(const Band& bd, int nshift, const double* shifts_dev, int32_t
   bool lds = inertia_lds(bd.b);
   size_t smem = lds ? (size_t)(bd.b + 2) * (bd.b + 2) * sizeof(c128) : 0;
   if (lds) {
-    (void)hipFuncSetAttribute((const void*)k_band_ldlh_inertia,
+    (void)hipFuncSetAttribute((const void*)k_band_ldlh_inertia<true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
     (void)hipGetLastError();
   }
   ProfScope ps(FB_PROF_INERTIA, st, 4.0 * (double)bd.n * bd.b * bd.b * nshift);
-  k_band_ldlh_inertia<<<nshift, kInertiaThreads, smem, st>>>(
-      bd.Bd, bd.n, bd.b, shifts_dev, bd.stats, cnt_dev, (c128*)scratch, lds ? 1 : 0);
+  if (lds)
+    k_band_ldlh_inertia<true><<<nshift, kInertiaThreads, smem, st>>>(
+        bd.Bd, bd.n, bd.b, shifts_dev, bd.stats, cnt_dev, (c128*)scratch);
+  else
+    k_band_ldlh_inertia<false><<<nshift, kInertiaThreads, smem, st>>>(
+        bd.Bd, bd.n, bd.b, shifts_dev, bd.stats, cnt_dev, (c128*)scratch);
   FB_HIP(hipGetLastError());
   return 0;
 }

@@ -19,6 +19,12 @@
 //   U(k,k), U(k,k+1), U(k,k+2).
 // A second kernel replaces Lh11 and U(k,k) by their inverses, so that the
 // solves are chains of dense b x b products.
+//
+// Within a block the multipliers are written to a per-system scratch under a
+// storage row that follows each window row through the interchanges (an O(1)
+// swap of two table entries), and gathered into row order once at the end of
+// the block; the entering row of the next step is fetched from B while the
+// current step runs.
 #include "solve_job.h"
 #include "prof.h"
 
@@ -32,22 +38,23 @@ struct FactorOut {
   cx<R>* mats;     // nsys * K * 5 * b * b
   int16_t* perm;   // nsys * K * 2b
   int32_t* info;   // nsys
+  cx<R>* lscr;     // nsys * 2 * 2b * b: multipliers of the current block by storage row
 };
 
-template <typename R>
-__device__ __forceinline__ cx<R> shifted_entry(const c128* __restrict__ Bd, int64_t n,
-                                               int b, int64_t i, int64_t c, c128 z) {
+template <typename R, typename PB>
+__device__ __forceinline__ cx<R> shifted_entry(PB Bd, int64_t n, int b, int64_t i, int64_t c,
+                                               c128 z) {
   // A(i, c) of zI - B, padded with the identity beyond n
   if (i >= n || c >= n) return mk<R>(i == c ? (R)1 : (R)0, (R)0);
   int64_t d = i - c;
   c128 v;
   if (d >= 0) {
     if (d > b) return mk<R>(0, 0);
-    c128 e = Bd[d * n + c];
+    c128 e = gld(Bd + d * n + c);
     v = mk(-e.x, -e.y);
   } else {
     if (-d > b) return mk<R>(0, 0);
-    c128 e = Bd[(-d) * n + i];
+    c128 e = gld(Bd + (-d) * n + i);
     v = mk(-e.x, e.y);  // -conj(B(c, i))
   }
   if (d == 0) {
@@ -57,11 +64,10 @@ __device__ __forceinline__ cx<R> shifted_entry(const c128* __restrict__ Bd, int6
   return mk<R>((R)v.x, (R)v.y);
 }
 
-template <typename R>
+template <typename R, bool USE_LDS>
 __global__ void __launch_bounds__(kLuThreads)
-k_band_lu(const c128* __restrict__ Bd, int64_t n, int b, int nb, int K,
-          const c128* __restrict__ zs, FactorOut<R> out, cx<R>* __restrict__ gwin,
-          int use_lds) {
+k_band_lu(const c128* __restrict__ Bd_, int64_t n, int b, int nb, int K,
+          const c128* __restrict__ zs, FactorOut<R> out, cx<R>* __restrict__ gwin) {
   extern __shared__ char lds_raw[];
   const int MR = b + 2, MC = 2 * b + 2;
   const int s = blockIdx.x;
@@ -69,23 +75,33 @@ k_band_lu(const c128* __restrict__ Bd, int64_t n, int b, int nb, int K,
   const int64_t npad = (int64_t)K * nb;
   const c128 z = zs[s];
 
-  // LDS: phys[MR] int, idx[2][2nb] int, piv info, lvec[b+1] cx<R>, then window
+  // LDS: phys[MR] int, idx[2][2nb] int, piv info[4], lrow[2][2nb] int,
+  // lvec[b+1] cx<R>, then the window
   int* phys = reinterpret_cast<int*>(lds_raw);
   int* idx = phys + MR;                   // two perm buffers (block parity)
   int* pivp = idx + 4 * nb;               // [0] = pivot row of this step
-  cx<R>* lvec = reinterpret_cast<cx<R>*>(lds_raw + ((sizeof(int) * (MR + 4 * nb + 4) + 15) & ~15));
-  cx<R>* W = use_lds ? lvec + b + 1 : gwin + (size_t)s * MR * MC;
+  int* lrow = pivp + 4;                   // two storage-row tables (block parity)
+  cx<R>* lvec = reinterpret_cast<cx<R>*>(lds_raw + ((sizeof(int) * (MR + 8 * nb + 4) + 15) & ~15));
+  // the window's memory is a compile-time choice, so that LDS accesses are
+  // LDS instructions rather than flat ones
+  cx<R>* W = USE_LDS ? lvec + b + 1 : gwin + (size_t)s * MR * MC;
+  const c128* Bd = Bd_;
 
   cx<R>* mats = out.mats + (size_t)s * K * 5 * nb * nb;
   int16_t* permg = out.perm + (size_t)s * K * 2 * nb;
   const size_t bb = (size_t)nb * nb;
+  cx<R>* lscr = out.lscr + (size_t)s * 2 * 2 * bb;  // [parity][column][storage row]
+  int32_t* info = out.info;
 
-  // --- init: zero window, load rows 0..b, identity tables, zero block 0 Lh
+  // --- init: zero window, load rows 0..b, identity tables, zero block 0 scratch
   for (int e = t; e < MR * MC; e += blockDim.x) W[e] = mk<R>(0, 0);
   for (int e = t; e < MR; e += blockDim.x) phys[e] = e;
-  for (int e = t; e < 2 * nb; e += blockDim.x) idx[e] = e;
-  for (size_t e = t; e < 2 * bb; e += blockDim.x) mats[e] = mk<R>(0, 0);  // Lh11, Lh21 of block 0
-  if (t == 0) out.info[s] = 0;
+  for (int e = t; e < 2 * nb; e += blockDim.x) {
+    idx[e] = e;
+    lrow[e] = e;
+  }
+  for (size_t e = t; e < 2 * bb; e += blockDim.x) gst(lscr + e, mk<R>(0, 0));
+  if (t == 0) gst(info + s, 0);
   __syncthreads();
   {
     int64_t top = (int64_t)b < npad - 1 ? b : npad - 1;
@@ -97,15 +113,39 @@ k_band_lu(const c128* __restrict__ Bd, int64_t n, int b, int nb, int K,
   }
   __syncthreads();
 
+  // entering row of step j (row j+b+1, columns j+1 .. j+2b+1): entry
+  // e = t + q * kLuThreads of this thread, fetched one step ahead
+  constexpr int ER = 2;  // 2b+1 <= 2 * kLuThreads for b <= 255
+  auto fetch_row = [&](cx<R>* dst, int64_t jf) {
+    const int64_t inew = jf + b + 1;
+#pragma unroll
+    for (int q = 0; q < ER; ++q) {
+      const int e = t + q * kLuThreads;
+      cx<R> v = mk<R>(0, 0);
+      if (e <= 2 * b && inew < npad) {
+        const int64_t c = jf + 1 + e;
+        if (c < npad) v = shifted_entry<R>(Bd, n, b, inew, c, z);
+      }
+      dst[q] = v;
+    }
+  };
+
+  // update mapping: 2b columns in flight, kLuThreads / 2b row groups
+  const int ucols = 2 * b, ugrps = kLuThreads / ucols;
+  const int ucol = t % ucols, ugrp = t / ucols;
+
   int first_zero = 0;
   // running slots: row j sits in slot jr = j mod MR, column j in jcs = j mod MC;
   // an offset below MR (MC) needs at most one wrap
   int jr = 0, jcs = 0, k = 0, jj = 0;
   auto rslot = [&](int off) { int v = jr + off; return v >= MR ? v - MR : v; };
   auto cslot = [&](int off) { int v = jcs + off; return v >= MC ? v - MC : v; };
-  for (int64_t j = 0; j < npad; ++j) {
+  auto step = [&](int64_t j, const cx<R>* cur, cx<R>* nxt) {
+    if (j + 1 < npad) fetch_row(nxt, j + 1);
     const int par = k & 1;
     int* idxk = idx + par * 2 * nb;
+    int* lrk = lrow + par * 2 * nb;
+    cx<R>* scr = lscr + (size_t)par * 2 * bb;
     const int64_t last = (j + b < npad - 1) ? j + b : npad - 1;
     const int nr = (int)(last - j);               // rows below the pivot
     const int64_t cend = (j + 2 * b < npad - 1) ? j + 2 * b : npad - 1;
@@ -134,34 +174,34 @@ k_band_lu(const c128* __restrict__ Bd, int64_t n, int b, int nb, int K,
       }
       const int sj = jr, sp = rslot(bi);
       const int physj_old = phys[sj], physp_old = phys[sp];
-      // physical row of logical row j + r after the interchange
+      const int pw0 = jj + bi;
       cx<R> piv = W[(size_t)physp_old * MC + jc];
       cx<R> rp = cabs2(piv) > (R)0 ? cinv(piv) : mk<R>(0, 0);
       for (int r = t + 1; r <= nr; r += 64) {
+        // after the interchange, window row jj + r holds the old row j when
+        // r == bi; its storage row moves with it
         int pr = (r == bi) ? physj_old : phys[rslot(r)];
+        int srow = (r == bi) ? lrk[jj] : lrk[jj + r];
         cx<R> l = W[(size_t)pr * MC + jc] * rp;
         lvec[r - 1] = l;
-        int wr = jj + r;  // window row of the block
-        if (wr < nb)
-          mats[((size_t)k * 5 + 0) * bb + (size_t)jj * nb + wr] = l;
-        else
-          mats[((size_t)k * 5 + 1) * bb + (size_t)jj * nb + (wr - nb)] = l;
+        gst(scr + (size_t)jj * 2 * nb + srow, l);
       }
       if (t == 0) {
         phys[sj] = physp_old;
         phys[sp] = physj_old;
-        int pw0 = jj + bi;
         int a = idxk[jj];
         idxk[jj] = idxk[pw0];
         idxk[pw0] = a;
+        a = lrk[jj];
+        lrk[jj] = lrk[pw0];
+        lrk[pw0] = a;
         pivp[0] = pw0;
         if (!(cabs2(piv) > (R)0) && first_zero == 0) first_zero = (int)(j + 1);
       }
     }
     __syncthreads();
 
-    // ---- phase B (all): U row, multiplier interchange, update, entering row
-    const int pw = pivp[0];
+    // ---- phase B (all): U row, update, entering row, block end
     const int prj = phys[jr];
     {
       // U row j: columns k nb .. k nb+3nb-1 of blocks U(k,k), U(k,k+1), U(k,k+2)
@@ -170,57 +210,72 @@ k_band_lu(const c128* __restrict__ Bd, int64_t n, int b, int nb, int K,
         cx<R> v = mk<R>(0, 0);
         if (co >= 0 && co <= nc) v = W[(size_t)prj * MC + cslot(co)];
         int which = 2 + e / nb;
-        mats[((size_t)k * 5 + which) * bb + (size_t)(e % nb) * nb + jj] = v;
+        gst(mats + ((size_t)k * 5 + which) * bb + (size_t)(e % nb) * nb + jj, v);
       }
-      // keep Lh in the form P A = Lh U: earlier multipliers follow the rows
-      if (pw != jj) {
-        for (int c = t; c < jj; c += blockDim.x) {
-          size_t a0 = (jj < nb) ? ((size_t)k * 5 + 0) * bb + (size_t)c * nb + jj
-                                : ((size_t)k * 5 + 1) * bb + (size_t)c * nb + (jj - nb);
-          size_t a1 = (pw < nb) ? ((size_t)k * 5 + 0) * bb + (size_t)c * nb + pw
-                                : ((size_t)k * 5 + 1) * bb + (size_t)c * nb + (pw - nb);
-          cx<R> va = mats[a0];
-          mats[a0] = mats[a1];
-          mats[a1] = va;
+      // rank-one update of rows j+1..last, columns j+1..cend: thread
+      // (ucol, ugrp) keeps one column and walks every ugrps-th row
+      if (ugrp < ugrps && ucol < nc) {
+        const int cs = cslot(ucol + 1);
+        const cx<R> u = W[(size_t)prj * MC + cs];
+        // rows in batches of UB: all loads of a batch before its stores (the
+        // rows are distinct physical rows, so nothing aliases)
+        constexpr int UB = 8;
+        for (int r0 = ugrp; r0 < nr; r0 += UB * ugrps) {
+          size_t a[UB];
+          cx<R> v[UB], l[UB];
+#pragma unroll
+          for (int q = 0; q < UB; ++q) {
+            const int ro = r0 + q * ugrps;
+            a[q] = ro < nr ? (size_t)phys[rslot(ro + 1)] * MC + cs : 0;
+          }
+#pragma unroll
+          for (int q = 0; q < UB; ++q) {
+            const int ro = r0 + q * ugrps;
+            if (ro < nr) {
+              v[q] = W[a[q]];
+              l[q] = lvec[ro];
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < UB; ++q) {
+            const int ro = r0 + q * ugrps;
+            if (ro < nr) {
+              v[q].x -= l[q].x * u.x - l[q].y * u.y;
+              v[q].y -= l[q].x * u.y + l[q].y * u.x;
+              W[a[q]] = v[q];
+            }
+          }
         }
-      }
-      // rank-one update of rows j+1..last, columns j+1..cend
-      for (int e = t; e < nr * nc; e += blockDim.x) {
-        int ro = e / nc, co = e - ro * nc;
-        int cs = cslot(co + 1);
-        size_t a = (size_t)phys[rslot(ro + 1)] * MC + cs;
-        cx<R> u = W[(size_t)prj * MC + cs];
-        cx<R> l = lvec[ro];
-        cx<R> v = W[a];
-        v.x -= l.x * u.x - l.y * u.y;
-        v.y -= l.x * u.y + l.y * u.x;
-        W[a] = v;
       }
       // column j+2b+1 enters: zero it in rows j+1..j+b (out of their band)
       {
         int cs = cslot(2 * b + 1);
         for (int r = t; r < b; r += blockDim.x) W[(size_t)phys[rslot(r + 1)] * MC + cs] = mk<R>(0, 0);
       }
-      // row j+b+1 enters (columns j+1 .. j+2b+1)
-      int64_t inew = j + b + 1;
-      if (inew < npad) {
+      // row j+b+1 enters (columns j+1 .. j+2b+1), fetched during the last step
+      if (j + b + 1 < npad) {
         int pr = phys[rslot(b + 1)];
-        for (int e = t; e <= 2 * b; e += blockDim.x) {
-          int64_t c = j + 1 + e;
-          cx<R> v = mk<R>(0, 0);
-          if (c < npad) v = shifted_entry<R>(Bd, n, b, inew, c, z);
-          W[(size_t)pr * MC + cslot(1 + e)] = v;
+#pragma unroll
+        for (int q = 0; q < ER; ++q) {
+          const int e = t + q * kLuThreads;
+          if (e <= 2 * b) W[(size_t)pr * MC + cslot(1 + e)] = cur[q];
         }
       }
       if (jj == nb - 1) {
-        // block k complete: publish its permutation, prepare block k+1
-        for (int e = t; e < 2 * nb; e += blockDim.x) {
-          permg[(size_t)k * 2 * nb + e] = (int16_t)idxk[e];
-          idx[(par ^ 1) * 2 * nb + e] = e;
+        // block k complete: multipliers into row order (P A_panel = Lh U),
+        // its permutation; fresh tables and scratch for block k+1
+        for (size_t e = t; e < 2 * bb; e += blockDim.x) {
+          const int c = (int)(e / (2 * nb)), wr = (int)(e % (2 * nb));
+          cx<R> v = gld(scr + (size_t)c * 2 * nb + lrk[wr]);
+          gst(mats + ((size_t)k * 5 + (wr < nb ? 0 : 1)) * bb + (size_t)c * nb + (wr < nb ? wr : wr - nb), v);
         }
-        if (k + 1 < K)
-          for (size_t e = t; e < 2 * bb; e += blockDim.x)
-            mats[((size_t)(k + 1) * 5) * bb + e] = mk<R>(0, 0);
+        cx<R>* scr1 = lscr + (size_t)(par ^ 1) * 2 * bb;
+        for (size_t e = t; e < 2 * bb; e += blockDim.x) gst(scr1 + e, mk<R>(0, 0));
+        for (int e = t; e < 2 * nb; e += blockDim.x) {
+          gst(permg + (size_t)k * 2 * nb + e, (int16_t)idxk[e]);
+          idx[(par ^ 1) * 2 * nb + e] = e;
+          lrow[(par ^ 1) * 2 * nb + e] = e;
+        }
       }
     }
     __syncthreads();
@@ -230,8 +285,14 @@ k_band_lu(const c128* __restrict__ Bd, int64_t n, int b, int nb, int K,
       jj = 0;
       ++k;
     }
+  };
+  cx<R> ra[ER], rb[ER];
+  fetch_row(ra, 0);
+  for (int64_t j = 0; j < npad; j += 2) {
+    step(j, ra, rb);
+    if (j + 1 < npad) step(j + 1, rb, ra);
   }
-  if (t == 0 && first_zero) out.info[s] = first_zero;
+  if (t == 0 && first_zero) gst(info + s, first_zero);
 }
 
 // In-place inverses of the unit lower Lh11 and the upper U(k,k) of every
@@ -241,19 +302,19 @@ k_band_lu(const c128* __restrict__ Bd, int64_t n, int b, int nb, int K,
 //   U = [U11 u; 0 ujj]:    U^{-1} column j above the diagonal = -U11^{-1} u / ujj
 // The matrix is staged in LDS when it fits, else worked on in place in global
 // memory; only the column being replaced is copied aside.
-template <typename R>
+template <typename R, bool USE_LDS>
 __global__ void __launch_bounds__(256)
-k_block_invert(cx<R>* __restrict__ mats, int b, int nblk, int use_lds) {
+k_block_invert(cx<R>* __restrict__ mats, int b, int nblk) {
   extern __shared__ char lds_raw[];
   const int g = blockIdx.x;
   const int blk = g >> 1, which = g & 1;  // 0: Lh11 (slot 0), 1: U(k,k) (slot 2)
   if (blk >= nblk) return;
   cx<R>* M = mats + ((size_t)blk * 5 + (which ? 2 : 0)) * b * b;
   cx<R>* xv = reinterpret_cast<cx<R>*>(lds_raw);
-  cx<R>* A = use_lds ? xv + b : M;
+  cx<R>* A = USE_LDS ? xv + b : M;
   const int t = threadIdx.x;
   const int bb = b * b;
-  if (use_lds) {
+  if (USE_LDS) {
     for (int e = t; e < bb; e += blockDim.x) A[e] = M[e];
     __syncthreads();
   }
@@ -285,14 +346,14 @@ k_block_invert(cx<R>* __restrict__ mats, int b, int nblk, int use_lds) {
     }
   }
   __syncthreads();
-  if (use_lds)
+  if (USE_LDS)
     for (int e = t; e < bb; e += blockDim.x) M[e] = A[e];
 }
 
 template <typename R>
 static size_t lu_lds_head_bytes(int b) {
   const int nb = block_size(b);
-  size_t head = (sizeof(int) * (size_t)((b + 2) + 4 * nb + 4) + 15) & ~(size_t)15;
+  size_t head = (sizeof(int) * (size_t)((b + 2) + 8 * nb + 4) + 15) & ~(size_t)15;
   return head + sizeof(cx<R>) * ((size_t)b + 1);
 }
 template <typename R>
@@ -308,39 +369,44 @@ size_t lu_window_scratch(int b, int nsys) {
 
 template <typename R>
 int launch_lu_impl(const Band& bd, int nsys, const c128* z_dev, cx<R>* mats, int16_t* perm,
-                   int32_t* info, cx<R>* scratch, hipStream_t st) {
+                   int32_t* info, cx<R>* scratch, cx<R>* lscr, hipStream_t st) {
   const int b = bd.b;
   const int nb = block_size(b);
   const int K = (int)((bd.n + nb - 1) / nb);
-  FactorOut<R> o{mats, perm, info};
+  FactorOut<R> o{mats, perm, info, lscr};
   bool lds = lu_lds_bytes<R>(b) <= kLdsBudget;
   size_t smem = lds ? lu_lds_bytes<R>(b) : lu_lds_head_bytes<R>(b);
-  (void)hipFuncSetAttribute((const void*)k_band_lu<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)kLdsBudget);
+  (void)hipFuncSetAttribute((const void*)k_band_lu<R, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
   (void)hipGetLastError();
   {
     ProfScope ps(FB_PROF_LU, st, 16.0 * (double)bd.n * b * b * nsys);
-    k_band_lu<R><<<nsys, kLuThreads, smem, st>>>(bd.Bd, bd.n, b, nb, K, z_dev, o, scratch,
-                                                  lds ? 1 : 0);
+    if (lds)
+      k_band_lu<R, true><<<nsys, kLuThreads, smem, st>>>(bd.Bd, bd.n, b, nb, K, z_dev, o, scratch);
+    else
+      k_band_lu<R, false><<<nsys, kLuThreads, smem, st>>>(bd.Bd, bd.n, b, nb, K, z_dev, o, scratch);
     FB_HIP(hipGetLastError());
   }
   size_t full = sizeof(cx<R>) * ((size_t)nb * nb + nb);
   bool ilds = full <= kLdsBudget;
   size_t ismem = ilds ? full : sizeof(cx<R>) * (size_t)nb;
-  (void)hipFuncSetAttribute((const void*)k_block_invert<R>,
+  (void)hipFuncSetAttribute((const void*)k_block_invert<R, true>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
   (void)hipGetLastError();
   int nblk = nsys * K;
   ProfScope ps(FB_PROF_INVERT, st, 8.0 * 2.0 * nblk * (double)nb * nb * nb / 3.0);
-  k_block_invert<R><<<2 * nblk, 256, ismem, st>>>(mats, nb, nblk, ilds ? 1 : 0);
+  if (ilds)
+    k_block_invert<R, true><<<2 * nblk, 256, ismem, st>>>(mats, nb, nblk);
+  else
+    k_block_invert<R, false><<<2 * nblk, 256, ismem, st>>>(mats, nb, nblk);
   FB_HIP(hipGetLastError());
   return 0;
 }
 
 template int launch_lu_impl<float>(const Band&, int, const c128*, c64*, int16_t*, int32_t*, c64*,
-                                   hipStream_t);
+                                   c64*, hipStream_t);
 template int launch_lu_impl<double>(const Band&, int, const c128*, c128*, int16_t*, int32_t*,
-                                    c128*, hipStream_t);
+                                    c128*, c128*, hipStream_t);
 template size_t lu_window_scratch<float>(int, int);
 template size_t lu_window_scratch<double>(int, int);
 

@@ -21,6 +21,22 @@ struct JacobiJob {
 };
 
 int fill_zero(c128* p, int64_t rows, int64_t cols, int64_t ld, hipStream_t st);
+
+// Q += sum_p w_p X_p over the (node, direction) solutions of one slice, in
+// the order p = 0, 1, ... (real B: Q += 2 Re(w_p X_p)).
+constexpr int kMaxPairs = 128;
+struct AccJob {
+  c128* Q;
+  int64_t ldq;
+  const c128* X[kMaxPairs];
+  int64_t ldx;
+  c128 w[kMaxPairs];
+  int32_t np;
+  int32_t m;
+  int32_t acc_real;
+  int32_t pad_;
+};
+int accumulate_pairs(const AccJob* jobs_dev, int njobs, int64_t n, int max_m, hipStream_t st);
 int gather_cols(const void* src, int64_t lds, bool real_src, c128* dst, int64_t ldd,
                 int64_t rows, int cols, const int32_t* idx_dev, const double* scale_dev,
                 hipStream_t st);

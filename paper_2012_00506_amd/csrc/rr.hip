@@ -26,6 +26,34 @@ int fill_zero(c128* p, int64_t rows, int64_t cols, int64_t ld, hipStream_t st) {
 }
 
 // dst[:, k] = src[:, idx[k]] * (scale ? scale[k] : 1); real_src: src is double
+__global__ void __launch_bounds__(256)
+k_accumulate_pairs(const AccJob* __restrict__ jobs, int64_t n) {
+  const AccJob& J = jobs[blockIdx.y];
+  const int64_t total = n * J.m;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t col = e / n, row = e - col * n;
+    c128* q = J.Q + col * J.ldq + row;
+    c128 acc = gld(q);
+    for (int p = 0; p < J.np; ++p) {
+      c128 wv = J.w[p] * gld(J.X[p] + col * J.ldx + row);
+      if (J.acc_real)
+        acc.x += 2.0 * wv.x;
+      else
+        acc = acc + wv;
+    }
+    gst(q, acc);
+  }
+}
+
+int accumulate_pairs(const AccJob* jobs_dev, int njobs, int64_t n, int max_m, hipStream_t st) {
+  if (njobs <= 0 || max_m <= 0) return 0;
+  int64_t blocks = std::min<int64_t>((n * max_m + 255) / 256, 2048);
+  k_accumulate_pairs<<<dim3((unsigned)blocks, njobs), 256, 0, st>>>(jobs_dev, n);
+  FB_HIP(hipGetLastError());
+  return 0;
+}
+
 __global__ void k_gather_cols(const void* __restrict__ src, int64_t lds, int real_src,
                               c128* __restrict__ dst, int64_t ldd, int64_t rows, int cols,
                               const int32_t* __restrict__ idx, const double* __restrict__ scale) {

@@ -63,8 +63,13 @@ k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* 
   const int job = remap_job(blockIdx.x, njobs);
   if (job >= njobs) return;
   const ResJob jb = jobs[job];
+  const c128* jx = jb.x;
+  const c128* jy = jb.y;
+  c128* jr = jb.r;
+  const c128* Bg = Bblk;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int w = wv % NRW, cb0 = 16 * (wv / NRW);
+  const int w = __builtin_amdgcn_readfirstlane(wv % NRW);
+  const int cb0 = __builtin_amdgcn_readfirstlane(16 * (wv / NRW));
   const int nthr = NB * 4 * (T / 16);
   const int c0 = jb.col0;
   const int nc = jb.ncol;
@@ -75,7 +80,7 @@ k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* 
       int row = e / T, col = e % T;
       int64_t i = (int64_t)k * NB + row;
       X[slot * NB * T + e] =
-          (k < K && i < n && col < nc) ? jb.x[(int64_t)(c0 + col) * jb.ldx + i] : mk(0.0, 0.0);
+          (k < K && i < n && col < nc) ? gld(jx + (int64_t)(c0 + col) * jb.ldx + i) : mk(0.0, 0.0);
     }
   };
   for (int e = t; e < NB * T; e += nthr) X[2 * NB * T + e] = mk(0.0, 0.0);  // x_{-1}
@@ -92,13 +97,13 @@ k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* 
     for (int r = 0; r < 4; ++r) {
       int row = 16 * w + MF<double>::row(lane, r);
       int64_t i = (int64_t)k * NB + row;
-      c128 yv = (i < n && col < nc) ? jb.y[(int64_t)(c0 + col) * jb.ldy + i] : mk(0.0, 0.0);
+      c128 yv = (i < n && col < nc) ? gld(jy + (int64_t)(c0 + col) * jb.ldy + i) : mk(0.0, 0.0);
       c128 v = yv - zz * Xk[row * T + col];
       acc.re[0][r] = v.x;
       acc.im[0][r] = v.y;
       yy += cabs2(yv);
     }
-    const c128* Bk = Bblk + (size_t)k * 3 * bb;
+    const c128* Bk = Bg + (size_t)k * 3 * bb;
     if (k > 0)
       wave_prod<double, NB, NC, false, false>(acc, Bk, X + ((k + 2) % 3) * NB * T, T, nullptr, w,
                                               cb0, lane, 16 * w, NB);
@@ -112,7 +117,7 @@ k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* 
       int64_t i = (int64_t)k * NB + row;
       if (i < n && col < nc) {
         c128 v = mk(acc.re[0][r], acc.im[0][r]);
-        jb.r[(int64_t)(c0 + col) * jb.ldr + i] = v;
+        gst(jr + (int64_t)(c0 + col) * jb.ldr + i, v);
         rr += cabs2(v);
       }
     }

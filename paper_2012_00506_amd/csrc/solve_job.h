@@ -15,10 +15,7 @@ struct SolveJob {
   c128* out;      // solution (written, or added to when add != 0)
   int64_t ldin, ldmid, ldout;
   int32_t add;
-  int32_t acc_real;  // accumulate 2 Re(w x) instead of w x
-  c128* acc;         // if set: acc += w * (solution written to out)
-  int64_t ldacc;
-  c128 w;
+  int32_t pad_;
 };
 
 // r = y - A x for one tile (A = zI - B, or its conjugate transpose).
@@ -39,7 +36,7 @@ int launch_solve_jobs(const cx<R>* mats, const int16_t* perm, int64_t n, int b, 
                       const SolveJob* jobs_dev, double work, hipStream_t st);
 template <typename R>
 int launch_lu_impl(const Band& bd, int nsys, const c128* z_dev, cx<R>* mats, int16_t* perm,
-                   int32_t* info, cx<R>* scratch, hipStream_t st);
+                   int32_t* info, cx<R>* scratch, cx<R>* lscr, hipStream_t st);
 template <typename R>
 size_t lu_window_scratch(int b, int nsys);
 
@@ -65,6 +62,7 @@ struct FactorBufs {
   int16_t* perm = nullptr;
   int32_t* info = nullptr;
   cx<R>* scratch = nullptr;
+  cx<R>* lscr = nullptr;  // per system 2 x 2nb x nb multiplier scratch
   c128* z = nullptr;
 };
 template <typename R>
@@ -89,6 +87,7 @@ struct RefineBufs {
 };
 void carve_refine(Arena& ar, const Band& bd, int tile, int max_jobs, bool ir, bool need_res,
                   RefineBufs& rb);
+size_t refine_bytes(const Band& bd, int tile, int max_jobs, bool ir, bool need_res);
 template <typename R>
 int solve_refine(const Band& bd, const cx<R>* mats, const int16_t* perm,
                  const std::vector<SolveJob>& jobs, const std::vector<c128>& zsys, bool ir,

@@ -57,57 +57,73 @@ struct Frag {
   cx<R> a[NB / 4];
 };
 
-template <typename R, int NB, bool CONJT>
-__device__ __forceinline__ void frag_load(Frag<R, NB>& f, const cx<R>* __restrict__ A, int w,
-                                          int lane, int k0, int k1) {
+// k ranges [k0, k1) are multiples of 16 and the same for the whole wave
+// (readfirstlane makes that visible to the compiler, so that the range test
+// is one scalar branch per 16-row chunk and a chunk's LDS reads issue
+// together).
+template <typename R, int NB, bool CONJT, typename PA>
+__device__ __forceinline__ void frag_load(Frag<R, NB>& f, PA A, int w, int lane, int k0, int k1) {
   const int i = 16 * w + (lane & 15), kq = lane >> 4;
+  const int c0 = __builtin_amdgcn_readfirstlane(k0) >> 4;
+  const int c1 = __builtin_amdgcn_readfirstlane(k1) >> 4;
 #pragma unroll
-  for (int s = 0; s < NB / 4; ++s) {
-    const int kk = 4 * s;
-    if (kk < k0 || kk >= k1) continue;
-    const int k = kk + kq;
-    f.a[s] = CONJT ? A[(size_t)i * NB + k] : A[(size_t)k * NB + i];
+  for (int ch = 0; ch < NB / 16; ++ch) {
+    if (ch < c0 || ch >= c1) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = 16 * ch + 4 * q + kq;
+      f.a[4 * ch + q] = CONJT ? A[(size_t)i * NB + k] : A[(size_t)k * NB + i];
+    }
   }
 }
 
-// acc += op(A) * B over k in [k0, k1) (multiples of 4) from prefetched
-// fragments; NEG subtracts.  B row k is LDS row rmap[k] (or k when rmap is
-// null), row stride ldb elements, columns from cb0.
+// acc += op(A) * B over k in [k0, k1) from prefetched fragments; NEG
+// subtracts.  B row k is LDS row rmap[k] (or k when rmap is null), row
+// stride ldb elements, columns from cb0.
 template <typename R, int NB, int NC, bool CONJT, bool NEG>
 __device__ __forceinline__ void frag_mma(Acc<R, NC>& acc, const Frag<R, NB>& f, const cx<R>* Bl,
                                          int ldb, const int* rmap, int cb0, int lane, int k0,
                                          int k1) {
   const int kq = lane >> 4;
   const int j = lane & 15;
+  const int c0 = __builtin_amdgcn_readfirstlane(k0) >> 4;
+  const int c1 = __builtin_amdgcn_readfirstlane(k1) >> 4;
 #pragma unroll
-  for (int s = 0; s < NB / 4; ++s) {
-    const int kk = 4 * s;
-    if (kk < k0 || kk >= k1) continue;
-    const int k = kk + kq;
-    cx<R> a = f.a[s];
-    R ar = a.x, ai = CONJT ? -a.y : a.y;
-    if (NEG) {
-      ar = -ar;
-      ai = -ai;
+  for (int ch = 0; ch < NB / 16; ++ch) {
+    if (ch < c0 || ch >= c1) continue;
+    cx<R> bv[4][NC];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = 16 * ch + 4 * q + kq;
+      const int br = rmap ? rmap[k] : k;
+      const cx<R>* bp = Bl + (size_t)br * ldb + cb0 + j;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) bv[q][c] = bp[16 * c];
     }
-    const R nai = -ai;
-    const int br = rmap ? rmap[k] : k;
-    const cx<R>* bp = Bl + (size_t)br * ldb + cb0 + j;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      cx<R> bv = bp[16 * c];
-      acc.re[c] = MF<R>::mma(ar, bv.x, acc.re[c]);
-      acc.re[c] = MF<R>::mma(nai, bv.y, acc.re[c]);
-      acc.im[c] = MF<R>::mma(ar, bv.y, acc.im[c]);
-      acc.im[c] = MF<R>::mma(ai, bv.x, acc.im[c]);
+    for (int q = 0; q < 4; ++q) {
+      cx<R> a = f.a[4 * ch + q];
+      R ar = a.x, ai = CONJT ? -a.y : a.y;
+      if (NEG) {
+        ar = -ar;
+        ai = -ai;
+      }
+      const R nai = -ai;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        acc.re[c] = MF<R>::mma(ar, bv[q][c].x, acc.re[c]);
+        acc.re[c] = MF<R>::mma(nai, bv[q][c].y, acc.re[c]);
+        acc.im[c] = MF<R>::mma(ar, bv[q][c].y, acc.im[c]);
+        acc.im[c] = MF<R>::mma(ai, bv[q][c].x, acc.im[c]);
+      }
     }
   }
 }
 
-template <typename R, int NB, int NC, bool CONJT, bool NEG>
-__device__ __forceinline__ void wave_prod(Acc<R, NC>& acc, const cx<R>* __restrict__ A,
-                                          const cx<R>* Bl, int ldb, const int* rmap, int w,
-                                          int cb0, int lane, int k0, int k1) {
+template <typename R, int NB, int NC, bool CONJT, bool NEG, typename PA>
+__device__ __forceinline__ void wave_prod(Acc<R, NC>& acc, PA A, const cx<R>* Bl, int ldb,
+                                          const int* rmap, int w, int cb0, int lane, int k0,
+                                          int k1) {
   Frag<R, NB> f;
   frag_load<R, NB, CONJT>(f, A, w, lane, k0, k1);
   frag_mma<R, NB, NC, CONJT, NEG>(acc, f, Bl, ldb, rmap, cb0, lane, k0, k1);
@@ -149,13 +165,13 @@ static __device__ __forceinline__ int remap_job(int bid, int njobs) {
 }
 
 // ---------------------------------------------------------------- MFMA block solve
-// One workgroup per job with one wave per 16 x 16 output tile of a block
-// product ((NB/16) x (T/16) waves); LDS holds 4 NB x T blocks.
-template <typename R, int NB, int T, bool PREF>
-__global__ void __launch_bounds__(NB * 4 * (T / 16))
+// One workgroup per job with one wave per 16 x (16 NC) output tile of a block
+// product ((NB/16) x (T/(16 NC)) waves; a wave with NC > 1 reuses each factor
+// fragment for NC column tiles); LDS holds 4 NB x T blocks.
+template <typename R, int NB, int T, bool PREF, int NC>
+__global__ void __launch_bounds__(NB * 4 * (T / (16 * NC)))
 k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, int64_t n,
              int K, const SolveJob* __restrict__ jobs, int njobs) {
-  constexpr int NC = 1;
   constexpr int NRW = NB / 16;
   extern __shared__ char lds_raw[];
   int* sp = reinterpret_cast<int*>(lds_raw);                        // 2 NB perm entries
@@ -164,36 +180,32 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
   if (job >= njobs) return;
   const SolveJob jb = jobs[job];
   const int t = threadIdx.x, lane = t & 63;
-  const int w = (t >> 6) % NRW, cb0 = 16 * ((t >> 6) / NRW);  // row block, column base
-  const int nthr = NB * 4 * (T / 16);
+  // row block and column base of this wave (wave-uniform: scalar registers)
+  const int w = __builtin_amdgcn_readfirstlane((t >> 6) % NRW);
+  const int cb0 = __builtin_amdgcn_readfirstlane(16 * NC * ((t >> 6) / NRW));
+  const int nthr = NB * 4 * (T / (16 * NC));
   const size_t bb = (size_t)NB * NB;
   const cx<R>* F = mats + (size_t)jb.sys * K * 5 * bb;
   const int16_t* P = permg + (size_t)jb.sys * K * 2 * NB;
   const c128* in = jb.in + (int64_t)jb.col0 * jb.ldin;
   c128* mid = jb.mid + (int64_t)jb.col0 * jb.ldmid;
   c128* out = jb.out + (int64_t)jb.col0 * jb.ldout;
-  c128* accp = jb.acc ? jb.acc + (int64_t)jb.col0 * jb.ldacc : nullptr;
   const int ncol = jb.ncol;
 
   auto emit = [&](int64_t row, int col, cx<R> v) {
     if (row >= n || col >= ncol) return;
     c128 x = mk((double)v.x, (double)v.y);
     c128* o = out + (int64_t)col * jb.ldout + row;
-    *o = jb.add ? *o + x : x;
-    if (accp) {
-      c128* a = accp + (int64_t)col * jb.ldacc + row;
-      c128 wv = jb.w * x;
-      if (jb.acc_real) wv = mk(2.0 * wv.x, 0.0);
-      *a = *a + wv;
-    }
+    if (jb.add) x = gld(o) + x;
+    gst(o, x);
   };
-  auto gload = [&](const c128* base, int64_t ld, int64_t row, int col) -> cx<R> {
+  auto gload = [&](auto base, int64_t ld, int64_t row, int col) -> cx<R> {
     if (row >= n || col >= ncol) return mk<R>(0, 0);
-    c128 v = base[(int64_t)col * ld + row];
+    c128 v = gld(base + (int64_t)col * ld + row);
     return mk<R>((R)v.x, (R)v.y);
   };
   // accumulator <-> global rows k NB + (wave rows)
-  auto acc_from_g = [&](Acc<R, NC>& acc, const c128* base, int64_t ld, int64_t row0) {
+  auto acc_from_g = [&](Acc<R, NC>& acc, auto base, int64_t ld, int64_t row0) {
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -203,7 +215,7 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
         acc.im[c][r] = v.y;
       }
   };
-  auto acc_to_g = [&](const Acc<R, NC>& acc, c128* base, int64_t ld, int64_t row0) {
+  auto acc_to_g = [&](const Acc<R, NC>& acc, auto base, int64_t ld, int64_t row0) {
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -211,7 +223,7 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
         int64_t row = row0 + 16 * w + MF<R>::row(lane, r);
         int col = cb0 + 16 * c + (lane & 15);
         if (row < n && col < ncol)
-          base[(int64_t)col * ld + row] = mk((double)acc.re[c][r], (double)acc.im[c][r]);
+          gst(base + (int64_t)col * ld + row, mk((double)acc.re[c][r], (double)acc.im[c][r]));
       }
   };
   auto acc_emit = [&](const Acc<R, NC>& acc, int64_t row0) {
@@ -223,7 +235,7 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
              mk<R>(acc.re[c][r], acc.im[c][r]));
   };
   auto load_perm = [&](int k) {
-    for (int e = t; e < 2 * NB; e += nthr) sp[e] = P[(size_t)k * 2 * NB + e];
+    for (int e = t; e < 2 * NB; e += nthr) sp[e] = gld(P + (size_t)k * 2 * NB + e);
   };
   const int lo_tri = 16 * w + 16;  // k < lo_tri: lower triangle rows of this wave
   const int up_tri = 16 * w;       // k >= up_tri: upper triangle
@@ -231,19 +243,24 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
   // initial accumulator values for the wave's rows of block k, prefetched
   // into registers one step ahead
   struct Pre {
-    cx<R> v[4];
+    cx<R> v[NC][4];
   };
-  auto pre_load = [&](Pre& p, const c128* base, int64_t ld, int k) {
+  auto pre_load = [&](Pre& p, auto base, int64_t ld, int k) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      p.v[r] = gload(base, ld, (int64_t)k * NB + 16 * w + MF<R>::row(lane, r), cb0 + (lane & 15));
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        p.v[c][r] = gload(base, ld, (int64_t)k * NB + 16 * w + MF<R>::row(lane, r),
+                          cb0 + 16 * c + (lane & 15));
   };
   auto pre_to_acc = [&](Acc<R, NC>& acc, const Pre& p) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      acc.re[0][r] = p.v[r].x;
-      acc.im[0][r] = p.v[r].y;
-    }
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        acc.re[c][r] = p.v[c][r].x;
+        acc.im[c][r] = p.v[c][r].y;
+      }
   };
   Acc<R, NC> acc;
   Frag<R, NB> fa, fb, fc;
@@ -393,49 +410,51 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
 }
 
 
-template <typename R, int NB, int T, bool PREF>
+template <typename R, int NB, int T, bool PREF, int NC>
 int launch_nb(const cx<R>* mats, const int16_t* perm, int64_t n, int njobs,
               const SolveJob* jobs_dev, hipStream_t st) {
   const int K = (int)((n + NB - 1) / NB);
   size_t smem = ((2 * NB * sizeof(int) + 15) & ~(size_t)15) + (size_t)4 * NB * T * sizeof(cx<R>);
-  (void)hipFuncSetAttribute((const void*)k_band_solve<R, NB, T, PREF>,
+  (void)hipFuncSetAttribute((const void*)k_band_solve<R, NB, T, PREF, NC>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   (void)hipGetLastError();
   for (int j0 = 0; j0 < njobs; j0 += 1 << 20) {
     int nj = njobs - j0 < (1 << 20) ? njobs - j0 : (1 << 20);
     int grid = 8 * ((nj + 7) / 8);
-    k_band_solve<R, NB, T, PREF><<<grid, NB * 4 * (T / 16), smem, st>>>(mats, perm, n, K,
-                                                                         jobs_dev + j0, nj);
+    k_band_solve<R, NB, T, PREF, NC><<<grid, NB * 4 * (T / (16 * NC)), smem, st>>>(
+        mats, perm, n, K, jobs_dev + j0, nj);
     FB_HIP(hipGetLastError());
   }
   return 0;
 }
 
-template <typename R, int T, bool PREF>
+template <typename R, int T, bool PREF, int NC>
 int launch_t(const cx<R>* mats, const int16_t* perm, int64_t n, int nb, int njobs,
              const SolveJob* jobs_dev, hipStream_t st) {
   switch (nb) {
-    case 16: return launch_nb<R, 16, T, PREF>(mats, perm, n, njobs, jobs_dev, st);
-    case 32: return launch_nb<R, 32, T, PREF>(mats, perm, n, njobs, jobs_dev, st);
-    case 48: return launch_nb<R, 48, T, PREF>(mats, perm, n, njobs, jobs_dev, st);
-    case 64: return launch_nb<R, 64, T, PREF>(mats, perm, n, njobs, jobs_dev, st);
-    case 80: return launch_nb<R, 80, T, PREF>(mats, perm, n, njobs, jobs_dev, st);
-    case 96: return launch_nb<R, 96, T, PREF>(mats, perm, n, njobs, jobs_dev, st);
-    case 112: return launch_nb<R, 112, T, PREF>(mats, perm, n, njobs, jobs_dev, st);
-    case 128: return launch_nb<R, 128, T, PREF>(mats, perm, n, njobs, jobs_dev, st);
+    case 16: return launch_nb<R, 16, T, PREF, NC>(mats, perm, n, njobs, jobs_dev, st);
+    case 32: return launch_nb<R, 32, T, PREF, NC>(mats, perm, n, njobs, jobs_dev, st);
+    case 48: return launch_nb<R, 48, T, PREF, NC>(mats, perm, n, njobs, jobs_dev, st);
+    case 64: return launch_nb<R, 64, T, PREF, NC>(mats, perm, n, njobs, jobs_dev, st);
+    case 80: return launch_nb<R, 80, T, PREF, NC>(mats, perm, n, njobs, jobs_dev, st);
+    case 96: return launch_nb<R, 96, T, PREF, NC>(mats, perm, n, njobs, jobs_dev, st);
+    case 112: return launch_nb<R, 112, T, PREF, NC>(mats, perm, n, njobs, jobs_dev, st);
+    case 128: return launch_nb<R, 128, T, PREF, NC>(mats, perm, n, njobs, jobs_dev, st);
     default: return FB_ERR_INTERNAL;
   }
 }
 
-// every (tile width, prefetch) variant of one precision
+// every (tile width, prefetch, tiles per wave) variant of one precision
 template <typename R>
 int launch_variant(int variant, const cx<R>* mats, const int16_t* perm, int64_t n, int nb,
                    int njobs, const SolveJob* jobs_dev, hipStream_t st) {
   switch (variant) {
-    case 0: return launch_t<R, 16, false>(mats, perm, n, nb, njobs, jobs_dev, st);
-    case 1: return launch_t<R, 16, true>(mats, perm, n, nb, njobs, jobs_dev, st);
-    case 2: return launch_t<R, 32, false>(mats, perm, n, nb, njobs, jobs_dev, st);
-    case 3: return launch_t<R, 32, true>(mats, perm, n, nb, njobs, jobs_dev, st);
+    case 0: return launch_t<R, 16, false, 1>(mats, perm, n, nb, njobs, jobs_dev, st);
+    case 1: return launch_t<R, 16, true, 1>(mats, perm, n, nb, njobs, jobs_dev, st);
+    case 2: return launch_t<R, 32, false, 1>(mats, perm, n, nb, njobs, jobs_dev, st);
+    case 3: return launch_t<R, 32, true, 1>(mats, perm, n, nb, njobs, jobs_dev, st);
+    case 4: return launch_t<R, 32, false, 2>(mats, perm, n, nb, njobs, jobs_dev, st);
+    case 5: return launch_t<R, 32, true, 2>(mats, perm, n, nb, njobs, jobs_dev, st);
     default: return FB_ERR_INTERNAL;
   }
 }

@@ -4,11 +4,13 @@
 
 namespace fb {
 
-// variant v: tile width (16 or 32 right-hand sides) and whether the factor
-// fragments of the next block product are prefetched into registers
-constexpr int kNumVariants = 4;
+// variant v: tile width (16 or 32 right-hand sides), whether the factor
+// fragments of the next block product are prefetched into registers, and
+// how many 16-column tiles one wave computes (1, or 2 for v >= 4)
+constexpr int kNumVariants = 6;
 inline int variant_tile(int v) { return v >= 2 ? 32 : 16; }
 inline bool variant_prefetch(int v) { return (v & 1) != 0; }
+inline int variant_nc(int v) { return v >= 4 ? 2 : 1; }
 bool variant_fits(size_t rsize, int nb, int v);
 int tuned_variant(size_t rsize, int nb);
 void set_tuned_variant(size_t rsize, int nb, int v);

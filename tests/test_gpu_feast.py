@@ -120,3 +120,40 @@ def test_feast_real_n2048_b32(fb, precision):
     print(f"real n2048 precision={precision}: iters={r.iters} info={r.info}", flush=True)
     check_slice(r, ab, -1.0, 1.0, ref)
     assert r.iters <= 6
+
+
+@pytest.mark.parametrize("cplx", [True, False])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_filter_against_oracle_and_pair_grouping(fb, cplx, precision):
+    """feast_filter: Q = r(B) Y against the oracle's node sum, and bit-identical
+    Q whether the (node, direction) pairs run one, three or all per launch or
+    one slice at a time (the node sum is taken in pair order in every case).
+    Oracle bar: FP64 solves agree to kappa n eps (kappa ~ 1e2 here); the
+    refined complex64 solves to kappa * ir_tol each, summed over 16 terms of
+    size |w_j| / Im z_j <= 0.4 ||Y||: 1e-8 relative to ||Q||."""
+    from oracle import bandlu as olu
+    from oracle import quadrature as oq
+    n, b = 700, 11
+    print(f"filter cplx={cplx} precision={precision}", flush=True)
+    ab = synth.band_matrix(n, b, 61, cplx, -12, 12)
+    edges = [-9.0, -4.0, 0.5, 3.0]
+    ms = [37, 20, 45]
+    Yh = [synth.rhs_block(n, m, 70 + i, cplx) for i, m in enumerate(ms)]
+    Y = [fb.to_colmajor(y) for y in Yh]
+    out = {}
+    for key, kw in (("all", {}), ("one", {"pairs": 1}), ("three", {"pairs": 3}),
+                    ("plain", {"batched": False})):
+        r = fb.feast_filter(ab, edges[:-1], edges[1:], Y, precision=precision, ir_tol=1e-12,
+                            with_resid=True, **kw)
+        assert r.status == 0
+        out[key] = [q.cpu().numpy() for q in r.Q]
+    for key in ("one", "three", "plain"):
+        for i in range(3):
+            assert np.array_equal(out[key][i], out["all"][i]), (key, i)
+    tol = 1e-11 if precision == 0 else 1e-8
+    for i in range(3):
+        z, w = oq.contour(edges[i], edges[i + 1], 8)
+        F = [olu.shifted_band_lu(ab, zj) for zj in z]
+        Qr = ofeast.filter_apply(ab, F, w, Yh[i])
+        err = np.linalg.norm(out["all"][i] - Qr) / np.linalg.norm(Qr)
+        assert err <= tol, (i, err)
