@@ -17,7 +17,9 @@ Readings of points the paper leaves open:
 * orthonormalisation (the mass matrix of the standard problem is I):
   Q is replaced by Q V s^{-1/2} from the eigen-decomposition Q^H Q = V s V^H,
   dropping directions with s_k <= 1e-14 max(s) (if any are dropped, the
-  next start block keeps the trailing columns of the previous one);
+  next start block keeps the trailing columns of the previous one); the
+  step is applied twice, since one pass leaves Q^H Q - I as large as the
+  rounding error times the spread of s;
 * for complex Hermitian B the filter is
   Q = sum_j [w_j (z_j I - B)^{-1} Y + conj(w_j) (z_j I - B)^{-H} Y];
   for real symmetric B with real Y it is Q = sum_j 2 Re[w_j (z_j I - B)^{-1} Y].
@@ -62,13 +64,22 @@ def filter_apply(ab: np.ndarray, factors, w, Y: np.ndarray) -> np.ndarray:
     return Q
 
 
-def orthonormalise(Q: np.ndarray, drop: float = 1e-14):
-    """Q V s^{-1/2} over the kept directions of Q^H Q = V s V^H."""
+def _orthonormalise_once(Q: np.ndarray, drop: float):
     G = Q.conj().T @ Q
     G = 0.5 * (G + G.conj().T)
     s, V = np.linalg.eigh(G)
     keep = s > drop * s.max() if s.max() > 0 else np.zeros(len(s), bool)
-    return (Q @ V[:, keep]) / np.sqrt(s[keep]), int(keep.sum())
+    return (Q @ V[:, keep]) / np.sqrt(s[keep])
+
+
+def orthonormalise(Q: np.ndarray, drop: float = 1e-14):
+    """Q V s^{-1/2} over the kept directions of Q^H Q = V s V^H, applied
+    twice: after one pass Q'^H Q' = I + E with E growing with the spread of
+    s (the filtered block is ill-conditioned by design); the second pass
+    brings E to rounding level."""
+    Q1 = _orthonormalise_once(Q, drop)
+    Q2 = _orthonormalise_once(Q1, drop)
+    return Q2, Q2.shape[1]
 
 
 def rayleigh_ritz(ab: np.ndarray, Q: np.ndarray):

@@ -250,6 +250,8 @@ int feast_impl(const fb_band* B, int nslice, const double* lo, const double* hi,
     b.sweeps = ar.take<int32_t>(1);
   }
   JacobiJob* jj_dev = ar.take<JacobiJob>(nslice);
+  EigWork ew;
+  carve_eig_work(ar, std::vector<int>(m0, m0 + nslice), ew);
   int32_t* perm_dev = ar.take<int32_t>(maxm);
   AccJob* acc_dev = ar.take<AccJob>(nslice);
   const int tile = solve_tile<R>(bd.b);
@@ -342,6 +344,7 @@ int feast_impl(const fb_band* B, int nslice, const double* lo, const double* hi,
       for (int i = 0; i < nslice; ++i) {
         Yc[i] = sb[i].Y;
         Qc[i] = sb[i].Q;
+        Xp[(size_t)i * P] = sb[i].X;  // X and Y trade places every iteration
       }
       FB_TRY(filter_apply<R>(bd, f, ne, act, m0, Yc.data(), lds.data(), Qc.data(), lds.data(),
                              Xp.data(), P, acc_dev, zsys, wsys, cplx, o->batched != 0, ir,
@@ -366,11 +369,11 @@ int feast_impl(const fb_band* B, int nslice, const double* lo, const double* hi,
       J.sweeps = sb[i].sweeps;
       jj.push_back(J);
     }
-    FB_HIP(hipMemcpyAsync(jj_dev, jj.data(), sizeof(JacobiJob) * jj.size(), hipMemcpyHostToDevice, st));
-    FB_TRY(launch_jacobi((int)jj.size(), jj_dev, 60, 1e-14, st));
+    FB_TRY(reduced_eig(jj, jj_dev, ew, 60, 1e-14, st));
     for (int i : act) FB_TRY(gram_keep(sb[i].s, m0[i], 1e-14, sb[i].idx, sb[i].scale, sb[i].kept, st));
     for (int i : act) FB_HIP(hipMemcpyAsync(&kept[i], sb[i].kept, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     FB_HIP(hipStreamSynchronize(st));
+    std::vector<int> prev_kept(kept);
     jj.clear();
     for (int i : act) {
       int m = m0[i], k = kept[i];
@@ -378,10 +381,44 @@ int feast_impl(const fb_band* B, int nslice, const double* lo, const double* hi,
       // V' = W[:, idx] diag(scale) (m x k) into V; Q' = Q V' into X
       FB_TRY(gather_cols(sb[i].W, m, false, sb[i].V, m, m, k, sb[i].idx, sb[i].scale, st));
       FB_TRY(zgemm(st, false, (int)n, k, m, sb[i].Q, n, sb[i].V, m, sb[i].X, n));
-      // B Q' into Y (the start block is no longer needed this iteration)
-      FB_TRY(band_matmul(bd, sb[i].X, n, sb[i].Y, n, k, st));
-      // A_q = Q'^H B Q' (k x k) into G
-      FB_TRY(zgemm(st, true, k, k, (int)n, sb[i].X, n, sb[i].Y, n, sb[i].G, k));
+      // second pass: Q'^H Q' = I + E with E growing with the spread of s;
+      // orthonormalising Q' once more makes the basis orthonormal to
+      // rounding, which the eigen-residual floor needs
+      FB_TRY(zgemm(st, true, k, k, (int)n, sb[i].X, n, sb[i].X, n, sb[i].G, k));
+      FB_TRY(hermitize(sb[i].G, k, k, st));
+      JacobiJob J{};
+      J.m = k;
+      J.A = sb[i].G;
+      J.lda = k;
+      J.V = sb[i].V;
+      J.ldv = k;
+      J.W = sb[i].W;
+      J.ldw = k;
+      J.w = sb[i].s;
+      J.order = sb[i].order;
+      J.sweeps = sb[i].sweeps;
+      jj.push_back(J);
+    }
+    if (!jj.empty()) FB_TRY(reduced_eig(jj, jj_dev, ew, 60, 1e-14, st));
+    for (int i : act)
+      if (kept[i] > 0)
+        FB_TRY(gram_keep(sb[i].s, kept[i], 1e-14, sb[i].idx, sb[i].scale, sb[i].kept, st));
+    for (int i : act)
+      if (kept[i] > 0)
+        FB_HIP(hipMemcpyAsync(&kept[i], sb[i].kept, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FB_HIP(hipStreamSynchronize(st));
+    jj.clear();
+    for (int i : act) {
+      int k = kept[i];
+      if (k <= 0) continue;
+      // Q'' = Q' W2[:, idx] diag(scale) into Q (the filter sum is spent)
+      const int k1 = (int)prev_kept[i];
+      FB_TRY(gather_cols(sb[i].W, k1, false, sb[i].V, k1, k1, k, sb[i].idx, sb[i].scale, st));
+      FB_TRY(zgemm(st, false, (int)n, k, k1, sb[i].X, n, sb[i].V, k1, sb[i].Q, n));
+      // B Q'' into Y (its trailing columns keep the start vectors)
+      FB_TRY(band_matmul(bd, sb[i].Q, n, sb[i].Y, n, k, st));
+      // A_q = Q''^H B Q'' (k x k) into G
+      FB_TRY(zgemm(st, true, k, k, (int)n, sb[i].Q, n, sb[i].Y, n, sb[i].G, k));
       FB_TRY(hermitize(sb[i].G, k, k, st));
       JacobiJob J{};
       J.m = k;
@@ -396,18 +433,15 @@ int feast_impl(const fb_band* B, int nslice, const double* lo, const double* hi,
       J.sweeps = sb[i].sweeps;
       jj.push_back(J);
     }
-    if (!jj.empty()) {
-      FB_HIP(hipMemcpyAsync(jj_dev, jj.data(), sizeof(JacobiJob) * jj.size(), hipMemcpyHostToDevice, st));
-      FB_TRY(launch_jacobi((int)jj.size(), jj_dev, 60, 1e-14, st));
-    }
+    if (!jj.empty()) FB_TRY(reduced_eig(jj, jj_dev, ew, 60, 1e-14, st));
     for (int i : act) {
       int m = m0[i], k = kept[i];
       if (k <= 0) continue;
-      // Ritz vectors X = Q' W into Q; residuals; Q becomes the next start block
-      FB_TRY(zgemm(st, false, (int)n, k, k, sb[i].X, n, sb[i].W, k, sb[i].Q, n));
-      FB_TRY(eig_residuals(bd, sb[i].Q, n, sb[i].lam, k, sb[i].part, sb[i].res, st));
+      // Ritz vectors X = Q'' W into X; residuals; X becomes the next start block
+      FB_TRY(zgemm(st, false, (int)n, k, k, sb[i].Q, n, sb[i].W, k, sb[i].X, n));
+      FB_TRY(eig_residuals(bd, sb[i].X, n, sb[i].lam, k, sb[i].part, sb[i].res, st));
       if (k < m)  // rank-deficient filter output: keep the trailing start vectors
-        FB_HIP(hipMemcpy2DAsync(sb[i].Q + (size_t)k * n, n * sizeof(c128), sb[i].Y + (size_t)k * n,
+        FB_HIP(hipMemcpy2DAsync(sb[i].X + (size_t)k * n, n * sizeof(c128), sb[i].Y + (size_t)k * n,
                                 n * sizeof(c128), n * sizeof(c128), m - k,
                                 hipMemcpyDeviceToDevice, st));
       hl[i].resize(k);
@@ -417,7 +451,7 @@ int feast_impl(const fb_band* B, int nslice, const double* lo, const double* hi,
     }
     FB_HIP(hipStreamSynchronize(st));
     for (int i : act) {
-      std::swap(sb[i].Y, sb[i].Q);  // next start block = all Ritz vectors
+      std::swap(sb[i].Y, sb[i].X);  // next start block = all Ritz vectors
       iters[i] = it;
       int k = kept[i], g = 0, in = 0;
       for (int c = 0; c < k; ++c) {

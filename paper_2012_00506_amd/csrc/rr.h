@@ -2,6 +2,8 @@
 #pragma once
 #include <algorithm>
 
+#include <vector>
+
 #include "fb_internal.h"
 
 namespace fb {
@@ -49,6 +51,27 @@ size_t eig_resid_part_doubles(int64_t n, int m);
 int eig_residuals(const Band& bd, const c128* X, int64_t ldx, const double* lam, int m,
                   double* part, double* res, hipStream_t st);
 int launch_jacobi(int njobs, JacobiJob* jobs_dev, int max_sweeps, double tol, hipStream_t st);
+
+// Parallel block Jacobi (many workgroups per matrix) for larger matrices:
+// work holds block_jacobi_bytes(m) per job, dv_dev one device descriptor
+// per job (kBjDescBytes), norms_dev 2 doubles per job.  Synchronises.
+constexpr size_t kBjDescBytes = 64;
+size_t block_jacobi_bytes(int m);
+int block_jacobi(const std::vector<JacobiJob>& jobs, const JacobiJob* jobs_dev, char* work,
+                 void* dv_dev, double* norms_dev, int max_sweeps, double tol, hipStream_t st);
+
+// Hermitian eigensolver dispatch: matrices up to kSmallJacobi on one
+// workgroup each, larger ones by block Jacobi.
+constexpr int kSmallJacobi = 256;
+struct EigWork {
+  char* bj = nullptr;       // block Jacobi buffers
+  void* dv = nullptr;       // descriptors
+  double* norms = nullptr;  // per-job norms
+};
+size_t eig_work_bytes(const std::vector<int>& ms);
+void carve_eig_work(struct Arena& ar, const std::vector<int>& ms, EigWork& w);
+int reduced_eig(std::vector<JacobiJob> jobs, JacobiJob* jobs_dev, const EigWork& w,
+                int max_sweeps, double tol, hipStream_t st);
 int gram_keep(const double* s, int m, double drop, int32_t* idx, double* scale, int32_t* kept,
               hipStream_t st);
 

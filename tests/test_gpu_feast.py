@@ -157,3 +157,19 @@ def test_filter_against_oracle_and_pair_grouping(fb, cplx, precision):
         Qr = ofeast.filter_apply(ab, F, w, Yh[i])
         err = np.linalg.norm(out["all"][i] - Qr) / np.linalg.norm(Qr)
         assert err <= tol, (i, err)
+
+
+def test_feast_block_jacobi_sizes(fb):
+    """A slice whose search space (m0 = 420) takes the multi-workgroup block
+    Jacobi for both reduced eigenproblems, complex Hermitian B."""
+    n, b = 3000, 12
+    ab = synth.band_matrix(n, b, 77, True, -20, 20)
+    ev = eigvals_banded(ab, lower=True)
+    lo, hi = -3.0, 1.5
+    ref = ev[(ev >= lo) & (ev < hi)]
+    m0 = m0_rule(len(ref))
+    assert m0 > 256
+    Yh, Y = start_block(fb, n, m0, 77, True)
+    [r] = fb.feast_band_slice(ab, [lo], [hi], [Y], precision=1)
+    print(f"block-Jacobi slice: m={len(ref)} m0={m0} iters={r.iters} info={r.info}", flush=True)
+    check_slice(r, ab, lo, hi, ref)
