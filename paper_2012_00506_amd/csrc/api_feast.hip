@@ -206,33 +206,36 @@ static int pairs_per_launch(double budget, int fixed, bool batched, int npair, s
   return std::max(1, std::min(p, std::min(npair, kMaxPairs)));
 }
 
+// Workspace of one wave of slices: W slots of m0 <= maxm each.
 template <typename R>
-int feast_impl(const fb_band* B, int nslice, const double* lo, const double* hi, const int32_t* m0,
-               const int32_t* m_expected, void* const* Y, const int64_t* ldy,
-               double* const* evals, double* const* resid, int32_t* m_found, int32_t* iters,
-               int32_t* info, const fb_feast_opts* o, void* work, size_t* lwork, hipStream_t st) {
-  const bool ir = o->precision == 1;
-  const int ne = o->n_nodes;
-  Arena ar;
-  ar.base = (char*)work;
-  ar.cap = *lwork;
-  Band bd;
-  FB_TRY(ingest_band(B, bd, ar, st));
-  const int64_t n = B->n;
-  const bool cplx = B->dtype == FB_COMPLEX128;
-  const int nsys = nslice * ne;
+struct FeastBufs {
   FactorBufs<R> f;
-  carve_factors<R>(ar, bd, nsys, f);
-  double* shifts = ar.take<double>(2 * nslice);
-  int32_t* cnt = ar.take<int32_t>(6 * nslice);
-  size_t iscr = inertia_scratch_bytes(bd, 2 * nslice);
-  void* iscratch = iscr ? (void*)ar.take<char>(iscr) : nullptr;
-  std::vector<SliceBufs> sb(nslice);
-  int maxm = 1;
-  for (int i = 0; i < nslice; ++i) {
-    int m = m0[i];
-    maxm = std::max(maxm, m);
-    SliceBufs& b = sb[i];
+  double* shifts = nullptr;
+  int32_t* cnt = nullptr;
+  void* iscratch = nullptr;
+  std::vector<SliceBufs> sb;
+  JacobiJob* jj_dev = nullptr;
+  EigWork ew;
+  int32_t* perm_dev = nullptr;
+  AccJob* acc_dev = nullptr;
+  int tile = 16, P = 1;
+  std::vector<c128*> Xp;  // slot * P + pair
+  RefineBufs rb;
+};
+
+template <typename R>
+void carve_feast(Arena& ar, const Band& bd, int W, int maxm, int ne, bool ir, int P,
+                 FeastBufs<R>& fb) {
+  const int64_t n = bd.n;
+  carve_factors<R>(ar, bd, W * ne, fb.f);
+  fb.shifts = ar.take<double>(2 * W);
+  fb.cnt = ar.take<int32_t>(6 * W);
+  size_t iscr = inertia_scratch_bytes(bd, 2 * W);
+  fb.iscratch = iscr ? (void*)ar.take<char>(iscr) : nullptr;
+  fb.sb.assign(W, SliceBufs{});
+  const int m = maxm;
+  for (int a = 0; a < W; ++a) {
+    SliceBufs& b = fb.sb[a];
     b.Y = ar.take<c128>((size_t)n * m);
     b.Q = ar.take<c128>((size_t)n * m);
     b.X = ar.take<c128>((size_t)n * m);
@@ -249,35 +252,44 @@ int feast_impl(const fb_band* B, int nslice, const double* lo, const double* hi,
     b.kept = ar.take<int32_t>(1);
     b.sweeps = ar.take<int32_t>(1);
   }
-  JacobiJob* jj_dev = ar.take<JacobiJob>(nslice);
-  EigWork ew;
-  carve_eig_work(ar, std::vector<int>(m0, m0 + nslice), ew);
-  int32_t* perm_dev = ar.take<int32_t>(maxm);
-  AccJob* acc_dev = ar.take<AccJob>(nslice);
-  const int tile = solve_tile<R>(bd.b);
-  int max_jobs = 0;
-  size_t cols = 0;
-  for (int i = 0; i < nslice; ++i) {
-    max_jobs += (m0[i] + tile - 1) / tile;
-    cols += m0[i];
+  fb.jj_dev = ar.take<JacobiJob>(W);
+  carve_eig_work(ar, std::vector<int>(W, maxm), fb.ew);
+  fb.perm_dev = ar.take<int32_t>(maxm);
+  fb.acc_dev = ar.take<AccJob>(W);
+  fb.tile = solve_tile<R>(bd.b);
+  const int max_jobs = W * ((maxm + fb.tile - 1) / fb.tile);
+  fb.P = P;
+  fb.Xp.assign((size_t)W * P, nullptr);
+  for (int a = 0; a < W; ++a) {
+    fb.Xp[(size_t)a * P] = fb.sb[a].X;
+    for (int p = 1; p < P; ++p) fb.Xp[(size_t)a * P + p] = ar.take<c128>((size_t)n * m);
   }
-  const int npair = ne * (cplx ? 2 : 1);
-  const int P = pairs_per_launch(o->hbm_budget, o->pairs, o->batched != 0, npair,
-                                 ar.used + refine_bytes(bd, tile, max_jobs, ir, ir),
-                                 (size_t)n * cols * sizeof(c128));
-  // pair 0 uses the slice's X buffer, pairs 1.. P-1 a pool
-  std::vector<c128*> Xp((size_t)nslice * P);
-  for (int i = 0; i < nslice; ++i) {
-    Xp[(size_t)i * P] = sb[i].X;
-    for (int p = 1; p < P; ++p) Xp[(size_t)i * P + p] = ar.take<c128>((size_t)n * m0[i]);
-  }
-  RefineBufs rb;
-  carve_refine(ar, bd, tile, max_jobs * P, ir, ir, rb);
-  if (work == nullptr) {
-    *lwork = ar.used;
-    return 0;
-  }
-  if (!ar.fits()) return FB_ERR_NOMEM;
+  carve_refine(ar, bd, fb.tile, max_jobs * P, ir, ir, fb.rb);
+}
+
+// FEAST on nslice slices that share one wave's workspace.
+template <typename R>
+int feast_wave(const Band& bd, int nslice, const double* lo, const double* hi, const int32_t* m0,
+               const int32_t* m_expected, void* const* Y, const int64_t* ldy,
+               double* const* evals, double* const* resid, int32_t* m_found, int32_t* iters,
+               int32_t* info, const fb_feast_opts* o, FeastBufs<R>& fbuf, hipStream_t st) {
+  const bool ir = o->precision == 1;
+  const int ne = o->n_nodes;
+  const int64_t n = bd.n;
+  const bool cplx = bd.cplx;
+  const int nsys = nslice * ne;
+  FactorBufs<R>& f = fbuf.f;
+  double* shifts = fbuf.shifts;
+  int32_t* cnt = fbuf.cnt;
+  void* iscratch = fbuf.iscratch;
+  std::vector<SliceBufs>& sb = fbuf.sb;
+  JacobiJob* jj_dev = fbuf.jj_dev;
+  const EigWork& ew = fbuf.ew;
+  int32_t* perm_dev = fbuf.perm_dev;
+  AccJob* acc_dev = fbuf.acc_dev;
+  const int P = fbuf.P;
+  std::vector<c128*>& Xp = fbuf.Xp;
+  RefineBufs& rb = fbuf.rb;
 
   // ---- exact counts (Sylvester inertia at the slice ends)
   double stats[3];
@@ -496,6 +508,74 @@ int feast_impl(const fb_band* B, int nslice, const double* lo, const double* hi,
     FB_HIP(hipMemcpyAsync(evals[i], ev.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
     FB_HIP(hipMemcpyAsync(resid[i], rs.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
     FB_HIP(hipStreamSynchronize(st));
+  }
+  return nbad;
+}
+
+// Slices are processed in waves: as many slices per wave (all of them if
+// they fit) and as many (node, direction) pairs per batched launch as the
+// HBM budget allows, choosing the pair that gives the most solve jobs per
+// launch.
+template <typename R>
+int feast_impl(const fb_band* B, int nslice, const double* lo, const double* hi, const int32_t* m0,
+               const int32_t* m_expected, void* const* Y, const int64_t* ldy,
+               double* const* evals, double* const* resid, int32_t* m_found, int32_t* iters,
+               int32_t* info, const fb_feast_opts* o, void* work, size_t* lwork, hipStream_t st) {
+  const bool ir = o->precision == 1;
+  const int ne = o->n_nodes;
+  Arena ar;
+  ar.base = (char*)work;
+  ar.cap = *lwork;
+  Band bd;
+  FB_TRY(ingest_band(B, bd, ar, st));
+  const int64_t n = B->n;
+  const bool cplx = B->dtype == FB_COMPLEX128;
+  int maxm = 1;
+  for (int i = 0; i < nslice; ++i) maxm = std::max(maxm, (int)m0[i]);
+  const int npair = ne * (cplx ? 2 : 1);
+  double budget = o->hbm_budget;
+  if (!(budget > 0)) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) tot = 0;
+    budget = 0.5 * (double)tot;
+  }
+  const size_t used0 = ar.used;
+  int W = 1, P = 1;
+  {
+    long best = -1;
+    for (int w = nslice; w >= 1; --w) {
+      Arena q;
+      q.used = used0;
+      FeastBufs<R> tmp;
+      carve_feast<R>(q, bd, w, maxm, ne, ir, 1, tmp);
+      const size_t per_pair = (size_t)w * n * maxm * sizeof(c128);
+      if ((double)q.used > budget && w > 1) continue;
+      const int p = pairs_per_launch(budget, o->pairs, o->batched != 0, npair,
+                                     q.used - per_pair * 0, per_pair);
+      const long score = (long)w * p;
+      if (score > best) {
+        best = score;
+        W = w;
+        P = p;
+      }
+      if (w == nslice && (p == npair || o->batched == 0)) break;  // everything in one wave
+    }
+  }
+  FeastBufs<R> fbuf;
+  carve_feast<R>(ar, bd, W, maxm, ne, ir, P, fbuf);
+  if (work == nullptr) {
+    *lwork = ar.used;
+    return 0;
+  }
+  if (!ar.fits()) return FB_ERR_NOMEM;
+  int nbad = 0;
+  for (int w0 = 0; w0 < nslice; w0 += W) {
+    const int nw = std::min(W, nslice - w0);
+    int rc = feast_wave<R>(bd, nw, lo + w0, hi + w0, m0 + w0,
+                           m_expected ? m_expected + w0 : nullptr, Y + w0, ldy + w0, evals + w0,
+                           resid + w0, m_found + w0, iters + w0, info + w0, o, fbuf, st);
+    if (rc < 0) return rc;
+    nbad += rc;
   }
   return nbad;
 }

@@ -173,3 +173,21 @@ def test_feast_block_jacobi_sizes(fb):
     [r] = fb.feast_band_slice(ab, [lo], [hi], [Y], precision=1)
     print(f"block-Jacobi slice: m={len(ref)} m0={m0} iters={r.iters} info={r.info}", flush=True)
     check_slice(r, ab, lo, hi, ref)
+
+
+def test_feast_waves_equal_one_wave(fb):
+    """A budget that admits one slice at a time (three waves) gives the same
+    results bit for bit as all slices in one wave (the pairs per launch held
+    fixed)."""
+    n = 600
+    ab = synth.band_matrix(n, 7, 45, True, -10, 10)
+    edges = [-7.0, -4.0, -1.5, 1.0]
+    ms = [m0_rule(oin.count_in(ab, edges[i], edges[i + 1])) for i in range(3)]
+    res = {}
+    for key, budget in (("one", 0.0), ("waves", 1.0)):
+        Ys = [start_block(fb, n, ms[i], 50 + i, True)[1] for i in range(3)]
+        res[key] = fb.feast_band_slice(ab, edges[:-1], edges[1:], Ys, hbm_budget=budget, pairs=2)
+    for i in range(3):
+        assert res["one"][i].info == 0
+        assert np.array_equal(res["one"][i].evals, res["waves"][i].evals)
+        assert torch.equal(res["one"][i].Y, res["waves"][i].Y)
