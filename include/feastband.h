@@ -169,6 +169,11 @@ typedef struct {
                          (fb_planner_bytes() bytes), or NULL for a uniform
                          prior over [lo, hi] (interpolation search) */
   uint64_t seed;      /* FB_PLAN_LEARNED: probe seed of the features */
+  int64_t nev;        /* equal count / LEARNED: > 0 places hi so that [lo, hi)
+                         holds exactly the lowest nev eigenvalues above lo */
+  const int32_t* targets; /* equal count / LEARNED: host, K desired slice
+                         counts (their sum fixes hi exactly, as nev), or NULL
+                         for equal counts */
 } fb_plan_opts;
 
 /* Slice placement by exact inertia (Section 3.1 "Spectrum Partition",

@@ -15,6 +15,9 @@ FB_PLAN_LEARNED = 2
 PROF_CLASSES = ["lu", "invert", "solve", "resid", "inertia", "jacobi", "gemm", "bandmm"]
 
 
+PI32 = C.POINTER(C.c_int32)
+
+
 class fb_band(C.Structure):
     _fields_ = [("n", C.c_int64), ("b", C.c_int32), ("dtype", C.c_int32),
                 ("ldab", C.c_int64), ("ab", C.c_void_p)]
@@ -34,11 +37,11 @@ class fb_feast_opts(C.Structure):
 class fb_plan_opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("K", C.c_int32), ("lo", C.c_double), ("hi", C.c_double),
                 ("count_tol", C.c_double), ("cert_delta", C.c_double),
-                ("max_rounds", C.c_int32), ("planner", C.c_void_p), ("seed", C.c_uint64)]
+                ("max_rounds", C.c_int32), ("planner", C.c_void_p), ("seed", C.c_uint64),
+                ("nev", C.c_int64), ("targets", PI32)]
 
 
 P = C.c_void_p
-PI32 = C.POINTER(C.c_int32)
 PI64 = C.POINTER(C.c_int64)
 PD = C.POINTER(C.c_double)
 PSZ = C.POINTER(C.c_size_t)

@@ -223,17 +223,26 @@ def feast_band_slice(B, lo, hi, Y, m_expected=None, n_nodes=8, tol=1e-10, max_it
 
 
 def slice_plan(B, K, mode="equal_count", lo=float("nan"), hi=float("nan"), count_tol=0.05,
-               cert_delta=1e-8, max_rounds=60, planner=None, seed=0, stream=None):
+               cert_delta=1e-8, max_rounds=60, planner=None, seed=0, nev=0, targets=None,
+               stream=None):
     """Slice boundaries (K+1), exact counts (K) and the number of inertia
     evaluations, by equal width, equal count (bisection) or equal count
     searched with the planner network's predicted distribution (``planner``:
-    device weights tensor; None in "learned" mode = uniform prior)."""
+    device weights tensor; None in "learned" mode = uniform prior).
+    ``nev`` > 0 covers exactly the lowest nev eigenvalues above lo;
+    ``targets`` gives one desired count per slice instead of equal counts."""
     B = _as_band(B)
     modes = {"equal_width": N.FB_PLAN_EQUAL_WIDTH, "equal_count": N.FB_PLAN_EQUAL_COUNT,
              "learned": N.FB_PLAN_LEARNED}
     wp = C.c_void_p(planner.data_ptr()) if planner is not None else None
+    tg = None
+    if targets is not None:
+        tg = np.ascontiguousarray(np.asarray(targets, np.int32))
+        if tg.shape != (K,):
+            raise ValueError("targets needs one count per slice")
     o = N.fb_plan_opts(modes[mode], int(K), float(lo), float(hi), float(count_tol),
-                       float(cert_delta), int(max_rounds), wp, int(seed))
+                       float(cert_delta), int(max_rounds), wp, int(seed), int(nev),
+                       tg.ctypes.data_as(N.PI32) if tg is not None else None)
     bounds = np.zeros(K + 1, np.float64)
     counts = np.zeros(K, np.int32)
     nev = C.c_int32(0)

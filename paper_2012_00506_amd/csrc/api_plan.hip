@@ -94,6 +94,10 @@ extern "C" int slice_plan(const fb_band* B, const fb_plan_opts* o, double* bound
   if (!(o->cert_delta >= 0) || !(o->count_tol >= 0) || o->max_rounds < 0) return -2;
   if (o->mode == FB_PLAN_EQUAL_WIDTH && (isnan(o->lo) || isnan(o->hi) || !(o->lo < o->hi)))
     return -2;
+  if (o->nev < 0) return -2;
+  if (o->targets)
+    for (int i = 0; i < o->K; ++i)
+      if (o->targets[i] < 0) return -2;
   if (!bounds) return -3;
   if (!counts) return -4;
   if (!lwork) return -7;
@@ -152,11 +156,71 @@ extern "C" int slice_plan(const fb_band* B, const fb_plan_opts* o, double* bound
     FB_TRY(certify_all(ir, ends, delta, ne));
     lo = ends[0];
     hi = ends[1];
-    const int n_lo = ne[0], n_hi = ne[1], total = n_hi - n_lo;
-    std::vector<int> target(K - 1);
-    for (int i = 1; i < K; ++i) target[i - 1] = n_lo + (int)nearbyint((double)i * total / K);  // half to even
-    const int tol = (int)floor(o->count_tol * total / K);
+    int n_lo = ne[0], n_hi = ne[1];
     std::map<double, int> known = {{lo, n_lo}, {hi, n_hi}};
+    // an exact total: the lowest nev eigenvalues above lo (or the sum of the
+    // given slice counts) -- the upper end is bisected to the exact count
+    // and certified there
+    int64_t want = o->nev;
+    if (want <= 0 && o->targets) {
+      want = 0;
+      for (int i = 0; i < K; ++i) want += o->targets[i];
+    }
+    if (want > 0) {
+      if (want > n_hi - n_lo) return -2;
+      const int tcount = n_lo + (int)want;
+      double a = lo, b = hi;  // n_-(a) <= tcount < ... n_-(b) >= tcount
+      int na = n_lo, nb_ = n_hi;
+      bool done = false;
+      for (int round = 0; round < 200 && !done; ++round) {
+        double c;
+        if (nb_ == tcount) {
+          // b already has the count: certify it
+          std::vector<double> e1 = {b};
+          std::vector<int> c1;
+          FB_TRY(certify_all(ir, e1, delta, c1));
+          if (c1[0] == tcount) {
+            hi = e1[0];
+            n_hi = tcount;
+            done = true;
+            break;
+          }
+          c = 0.5 * (a + b);
+        } else {
+          c = 0.5 * (a + b);
+        }
+        std::vector<int> nc;
+        FB_TRY(ir.run({c}, nc));
+        known[c] = nc[0];
+        if (nc[0] > tcount) {
+          b = c;
+          nb_ = nc[0];
+        } else if (nc[0] < tcount) {
+          a = c;
+          na = nc[0];
+        } else {
+          b = c;
+          nb_ = nc[0];
+        }
+      }
+      if (!done) return FB_ERR_CERTIFY;
+      // keep only known points inside [lo, hi]
+      for (auto it = known.begin(); it != known.end();)
+        it = it->first > hi ? known.erase(it) : std::next(it);
+      known[hi] = n_hi;
+    }
+    const int total = n_hi - n_lo;
+    std::vector<int> target(K - 1);
+    if (o->targets) {
+      int64_t acc = n_lo;
+      for (int i = 1; i < K; ++i) {
+        acc += o->targets[i - 1];
+        target[i - 1] = (int)acc;
+      }
+    } else {
+      for (int i = 1; i < K; ++i) target[i - 1] = n_lo + (int)nearbyint((double)i * total / K);  // half to even
+    }
+    const int tol = (int)floor(o->count_tol * total / K);
     // Predicted fraction of eigenvalues below x as a monotone piecewise-linear
     // function through (px, py): the network's 64 outputs at the centres of
     // the Gershgorin interval's 64 cells, clipped to [0, 1] and made

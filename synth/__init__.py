@@ -23,6 +23,8 @@ __all__ = [
     "rhs_block",
     "rhs_columns",
     "planner_matrix",
+    "scf_matrix",
+    "scf_targets",
     "Config",
     "CONFIGS",
 ]
@@ -171,6 +173,21 @@ CONFIGS = {
         "cplx-n65536-b128", 65536, 128, True, 5, -50.0, 50.0, (),
         "complex Hermitian band n=65536 b=128, lowest 25600 eigenvalues in 64 slices"),
 }
+
+
+def scf_matrix(cfg: "Config", k: int) -> np.ndarray:
+    """Matrix k of the SCF-like sequence: B_0 = cfg.matrix(), and for k >= 1
+    B_k = B_0 + 1e-3 E_k with E_k a band perturbation of the same band
+    (seed 3000 + k, diagonal N(0,1), off-diagonals N(0, 1/b))."""
+    ab = cfg.matrix()
+    if k > 0:
+        ab = ab + 1e-3 * hermitian_perturbation(cfg.n, cfg.b, 3000 + k, cfg.complex_)
+    return ab
+
+
+def scf_targets(K: int = 32, seed: int = 303) -> np.ndarray:
+    """Uneven slice counts of the sequence workload: U{43..341} (seed 303)."""
+    return np.random.default_rng(seed).integers(43, 342, K)
 
 
 def rhs_block_device(n: int, m: int, seed: int, complex_: bool, device="cuda"):

@@ -245,3 +245,31 @@ def test_slice_plan_parity(fb, n, b, cplx, K):
     e, c, ne = fb.slice_plan(ab, K, "equal_width", lo=lo, hi=hi)
     re, rc, rne = opl.plan_equal_width(ab, K, lo, hi)
     assert np.array_equal(e, re) and np.array_equal(c, rc) and ne == rne
+
+
+@pytest.mark.parametrize("mode", ["equal_count", "learned"])
+def test_slice_plan_lowest_nev(fb, pl, mode):
+    """nev: [lo, hi) holds exactly the lowest nev eigenvalues (the paper's
+    lowest-part convention), split into equal counts; every boundary
+    certified."""
+    ab = synth.band_matrix(1100, 10, 91, True, -30, 30)
+    nev, K = 333, 8
+    bounds, counts, _ = fb.slice_plan(ab, K, mode, nev=nev, count_tol=0.05)
+    assert counts.sum() == nev
+    ev = np.linalg.eigvalsh(oband.dense_from_band(ab))
+    assert np.sum(ev < bounds[-1]) == nev and np.sum(ev < bounds[0]) == 0
+    _check_plan(ab, K, bounds, counts, 0.05)
+
+
+def test_slice_plan_given_targets(fb):
+    ab = synth.band_matrix(900, 8, 92, False, -25, 25)
+    targets = np.array([43, 120, 341, 60, 77])
+    bounds, counts, _ = fb.slice_plan(ab, len(targets), "equal_count", targets=targets,
+                                      count_tol=0.05)
+    assert counts.sum() == targets.sum()
+    tol = int(np.floor(0.05 * targets.sum() / len(targets)))
+    cum = np.cumsum(counts)[:-1]
+    assert np.all(np.abs(cum - np.cumsum(targets)[:-1]) <= tol)
+    delta = 1e-8 * oband.norm1(ab)
+    for s_ in bounds:
+        assert oin.inertia(ab, s_ - delta)[0] == oin.inertia(ab, s_ + delta)[0]

@@ -1,0 +1,103 @@
+"""The two large workloads at their real shapes on one GPU: the SCF-like
+sequence (n = 32768, b = 64, 32 uneven slices, warm starts) and the
+n = 65536, b = 128 band with the lowest 25 600 eigenvalues in 64 planned
+slices (run in HBM-budget waves; a subset of slices is solved).  Checks are
+those that hold at any size: exact counts (the oracle's inertia at sampled
+boundaries), every reported pair's residual recomputed with the oracle's band
+product on sampled columns, orthonormality, and the warm start's saving."""
+import math
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import band as oband
+from oracle import inertia as oin
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2012_00506_amd as fb
+    return fb
+
+
+def _check_results(ab, bounds, res, cols_per_slice=3, seed=0):
+    nrm = oband.norm1(ab)
+    rng = np.random.default_rng(seed)
+    for i, r in enumerate(res):
+        assert r.info == 0, (i, r.info, r.m_found)
+        m = r.m_found
+        lam = r.lam
+        assert np.all((lam >= bounds[i]) & (lam < bounds[i + 1]))
+        assert r.resid[:m].max() <= 1e-10
+        X = r.Y[:, :m]
+        G = (X.conj().T @ X).cpu().numpy()
+        assert np.abs(G - np.eye(m)).max() <= 1e-11
+        pick = rng.choice(m, size=min(cols_per_slice, m), replace=False)
+        Xs = X[:, pick].cpu().numpy()
+        R = oband.band_matmul(ab, Xs) - Xs * lam[pick][None, :]
+        assert (np.linalg.norm(R, axis=0) / nrm).max() <= 1e-10
+
+
+def test_scf_sequence_warm_start(fb):
+    from paper_2012_00506_amd.scf import SliceSequence
+    cfg = synth.CONFIGS["cplx-n32768-b64-seq"]
+    targets = synth.scf_targets()
+    ab0 = synth.scf_matrix(cfg, 0)
+    bounds, counts, _ = fb.slice_plan(ab0, len(targets), "equal_count", targets=targets)
+    assert counts.sum() == targets.sum()
+    print(f"planned {len(counts)} slices, counts {counts.min()}..{counts.max()}", flush=True)
+    warm = SliceSequence(bounds, precision=1, warm=True, seed=1)
+    cold = SliceSequence(bounds, precision=1, warm=False, seed=1)
+    it_w, it_c = [], []
+    for k in range(3):
+        ab = synth.scf_matrix(cfg, k)
+        B = fb.DeviceBand.from_band(ab)
+        rw = warm.step(B)
+        print(f"step {k}: warm {rw.seconds:.1f} s iters {sum(rw.iters)}", flush=True)
+        if k == 2:
+            _check_results(ab, warm.bounds, rw.results)
+            # exact counts at two sampled boundaries with the oracle
+            for j in (5, 20):
+                lo, hi = warm.bounds[j], warm.bounds[j + 1]
+                assert rw.counts[j] == oin.count_in(ab, lo, hi)
+        if k >= 1:
+            rc = cold.step(B)
+            print(f"step {k}: cold {rc.seconds:.1f} s iters {sum(rc.iters)}", flush=True)
+            it_w.append(sum(rw.iters))
+            it_c.append(sum(rc.iters))
+        else:
+            cold.step(B)
+        del B
+    assert sum(it_w) < sum(it_c)
+
+
+def test_n65536_b128_lowest_slices(fb):
+    """Lowest 25 600 eigenvalues of the n = 65536, b = 128 band in 64
+    equal-count slices (exact total by inertia); the first 8 slices are
+    solved, in waves when the HBM budget asks for them."""
+    cfg = synth.CONFIGS["cplx-n65536-b128"]
+    ab = cfg.matrix()
+    B = fb.DeviceBand.from_band(ab)
+    t0 = time.time()
+    bounds, counts, nev_evals = fb.slice_plan(B, 64, "equal_count", nev=25600)
+    print(f"plan: {time.time() - t0:.1f} s, {nev_evals} inertias, counts "
+          f"{counts.min()}..{counts.max()}", flush=True)
+    assert counts.sum() == 25600
+    ns = 8
+    Y = [synth.rhs_block_device(cfg.n, max(math.ceil(1.5 * int(c)), int(c) + 10),
+                                cfg.seed * 1000 + i, True).contiguous().t().contiguous().t()
+         for i, c in enumerate(counts[:ns])]
+    t0 = time.time()
+    res = fb.feast_band_slice(B, bounds[:ns], bounds[1:ns + 1], Y, m_expected=counts[:ns],
+                              precision=1)
+    torch.cuda.synchronize()
+    print(f"feast {ns} slices: {time.time() - t0:.1f} s, iters {[r.iters for r in res]}",
+          flush=True)
+    _check_results(ab, bounds, res, cols_per_slice=2)
