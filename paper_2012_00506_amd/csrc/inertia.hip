@@ -1,14 +1,15 @@
 // Sylvester inertia of B - sigma I by band LDL^H without pivoting (FP64),
 // one workgroup per shift.
 //
-// The live part of the factorisation at step k is the lower triangle of the
-// rows/columns k .. k+b of the partially reduced matrix.  Row k+b+1 (still
-// untouched by the elimination) is loaded during step k for use at step k+1.
-// Both are kept in an M x M circular window, M = b + 2, slot
-// (c mod M, i mod M) holding A(i, c) for c <= i: every live entry has a
-// distinct slot, the entering row (row slot (k-1) mod M) is neither read nor
-// written by step k, and a single barrier per step suffices.  The window sits in LDS when it fits and
-// in a per-shift global scratch area otherwise.
+// The live part of the factorisation at step k is the lower triangle of rows
+// k .. k+b+1 (row k+b+1 still untouched, loaded during step k for use from
+// step k+1).  It is kept in LDS by diagonals: diagonal d (entries A(c+d, c))
+// is a circular buffer of L_d = b+2-d slots indexed by c mod L_d, which holds
+// exactly its live columns k .. k+b+1-d, so the whole triangle takes
+// (b+2)(b+3)/2 entries (136 KB at b = 128).  The slot freed by column k-1 of
+// each diagonal receives the entering row's entry, which step k neither reads
+// nor writes, so a single barrier per step suffices; k mod L_d is kept per
+// diagonal in LDS, double-buffered by step parity.
 #include "fb_internal.h"
 #include "prof.h"
 
@@ -20,43 +21,68 @@ static const size_t kLdsBudget = 160 * 1024;
 __device__ __forceinline__ c128 band_entry(const c128* __restrict__ Bd, int64_t n,
                                            int64_t i, int64_t c, double sigma) {
   // A(i, c) = B(i, c) - sigma * delta_ic for 0 <= i - c <= b (caller checks)
-  c128 v = Bd[(i - c) * n + c];
+  c128 v = gld(Bd + (i - c) * n + c);
   if (i == c) v.x -= sigma;
   return v;
 }
 
-template <bool USE_LDS>
+static size_t inertia_lds_bytes(int b) {
+  const size_t tri = (size_t)(b + 2) * (b + 3) / 2;
+  return tri * sizeof(c128) + 3 * (size_t)(b + 2) * sizeof(int) + 64;
+}
+
 __global__ void __launch_bounds__(kInertiaThreads)
 k_band_ldlh_inertia(const c128* __restrict__ Bd, int64_t n, int b,
                     const double* __restrict__ shifts, const double* __restrict__ stats,
-                    int32_t* __restrict__ counts, c128* __restrict__ gwin) {
-  extern __shared__ c128 lds_win[];
+                    int32_t* __restrict__ counts) {
+  extern __shared__ char lds_raw[];
   const int M = b + 2;
+  const int tri = M * (M + 1) / 2;
+  c128* D = reinterpret_cast<c128*>(lds_raw);
+  int* off = reinterpret_cast<int*>(D + tri);  // start of diagonal d
+  int* kd = off + M;                           // [2][M]: k mod L_d, by step parity
   const int s = blockIdx.x;
-  // the LDS window is a compile-time choice, so that its accesses are LDS
-  // instructions rather than flat ones
-  c128* W = USE_LDS ? lds_win : gwin + (size_t)s * M * M;
   const double sigma = shifts[s];
   const double eps = 2.220446049250313e-16;
   const double pivmin = eps * eps * stats[0];
   const int t = threadIdx.x;
 
-  // initial window: rows/columns 0 .. min(b, n-1)
-  int64_t top = (int64_t)b < n ? b : n - 1;
-  for (int idx = t; idx < M * M; idx += blockDim.x) {
-    int cs = idx / M, rs = idx % M;
-    int64_t c = cs, i = rs;
-    c128 v = mk(0.0, 0.0);
-    if (c <= i && i <= top && i - c <= b) v = band_entry(Bd, n, i, c, sigma);
-    W[cs * M + rs] = v;
+  for (int e = t; e < tri; e += blockDim.x) D[e] = mk(0.0, 0.0);
+  for (int d = t; d < M; d += blockDim.x) {
+    off[d] = d * M - d * (d - 1) / 2;
+    kd[d] = 0;
+    kd[M + d] = 0;
   }
+  __syncthreads();
+  // initial window: rows/columns 0 .. min(b, n-1)
+  const int64_t top = (int64_t)b < n ? b : n - 1;
+  for (int e = t; e < M * M; e += blockDim.x) {
+    const int c = e / M, i = e % M;
+    if (c <= i && i <= top && i - c <= b) D[off[i - c] + c] = band_entry(Bd, n, i, c, sigma);
+  }
+  // update mapping: columns jc = 1 + ucol of the trailing triangle, every
+  // ugrps-th diagonal
+  const int ucols = b, ugrps = kInertiaThreads / (b > 0 ? b : 1);
+  const int ucol = t % ucols, ugrp = t / ucols;
+  const int jc = ucol + 1;
+  // entering row entries: diagonal d = t (<= b), fetched one step ahead
+  c128 ent = mk(0.0, 0.0);
+  auto fetch = [&](int64_t k) {
+    const int64_t inew = k + b + 1;
+    c128 v = mk(0.0, 0.0);
+    if (t <= b && inew < n) v = band_entry(Bd, n, inew, inew - t, sigma);
+    return v;
+  };
+  ent = fetch(0);
   __syncthreads();
 
   int neg = 0, zero = 0;
-  int ks = 0;  // k mod M; offsets below M need at most one wrap
-  auto slot = [&](int off) { int v = ks + off; return v >= M ? v - M : v; };
   for (int64_t k = 0; k < n; ++k) {
-    double dk = W[ks * M + ks].x;
+    const int* kc = kd + (k & 1) * M;
+    int* kn = kd + ((k & 1) ^ 1) * M;
+    const c128 cur = ent;
+    if (k + 1 < n) ent = fetch(k + 1);
+    double dk = D[off[0] + kc[0]].x;
     if (fabs(dk) < pivmin) {
       ++zero;
       dk = -pivmin;
@@ -65,32 +91,34 @@ k_band_ldlh_inertia(const c128* __restrict__ Bd, int64_t n, int b,
     }
     const int m = (int)((n - 1 - k) < b ? (n - 1 - k) : b);
     const double rdk = 1.0 / dk;
-    // rank-one update of the trailing triangle: for k < c <= i <= k+m
-    // A(i, c) -= A(i, k) conj(A(c, k)) / d_k
-    for (int idx = t; idx < m * m; idx += blockDim.x) {
-      int ii = idx / m + 1;  // i - k
-      int jc = idx - (ii - 1) * m + 1;  // c - k
-      if (jc > ii) continue;
-      int is = slot(ii), cs = slot(jc);
-      c128 aik = W[ks * M + is];
-      c128 ack = W[ks * M + cs];
-      c128 upd = W[cs * M + is];
-      c128 p = aik * cconj(ack);
-      upd.x -= p.x * rdk;
-      upd.y -= p.y * rdk;
-      W[cs * M + is] = upd;
-    }
-    // entering row i = k+b+1 (columns k+1 .. k+b+1), used from step k+1 on
-    int64_t inew = k + b + 1;
-    if (inew < n) {
-      const int rs = slot(b + 1);
-      for (int jc = t; jc <= b; jc += blockDim.x) {
-        int64_t c = inew - b + jc;  // columns inew-b .. inew
-        W[slot(1 + jc) * M + rs] = band_entry(Bd, n, inew, c, sigma);
+    // A(k+jc+d, k+jc) -= A(k+jc+d, k) conj(A(k+jc, k)) / d_k, 1 <= jc, jc+d <= m
+    if (ugrp < ugrps && jc <= m) {
+      const c128 ack = D[off[jc] + kc[jc]];
+      const c128 ackr = mk(ack.x * rdk, -ack.y * rdk);  // conj(A(c,k)) / d_k
+      for (int d = ugrp; d + jc <= m; d += ugrps) {
+        const int ii = d + jc;
+        const int L = M - d;
+        int sl = kc[d] + jc;
+        if (sl >= L) sl -= L;
+        const c128 aik = D[off[ii] + kc[ii]];
+        c128 v = D[off[d] + sl];
+        v.x -= aik.x * ackr.x - aik.y * ackr.y;
+        v.y -= aik.x * ackr.y + aik.y * ackr.x;
+        D[off[d] + sl] = v;
       }
     }
+    // entering row k+b+1 into the slot column k-1 left on every diagonal
+    if (t <= b && k + b + 1 < n) {
+      const int L = M - t;
+      int sl = kc[t] - 1;
+      if (sl < 0) sl += L;
+      D[off[t] + sl] = cur;
+    }
+    if (t < M) {
+      int v = kc[t] + 1;
+      kn[t] = v >= M - t ? 0 : v;
+    }
     __syncthreads();
-    ks = slot(1);
   }
   if (t == 0) {
     counts[3 * s + 0] = neg;
@@ -99,30 +127,24 @@ k_band_ldlh_inertia(const c128* __restrict__ Bd, int64_t n, int b,
   }
 }
 
-static bool inertia_lds(int b) { return (size_t)(b + 2) * (b + 2) * sizeof(c128) <= kLdsBudget; }
-
 size_t inertia_scratch_bytes(const Band& bd, int nshift) {
-  if (inertia_lds(bd.b)) return 0;
-  return (size_t)nshift * (bd.b + 2) * (bd.b + 2) * sizeof(c128);
+  (void)bd;
+  (void)nshift;
+  return 0;  // the window always fits in LDS (b <= 128)
 }
 
 int launch_inertia(const Band& bd, int nshift, const double* shifts_dev, int32_t* cnt_dev,
                    void* scratch, hipStream_t st) {
+  (void)scratch;
   if (nshift <= 0) return 0;
-  bool lds = inertia_lds(bd.b);
-  size_t smem = lds ? (size_t)(bd.b + 2) * (bd.b + 2) * sizeof(c128) : 0;
-  if (lds) {
-    (void)hipFuncSetAttribute((const void*)k_band_ldlh_inertia<true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
-    (void)hipGetLastError();
-  }
+  const size_t smem = inertia_lds_bytes(bd.b);
+  if (smem > kLdsBudget) return FB_ERR_INTERNAL;
+  (void)hipFuncSetAttribute((const void*)k_band_ldlh_inertia,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
+  (void)hipGetLastError();
   ProfScope ps(FB_PROF_INERTIA, st, 4.0 * (double)bd.n * bd.b * bd.b * nshift);
-  if (lds)
-    k_band_ldlh_inertia<true><<<nshift, kInertiaThreads, smem, st>>>(
-        bd.Bd, bd.n, bd.b, shifts_dev, bd.stats, cnt_dev, (c128*)scratch);
-  else
-    k_band_ldlh_inertia<false><<<nshift, kInertiaThreads, smem, st>>>(
-        bd.Bd, bd.n, bd.b, shifts_dev, bd.stats, cnt_dev, (c128*)scratch);
+  k_band_ldlh_inertia<<<nshift, kInertiaThreads, smem, st>>>(bd.Bd, bd.n, bd.b, shifts_dev,
+                                                               bd.stats, cnt_dev);
   FB_HIP(hipGetLastError());
   return 0;
 }
