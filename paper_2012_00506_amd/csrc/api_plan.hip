@@ -301,9 +301,12 @@ extern "C" int slice_plan(const fb_band* B, const fb_plan_opts* o, double* bound
             // The exact counts at the bracket ends rescale the predicted
             // distribution inside it; invert it at the target.  A bracket
             // that did not halve over the last two rounds is bisected.
+            // Inside two cells of the prediction the network has nothing
+            // to add to the exact counts: plain linear interpolation.
             const double fa = fhat(xa), fb = fhat(xb);
             const double frac = (double)(t - vs[ia]) / (double)(vs[ib] - vs[ia]);
-            double g = fb > fa ? finv(fa + frac * (fb - fa)) : xa + frac * w;
+            const double cell = (px.back() - px.front()) / kPlanOutputs;
+            double g = (fb > fa && w > 2.0 * cell) ? finv(fa + frac * (fb - fa)) : xa + frac * w;
             s = std::min(xb - 0.01 * w, std::max(xa + 0.01 * w, g));
           }
           w2[i] = w1[i];

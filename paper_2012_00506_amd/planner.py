@@ -71,8 +71,9 @@ def build_dataset(indices, make_matrix, log=None):
     return np.array(X), np.array(Y)
 
 
-def train(X, Y, epochs=200, batch=64, lr=1e-3, seed=0, device="cuda", log=None):
-    """Adam on the GPU with the library's own forward/backward kernels."""
+def train(X, Y, epochs=200, batch=64, lr=1e-3, seed=0, device="cuda", log=None, on_epoch=None):
+    """Adam on the GPU with the library's own forward/backward kernels;
+    on_epoch(epoch, weights) is called after every epoch."""
     w = init_weights(seed, device)
     opt = torch.zeros(2 * w.numel(), dtype=torch.float32, device=device)
     Xt = torch.as_tensor(X, dtype=torch.float32, device=device)
@@ -89,6 +90,8 @@ def train(X, Y, epochs=200, batch=64, lr=1e-3, seed=0, device="cuda", log=None):
             t += 1
             tot += api.planner_train_step(w, opt, Xt[idx], Yt[idx], lr, t) * len(idx)
         hist.append(tot / max(1, (n // batch) * batch if n >= batch else n))
+        if on_epoch:
+            on_epoch(ep, w)
         if log and (ep + 1) % 50 == 0:
             log(f"  epoch {ep + 1}: train mse {hist[-1]:.3e}")
     return w, hist
@@ -116,28 +119,55 @@ def gain(w, matrices, K_list=(16, 64), count_tol=0.05):
 
 
 def main():
+    """Train on the seeded planner family (indices 0..train-1), select the
+    epoch by validation loss (the next `val` indices) and report the test
+    loss and the inertia-evaluation gain on the `gain` first test matrices."""
     import synth
     p = argparse.ArgumentParser()
     p.add_argument("--train", type=int, default=1600)
+    p.add_argument("--val", type=int, default=200)
     p.add_argument("--test", type=int, default=200)
+    p.add_argument("--gain", type=int, default=50)
     p.add_argument("--epochs", type=int, default=300)
+    p.add_argument("--scale", type=int, default=1, help="n divisor of the family (quick runs)")
     p.add_argument("--out", default=None)
     a = p.parse_args()
     log = lambda s: print(s, flush=True)
-    make = lambda i: synth.planner_matrix(i)[0]
+    make = lambda i: synth.planner_matrix(i, scale=a.scale)[0]
+    t0 = time.time()
     log(f"building {a.train} training samples")
     X, Y = build_dataset(range(a.train), make, log)
-    log(f"building {a.test} test samples")
-    Xv, Yv = build_dataset(range(a.train, a.train + a.test), make, log)
-    w, hist = train(X, Y, epochs=a.epochs, log=log)
-    mse = float(np.mean((predict(w, Xv) - Yv) ** 2))
-    rows = gain(w, [(i, make(i)) for i in range(a.train, a.train + a.test)])
-    out = {"train_mse": hist[-1], "test_mse": mse,
-           "mean_inertia_bisection": float(np.mean([r["bisection"] for r in rows])),
-           "mean_inertia_learned": float(np.mean([r["learned"] for r in rows]))}
-    print(json.dumps(out))
+    i0 = a.train
+    log(f"building {a.val} validation and {a.test} test samples")
+    Xv, Yv = build_dataset(range(i0, i0 + a.val), make, log)
+    Xt, Yt = build_dataset(range(i0 + a.val, i0 + a.val + a.test), make, log)
+    t_data = time.time() - t0
+    t0 = time.time()
+    best = {"mse": float("inf")}
+
+    def keep_best(ep, w):
+        mse = float(np.mean((predict(w, Xv) - Yv) ** 2))
+        if mse < best["mse"]:
+            best.update(mse=mse, epoch=ep, w=w.clone())
+
+    w, hist = train(X, Y, epochs=a.epochs, log=log, on_epoch=keep_best)
+    t_train = time.time() - t0
+    w = best["w"]
+    test_mse = float(np.mean((predict(w, Xt) - Yt) ** 2))
+    t0 = time.time()
+    ids = range(i0 + a.val, i0 + a.val + min(a.gain, a.test))
+    rows = gain(w, [(i, make(i)) for i in ids])
+    t_gain = time.time() - t0
+    out = {"train": a.train, "val": a.val, "test": a.test, "scale": a.scale,
+           "train_mse": hist[-1], "val_mse": best["mse"], "best_epoch": best["epoch"],
+           "test_mse": test_mse, "seconds": {"labels": t_data, "train": t_train, "gain": t_gain}}
+    for K in sorted({r["K"] for r in rows}):
+        rk = [r for r in rows if r["K"] == K]
+        out[f"K{K}"] = {m: float(np.mean([r[m] for r in rk]))
+                        for m in ("bisection", "uniform", "learned")}
+    print(json.dumps(out), flush=True)
     if a.out:
-        np.savez(a.out, weights=w.cpu().numpy())
+        np.save(a.out, w.cpu().numpy())
 
 
 if __name__ == "__main__":
