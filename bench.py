@@ -75,7 +75,7 @@ def recorded_traffic(workload: str, precision: int):
             rec = json.load(fh)
     except OSError:
         return None
-    ent = rec.get("c64" if precision == 1 else "c128")
+    ent = rec.get("c64" if precision == 1 else "c128")  # only the complex64 kernel is recorded
     if not ent or rec.get("source_sha256") != solve_source_hash():
         return None
     return ent["hbm_bytes_per_launch"]
