@@ -158,7 +158,8 @@ int filter_apply(const Band& bd, const FactorBufs<R>& f, int ne, const std::vect
             jb.ldin = ldyc[i];
             jb.mid = Xp[(size_t)i * P + p];
             jb.out = Xp[(size_t)i * P + p];
-            jb.ldmid = jb.ldout = n;
+            jb.ldout = n;
+            jb.ldmid = n * (int64_t)(sizeof(c128) / sizeof(cx<R>));
             jobs.push_back(jb);
           }
         }

@@ -262,7 +262,7 @@ int solve_refine(const Band& bd, const cx<R>* mats, const int16_t* perm,
           c.in = rj[g].r;
           c.mid = rj[g].r;
           c.ldin = bd.n;
-          c.ldmid = bd.n;
+          c.ldmid = bd.n * (int64_t)(sizeof(c128) / sizeof(cx<R>));
           c.add = 1;
           cj.push_back(c);
         }
@@ -320,7 +320,7 @@ int shifted_solve_impl(const fb_band* B, int nsys, const double* z, const int32_
         jb.mid = out;
         jb.out = out;
         jb.ldin = ldy[s];
-        jb.ldmid = ldx[s];
+        jb.ldmid = ldx[s] * (int64_t)(sizeof(c128) / sizeof(cx<R>));
         jb.ldout = ldx[s];
         jobs.push_back(jb);
       }

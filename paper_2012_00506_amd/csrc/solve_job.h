@@ -11,7 +11,9 @@ struct SolveJob {
   int32_t col0;   // first column of the tile
   int32_t ncol;   // columns in the tile (<= tile width)
   const c128* in; // right-hand sides (columns from col0)
-  c128* mid;      // forward-sweep intermediates (may alias in or out)
+  void* mid;      // forward-sweep intermediates in the factors' complex type,
+                  // ldmid in those elements; may alias in or out column by
+                  // column (same column start, ldmid = ld * 16 / element size)
   c128* out;      // solution (written, or added to when add != 0)
   int64_t ldin, ldmid, ldout;
   int32_t add;

@@ -164,6 +164,15 @@ static __device__ __forceinline__ int remap_job(int bid, int njobs) {
   return (bid % 8) * per + bid / 8;
 }
 
+// One block's initial accumulator values for a wave, raw (c128 for the
+// right-hand sides, the factors' type for the intermediates), converted when
+// first used so that the loads do not wait where they are issued.
+template <typename E, int NC>
+struct PreT {
+  E v[NC][4];
+  int k;
+};
+
 // ---------------------------------------------------------------- MFMA block solve
 // One workgroup per job with one wave per 16 x (16 NC) output tile of a block
 // product ((NB/16) x (T/(16 NC)) waves; a wave with NC > 1 reuses each factor
@@ -188,33 +197,38 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
   const cx<R>* F = mats + (size_t)jb.sys * K * 5 * bb;
   const int16_t* P = permg + (size_t)jb.sys * K * 2 * NB;
   const c128* in = jb.in + (int64_t)jb.col0 * jb.ldin;
-  c128* mid = jb.mid + (int64_t)jb.col0 * jb.ldmid;
+  cx<R>* mid = reinterpret_cast<cx<R>*>(jb.mid) + (int64_t)jb.col0 * jb.ldmid;
   c128* out = jb.out + (int64_t)jb.col0 * jb.ldout;
   const int ncol = jb.ncol;
 
-  auto emit = [&](int64_t row, int col, cx<R> v) {
-    if (row >= n || col >= ncol) return;
-    c128 x = mk((double)v.x, (double)v.y);
-    c128* o = out + (int64_t)col * jb.ldout + row;
-    if (jb.add) x = gld(o) + x;
-    gst(o, x);
+  // Global loads are branch-free (an out-of-range element reads the tile's
+  // first element and is zeroed when used), so that a group of loads issues
+  // together and waits once, where its values are first needed.
+  auto okf = [&](int64_t row, int col) { return row < n && col < ncol; };
+  auto gaddr = [&](auto base, int64_t ld, int64_t row, int col) {
+    return base + (okf(row, col) ? (int64_t)col * ld + row : 0);
   };
-  auto gload = [&](auto base, int64_t ld, int64_t row, int col) -> cx<R> {
-    if (row >= n || col >= ncol) return mk<R>(0, 0);
-    c128 v = gld(base + (int64_t)col * ld + row);
-    return mk<R>((R)v.x, (R)v.y);
+  auto conv = [&](auto v, bool ok) -> cx<R> {
+    return ok ? mk<R>((R)v.x, (R)v.y) : mk<R>(0, 0);
   };
-  // accumulator <-> global rows k NB + (wave rows)
-  auto acc_from_g = [&](Acc<R, NC>& acc, auto base, int64_t ld, int64_t row0) {
+  // x into the output (added to it for a correction), a batch at a time:
+  // all loads of the batch first, then the stores
+  auto emit_batch = [&](auto& row, auto& col, auto& v, auto& valid) {
+    constexpr int NQ = sizeof(valid) / sizeof(valid[0]);
+    c128 old[NQ];
+    if (jb.add) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+      for (int q = 0; q < NQ; ++q) old[q] = gld(gaddr(out, jb.ldout, row[q], col[q]));
+    }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        cx<R> v = gload(base, ld, row0 + 16 * w + MF<R>::row(lane, r), cb0 + 16 * c + (lane & 15));
-        acc.re[c][r] = v.x;
-        acc.im[c][r] = v.y;
-      }
+    for (int q = 0; q < NQ; ++q) {
+      if (!valid[q] || !okf(row[q], col[q])) continue;
+      c128 x = mk((double)v[q].x, (double)v[q].y);
+      if (jb.add) x = old[q] + x;
+      gst(out + (int64_t)col[q] * jb.ldout + row[q], x);
+    }
   };
+  constexpr int RE = 4 * NC;
   auto acc_to_g = [&](const Acc<R, NC>& acc, auto base, int64_t ld, int64_t row0) {
 #pragma unroll
     for (int c = 0; c < NC; ++c)
@@ -223,54 +237,110 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
         int64_t row = row0 + 16 * w + MF<R>::row(lane, r);
         int col = cb0 + 16 * c + (lane & 15);
         if (row < n && col < ncol)
-          gst(base + (int64_t)col * ld + row, mk((double)acc.re[c][r], (double)acc.im[c][r]));
+          gst(base + (int64_t)col * ld + row, mk<R>(acc.re[c][r], acc.im[c][r]));
       }
   };
   auto acc_emit = [&](const Acc<R, NC>& acc, int64_t row0) {
+    int64_t rows[RE];
+    int cols[RE];
+    cx<R> v[RE];
+    bool valid[RE];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        emit(row0 + 16 * w + MF<R>::row(lane, r), cb0 + 16 * c + (lane & 15),
-             mk<R>(acc.re[c][r], acc.im[c][r]));
+      for (int r = 0; r < 4; ++r) {
+        const int q = 4 * c + r;
+        rows[q] = row0 + 16 * w + MF<R>::row(lane, r);
+        cols[q] = cb0 + 16 * c + (lane & 15);
+        v[q] = mk<R>(acc.re[c][r], acc.im[c][r]);
+        valid[q] = true;
+      }
+    emit_batch(rows, cols, v, valid);
+  };
+  // a whole NB x T block of global rows (row0 ..) into LDS rows (dst)
+  constexpr int NTHR = NB * 4 * (T / (16 * NC));
+  constexpr int RF = NB * T / NTHR;  // elements per thread
+  struct Fill {
+    c128 v[RF];
+  };
+  auto fill_issue = [&](Fill& f, auto base, int64_t ld, int64_t row0) {
+#pragma unroll
+    for (int q = 0; q < RF; ++q) {
+      const int e = t + q * NTHR;
+      f.v[q] = gld(gaddr(base, ld, row0 + e / T, e % T));
+    }
+  };
+  auto fill_store = [&](const Fill& f, cx<R>* dst, int64_t row0) {
+#pragma unroll
+    for (int q = 0; q < RF; ++q) {
+      const int e = t + q * NTHR;
+      dst[e] = conv(f.v[q], okf(row0 + e / T, e % T));
+    }
   };
   auto load_perm = [&](int k) {
     for (int e = t; e < 2 * NB; e += nthr) sp[e] = gld(P + (size_t)k * 2 * NB + e);
+  };
+  // the permutation of block k fetched early into registers, stored later
+  constexpr int RP = (2 * NB + NTHR - 1) / NTHR;
+  struct PermPre {
+    int16_t v[RP];
+  };
+  auto perm_issue = [&](PermPre& pp, int k) {
+#pragma unroll
+    for (int q = 0; q < RP; ++q) {
+      const int e = t + q * NTHR;
+      pp.v[q] = gld(P + (size_t)k * 2 * NB + (e < 2 * NB ? e : 0));
+    }
+  };
+  auto perm_store = [&](const PermPre& pp) {
+#pragma unroll
+    for (int q = 0; q < RP; ++q) {
+      const int e = t + q * NTHR;
+      if (e < 2 * NB) sp[e] = pp.v[q];
+    }
   };
   const int lo_tri = 16 * w + 16;  // k < lo_tri: lower triangle rows of this wave
   const int up_tri = 16 * w;       // k >= up_tri: upper triangle
   auto blk = [&](int k, int slot) { return F + ((size_t)k * 5 + slot) * bb; };
   // initial accumulator values for the wave's rows of block k, prefetched
   // into registers one step ahead
-  struct Pre {
-    cx<R> v[NC][4];
-  };
-  auto pre_load = [&](Pre& p, auto base, int64_t ld, int k) {
+  auto pre_load = [&](auto& p, auto base, int64_t ld, int k) {
+    p.k = k;
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        p.v[c][r] = gload(base, ld, (int64_t)k * NB + 16 * w + MF<R>::row(lane, r),
-                          cb0 + 16 * c + (lane & 15));
+        p.v[c][r] = gld(gaddr(base, ld, (int64_t)k * NB + 16 * w + MF<R>::row(lane, r),
+                              cb0 + 16 * c + (lane & 15)));
   };
-  auto pre_to_acc = [&](Acc<R, NC>& acc, const Pre& p) {
+  auto pre_to_acc = [&](Acc<R, NC>& acc, const auto& p) {
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        acc.re[c][r] = p.v[c][r].x;
-        acc.im[c][r] = p.v[c][r].y;
+        const cx<R> v = conv(p.v[c][r], okf((int64_t)p.k * NB + 16 * w + MF<R>::row(lane, r),
+                                            cb0 + 16 * c + (lane & 15)));
+        acc.re[c][r] = v.x;
+        acc.im[c][r] = v.y;
       }
   };
   Acc<R, NC> acc;
   Frag<R, NB> fa, fb, fc;
-  Pre pv;
+  PreT<cx<R>, NC> pvm;  // intermediates (backward sweeps)
+  PreT<c128, NC> pvi;   // right-hand sides (H forward)
 
   if (jb.dir == 0) {
     // ---------------------------------------------------------- N forward
     cx<R>* W = S;                 // window, 2 NB x T
     cx<R>* Yt = S + 2 * NB * T;   // y_top, NB x T
-    for (int e = t; e < 2 * NB * T; e += nthr) W[e] = gload(in, jb.ldin, e / T, e % T);
+    {
+      Fill f0, f1;
+      fill_issue(f0, in, jb.ldin, 0);
+      fill_issue(f1, in, jb.ldin, NB);
+      fill_store(f0, W, 0);
+      fill_store(f1, W + NB * T, NB);
+    }
+    Fill fr;
     load_perm(0);
     if (PREF) frag_load<R, NB, false>(fa, blk(0, 0), w, lane, 0, lo_tri);
     __syncthreads();
@@ -282,15 +352,17 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
       acc_to_lds(acc, Yt, T, nullptr, w, cb0, lane);
       acc_to_g(acc, mid, jb.ldmid, (int64_t)k * NB);
       __syncthreads();
+      fill_issue(fr, in, jb.ldin, (int64_t)(k + 2) * NB);  // consumed after the product
+      PermPre pnext;
+      if (k + 1 < K) perm_issue(pnext, k + 1);
       if (PREF && k + 1 < K) frag_load<R, NB, false>(fa, blk(k + 1, 0), w, lane, 0, lo_tri);
       if (!PREF) frag_load<R, NB, false>(fb, blk(k, 1), w, lane, 0, NB);
       acc_from_lds(acc, W, T, sp + NB, w, cb0, lane);
       frag_mma<R, NB, NC, false, true>(acc, fb, Yt, T, nullptr, cb0, lane, 0, NB);
       __syncthreads();
       acc_to_lds(acc, W, T, nullptr, w, cb0, lane);
-      for (int e = t; e < NB * T; e += nthr)
-        W[NB * T + e] = gload(in, jb.ldin, (int64_t)(k + 2) * NB + e / T, e % T);
-      if (k + 1 < K) load_perm(k + 1);
+      fill_store(fr, W + NB * T, (int64_t)(k + 2) * NB);
+      if (k + 1 < K) perm_store(pnext);
       __syncthreads();
     }
     // ---------------------------------------------------------- N backward
@@ -300,12 +372,12 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
     for (int e = t; e < 2 * NB * T; e += nthr) S[e] = mk<R>(0, 0);
     // fa = U(k,k+1), fb = U(k,k+2), fc = U(k,k)^{-1}, pv = y_k: prefetched
     if (PREF) frag_load<R, NB, false>(fc, blk(K - 1, 2), w, lane, up_tri, NB);
-    pre_load(pv, mid, jb.ldmid, K - 1);
+    pre_load(pvm, mid, jb.ldmid, K - 1);
     __syncthreads();
     for (int k = K - 1; k >= 0; --k) {
       if (!PREF && k + 1 < K) frag_load<R, NB, false>(fa, blk(k, 3), w, lane, 0, NB);
       if (!PREF && k + 2 < K) frag_load<R, NB, false>(fb, blk(k, 4), w, lane, 0, lo_tri);
-      pre_to_acc(acc, pv);
+      pre_to_acc(acc, pvm);
       if (k + 1 < K) frag_mma<R, NB, NC, false, true>(acc, fa, X1, T, nullptr, cb0, lane, 0, NB);
       if (k + 2 < K) frag_mma<R, NB, NC, false, true>(acc, fb, X2, T, nullptr, cb0, lane, 0, lo_tri);
       acc_to_lds(acc, V, T, nullptr, w, cb0, lane);
@@ -313,7 +385,7 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
       if (k > 0) {
         if (PREF && k < K) frag_load<R, NB, false>(fa, blk(k - 1, 3), w, lane, 0, NB);
         if (PREF && k + 1 < K) frag_load<R, NB, false>(fb, blk(k - 1, 4), w, lane, 0, lo_tri);
-        pre_load(pv, mid, jb.ldmid, k - 1);
+        pre_load(pvm, mid, jb.ldmid, k - 1);
       }
       if (!PREF) frag_load<R, NB, false>(fc, blk(k, 2), w, lane, up_tri, NB);
       acc.zero();
@@ -334,12 +406,12 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
     for (int e = t; e < 2 * NB * T; e += nthr) S[e] = mk<R>(0, 0);
     // fa = U(k-1,k)^H, fb = U(k-2,k)^H, fc = U(k,k)^{-H}, pv = y_k
     if (PREF) frag_load<R, NB, true>(fc, blk(0, 2), w, lane, 0, lo_tri);
-    pre_load(pv, in, jb.ldin, 0);
+    pre_load(pvi, in, jb.ldin, 0);
     __syncthreads();
     for (int k = 0; k < K; ++k) {
       if (!PREF && k >= 1) frag_load<R, NB, true>(fa, blk(k - 1, 3), w, lane, 0, NB);
       if (!PREF && k >= 2) frag_load<R, NB, true>(fb, blk(k - 2, 4), w, lane, up_tri, NB);
-      pre_to_acc(acc, pv);
+      pre_to_acc(acc, pvi);
       if (k >= 1) frag_mma<R, NB, NC, true, true>(acc, fa, W1, T, nullptr, cb0, lane, 0, NB);
       if (k >= 2) frag_mma<R, NB, NC, true, true>(acc, fb, W2, T, nullptr, cb0, lane, up_tri, NB);
       acc_to_lds(acc, V, T, nullptr, w, cb0, lane);
@@ -347,7 +419,7 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
       if (k + 1 < K) {
         if (PREF) frag_load<R, NB, true>(fa, blk(k, 3), w, lane, 0, NB);
         if (PREF && k >= 1) frag_load<R, NB, true>(fb, blk(k - 1, 4), w, lane, up_tri, NB);
-        pre_load(pv, in, jb.ldin, k + 1);
+        pre_load(pvi, in, jb.ldin, k + 1);
       }
       if (!PREF) frag_load<R, NB, true>(fc, blk(k, 2), w, lane, 0, lo_tri);
       acc.zero();
@@ -370,17 +442,19 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
     // fa = Lh21^H, fc = (Lh11^{-1})^H, pv = w_k
     if (PREF) frag_load<R, NB, true>(fa, blk(K - 1, 1), w, lane, 0, NB);
     if (PREF) frag_load<R, NB, true>(fc, blk(K - 1, 0), w, lane, up_tri, NB);
-    pre_load(pv, mid, jb.ldmid, K - 1);
+    pre_load(pvm, mid, jb.ldmid, K - 1);
     __syncthreads();
     for (int k = K - 1; k >= 0; --k) {
       if (!PREF) frag_load<R, NB, true>(fa, blk(k, 1), w, lane, 0, NB);
-      pre_to_acc(acc, pv);
+      pre_to_acc(acc, pvm);
       frag_mma<R, NB, NC, true, true>(acc, fa, Cb, T, nullptr, cb0, lane, 0, NB);
       acc_to_lds(acc, T1, T, nullptr, w, cb0, lane);
       __syncthreads();
+      PermPre pnext;
       if (k > 0) {
         if (PREF) frag_load<R, NB, true>(fa, blk(k - 1, 1), w, lane, 0, NB);
-        pre_load(pv, mid, jb.ldmid, k - 1);
+        pre_load(pvm, mid, jb.ldmid, k - 1);
+        perm_issue(pnext, k - 1);
       }
       if (!PREF) frag_load<R, NB, true>(fc, blk(k, 0), w, lane, up_tri, NB);
       acc.zero();
@@ -388,24 +462,49 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
       if (PREF && k > 0) frag_load<R, NB, true>(fc, blk(k - 1, 0), w, lane, up_tri, NB);
       acc_to_lds(acc, Vt, T, nullptr, w, cb0, lane);
       __syncthreads();
-      // x_win = P^T [top ; carry]
-      for (int e = t; e < 2 * NB * T; e += nthr) {
-        int i = e / T, col = e % T;
-        cx<R> v = i < NB ? Vt[i * T + col] : Cb[(i - NB) * T + col];
-        int d = sp[i];
-        if (d >= NB)
-          emit((int64_t)k * NB + d, col, v);
-        else
-          Cn[d * T + col] = v;
+      // x_win = P^T [top ; carry]: rows that leave the window are emitted
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        int64_t rows[RF];
+        int cols[RF];
+        cx<R> vals[RF];
+        bool valid[RF];
+#pragma unroll
+        for (int q = 0; q < RF; ++q) {
+          const int e = t + (h * RF + q) * NTHR;
+          const int i = e / T, col = e % T;
+          const cx<R> v = i < NB ? Vt[i * T + col] : Cb[(i - NB) * T + col];
+          const int d = sp[i];
+          valid[q] = d >= NB;
+          rows[q] = (int64_t)k * NB + d;
+          cols[q] = col;
+          vals[q] = v;
+          if (d < NB) Cn[d * T + col] = v;
+        }
+        emit_batch(rows, cols, vals, valid);
       }
       __syncthreads();
       cx<R>* tmp = Cb;
       Cb = Cn;
       Cn = tmp;
-      if (k > 0) load_perm(k - 1);
+      if (k > 0) perm_store(pnext);
       __syncthreads();
     }
-    for (int e = t; e < NB * T; e += nthr) emit(e / T, e % T, Cb[e]);
+    {
+      int64_t rows[RF];
+      int cols[RF];
+      cx<R> vals[RF];
+      bool valid[RF];
+#pragma unroll
+      for (int q = 0; q < RF; ++q) {
+        const int e = t + q * NTHR;
+        valid[q] = true;
+        rows[q] = e / T;
+        cols[q] = e % T;
+        vals[q] = Cb[e];
+      }
+      emit_batch(rows, cols, vals, valid);
+    }
   }
 }
 

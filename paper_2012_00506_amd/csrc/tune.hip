@@ -97,8 +97,10 @@ int autotune_impl(const fb_band* B, int nsys, int m, const char* path, int32_t* 
           jb.ncol = std::min(tile, m - c0);
           jb.in = Y;
           jb.ldin = bd.n;
-          jb.out = jb.mid = X + ((size_t)s * 2 + dir) * bd.n * m;
-          jb.ldout = jb.ldmid = bd.n;
+          jb.out = X + ((size_t)s * 2 + dir) * bd.n * m;
+          jb.mid = jb.out;
+          jb.ldout = bd.n;
+          jb.ldmid = bd.n * (int64_t)(sizeof(c128) / sizeof(cx<R>));
           jobs.push_back(jb);
         }
     FB_HIP(hipMemcpyAsync(jobs_dev, jobs.data(), sizeof(SolveJob) * jobs.size(),
