@@ -75,30 +75,60 @@ k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* 
   const int nc = jb.ncol;
   const size_t bb = (size_t)NB * NB;
   const c128 zz = jb.dir ? mk(jb.z.x, -jb.z.y) : jb.z;
-  auto xload = [&](int k, int slot) {
-    for (int e = t; e < NB * T; e += nthr) {
-      int row = e / T, col = e % T;
-      int64_t i = (int64_t)k * NB + row;
-      X[slot * NB * T + e] =
-          (k < K && i < n && col < nc) ? gld(jx + (int64_t)(c0 + col) * jb.ldx + i) : mk(0.0, 0.0);
+  // branch-free loads (clamped address, zeroed when stored), issued one
+  // block row ahead so that their latency overlaps the products
+  constexpr int NTH = NB * 4 * (T / 16);
+  constexpr int RX = NB * T / NTH;
+  auto xok = [&](int k, int e) {
+    const int64_t i = (int64_t)k * NB + e / T;
+    return k < K && i < n && (e % T) < nc;
+  };
+  auto xaddr = [&](int k, int e) {
+    return jx + (xok(k, e) ? (int64_t)(c0 + e % T) * jb.ldx + (int64_t)k * NB + e / T : 0);
+  };
+  auto xissue = [&](c128* xr, int k) {
+#pragma unroll
+    for (int q = 0; q < RX; ++q) xr[q] = gld(xaddr(k, t + q * NTH));
+  };
+  auto xstore = [&](const c128* xr, int k, int slot) {
+#pragma unroll
+    for (int q = 0; q < RX; ++q) {
+      const int e = t + q * NTH;
+      X[slot * NB * T + e] = xok(k, e) ? xr[q] : mk(0.0, 0.0);
+    }
+  };
+  const int col = cb0 + (lane & 15);
+  auto yok = [&](int k, int r) {
+    const int64_t i = (int64_t)k * NB + 16 * w + MF<double>::row(lane, r);
+    return i < n && col < nc;
+  };
+  auto yissue = [&](c128* yr, int k) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t i = (int64_t)k * NB + 16 * w + MF<double>::row(lane, r);
+      yr[r] = gld(jy + (yok(k, r) ? (int64_t)(c0 + col) * jb.ldy + i : 0));
     }
   };
   for (int e = t; e < NB * T; e += nthr) X[2 * NB * T + e] = mk(0.0, 0.0);  // x_{-1}
-  xload(0, 0);
+  c128 xr[RX], yr[4], yn[4];
+  xissue(xr, 0);
+  xstore(xr, 0, 0);
+  xissue(xr, 1);
+  yissue(yr, 0);
   double rr = 0.0, yy = 0.0;
-  const int col = cb0 + (lane & 15);
   Acc<double, NC> acc;
   for (int k = 0; k < K; ++k) {
-    xload(k + 1, (k + 1) % 3);
+    xstore(xr, k + 1, (k + 1) % 3);
     __syncthreads();
+    if (k + 2 <= K) xissue(xr, k + 2);
+    if (k + 1 < K) yissue(yn, k + 1);
     const c128* Xk = X + (k % 3) * NB * T;
     // acc = y_k - zz x_k
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      int row = 16 * w + MF<double>::row(lane, r);
-      int64_t i = (int64_t)k * NB + row;
-      c128 yv = (i < n && col < nc) ? gld(jy + (int64_t)(c0 + col) * jb.ldy + i) : mk(0.0, 0.0);
-      c128 v = yv - zz * Xk[row * T + col];
+      const int row = 16 * w + MF<double>::row(lane, r);
+      const c128 yv = yok(k, r) ? yr[r] : mk(0.0, 0.0);
+      const c128 v = yv - zz * Xk[row * T + col];
       acc.re[0][r] = v.x;
       acc.im[0][r] = v.y;
       yy += cabs2(yv);
@@ -121,6 +151,8 @@ k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* 
         rr += cabs2(v);
       }
     }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) yr[r] = yn[r];
     __syncthreads();
   }
   // column sums: lanes l, l+16, l+32, l+48 share a column; then across row waves
