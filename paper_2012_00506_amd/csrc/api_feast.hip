@@ -164,7 +164,7 @@ int filter_apply(const Band& bd, const FactorBufs<R>& f, int ne, const std::vect
           }
         }
       }
-      FB_TRY(solve_refine<R>(bd, f.mats, f.perm, jobs, zsys, ir, ir_tol, ir_max, need_res, rb,
+      FB_TRY(solve_refine<R>(bd, f.mats, f.matsT, f.perm, jobs, zsys, ir, ir_tol, ir_max, need_res, rb,
                              sys_res, sys_pass, unconverged, st));
       for (size_t a = 0; a < act.size(); ++a) {
         if (!batched && a != g) continue;

@@ -32,6 +32,7 @@ void carve_factors(Arena& ar, const Band& bd, int nsys, FactorBufs<R>& f) {
   int K = (int)((bd.n + nb - 1) / nb);
   size_t bb = (size_t)nb * nb;
   f.mats = ar.take<cx<R>>((size_t)nsys * K * 5 * bb);
+  f.matsT = sizeof(R) == 4 ? ar.take<cx<R>>((size_t)nsys * K * 5 * bb) : nullptr;
   f.perm = ar.take<int16_t>((size_t)nsys * K * 2 * nb);
   f.info = ar.take<int32_t>(nsys);
   size_t sc = lu_window_scratch<R>(bd.b, nsys);
@@ -44,7 +45,8 @@ template <typename R>
 int factor_systems(const Band& bd, int nsys, const double* z_host, FactorBufs<R>& f,
                    hipStream_t st) {
   FB_HIP(hipMemcpyAsync(f.z, z_host, sizeof(c128) * nsys, hipMemcpyHostToDevice, st));
-  FB_TRY(launch_lu_impl<R>(bd, nsys, f.z, f.mats, f.perm, f.info, f.scratch, f.lscr, st));
+  FB_TRY(launch_lu_impl<R>(bd, nsys, f.z, f.mats, f.matsT, f.perm, f.info, f.scratch, f.lscr,
+                           st));
   std::vector<int32_t> info(nsys);
   FB_HIP(hipMemcpyAsync(info.data(), f.info, sizeof(int32_t) * nsys, hipMemcpyDeviceToHost, st));
   FB_HIP(hipStreamSynchronize(st));
@@ -171,7 +173,7 @@ size_t refine_bytes(const Band& bd, int tile, int max_jobs, bool ir, bool need_r
 // correction solves of their tiles until they pass or ir_max passes are
 // spent.  Groups are processed in waves that bound the residual buffers.
 template <typename R>
-int solve_refine(const Band& bd, const cx<R>* mats, const int16_t* perm,
+int solve_refine(const Band& bd, const cx<R>* mats, const cx<R>* matsT, const int16_t* perm,
                  const std::vector<SolveJob>& jobs, const std::vector<c128>& zsys, bool ir,
                  double ir_tol, int ir_max, bool need_res, RefineBufs& rb,
                  std::vector<double>& sys_res, std::vector<int32_t>& sys_pass, int* unconverged,
@@ -182,7 +184,7 @@ int solve_refine(const Band& bd, const cx<R>* mats, const int16_t* perm,
   FB_HIP(hipMemcpyAsync(rb.jobs_dev, jobs.data(), sizeof(SolveJob) * njobs, hipMemcpyHostToDevice, st));
   double cols = 0;
   for (const SolveJob& jb : jobs) cols += jb.ncol;
-  FB_TRY(launch_solve_jobs<R>(mats, perm, bd.n, bd.b, njobs, rb.jobs_dev,
+  FB_TRY(launch_solve_jobs<R>(mats, matsT, perm, bd.n, bd.b, njobs, rb.jobs_dev,
                               solve_flops(bd.n, bd.b, cols), st));
   if (!need_res) return 0;
   // groups [first, last] of consecutive jobs
@@ -273,18 +275,18 @@ int solve_refine(const Band& bd, const cx<R>* mats, const int16_t* perm,
                             hipMemcpyHostToDevice, st));
       double ccols = 0;
       for (const SolveJob& c : cj) ccols += c.ncol;
-      FB_TRY(launch_solve_jobs<R>(mats, perm, bd.n, bd.b, (int)cj.size(), rb.cjobs_dev,
+      FB_TRY(launch_solve_jobs<R>(mats, matsT, perm, bd.n, bd.b, (int)cj.size(), rb.cjobs_dev,
                                   solve_flops(bd.n, bd.b, ccols), st));
     }
   }
   return 0;
 }
 
-template int solve_refine<float>(const Band&, const c64*, const int16_t*,
+template int solve_refine<float>(const Band&, const c64*, const c64*, const int16_t*,
                                  const std::vector<SolveJob>&, const std::vector<c128>&, bool,
                                  double, int, bool, RefineBufs&, std::vector<double>&,
                                  std::vector<int32_t>&, int*, hipStream_t);
-template int solve_refine<double>(const Band&, const c128*, const int16_t*,
+template int solve_refine<double>(const Band&, const c128*, const c128*, const int16_t*,
                                   const std::vector<SolveJob>&, const std::vector<c128>&, bool,
                                   double, int, bool, RefineBufs&, std::vector<double>&,
                                   std::vector<int32_t>&, int*, hipStream_t);
@@ -340,7 +342,7 @@ int shifted_solve_impl(const fb_band* B, int nsys, const double* z, const int32_
   std::vector<double> sys_res(nsys, 0.0);
   std::vector<int32_t> sys_pass(nsys, 0);
   int unconverged = 0;
-  FB_TRY(solve_refine<R>(bd, f.mats, f.perm, jobs, zsys, ir, o->ir_tol, o->ir_max, need_res, rb,
+  FB_TRY(solve_refine<R>(bd, f.mats, f.matsT, f.perm, jobs, zsys, ir, o->ir_tol, o->ir_max, need_res, rb,
                          sys_res, sys_pass, &unconverged, st));
   FB_HIP(hipStreamSynchronize(st));
   if (resid)

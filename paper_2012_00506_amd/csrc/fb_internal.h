@@ -12,8 +12,10 @@
 namespace fb {
 
 // ------------------------------------------------------------------ complex
+// aligned to its full size, so that a complex element moves with one 64-bit
+// (complex64) or 128-bit (complex128) LDS access rather than two 32-bit ones
 template <typename T>
-struct cx {
+struct alignas(2 * sizeof(T)) cx {
   T x, y;
 };
 using c64 = cx<float>;

@@ -35,7 +35,7 @@ __global__ void __launch_bounds__(kInertiaThreads)
 k_band_ldlh_inertia(const c128* __restrict__ Bd, int64_t n, int b,
                     const double* __restrict__ shifts, const double* __restrict__ stats,
                     int32_t* __restrict__ counts) {
-  extern __shared__ char lds_raw[];
+  extern __shared__ __align__(16) char lds_raw[];
   const int M = b + 2;
   const int tri = M * (M + 1) / 2;
   c128* D = reinterpret_cast<c128*>(lds_raw);

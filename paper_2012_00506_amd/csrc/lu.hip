@@ -64,11 +64,50 @@ __device__ __forceinline__ cx<R> shifted_entry(PB Bd, int64_t n, int b, int64_t 
   return mk<R>((R)v.x, (R)v.y);
 }
 
+// ---- wave-wide reductions of wave 0 for the pivot search, by DPP lane moves
+// within rows of 16 lanes (xor 1, xor 2, half mirror, mirror) and reads of
+// lanes 0, 16, 32 and 48; every lane of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+  return ((uint64_t)dpp32<CTRL>((uint32_t)(v >> 32)) << 32) | dpp32<CTRL>((uint32_t)v);
+}
+__device__ __forceinline__ uint64_t rdlane64(uint64_t v, int l) {
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), l) << 32) |
+         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+}
+template <typename U, bool MAX>
+__device__ __forceinline__ U wave_reduce(U v) {
+  auto pick = [](U a, U b) { return MAX ? (a > b ? a : b) : (a < b ? a : b); };
+  if constexpr (sizeof(U) == 8) {
+    v = pick(v, dpp64<0xB1>(v));   // quad_perm [1,0,3,2]
+    v = pick(v, dpp64<0x4E>(v));   // quad_perm [2,3,0,1]
+    v = pick(v, dpp64<0x141>(v));  // row_half_mirror
+    v = pick(v, dpp64<0x140>(v));  // row_mirror
+    return pick(pick(rdlane64(v, 0), rdlane64(v, 16)), pick(rdlane64(v, 32), rdlane64(v, 48)));
+  } else {
+    v = pick(v, dpp32<0xB1>(v));
+    v = pick(v, dpp32<0x4E>(v));
+    v = pick(v, dpp32<0x141>(v));
+    v = pick(v, dpp32<0x140>(v));
+    auto rd = [&](int l) { return (U)__builtin_amdgcn_readlane((int)v, l); };
+    return pick(pick(rd(0), rd(16)), pick(rd(32), rd(48)));
+  }
+}
+// bit pattern of a non-negative float or double: ordered as the value
+__device__ __forceinline__ uint32_t ordered_bits(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ uint64_t ordered_bits(double v) {
+  return (uint64_t)__double_as_longlong(v);
+}
+
 template <typename R, bool USE_LDS>
 __global__ void __launch_bounds__(kLuThreads)
 k_band_lu(const c128* __restrict__ Bd_, int64_t n, int b, int nb, int K,
           const c128* __restrict__ zs, FactorOut<R> out, cx<R>* __restrict__ gwin) {
-  extern __shared__ char lds_raw[];
+  extern __shared__ __align__(16) char lds_raw[];
   const int MR = b + 2, MC = 2 * b + 2;
   const int s = blockIdx.x;
   const int t = threadIdx.x;
@@ -114,20 +153,34 @@ k_band_lu(const c128* __restrict__ Bd_, int64_t n, int b, int nb, int K,
   __syncthreads();
 
   // entering row of step j (row j+b+1, columns j+1 .. j+2b+1): entry
-  // e = t + q * kLuThreads of this thread, fetched one step ahead
+  // e = t + q * kLuThreads of this thread, fetched one step ahead as the raw
+  // complex128 element of B it comes from (B(i, c) at d = i - c = b - e >= 0,
+  // B(c, i) above the diagonal), with a branch-free address, so that the
+  // loads stay in flight until the row is stored a step later
   constexpr int ER = 2;  // 2b+1 <= 2 * kLuThreads for b <= 255
-  auto fetch_row = [&](cx<R>* dst, int64_t jf) {
+  auto fetch_row = [&](c128* raw, int64_t jf) {
     const int64_t inew = jf + b + 1;
 #pragma unroll
     for (int q = 0; q < ER; ++q) {
       const int e = t + q * kLuThreads;
-      cx<R> v = mk<R>(0, 0);
-      if (e <= 2 * b && inew < npad) {
-        const int64_t c = jf + 1 + e;
-        if (c < npad) v = shifted_entry<R>(Bd, n, b, inew, c, z);
-      }
-      dst[q] = v;
+      const int64_t c = jf + 1 + e;
+      const int d = b - e;
+      const bool ok = e <= 2 * b && inew < n && c < n;
+      const int64_t off = d >= 0 ? (int64_t)d * n + c : (int64_t)(-d) * n + inew;
+      raw[q] = gld(Bd + (ok ? off : 0));
     }
+  };
+  // A(i, c) = z delta_ic - B(i, c) of the entering row from its raw element
+  // (identity beyond n, zero beyond the padded order)
+  auto row_entry = [&](c128 v, int64_t jf, int q) -> cx<R> {
+    const int64_t inew = jf + b + 1;
+    const int e = t + q * kLuThreads;
+    const int64_t c = jf + 1 + e;
+    const int d = b - e;
+    if (e > 2 * b || inew >= npad || c >= npad) return mk<R>(0, 0);
+    if (inew >= n || c >= n) return mk<R>(d == 0 ? (R)1 : (R)0, (R)0);
+    if (d == 0) return mk<R>((R)(z.x - v.x), (R)z.y);  // the diagonal of B is real
+    return d > 0 ? mk<R>((R)-v.x, (R)-v.y) : mk<R>((R)-v.x, (R)v.y);
   };
 
   // update mapping: 2b columns in flight, kLuThreads / 2b row groups
@@ -140,7 +193,27 @@ k_band_lu(const c128* __restrict__ Bd_, int64_t n, int b, int nb, int K,
   int jr = 0, jcs = 0, k = 0, jj = 0;
   auto rslot = [&](int off) { int v = jr + off; return v >= MR ? v - MR : v; };
   auto cslot = [&](int off) { int v = jcs + off; return v >= MC ? v - MC : v; };
-  auto step = [&](int64_t j, const cx<R>* cur, cx<R>* nxt) {
+  auto step = [&](int64_t j, const c128* cur, c128* nxt) {
+    // Row j+b+1 enters (columns j+1 .. j+2b+1, fetched during the last step)
+    // into the physical row that row j-1 left, and column j+2b+1 (the slot
+    // column j-1 left) is zeroed in rows j .. j+b: after this step's
+    // interchange rows j+1 .. j+b are among them, and the column is out of
+    // their band.  Both slots are free since the end of the last step and
+    // neither is read before the next barrier.  Storing them first, before
+    // this step issues its own global loads and stores, means the wait for
+    // the fetched row covers only memory operations a whole step old.
+    if (j + b + 1 < npad) {
+      const int pr = phys[rslot(b + 1)];
+#pragma unroll
+      for (int q = 0; q < ER; ++q) {
+        const int e = t + q * kLuThreads;
+        if (e <= 2 * b) W[(size_t)pr * MC + cslot(1 + e)] = row_entry(cur[q], j, q);
+      }
+    }
+    {
+      const int cs = cslot(2 * b + 1);
+      for (int r = t; r <= b; r += blockDim.x) W[(size_t)phys[rslot(r)] * MC + cs] = mk<R>(0, 0);
+    }
     if (j + 1 < npad) fetch_row(nxt, j + 1);
     const int par = k & 1;
     int* idxk = idx + par * 2 * nb;
@@ -154,23 +227,25 @@ k_band_lu(const c128* __restrict__ Bd_, int64_t n, int b, int nb, int K,
 
     // ---- phase A (wave 0): pivot search, interchange, multipliers
     if (t < 64) {
-      R best = (R)-1;
+      // largest |a|^2 of the column, ties to the lowest row: per lane over its
+      // rows in increasing order, then the largest value over the wave and
+      // the lowest row holding it
+      R best = (R)0;
       int bi = 0x7fffffff;
       for (int r = t; r <= nr; r += 64) {
         cx<R> a = W[(size_t)phys[rslot(r)] * MC + jc];
         R v = cabs2(a);
-        if (v > best) {  // rows scanned in increasing order per lane
+        if (!(v >= (R)0)) v = (R)0;  // a NaN entry is never preferred
+        if (bi == 0x7fffffff || v > best) {
           best = v;
           bi = r;
         }
       }
-      for (int off = 32; off > 0; off >>= 1) {
-        R ob = __shfl_xor(best, off, 64);
-        int oi = __shfl_xor(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
+      {
+        const auto mb = wave_reduce<decltype(ordered_bits(best)), true>(ordered_bits(best));
+        const uint32_t cand =
+            (bi != 0x7fffffff && ordered_bits(best) == mb) ? (uint32_t)bi : 0x7fffffffu;
+        bi = (int)wave_reduce<uint32_t, false>(cand);
       }
       const int sj = jr, sp = rslot(bi);
       const int physj_old = phys[sj], physp_old = phys[sp];
@@ -247,27 +322,30 @@ k_band_lu(const c128* __restrict__ Bd_, int64_t n, int b, int nb, int K,
           }
         }
       }
-      // column j+2b+1 enters: zero it in rows j+1..j+b (out of their band)
-      {
-        int cs = cslot(2 * b + 1);
-        for (int r = t; r < b; r += blockDim.x) W[(size_t)phys[rslot(r + 1)] * MC + cs] = mk<R>(0, 0);
-      }
-      // row j+b+1 enters (columns j+1 .. j+2b+1), fetched during the last step
-      if (j + b + 1 < npad) {
-        int pr = phys[rslot(b + 1)];
-#pragma unroll
-        for (int q = 0; q < ER; ++q) {
-          const int e = t + q * kLuThreads;
-          if (e <= 2 * b) W[(size_t)pr * MC + cslot(1 + e)] = cur[q];
-        }
-      }
       if (jj == nb - 1) {
         // block k complete: multipliers into row order (P A_panel = Lh U),
         // its permutation; fresh tables and scratch for block k+1
-        for (size_t e = t; e < 2 * bb; e += blockDim.x) {
-          const int c = (int)(e / (2 * nb)), wr = (int)(e % (2 * nb));
-          cx<R> v = gld(scr + (size_t)c * 2 * nb + lrk[wr]);
-          gst(mats + ((size_t)k * 5 + (wr < nb ? 0 : 1)) * bb + (size_t)c * nb + (wr < nb ? wr : wr - nb), v);
+        // (batches of GB elements per thread: all loads of a batch, then
+        // its stores)
+        constexpr int GB = 8;
+        for (size_t e0 = t; e0 < 2 * bb; e0 += GB * blockDim.x) {
+          cx<R> v[GB];
+#pragma unroll
+          for (int q = 0; q < GB; ++q) {
+            const size_t e = e0 + (size_t)q * blockDim.x;
+            const size_t ec = e < 2 * bb ? e : 0;
+            const int c = (int)(ec / (2 * nb)), wr = (int)(ec % (2 * nb));
+            v[q] = gld(scr + (size_t)c * 2 * nb + lrk[wr]);
+          }
+#pragma unroll
+          for (int q = 0; q < GB; ++q) {
+            const size_t e = e0 + (size_t)q * blockDim.x;
+            if (e >= 2 * bb) continue;
+            const int c = (int)(e / (2 * nb)), wr = (int)(e % (2 * nb));
+            gst(mats + ((size_t)k * 5 + (wr < nb ? 0 : 1)) * bb + (size_t)c * nb +
+                    (wr < nb ? wr : wr - nb),
+                v[q]);
+          }
         }
         cx<R>* scr1 = lscr + (size_t)(par ^ 1) * 2 * bb;
         for (size_t e = t; e < 2 * bb; e += blockDim.x) gst(scr1 + e, mk<R>(0, 0));
@@ -286,7 +364,7 @@ k_band_lu(const c128* __restrict__ Bd_, int64_t n, int b, int nb, int K,
       ++k;
     }
   };
-  cx<R> ra[ER], rb[ER];
+  c128 ra[ER], rb[ER];
   fetch_row(ra, 0);
   for (int64_t j = 0; j < npad; j += 2) {
     step(j, ra, rb);
@@ -305,7 +383,7 @@ k_band_lu(const c128* __restrict__ Bd_, int64_t n, int b, int nb, int K,
 template <typename R, bool USE_LDS>
 __global__ void __launch_bounds__(256)
 k_block_invert(cx<R>* __restrict__ mats, int b, int nblk) {
-  extern __shared__ char lds_raw[];
+  extern __shared__ __align__(16) char lds_raw[];
   const int g = blockIdx.x;
   const int blk = g >> 1, which = g & 1;  // 0: Lh11 (slot 0), 1: U(k,k) (slot 2)
   if (blk >= nblk) return;
@@ -367,9 +445,39 @@ size_t lu_window_scratch(int b, int nsys) {
   return (size_t)nsys * (b + 2) * (2 * b + 2) * sizeof(cx<R>);
 }
 
+// Transposed copy of every nb x nb factor block (32 x 32 tiles through LDS),
+// read by the conjugate-transposed solves so that a wave's factor fragment
+// loads are contiguous along the block's rows.
 template <typename R>
-int launch_lu_impl(const Band& bd, int nsys, const c128* z_dev, cx<R>* mats, int16_t* perm,
-                   int32_t* info, cx<R>* scratch, cx<R>* lscr, hipStream_t st) {
+__global__ void __launch_bounds__(256)
+k_transpose_blocks(const cx<R>* __restrict__ src, cx<R>* __restrict__ dst, int nb) {
+  __shared__ cx<R> tile[32][33];
+  const size_t bb = (size_t)nb * nb;
+  const cx<R>* S = src + (size_t)blockIdx.x * bb;
+  cx<R>* D = dst + (size_t)blockIdx.x * bb;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int i0 = 0; i0 < nb; i0 += 32)
+    for (int j0 = 0; j0 < nb; j0 += 32) {
+      // tile of S at rows i0.., columns j0.. (element (i, j) at j * nb + i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = j0 + ty + 8 * q, i = i0 + tx;
+        if (i < nb && j < nb) tile[ty + 8 * q][tx] = gld(S + (size_t)j * nb + i);
+      }
+      __syncthreads();
+      // D(j, i) = S(i, j): D element (j, i) at i * nb + j
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + ty + 8 * q, j = j0 + tx;
+        if (i < nb && j < nb) gst(D + (size_t)i * nb + j, tile[tx][ty + 8 * q]);
+      }
+      __syncthreads();
+    }
+}
+
+template <typename R>
+int launch_lu_impl(const Band& bd, int nsys, const c128* z_dev, cx<R>* mats, cx<R>* matsT,
+                   int16_t* perm, int32_t* info, cx<R>* scratch, cx<R>* lscr, hipStream_t st) {
   const int b = bd.b;
   const int nb = block_size(b);
   const int K = (int)((bd.n + nb - 1) / nb);
@@ -400,13 +508,17 @@ int launch_lu_impl(const Band& bd, int nsys, const c128* z_dev, cx<R>* mats, int
   else
     k_block_invert<R, false><<<2 * nblk, 256, ismem, st>>>(mats, nb, nblk);
   FB_HIP(hipGetLastError());
+  if (matsT) {
+    k_transpose_blocks<R><<<5 * nblk, 256, 0, st>>>(mats, matsT, nb);
+    FB_HIP(hipGetLastError());
+  }
   return 0;
 }
 
-template int launch_lu_impl<float>(const Band&, int, const c128*, c64*, int16_t*, int32_t*, c64*,
-                                   c64*, hipStream_t);
-template int launch_lu_impl<double>(const Band&, int, const c128*, c128*, int16_t*, int32_t*,
-                                    c128*, c128*, hipStream_t);
+template int launch_lu_impl<float>(const Band&, int, const c128*, c64*, c64*, int16_t*,
+                                   int32_t*, c64*, c64*, hipStream_t);
+template int launch_lu_impl<double>(const Band&, int, const c128*, c128*, c128*, int16_t*,
+                                    int32_t*, c128*, c128*, hipStream_t);
 template size_t lu_window_scratch<float>(int, int);
 template size_t lu_window_scratch<double>(int, int);
 

@@ -16,10 +16,10 @@
 
 namespace fb {
 // the kernels live in solve_f32.hip / solve_f64.hip
-extern template int launch_variant<float>(int, const c64*, const int16_t*, int64_t, int, int,
-                                          const SolveJob*, hipStream_t);
-extern template int launch_variant<double>(int, const c128*, const int16_t*, int64_t, int, int,
-                                           const SolveJob*, hipStream_t);
+extern template int launch_variant<float>(int, const c64*, const c64*, const int16_t*, int64_t,
+                                          int, int, const SolveJob*, hipStream_t);
+extern template int launch_variant<double>(int, const c128*, const c128*, const int16_t*, int64_t,
+                                           int, int, const SolveJob*, hipStream_t);
 }  // namespace fb
 
 namespace fb {
@@ -31,18 +31,20 @@ int solve_tile(int b) {
 }
 
 template <typename R>
-int launch_solve_jobs(const cx<R>* mats, const int16_t* perm, int64_t n, int b, int njobs,
-                      const SolveJob* jobs_dev, double work, hipStream_t st) {
+int launch_solve_jobs(const cx<R>* mats, const cx<R>* matsT, const int16_t* perm, int64_t n,
+                      int b, int njobs, const SolveJob* jobs_dev, double work, hipStream_t st) {
   if (njobs <= 0) return 0;
+  if (sizeof(R) == 4 && matsT == nullptr) return FB_ERR_INTERNAL;
   ProfScope ps(FB_PROF_SOLVE, st, work);
   const int nb = block_size(b);
-  return launch_variant<R>(tuned_variant(sizeof(R), nb), mats, perm, n, nb, njobs, jobs_dev, st);
+  return launch_variant<R>(tuned_variant(sizeof(R), nb), mats, matsT, perm, n, nb, njobs,
+                           jobs_dev, st);
 }
 
-template int launch_solve_jobs<float>(const c64*, const int16_t*, int64_t, int, int,
+template int launch_solve_jobs<float>(const c64*, const c64*, const int16_t*, int64_t, int, int,
                                       const SolveJob*, double, hipStream_t);
-template int launch_solve_jobs<double>(const c128*, const int16_t*, int64_t, int, int,
-                                       const SolveJob*, double, hipStream_t);
+template int launch_solve_jobs<double>(const c128*, const c128*, const int16_t*, int64_t, int,
+                                       int, const SolveJob*, double, hipStream_t);
 template int solve_tile<float>(int);
 template int solve_tile<double>(int);
 
@@ -57,7 +59,7 @@ __global__ void __launch_bounds__(NB * 4 * (T / 16))
 k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* __restrict__ jobs,
                  int njobs, double* __restrict__ part) {
   constexpr int NC = 1, NRW = NB / 16, NW = NRW * (T / 16);
-  extern __shared__ char lds_raw[];
+  extern __shared__ __align__(16) char lds_raw[];
   c128* X = reinterpret_cast<c128*>(lds_raw);              // 3 slots of NB x T
   double* red = reinterpret_cast<double*>(X + 3 * NB * T);  // 2 x NW x 16
   const int job = remap_job(blockIdx.x, njobs);

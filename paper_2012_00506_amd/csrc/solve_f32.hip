@@ -2,6 +2,6 @@
 #include "solve_kernel.h"
 
 namespace fb {
-template int launch_variant<float>(int, const c64*, const int16_t*, int64_t, int, int,
-                                   const SolveJob*, hipStream_t);
+template int launch_variant<float>(int, const c64*, const c64*, const int16_t*, int64_t, int,
+                                   int, const SolveJob*, hipStream_t);
 }  // namespace fb

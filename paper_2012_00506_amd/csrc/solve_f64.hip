@@ -2,6 +2,6 @@
 #include "solve_kernel.h"
 
 namespace fb {
-template int launch_variant<double>(int, const c128*, const int16_t*, int64_t, int, int,
-                                    const SolveJob*, hipStream_t);
+template int launch_variant<double>(int, const c128*, const c128*, const int16_t*, int64_t, int,
+                                    int, const SolveJob*, hipStream_t);
 }  // namespace fb

@@ -33,12 +33,14 @@ struct ResJob {
 // Block size of the factor blocks: the band rounded up to the 16-row MFMA tile.
 inline int block_size(int b) { return (b + 15) / 16 * 16; }
 
+// mats: the factor blocks; matsT: their transposed copy, read by the
+// conjugate-transposed solves (required for complex64, null for complex128)
 template <typename R>
-int launch_solve_jobs(const cx<R>* mats, const int16_t* perm, int64_t n, int b, int njobs,
-                      const SolveJob* jobs_dev, double work, hipStream_t st);
+int launch_solve_jobs(const cx<R>* mats, const cx<R>* matsT, const int16_t* perm, int64_t n,
+                      int b, int njobs, const SolveJob* jobs_dev, double work, hipStream_t st);
 template <typename R>
-int launch_lu_impl(const Band& bd, int nsys, const c128* z_dev, cx<R>* mats, int16_t* perm,
-                   int32_t* info, cx<R>* scratch, cx<R>* lscr, hipStream_t st);
+int launch_lu_impl(const Band& bd, int nsys, const c128* z_dev, cx<R>* mats, cx<R>* matsT,
+                   int16_t* perm, int32_t* info, cx<R>* scratch, cx<R>* lscr, hipStream_t st);
 template <typename R>
 size_t lu_window_scratch(int b, int nsys);
 
@@ -61,6 +63,7 @@ inline double resid_flops(int64_t n, int b, double cols) {
 template <typename R>
 struct FactorBufs {
   cx<R>* mats = nullptr;
+  cx<R>* matsT = nullptr;  // complex64: every block transposed (H solves)
   int16_t* perm = nullptr;
   int32_t* info = nullptr;
   cx<R>* scratch = nullptr;
@@ -91,7 +94,7 @@ void carve_refine(Arena& ar, const Band& bd, int tile, int max_jobs, bool ir, bo
                   RefineBufs& rb);
 size_t refine_bytes(const Band& bd, int tile, int max_jobs, bool ir, bool need_res);
 template <typename R>
-int solve_refine(const Band& bd, const cx<R>* mats, const int16_t* perm,
+int solve_refine(const Band& bd, const cx<R>* mats, const cx<R>* matsT, const int16_t* perm,
                  const std::vector<SolveJob>& jobs, const std::vector<c128>& zsys, bool ir,
                  double ir_tol, int ir_max, bool need_res, RefineBufs& rb,
                  std::vector<double>& sys_res, std::vector<int32_t>& sys_pass, int* unconverged,

@@ -4,6 +4,7 @@
 #include "fb_internal.h"
 #include "prof.h"
 #include "solve_job.h"
+#include "tune.h"
 
 namespace fb {
 
@@ -60,8 +61,9 @@ struct Frag {
 // k ranges [k0, k1) are multiples of 16 and the same for the whole wave
 // (readfirstlane makes that visible to the compiler, so that the range test
 // is one scalar branch per 16-row chunk and a chunk's LDS reads issue
-// together).
-template <typename R, int NB, bool CONJT, typename PA>
+// together).  TS: A points at the transposed copy of the block (CONJT only),
+// so that the 16 lanes of a fragment row read consecutive elements.
+template <typename R, int NB, bool CONJT, typename PA, bool TS = false>
 __device__ __forceinline__ void frag_load(Frag<R, NB>& f, PA A, int w, int lane, int k0, int k1) {
   const int i = 16 * w + (lane & 15), kq = lane >> 4;
   const int c0 = __builtin_amdgcn_readfirstlane(k0) >> 4;
@@ -72,7 +74,7 @@ __device__ __forceinline__ void frag_load(Frag<R, NB>& f, PA A, int w, int lane,
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int k = 16 * ch + 4 * q + kq;
-      f.a[4 * ch + q] = CONJT ? A[(size_t)i * NB + k] : A[(size_t)k * NB + i];
+      f.a[4 * ch + q] = (CONJT && !TS) ? A[(size_t)i * NB + k] : A[(size_t)k * NB + i];
     }
   }
 }
@@ -176,13 +178,16 @@ struct PreT {
 // ---------------------------------------------------------------- MFMA block solve
 // One workgroup per job with one wave per 16 x (16 NC) output tile of a block
 // product ((NB/16) x (T/(16 NC)) waves; a wave with NC > 1 reuses each factor
-// fragment for NC column tiles); LDS holds 4 NB x T blocks.
+// fragment for NC column tiles); LDS holds 3 NB x T blocks.
 template <typename R, int NB, int T, bool PREF, int NC>
 __global__ void __launch_bounds__(NB * 4 * (T / (16 * NC)))
-k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, int64_t n,
-             int K, const SolveJob* __restrict__ jobs, int njobs) {
+k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
+             const int16_t* __restrict__ permg, int64_t n, int K,
+             const SolveJob* __restrict__ jobs, int njobs) {
+  // complex64 H solves read the transposed copy of the factor blocks
+  constexpr bool TS = sizeof(R) == 4;
   constexpr int NRW = NB / 16;
-  extern __shared__ char lds_raw[];
+  extern __shared__ __align__(16) char lds_raw[];
   int* sp = reinterpret_cast<int*>(lds_raw);                        // 2 NB perm entries
   cx<R>* S = reinterpret_cast<cx<R>*>(lds_raw + ((2 * NB * sizeof(int) + 15) & ~15));
   const int job = remap_job(blockIdx.x, njobs);
@@ -302,6 +307,8 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
   const int lo_tri = 16 * w + 16;  // k < lo_tri: lower triangle rows of this wave
   const int up_tri = 16 * w;       // k >= up_tri: upper triangle
   auto blk = [&](int k, int slot) { return F + ((size_t)k * 5 + slot) * bb; };
+  const cx<R>* FT = TS ? matsT + (size_t)jb.sys * K * 5 * bb : F;
+  auto blkh = [&](int k, int slot) { return FT + ((size_t)k * 5 + slot) * bb; };
   // initial accumulator values for the wave's rows of block k, prefetched
   // into registers one step ahead
   auto pre_load = [&](auto& p, auto base, int64_t ld, int k) {
@@ -405,26 +412,26 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
     cx<R>* V = S + 2 * NB * T;
     for (int e = t; e < 2 * NB * T; e += nthr) S[e] = mk<R>(0, 0);
     // fa = U(k-1,k)^H, fb = U(k-2,k)^H, fc = U(k,k)^{-H}, pv = y_k
-    if (PREF) frag_load<R, NB, true>(fc, blk(0, 2), w, lane, 0, lo_tri);
+    if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(0, 2), w, lane, 0, lo_tri);
     pre_load(pvi, in, jb.ldin, 0);
     __syncthreads();
     for (int k = 0; k < K; ++k) {
-      if (!PREF && k >= 1) frag_load<R, NB, true>(fa, blk(k - 1, 3), w, lane, 0, NB);
-      if (!PREF && k >= 2) frag_load<R, NB, true>(fb, blk(k - 2, 4), w, lane, up_tri, NB);
+      if (!PREF && k >= 1) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k - 1, 3), w, lane, 0, NB);
+      if (!PREF && k >= 2) frag_load<R, NB, true, const cx<R>*, TS>(fb, blkh(k - 2, 4), w, lane, up_tri, NB);
       pre_to_acc(acc, pvi);
       if (k >= 1) frag_mma<R, NB, NC, true, true>(acc, fa, W1, T, nullptr, cb0, lane, 0, NB);
       if (k >= 2) frag_mma<R, NB, NC, true, true>(acc, fb, W2, T, nullptr, cb0, lane, up_tri, NB);
       acc_to_lds(acc, V, T, nullptr, w, cb0, lane);
       __syncthreads();
       if (k + 1 < K) {
-        if (PREF) frag_load<R, NB, true>(fa, blk(k, 3), w, lane, 0, NB);
-        if (PREF && k >= 1) frag_load<R, NB, true>(fb, blk(k - 1, 4), w, lane, up_tri, NB);
+        if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k, 3), w, lane, 0, NB);
+        if (PREF && k >= 1) frag_load<R, NB, true, const cx<R>*, TS>(fb, blkh(k - 1, 4), w, lane, up_tri, NB);
         pre_load(pvi, in, jb.ldin, k + 1);
       }
-      if (!PREF) frag_load<R, NB, true>(fc, blk(k, 2), w, lane, 0, lo_tri);
+      if (!PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(k, 2), w, lane, 0, lo_tri);
       acc.zero();
       frag_mma<R, NB, NC, true, false>(acc, fc, V, T, nullptr, cb0, lane, 0, lo_tri);
-      if (PREF && k + 1 < K) frag_load<R, NB, true>(fc, blk(k + 1, 2), w, lane, 0, lo_tri);
+      if (PREF && k + 1 < K) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(k + 1, 2), w, lane, 0, lo_tri);
       acc_to_g(acc, mid, jb.ldmid, (int64_t)k * NB);
       acc_to_lds(acc, W2, T, nullptr, w, cb0, lane);
       __syncthreads();
@@ -433,36 +440,40 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
       W2 = tmp;
     }
     // ---------------------------------------------------------- H backward (L^H)
+    // Three rotating blocks: the carry (window bottom), the L^H step's
+    // intermediate and the window top.  The intermediate block is dead once
+    // the window top is formed, so it receives the next carry, and the two
+    // exchange roles for the next step.
     cx<R>* Vt = S;               // top of the window after the L^H step
-    cx<R>* T1 = S + NB * T;
+    cx<R>* T1 = S + NB * T;      // intermediate, then the next carry
     cx<R>* Cb = S + 2 * NB * T;  // carry: window bottom
-    cx<R>* Cn = S + 3 * NB * T;  // next carry
     for (int e = t; e < NB * T; e += nthr) Cb[e] = mk<R>(0, 0);
     load_perm(K - 1);
     // fa = Lh21^H, fc = (Lh11^{-1})^H, pv = w_k
-    if (PREF) frag_load<R, NB, true>(fa, blk(K - 1, 1), w, lane, 0, NB);
-    if (PREF) frag_load<R, NB, true>(fc, blk(K - 1, 0), w, lane, up_tri, NB);
+    if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(K - 1, 1), w, lane, 0, NB);
+    if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(K - 1, 0), w, lane, up_tri, NB);
     pre_load(pvm, mid, jb.ldmid, K - 1);
     __syncthreads();
     for (int k = K - 1; k >= 0; --k) {
-      if (!PREF) frag_load<R, NB, true>(fa, blk(k, 1), w, lane, 0, NB);
+      if (!PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k, 1), w, lane, 0, NB);
       pre_to_acc(acc, pvm);
       frag_mma<R, NB, NC, true, true>(acc, fa, Cb, T, nullptr, cb0, lane, 0, NB);
       acc_to_lds(acc, T1, T, nullptr, w, cb0, lane);
       __syncthreads();
       PermPre pnext;
       if (k > 0) {
-        if (PREF) frag_load<R, NB, true>(fa, blk(k - 1, 1), w, lane, 0, NB);
+        if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k - 1, 1), w, lane, 0, NB);
         pre_load(pvm, mid, jb.ldmid, k - 1);
         perm_issue(pnext, k - 1);
       }
-      if (!PREF) frag_load<R, NB, true>(fc, blk(k, 0), w, lane, up_tri, NB);
+      if (!PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(k, 0), w, lane, up_tri, NB);
       acc.zero();
       frag_mma<R, NB, NC, true, false>(acc, fc, T1, T, nullptr, cb0, lane, up_tri, NB);
-      if (PREF && k > 0) frag_load<R, NB, true>(fc, blk(k - 1, 0), w, lane, up_tri, NB);
+      if (PREF && k > 0) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(k - 1, 0), w, lane, up_tri, NB);
       acc_to_lds(acc, Vt, T, nullptr, w, cb0, lane);
       __syncthreads();
-      // x_win = P^T [top ; carry]: rows that leave the window are emitted
+      // x_win = P^T [top ; carry]: rows that leave the window are emitted,
+      // the others form the next carry in T1
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         int64_t rows[RF];
@@ -479,14 +490,14 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
           rows[q] = (int64_t)k * NB + d;
           cols[q] = col;
           vals[q] = v;
-          if (d < NB) Cn[d * T + col] = v;
+          if (d < NB) T1[d * T + col] = v;
         }
         emit_batch(rows, cols, vals, valid);
       }
       __syncthreads();
       cx<R>* tmp = Cb;
-      Cb = Cn;
-      Cn = tmp;
+      Cb = T1;
+      T1 = tmp;
       if (k > 0) perm_store(pnext);
       __syncthreads();
     }
@@ -510,10 +521,10 @@ k_band_solve(const cx<R>* __restrict__ mats, const int16_t* __restrict__ permg, 
 
 
 template <typename R, int NB, int T, bool PREF, int NC>
-int launch_nb(const cx<R>* mats, const int16_t* perm, int64_t n, int njobs,
+int launch_nb(const cx<R>* mats, const cx<R>* matsT, const int16_t* perm, int64_t n, int njobs,
               const SolveJob* jobs_dev, hipStream_t st) {
   const int K = (int)((n + NB - 1) / NB);
-  size_t smem = ((2 * NB * sizeof(int) + 15) & ~(size_t)15) + (size_t)4 * NB * T * sizeof(cx<R>);
+  size_t smem = solve_lds_bytes(NB, T, sizeof(cx<R>));
   (void)hipFuncSetAttribute((const void*)k_band_solve<R, NB, T, PREF, NC>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   (void)hipGetLastError();
@@ -521,39 +532,39 @@ int launch_nb(const cx<R>* mats, const int16_t* perm, int64_t n, int njobs,
     int nj = njobs - j0 < (1 << 20) ? njobs - j0 : (1 << 20);
     int grid = 8 * ((nj + 7) / 8);
     k_band_solve<R, NB, T, PREF, NC><<<grid, NB * 4 * (T / (16 * NC)), smem, st>>>(
-        mats, perm, n, K, jobs_dev + j0, nj);
+        mats, matsT, perm, n, K, jobs_dev + j0, nj);
     FB_HIP(hipGetLastError());
   }
   return 0;
 }
 
 template <typename R, int T, bool PREF, int NC>
-int launch_t(const cx<R>* mats, const int16_t* perm, int64_t n, int nb, int njobs,
-             const SolveJob* jobs_dev, hipStream_t st) {
+int launch_t(const cx<R>* mats, const cx<R>* matsT, const int16_t* perm, int64_t n, int nb,
+             int njobs, const SolveJob* jobs_dev, hipStream_t st) {
   switch (nb) {
-    case 16: return launch_nb<R, 16, T, PREF, NC>(mats, perm, n, njobs, jobs_dev, st);
-    case 32: return launch_nb<R, 32, T, PREF, NC>(mats, perm, n, njobs, jobs_dev, st);
-    case 48: return launch_nb<R, 48, T, PREF, NC>(mats, perm, n, njobs, jobs_dev, st);
-    case 64: return launch_nb<R, 64, T, PREF, NC>(mats, perm, n, njobs, jobs_dev, st);
-    case 80: return launch_nb<R, 80, T, PREF, NC>(mats, perm, n, njobs, jobs_dev, st);
-    case 96: return launch_nb<R, 96, T, PREF, NC>(mats, perm, n, njobs, jobs_dev, st);
-    case 112: return launch_nb<R, 112, T, PREF, NC>(mats, perm, n, njobs, jobs_dev, st);
-    case 128: return launch_nb<R, 128, T, PREF, NC>(mats, perm, n, njobs, jobs_dev, st);
+    case 16: return launch_nb<R, 16, T, PREF, NC>(mats, matsT, perm, n, njobs, jobs_dev, st);
+    case 32: return launch_nb<R, 32, T, PREF, NC>(mats, matsT, perm, n, njobs, jobs_dev, st);
+    case 48: return launch_nb<R, 48, T, PREF, NC>(mats, matsT, perm, n, njobs, jobs_dev, st);
+    case 64: return launch_nb<R, 64, T, PREF, NC>(mats, matsT, perm, n, njobs, jobs_dev, st);
+    case 80: return launch_nb<R, 80, T, PREF, NC>(mats, matsT, perm, n, njobs, jobs_dev, st);
+    case 96: return launch_nb<R, 96, T, PREF, NC>(mats, matsT, perm, n, njobs, jobs_dev, st);
+    case 112: return launch_nb<R, 112, T, PREF, NC>(mats, matsT, perm, n, njobs, jobs_dev, st);
+    case 128: return launch_nb<R, 128, T, PREF, NC>(mats, matsT, perm, n, njobs, jobs_dev, st);
     default: return FB_ERR_INTERNAL;
   }
 }
 
 // every (tile width, prefetch, tiles per wave) variant of one precision
 template <typename R>
-int launch_variant(int variant, const cx<R>* mats, const int16_t* perm, int64_t n, int nb,
-                   int njobs, const SolveJob* jobs_dev, hipStream_t st) {
+int launch_variant(int variant, const cx<R>* mats, const cx<R>* matsT, const int16_t* perm,
+                   int64_t n, int nb, int njobs, const SolveJob* jobs_dev, hipStream_t st) {
   switch (variant) {
-    case 0: return launch_t<R, 16, false, 1>(mats, perm, n, nb, njobs, jobs_dev, st);
-    case 1: return launch_t<R, 16, true, 1>(mats, perm, n, nb, njobs, jobs_dev, st);
-    case 2: return launch_t<R, 32, false, 1>(mats, perm, n, nb, njobs, jobs_dev, st);
-    case 3: return launch_t<R, 32, true, 1>(mats, perm, n, nb, njobs, jobs_dev, st);
-    case 4: return launch_t<R, 32, false, 2>(mats, perm, n, nb, njobs, jobs_dev, st);
-    case 5: return launch_t<R, 32, true, 2>(mats, perm, n, nb, njobs, jobs_dev, st);
+    case 0: return launch_t<R, 16, false, 1>(mats, matsT, perm, n, nb, njobs, jobs_dev, st);
+    case 1: return launch_t<R, 16, true, 1>(mats, matsT, perm, n, nb, njobs, jobs_dev, st);
+    case 2: return launch_t<R, 32, false, 1>(mats, matsT, perm, n, nb, njobs, jobs_dev, st);
+    case 3: return launch_t<R, 32, true, 1>(mats, matsT, perm, n, nb, njobs, jobs_dev, st);
+    case 4: return launch_t<R, 32, false, 2>(mats, matsT, perm, n, nb, njobs, jobs_dev, st);
+    case 5: return launch_t<R, 32, true, 2>(mats, matsT, perm, n, nb, njobs, jobs_dev, st);
     default: return FB_ERR_INTERNAL;
   }
 }

@@ -11,6 +11,11 @@ constexpr int kNumVariants = 6;
 inline int variant_tile(int v) { return v >= 2 ? 32 : 16; }
 inline bool variant_prefetch(int v) { return (v & 1) != 0; }
 inline int variant_nc(int v) { return v >= 4 ? 2 : 1; }
+// dynamic LDS of the block-solve kernel: 2 NB permutation entries and three
+// NB x T blocks of the factors' element type
+inline size_t solve_lds_bytes(int nb, int t, size_t elem) {
+  return ((2 * (size_t)nb * sizeof(int) + 15) & ~(size_t)15) + (size_t)3 * nb * t * elem;
+}
 bool variant_fits(size_t rsize, int nb, int v);
 int tuned_variant(size_t rsize, int nb);
 void set_tuned_variant(size_t rsize, int nb, int v);

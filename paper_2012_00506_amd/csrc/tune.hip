@@ -27,8 +27,7 @@ std::map<std::pair<int, int>, int>& table() {
 bool variant_fits(size_t rsize, int nb, int v) {
   // a refinement residual group (residual_cols(nb) columns) must cover a tile
   if (variant_tile(v) > residual_cols(nb)) return false;
-  size_t lds = ((2 * (size_t)nb * sizeof(int) + 15) & ~(size_t)15) +
-               (size_t)4 * nb * variant_tile(v) * 2 * rsize;
+  const size_t lds = solve_lds_bytes(nb, variant_tile(v), 2 * rsize);
   return lds <= 160 * 1024;
 }
 
@@ -106,10 +105,10 @@ int autotune_impl(const fb_band* B, int nsys, int m, const char* path, int32_t* 
     FB_HIP(hipMemcpyAsync(jobs_dev, jobs.data(), sizeof(SolveJob) * jobs.size(),
                           hipMemcpyHostToDevice, st));
     set_tuned_variant(sizeof(R), nb, v);
-    FB_TRY(launch_solve_jobs<R>(f.mats, f.perm, bd.n, bd.b, (int)jobs.size(), jobs_dev, 0.0, st));
+    FB_TRY(launch_solve_jobs<R>(f.mats, f.matsT, f.perm, bd.n, bd.b, (int)jobs.size(), jobs_dev, 0.0, st));
     FB_HIP(hipEventRecord(e0, st));
     for (int rep = 0; rep < 2; ++rep)
-      FB_TRY(launch_solve_jobs<R>(f.mats, f.perm, bd.n, bd.b, (int)jobs.size(), jobs_dev, 0.0,
+      FB_TRY(launch_solve_jobs<R>(f.mats, f.matsT, f.perm, bd.n, bd.b, (int)jobs.size(), jobs_dev, 0.0,
                                   st));
     FB_HIP(hipEventRecord(e1, st));
     FB_HIP(hipEventSynchronize(e1));

@@ -175,7 +175,7 @@ def test_every_solve_variant_parity(fb, precision, tmp_path):
     rsize = 4 if precision == 1 else 8
     tol_x, tol_r = (1e-9, 1e-12) if precision else (1e-11, 1e-13)
     for v in range(6):
-        lds = ((2 * nb * 4 + 15) // 16) * 16 + 4 * nb * (32 if v >= 2 else 16) * 2 * rsize
+        lds = ((2 * nb * 4 + 15) // 16) * 16 + 3 * nb * (32 if v >= 2 else 16) * 2 * rsize
         if lds > 160 * 1024 or (nb > 64 and v >= 2):
             continue
         path = tmp_path / f"tune{v}.json"
