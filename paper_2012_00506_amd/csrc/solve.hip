@@ -55,33 +55,6 @@ template int solve_tile<double>(int);
 // by NB x T product on f64 MFMA (three real products per complex one), one
 // wave per 16 x 16 output tile.  x blocks roll through three LDS slots.  Per
 // (job, column): sum |r|^2 and sum |y|^2.
-// p1 += Ar Br, p2 += Ai Bi, p3 += (Ar + Ai)(Br + Bi) over k in [k0, k1), so
-// that A B = (p1 - p2) + i (p3 - p1 - p2): three real products per complex
-// one (Gauss), with B from LDS as in frag_mma
-template <int NB>
-__device__ __forceinline__ void frag_mma_gauss(mf_d4& p1, mf_d4& p2, mf_d4& p3,
-                                               const Frag<double, NB>& f, const c128* Bl, int ldb,
-                                               int cb0, int lane, int k0, int k1) {
-  const int kq = lane >> 4;
-  const int j = lane & 15;
-  const int c0 = __builtin_amdgcn_readfirstlane(k0) >> 4;
-  const int c1 = __builtin_amdgcn_readfirstlane(k1) >> 4;
-#pragma unroll
-  for (int ch = 0; ch < NB / 16; ++ch) {
-    if (ch < c0 || ch >= c1) continue;
-    c128 bv[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) bv[q] = Bl[(size_t)(16 * ch + 4 * q + kq) * ldb + cb0 + j];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const c128 a = f.a[4 * ch + q];
-      p1 = MF<double>::mma(a.x, bv[q].x, p1);
-      p2 = MF<double>::mma(a.y, bv[q].y, p2);
-      p3 = MF<double>::mma(a.x + a.y, bv[q].x + bv[q].y, p3);
-    }
-  }
-}
-
 template <int NB, int T>
 __global__ void __launch_bounds__(NB * 4 * (T / 16))
 k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* __restrict__ jobs,
@@ -153,22 +126,16 @@ k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* 
     if (k + 1 < K) yissue(yn, k + 1);
     const c128* Xk = X + (k % 3) * NB * T;
     // (B x)_k by the three block products, then r = y - zz x + B x
-    mf_d4 p1, p2, p3;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) p1[r] = p2[r] = p3[r] = 0.0;
+    Acc<double, 1> acc;
+    acc.zero();
     const c128* Bk = Bg + (size_t)k * 3 * bb;
-    Frag<double, NB> f;
-    if (k > 0) {
-      frag_load<double, NB, false>(f, Bk, w, lane, 16 * w, NB);
-      frag_mma_gauss<NB>(p1, p2, p3, f, X + ((k + 2) % 3) * NB * T, T, cb0, lane, 16 * w, NB);
-    }
-    frag_load<double, NB, false>(f, Bk + bb, w, lane, 0, NB);
-    frag_mma_gauss<NB>(p1, p2, p3, f, Xk, T, cb0, lane, 0, NB);
-    if (k + 1 < K) {
-      frag_load<double, NB, false>(f, Bk + 2 * bb, w, lane, 0, 16 * w + 16);
-      frag_mma_gauss<NB>(p1, p2, p3, f, X + ((k + 1) % 3) * NB * T, T, cb0, lane, 0,
-                         16 * w + 16);
-    }
+    if (k > 0)
+      wave_prod<double, NB, 1, false, false>(acc, Bk, X + ((k + 2) % 3) * NB * T, T, nullptr, w,
+                                             cb0, lane, 16 * w, NB);
+    wave_prod<double, NB, 1, false, false>(acc, Bk + bb, Xk, T, nullptr, w, cb0, lane, 0, NB);
+    if (k + 1 < K)
+      wave_prod<double, NB, 1, false, false>(acc, Bk + 2 * bb, X + ((k + 1) % 3) * NB * T, T,
+                                             nullptr, w, cb0, lane, 0, 16 * w + 16);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * w + MF<double>::row(lane, r);
@@ -176,8 +143,7 @@ k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* 
       const c128 yv = yok(k, r) ? yr[r] : mk(0.0, 0.0);
       yy += cabs2(yv);
       if (i < n && col < nc) {
-        const c128 bx = mk(p1[r] - p2[r], p3[r] - p1[r] - p2[r]);
-        const c128 v = yv - zz * Xk[row * T + col] + bx;
+        const c128 v = yv - zz * Xk[row * T + col] + acc.get(0, r);
         gst(jr + (int64_t)(c0 + col) * jb.ldr + i, v);
         rr += cabs2(v);
       }

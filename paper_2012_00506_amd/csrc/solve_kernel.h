@@ -10,8 +10,8 @@ namespace fb {
 
 // ---------------------------------------------------------------- MFMA helpers
 // One wave computes a 16-row block of a complex product C (16 x T) +=
-// A (16 x K rows of an NB x NB block) * B (K x T, in LDS), as real
-// 16x16x4 MFMAs: Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br.  Lane l feeds
+// A (16 x K rows of an NB x NB block) * B (K x T, in LDS), as three real
+// 16x16x4 MFMAs per complex one (Gauss form, see Acc).  Lane l feeds
 // A[l % 16][k + l / 16] and B[k + l / 16][l % 16].  Register r of lane l
 // holds C[row][l % 16] with row = 4 (l / 16) + r for the f32 instruction and
 // row = l / 16 + 4 r for the f64 one (both checked on gfx950).
@@ -37,17 +37,29 @@ struct MF<double> {
   }
 };
 
+// Complex accumulator of NC 16 x 16 tiles in Gauss form: the value is
+// (p1 - p2) + i (p3 - p1 - p2), so that a complex product takes three real
+// MFMA products (p1 += Ar Br, p2 += Ai Bi, p3 += (Ar + Ai)(Br + Bi)).
 template <typename R, int NC>
 struct Acc {
-  typename MF<R>::V re[NC], im[NC];
+  typename MF<R>::V p1[NC], p2[NC], p3[NC];
   __device__ __forceinline__ void zero() {
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        re[c][r] = (R)0;
-        im[c][r] = (R)0;
+        p1[c][r] = (R)0;
+        p2[c][r] = (R)0;
+        p3[c][r] = (R)0;
       }
+  }
+  __device__ __forceinline__ cx<R> get(int c, int r) const {
+    return mk<R>(p1[c][r] - p2[c][r], p3[c][r] - p1[c][r] - p2[c][r]);
+  }
+  __device__ __forceinline__ void set(int c, int r, cx<R> v) {
+    p1[c][r] = v.x;
+    p2[c][r] = (R)0;
+    p3[c][r] = v.x + v.y;
   }
 };
 
@@ -110,13 +122,12 @@ __device__ __forceinline__ void frag_mma(Acc<R, NC>& acc, const Frag<R, NB>& f, 
         ar = -ar;
         ai = -ai;
       }
-      const R nai = -ai;
+      const R as = ar + ai;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        acc.re[c] = MF<R>::mma(ar, bv[q][c].x, acc.re[c]);
-        acc.re[c] = MF<R>::mma(nai, bv[q][c].y, acc.re[c]);
-        acc.im[c] = MF<R>::mma(ar, bv[q][c].y, acc.im[c]);
-        acc.im[c] = MF<R>::mma(ai, bv[q][c].x, acc.im[c]);
+        acc.p1[c] = MF<R>::mma(ar, bv[q][c].x, acc.p1[c]);
+        acc.p2[c] = MF<R>::mma(ai, bv[q][c].y, acc.p2[c]);
+        acc.p3[c] = MF<R>::mma(as, bv[q][c].x + bv[q][c].y, acc.p3[c]);
       }
     }
   }
@@ -141,7 +152,7 @@ __device__ __forceinline__ void acc_to_lds(const Acc<R, NC>& acc, cx<R>* L, int 
     for (int r = 0; r < 4; ++r) {
       int row = 16 * w + MF<R>::row(lane, r);
       int lr = rmap ? rmap[row] : row;
-      L[(size_t)lr * ldb + cb0 + 16 * c + (lane & 15)] = mk<R>(acc.re[c][r], acc.im[c][r]);
+      L[(size_t)lr * ldb + cb0 + 16 * c + (lane & 15)] = acc.get(c, r);
     }
 }
 template <typename R, int NC>
@@ -153,9 +164,7 @@ __device__ __forceinline__ void acc_from_lds(Acc<R, NC>& acc, const cx<R>* L, in
     for (int r = 0; r < 4; ++r) {
       int row = 16 * w + MF<R>::row(lane, r);
       int lr = rmap ? rmap[row] : row;
-      cx<R> v = L[(size_t)lr * ldb + cb0 + 16 * c + (lane & 15)];
-      acc.re[c][r] = v.x;
-      acc.im[c][r] = v.y;
+      acc.set(c, r, L[(size_t)lr * ldb + cb0 + 16 * c + (lane & 15)]);
     }
 }
 
@@ -242,7 +251,7 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
         int64_t row = row0 + 16 * w + MF<R>::row(lane, r);
         int col = cb0 + 16 * c + (lane & 15);
         if (row < n && col < ncol)
-          gst(base + (int64_t)col * ld + row, mk<R>(acc.re[c][r], acc.im[c][r]));
+          gst(base + (int64_t)col * ld + row, acc.get(c, r));
       }
   };
   auto acc_emit = [&](const Acc<R, NC>& acc, int64_t row0) {
@@ -257,7 +266,7 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
         const int q = 4 * c + r;
         rows[q] = row0 + 16 * w + MF<R>::row(lane, r);
         cols[q] = cb0 + 16 * c + (lane & 15);
-        v[q] = mk<R>(acc.re[c][r], acc.im[c][r]);
+        v[q] = acc.get(c, r);
         valid[q] = true;
       }
     emit_batch(rows, cols, v, valid);
@@ -325,10 +334,8 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const cx<R> v = conv(p.v[c][r], okf((int64_t)p.k * NB + 16 * w + MF<R>::row(lane, r),
-                                            cb0 + 16 * c + (lane & 15)));
-        acc.re[c][r] = v.x;
-        acc.im[c][r] = v.y;
+        acc.set(c, r, conv(p.v[c][r], okf((int64_t)p.k * NB + 16 * w + MF<R>::row(lane, r),
+                                          cb0 + 16 * c + (lane & 15))));
       }
   };
   Acc<R, NC> acc;
