@@ -193,6 +193,48 @@ int slice_plan(const fb_band* B, const fb_plan_opts* o, double* bounds,
                int32_t* counts, int32_t* n_inertia, void* work, size_t* lwork,
                void* stream);
 
+/* Options of slice placement from the previous eigenvalues of a sequence. */
+typedef struct {
+  int32_t K;          /* wanted slices; the clustering may return fewer */
+  int64_t nev;        /* the lowest nev eigenvalues are covered, 1 <= nev <= nprev */
+  double alpha;       /* relative step of the bound searches (1e-3) */
+  int32_t m1;         /* gap multiple of the bound step (6) */
+  double cert_delta;  /* as fb_plan_opts.cert_delta (1e-8) */
+  int32_t max_sweeps; /* clustering sweeps (100) */
+  int32_t max_steps;  /* steps of each bound search (1000) */
+} fb_prev_opts;
+
+/* Slices for the lowest nev eigenvalues of B from the eigenvalues of the
+ * previous matrix of a sequence (Section 3.1 "K-means Clustering" with
+ * Algorithm alg:kmeans; bounds of Section 3.2 "Validation and Other
+ * Details", Algorithm alg:lower_upper):
+ *   the previous d_1 <= ... <= d_nev are clustered into at most K groups of
+ *   consecutive values (simplified one-dimensional k-means: initial groups of
+ *   floor(nev/K) or floor(nev/K)+1 points, the first nev mod K larger; each
+ *   sweep moves every boundary, in order, to the first point above the
+ *   midpoint of the two neighbouring group centroids, a centroid being the
+ *   midpoint of the group's extreme points; an emptied group is dropped;
+ *   until no boundary moves or max_sweeps); an interior boundary is the
+ *   midpoint of the points on its two sides;
+ *   b_K = d_nev + s, s = max(alpha |d_nev|, m1 (d_nev - d_nev-1),
+ *   4 cert_delta ||B||_1 + 1e-12 ||B||_1), advanced by s until
+ *   n_-(b_K) >= nev; b_0 = d_1 - s0 (s0 likewise from d_1 and d_2 - d_1),
+ *   moved down by s0 until n_-(b_0) = 0;
+ *   every boundary is then certified as in slice_plan and the counts are
+ *   exact inertia differences.
+ *  prev    host, nprev ascending doubles
+ *  bounds  host, K+1 doubles (the first K_out+1 are set); counts host, K
+ *  K_out   host (may be NULL): slices returned, <= K
+ *  n_inertia host (may be NULL): shifts factorised
+ * Returns 0; -k for invalid argument k (nothing launched); FB_ERR_CERTIFY
+ * when a boundary cannot be certified, a bound search does not end within
+ * max_steps, or certified boundaries are out of order.  Synchronises the
+ * stream. */
+int slice_plan_prev(const fb_band* B, const double* prev, int64_t nprev,
+                    const fb_prev_opts* o, double* bounds, int32_t* counts,
+                    int32_t* K_out, int32_t* n_inertia, void* work, size_t* lwork,
+                    void* stream);
+
 /* Filter application only (the shifted solves of one FEAST iteration,
  * Section 2.2, eq:feast_L2 and the quadrature sum Q = sum_j w_j Q^(j)):
  * factor z_j I - B for every node of every slice, solve with Y[i]

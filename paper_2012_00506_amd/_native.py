@@ -41,6 +41,11 @@ class fb_plan_opts(C.Structure):
                 ("nev", C.c_int64), ("targets", PI32)]
 
 
+class fb_prev_opts(C.Structure):
+    _fields_ = [("K", C.c_int32), ("nev", C.c_int64), ("alpha", C.c_double), ("m1", C.c_int32),
+                ("cert_delta", C.c_double), ("max_sweeps", C.c_int32), ("max_steps", C.c_int32)]
+
+
 P = C.c_void_p
 PI64 = C.POINTER(C.c_int64)
 PD = C.POINTER(C.c_double)
@@ -57,6 +62,8 @@ SIGNATURES = {
                                    PI32, C.POINTER(fb_feast_opts), P, PSZ, P]),
     "slice_plan": (C.c_int, [C.POINTER(fb_band), C.POINTER(fb_plan_opts), PD, PI32, PI32, P,
                              PSZ, P]),
+    "slice_plan_prev": (C.c_int, [C.POINTER(fb_band), PD, C.c_int64, C.POINTER(fb_prev_opts), PD,
+                                  PI32, PI32, PI32, P, PSZ, P]),
     "feast_filter": (C.c_int, [C.POINTER(fb_band), C.c_int32, PD, PD, PI32, C.POINTER(P), PI64,
                                C.POINTER(P), PI64, PD, PI32, C.POINTER(fb_feast_opts), P, PSZ, P]),
     "fb_profile_enable": (C.c_int, [C.c_int32]),

@@ -259,6 +259,36 @@ def slice_plan(B, K, mode="equal_count", lo=float("nan"), hi=float("nan"), count
     return bounds, counts, int(nev.value)
 
 
+def slice_plan_prev(B, prev, nev, K, alpha=1e-3, m1=6, cert_delta=1e-8, max_sweeps=100,
+                    max_steps=1000, stream=None):
+    """Slices for the lowest ``nev`` eigenvalues of B from the ascending
+    eigenvalues ``prev`` of the previous matrix of a sequence: k-means
+    boundaries, searched outer bounds, all certified.  Returns (bounds
+    (K'+1), exact counts (K'), inertia evaluations), K' <= K."""
+    B = _as_band(B)
+    pv = np.ascontiguousarray(np.asarray(prev, np.float64))
+    o = N.fb_prev_opts(int(K), int(nev), float(alpha), int(m1), float(cert_delta),
+                       int(max_sweeps), int(max_steps))
+    bounds = np.zeros(K + 1, np.float64)
+    counts = np.zeros(K, np.int32)
+    kout = C.c_int32(0)
+    nev_ = C.c_int32(0)
+    bs = B.struct()
+    L = N.lib()
+    sh = C.c_void_p(_stream_handle(stream))
+    args = (C.byref(bs), pv.ctypes.data_as(N.PD), C.c_int64(pv.size), C.byref(o),
+            bounds.ctypes.data_as(N.PD), counts.ctypes.data_as(N.PI32), C.byref(kout),
+            C.byref(nev_))
+    lw = C.c_size_t(0)
+    N.check("slice_plan_prev", L.slice_plan_prev(*args, None, C.byref(lw), sh))
+    ws = _workspace(None, lw, B.data.device)
+    lw2 = C.c_size_t(ws.numel())
+    N.check("slice_plan_prev", L.slice_plan_prev(*args, C.c_void_p(ws.data_ptr()), C.byref(lw2),
+                                                 sh))
+    k = int(kout.value)
+    return bounds[:k + 1], counts[:k], int(nev_.value)
+
+
 @dataclass
 class FilterResult:
     Q: list

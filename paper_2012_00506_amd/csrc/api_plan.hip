@@ -1,7 +1,10 @@
 // C ABI: slice_plan -- slice boundaries by exact inertia (Section 3.1,
 // Approach-1 equal counts and Approach-2 equal widths; counts per slice from
-// two inertias as in Section 3.2).  Host control over batched GPU inertia:
-// every round evaluates all open boundaries in one launch.
+// two inertias as in Section 3.2) -- and slice_plan_prev, slices from the
+// previous eigenvalues of a sequence (Section 3.1 k-means, Algorithm
+// alg:kmeans; bounds of Section 3.2, Algorithm alg:lower_upper).  Host
+// control over batched GPU inertia: every round evaluates all open
+// boundaries in one launch.
 #include <math.h>
 
 #include <algorithm>
@@ -350,6 +353,127 @@ extern "C" int slice_plan(const fb_band* B, const fb_plan_opts* o, double* bound
   }
   for (int i = 0; i <= K; ++i) bounds[i] = edges[i];
   for (int i = 0; i < K; ++i) counts[i] = neg[i + 1] - neg[i];
+  if (n_inertia) *n_inertia = ir.evals;
+  return 0;
+}
+
+// ---------------------------------------------------------------- from previous eigenvalues
+namespace fb {
+
+// Simplified one-dimensional k-means of ascending d[0..n) into at most K
+// groups of consecutive points, held as split indices s (s[0] = 0, s.back()
+// = n); see slice_plan_prev in the header for the rule.
+static void kmeans_1d(const double* d, int64_t n, int K, int max_sweeps,
+                      std::vector<int64_t>& s) {
+  const int64_t q = n / K, r = n % K;
+  s.assign(1, 0);
+  for (int i = 0; i < K; ++i) s.push_back(s.back() + (i < r ? q + 1 : q));
+  s.erase(std::unique(s.begin(), s.end()), s.end());  // groups with no point
+  auto cen = [&](int64_t a, int64_t b) { return 0.5 * (d[a] + d[b - 1]); };
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    const std::vector<int64_t> old = s;
+    for (size_t j = 1; j + 1 < s.size(); ++j) {
+      if (s[j] <= s[j - 1] || s[j + 1] <= s[j]) continue;
+      const double c = 0.5 * (cen(s[j - 1], s[j]) + cen(s[j], s[j + 1]));
+      s[j] = std::upper_bound(d, d + n, c) - d;
+    }
+    std::sort(s.begin(), s.end());
+    s.erase(std::unique(s.begin(), s.end()), s.end());
+    if (s == old) break;
+  }
+}
+
+}  // namespace fb
+
+extern "C" int slice_plan_prev(const fb_band* B, const double* prev, int64_t nprev,
+                               const fb_prev_opts* o, double* bounds, int32_t* counts,
+                               int32_t* K_out, int32_t* n_inertia, void* work, size_t* lwork,
+                               void* stream) {
+  if (check_band(B)) return -1;
+  if (!prev || nprev < 1) return -2;
+  for (int64_t i = 0; i < nprev; ++i)
+    if (!isfinite(prev[i]) || (i > 0 && prev[i] < prev[i - 1])) return -2;
+  if (!o || o->K < 1 || o->K > 1 << 20 || o->nev < 1 || o->nev > nprev) return -4;
+  if (!(o->alpha >= 0) || o->m1 < 0 || !(o->cert_delta >= 0) || o->max_sweeps < 0 ||
+      o->max_steps < 1)
+    return -4;
+  if (!bounds) return -5;
+  if (!counts) return -6;
+  if (!lwork) return -10;
+  const int K = o->K;
+  hipStream_t st = (hipStream_t)stream;
+  Arena ar;
+  ar.base = (char*)work;
+  ar.cap = *lwork;
+  Band bd;
+  FB_TRY(ingest_band(B, bd, ar, st));
+  const int cap = 2 * (K + 1);
+  double* sh = ar.take<double>(cap);
+  int32_t* cnt = ar.take<int32_t>(3 * (size_t)cap);
+  size_t scb = inertia_scratch_bytes(bd, cap);
+  void* scratch = scb ? (void*)ar.take<char>(scb) : nullptr;
+  if (work == nullptr) {
+    *lwork = ar.used;
+    return 0;
+  }
+  if (!ar.fits()) return FB_ERR_NOMEM;
+  double stats[3];
+  FB_TRY(band_stats_host(bd, stats, st));
+  const double nrm = stats[0];
+  const double delta = o->cert_delta * nrm;
+  const double floor_ = 4.0 * o->cert_delta * nrm + 1e-12 * nrm;
+  InertiaRunner ir{&bd, sh, cnt, scratch, cap, st};
+  const int64_t nev = o->nev;
+  auto step = [&](double a, double gap) {
+    return std::max(std::max(o->alpha * fabs(a), (double)o->m1 * gap), floor_);
+  };
+  // lower bound: below every eigenvalue
+  double b0;
+  {
+    const double s0 = step(prev[0], nprev >= 2 ? prev[1] - prev[0] : 0.0);
+    double b = prev[0] - s0;
+    bool ok = false;
+    for (int it = 0; it < o->max_steps && !ok; ++it) {
+      std::vector<int> v;
+      FB_TRY(ir.run({b}, v));
+      if (v[0] == 0)
+        ok = true;
+      else
+        b = b - s0;
+    }
+    if (!ok) return FB_ERR_CERTIFY;
+    b0 = b;
+  }
+  // upper bound: at least nev eigenvalues below
+  double bK;
+  {
+    const double s1 = step(prev[nev - 1], nev >= 2 ? prev[nev - 1] - prev[nev - 2] : 0.0);
+    double b = prev[nev - 1] + s1;
+    bool ok = false;
+    for (int it = 0; it < o->max_steps && !ok; ++it) {
+      std::vector<int> v;
+      FB_TRY(ir.run({b}, v));
+      if (v[0] >= nev)
+        ok = true;
+      else
+        b = b + s1;
+    }
+    if (!ok) return FB_ERR_CERTIFY;
+    bK = b;
+  }
+  std::vector<int64_t> sp;
+  kmeans_1d(prev, nev, K, o->max_sweeps, sp);
+  std::vector<double> edges = {b0};
+  for (size_t j = 1; j + 1 < sp.size(); ++j) edges.push_back(0.5 * (prev[sp[j] - 1] + prev[sp[j]]));
+  edges.push_back(bK);
+  std::vector<int> neg;
+  FB_TRY(certify_all(ir, edges, delta, neg));
+  const int Kp = (int)edges.size() - 1;
+  for (int i = 0; i < Kp; ++i)
+    if (!(edges[i + 1] > edges[i])) return FB_ERR_CERTIFY;
+  for (int i = 0; i <= Kp; ++i) bounds[i] = edges[i];
+  for (int i = 0; i < Kp; ++i) counts[i] = neg[i + 1] - neg[i];
+  if (K_out) *K_out = Kp;
   if (n_inertia) *n_inertia = ir.evals;
   return 0;
 }

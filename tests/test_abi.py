@@ -112,3 +112,29 @@ def test_strerror(L):
     assert b"pivot" in L.fb_strerror(-2001)
     assert L.fb_strerror(0) == b"success"
     assert b"invalid" in L.fb_strerror(-3)
+
+
+def test_slice_plan_prev_argument_errors_and_query(L):
+    from paper_2012_00506_amd import _native as N
+    bs = _band(n=50, b=3)
+    prev = np.arange(20, dtype=np.float64)
+    pp = prev.ctypes.data_as(N.PD)
+    bounds = np.zeros(9)
+    counts = np.zeros(8, np.int32)
+    bp, cp = bounds.ctypes.data_as(N.PD), counts.ctypes.data_as(N.PI32)
+    lw = C.c_size_t(0)
+
+    def call(p=pp, n=20, o=None, b=bp, c=cp, lwp=C.byref(lw)):
+        o = o or N.fb_prev_opts(8, 10, 1e-3, 6, 1e-8, 100, 1000)
+        return L.slice_plan_prev(C.byref(bs), p, n, C.byref(o), b, c, None, None, None, lwp, None)
+
+    assert call(p=None) == -2
+    unsorted = prev[::-1].copy()
+    assert call(p=unsorted.ctypes.data_as(N.PD)) == -2
+    assert call(o=N.fb_prev_opts(0, 10, 1e-3, 6, 1e-8, 100, 1000)) == -4
+    assert call(o=N.fb_prev_opts(8, 21, 1e-3, 6, 1e-8, 100, 1000)) == -4  # nev > nprev
+    assert call(o=N.fb_prev_opts(8, 10, -1.0, 6, 1e-8, 100, 1000)) == -4
+    assert call(b=None) == -5
+    assert call(c=None) == -6
+    assert call(lwp=None) == -10
+    assert call() == 0 and lw.value > 0

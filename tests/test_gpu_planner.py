@@ -273,3 +273,21 @@ def test_slice_plan_given_targets(fb):
     delta = 1e-8 * oband.norm1(ab)
     for s_ in bounds:
         assert oin.inertia(ab, s_ - delta)[0] == oin.inertia(ab, s_ + delta)[0]
+
+
+@pytest.mark.parametrize("n,b,cplx,nev,K", [(700, 9, True, 300, 8), (1200, 30, False, 500, 16),
+                                            (400, 3, True, 50, 1), (300, 4, False, 6, 9)])
+def test_slice_plan_prev_parity(fb, n, b, cplx, nev, K):
+    """Slices from previous eigenvalues (k-means, bound searches,
+    certification) against the oracle: the same boundaries, counts, number
+    of slices and number of inertia evaluations."""
+    from oracle import planner as opl
+    ab = synth.band_matrix(n, b, 950 + n, cplx, -15, 15)
+    E = synth.hermitian_perturbation(n, b, 951 + n, cplx)
+    prev = np.linalg.eigvalsh(oband.dense_from_band(ab + 3e-2 * E))
+    e, c, ne = fb.slice_plan_prev(ab, prev, nev, K)
+    re, rc, rk, rne = opl.plan_prev(ab, prev, nev, K)
+    print(f"n={n} K'={len(c)} counts {list(c)[:6]} inertias {ne}", flush=True)
+    assert len(c) == rk <= K
+    assert np.array_equal(e, re) and np.array_equal(c, rc) and ne == rne
+    assert c.sum() >= nev

@@ -101,3 +101,31 @@ def test_n65536_b128_lowest_slices(fb):
     print(f"feast {ns} slices: {time.time() - t0:.1f} s, iters {[r.iters for r in res]}",
           flush=True)
     _check_results(ab, bounds, res, cols_per_slice=2)
+
+
+def test_scf_sequence_repartition(fb):
+    """Sequence with the slices re-placed on every matrix from the previous
+    eigenvalues (k-means and bound searches) and start blocks gathered from
+    the previous Ritz vectors by eigenvalue: every slice converges, counts
+    are exact and the lowest nev eigenvalues stay covered."""
+    from paper_2012_00506_amd.scf import SliceSequence
+    cfg = synth.Config("cplx-n8192-b32-seq", 8192, 32, True, 7, -50.0, 50.0, (),
+                       "small SCF-like sequence")
+    nev, K = 800, 8
+    ab0 = synth.scf_matrix(cfg, 0)
+    bounds, counts, _ = fb.slice_plan(ab0, K, "equal_count", nev=nev)
+    seq = SliceSequence(bounds, precision=1, warm=True, seed=2, replan_nev=nev)
+    for k in range(3):
+        ab = synth.scf_matrix(cfg, k)
+        B = fb.DeviceBand.from_band(ab)
+        r = seq.step(B)
+        print(f"step {k}: {len(r.counts)} slices, counts {r.counts}, iters {r.iters}, "
+              f"{r.seconds:.1f} s", flush=True)
+        assert all(i == 0 for i in r.info)
+        assert sum(r.counts) >= nev
+        assert oin.inertia(ab, seq.bounds[0])[0] == 0
+        assert oin.inertia(ab, seq.bounds[-1])[0] >= nev
+        for j in (0, len(r.counts) - 1):
+            assert r.counts[j] == oin.count_in(ab, seq.bounds[j], seq.bounds[j + 1])
+        _check_results(ab, seq.bounds, r.results)
+        del B
