@@ -166,12 +166,13 @@ def test_solve_cfg2_shape_sampled(fb):
         _check_against_oracle(ab, zs, Yh, r, 1e-10, 1e-12, cols=np.array([0, 17, 39]))
 
 
+@pytest.mark.parametrize("b", [64, 40, 9])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_every_solve_variant_parity(fb, precision, tmp_path):
+def test_every_solve_variant_parity(fb, precision, b, tmp_path):
     """Each block-solve variant the autotuner may pick gives oracle-parity
-    solutions (ragged n and tile tails; N and H)."""
-    n, b, m = 700, 64, 45
-    nb = 64
+    solutions (ragged n and tile tails; N and H; blocks of 64, 48, 16)."""
+    n, m = 700, 45
+    nb = (b + 15) // 16 * 16
     rsize = 4 if precision == 1 else 8
     tol_x, tol_r = (1e-9, 1e-12) if precision else (1e-11, 1e-13)
     for v in range(6):
