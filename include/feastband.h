@@ -120,10 +120,22 @@ typedef struct {
                           slice (batched = 0 uses one) */
   int32_t pairs;       /* > 0: exactly this many pairs per batched launch
                           (capped at 2 n_nodes), overriding hbm_budget */
+  int32_t rule;        /* quadrature of the contour integral (Section 2.2,
+                          eq:integral): 0 Gauss-Legendre in the angle of the
+                          upper half, 1 trapezoid (midpoint) rule with 2 n_nodes
+                          equispaced angles on the whole curve, of which the
+                          n_nodes on the upper half are used */
+  double ratio;        /* vertical over horizontal semi-axis of the contour
+                          through the slice ends: 1 (or 0) the circle, other
+                          positive values an ellipse
+                          z(t) = c + r (cos t + i ratio sin t) */
 } fb_feast_opts;
 
 /* FEAST on the slices [lo_i, hi_i) of B (Algorithm alg:FEAST, Section 2.2,
- * with the slice validation of Section 3.2):
+ * with the slice validation of Section 3.2).  Nodes z_j = z(t_j) on the upper
+ * half of the contour, weights w_j = (dt_j / (2 pi)) z'(t_j) / i with dt_j the
+ * quadrature weight in the angle (Gauss-Legendre: (pi/2) omega_j; trapezoid:
+ * pi / n_nodes):
  *   repeat: Q = sum_j [w_j (z_j I - B)^{-1} Y + conj(w_j)(z_j I - B)^{-H} Y]
  *           (real B: Q = sum_j 2 Re[w_j (z_j I - B)^{-1} Y]),
  *           orthonormalise Q, A_q = Q^H B Q, A_q W = W Lambda, X = Q W,

@@ -64,20 +64,34 @@ def filter_apply(ab: np.ndarray, factors, w, Y: np.ndarray) -> np.ndarray:
     return Q
 
 
-def _orthonormalise_once(Q: np.ndarray, drop: float):
+def _orthonormalise_once(Q: np.ndarray, drop: float, unit_columns: bool = False):
     G = Q.conj().T @ Q
     G = 0.5 * (G + G.conj().T)
     s, V = np.linalg.eigh(G)
     keep = s > drop * s.max() if s.max() > 0 else np.zeros(len(s), bool)
-    return (Q @ V[:, keep]) / np.sqrt(s[keep])
+    Q1 = (Q @ V[:, keep]) / np.sqrt(s[keep])
+    if unit_columns:
+        nr = np.linalg.norm(Q1, axis=0)
+        Q1 = Q1 / np.where(nr > 0, nr, 1.0)
+    return Q1
 
 
-def orthonormalise(Q: np.ndarray, drop: float = 1e-14):
+def orthonormalise(Q: np.ndarray, drop: float = 1e-14, floor: float = 1e-24):
     """Q V s^{-1/2} over the kept directions of Q^H Q = V s V^H, applied
     twice: after one pass Q'^H Q' = I + E with E growing with the spread of
     s (the filtered block is ill-conditioned by design); the second pass
-    brings E to rounding level."""
-    Q1 = _orthonormalise_once(Q, drop)
+    brings E to rounding level.  The first pass keeps every direction with
+    s > floor * max(s) and scales each resulting column to unit norm (an
+    eigenvalue solver accurate to eps max(s) in absolute terms, such as a
+    Jacobi method stopped on the off-diagonal norm, leaves the smallest s
+    inaccurate, and with them the scale s^(-1/2)); the rank decision,
+    s > drop * max(s), is taken in the second pass on the well-scaled block.
+    Truncating at drop in the first pass already discards the filtered
+    block's directions below 1e-7 of its largest, and with them the last
+    digits of the wanted eigenvectors: the residuals stall near 1e-8 when
+    the filter damps many directions that far (16 nodes, m0 >= 2m, flat
+    ellipses)."""
+    Q1 = _orthonormalise_once(Q, floor, unit_columns=True)
     Q2 = _orthonormalise_once(Q1, drop)
     return Q2, Q2.shape[1]
 
@@ -121,11 +135,12 @@ class SliceResult:
 
 def feast_slice(ab: np.ndarray, lo: float, hi: float, Y: np.ndarray,
                 n_nodes: int = 8, tol: float = 1e-10, max_iter: int = 20,
-                m_expected: int | None = None) -> SliceResult:
+                m_expected: int | None = None, rule: str = "gauss",
+                ratio: float = 1.0) -> SliceResult:
     """Eigenpairs of B in [lo, hi) by FEAST from the start block Y (n x m0)."""
     nrm = norm1(ab)
     m = count_in(ab, lo, hi) if m_expected is None else m_expected
-    z, w = contour(lo, hi, n_nodes)
+    z, w = contour(lo, hi, n_nodes, rule, ratio)
     factors = factor_nodes(ab, z)
     Y = np.array(Y, dtype=np.complex128 if np.iscomplexobj(ab) else np.float64, copy=True)
     m0 = Y.shape[1]

@@ -15,9 +15,18 @@ Readings (the paper is silent or garbled here):
   z_j = c + r e^{i theta_j}, w_j = (omega_j / 4) r e^{i theta_j}, and the filter
   becomes r(x) = sum_j 2 Re[w_j / (z_j - x)].
 
+Filter variants (the other contours and rules Section 2.2 names): an ellipse
+through the slice ends, z(t) = c + r (cos t + i rho sin t), and the trapezoid
+(midpoint) rule with 2k equispaced angles t_j = pi (j + 1/2) / k on the whole
+curve.  In general w_j = (dt_j / (2 pi)) z'(t_j) / i with dt_j the weight of the
+rule in the angle, (pi/2) omega_j for Gauss-Legendre and pi / k for the
+midpoint rule.
+
 Pinned by: ``numpy.polynomial.legendre.leggauss``, sum(omega) = 2, exactness
 on polynomials of degree <= 2k-1, and the closed forms r(c) = 1 and
-r(c +- r) = 1/2 (tests).
+r(c +- r) = 1/2 (tests); the midpoint rule on the circle by its closed form
+r(x) = 1 / (1 + ((x - c)/r)^(2k)); the ellipse by Cauchy's formula (r -> the
+indicator of the inside as k grows).
 """
 from __future__ import annotations
 
@@ -41,14 +50,25 @@ def gauss_legendre(k: int):
     return x, w
 
 
-def contour(lo: float, hi: float, k: int = 8):
-    """Half-circle Gauss-Legendre nodes z_j and weights w_j for the slice [lo, hi)."""
-    x, om = gauss_legendre(k)
+def contour(lo: float, hi: float, k: int = 8, rule: str = "gauss", ratio: float = 1.0):
+    """Nodes z_j and weights w_j on the upper half of the contour through the
+    slice ends [lo, hi): the circle (ratio 1) or an ellipse of vertical
+    semi-axis ratio * r, with the Gauss-Legendre or the midpoint rule."""
     c = 0.5 * (lo + hi)
     r = 0.5 * (hi - lo)
-    theta = 0.5 * np.pi * (1.0 - x)
-    e = np.exp(1j * theta)
-    return c + r * e, 0.25 * om * r * e
+    rho = ratio if ratio > 0 else 1.0
+    if rule == "gauss":
+        x, om = gauss_legendre(k)
+        theta = 0.5 * np.pi * (1.0 - x)
+        dt = 0.5 * np.pi * om
+    elif rule == "trapezoid":
+        theta = np.pi * (np.arange(k) + 0.5) / k
+        dt = np.full(k, np.pi / k)
+    else:
+        raise ValueError(rule)
+    z = c + r * (np.cos(theta) + 1j * rho * np.sin(theta))
+    dz_over_i = r * (rho * np.cos(theta) + 1j * np.sin(theta))  # z'(t) / i
+    return z, dt / (2.0 * np.pi) * dz_over_i
 
 
 def filter_value(lam, z, w):

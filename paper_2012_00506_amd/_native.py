@@ -31,7 +31,8 @@ class fb_solve_opts(C.Structure):
 class fb_feast_opts(C.Structure):
     _fields_ = [("n_nodes", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("precision", C.c_int32), ("ir_tol", C.c_double), ("ir_max", C.c_int32),
-                ("batched", C.c_int32), ("hbm_budget", C.c_double), ("pairs", C.c_int32)]
+                ("batched", C.c_int32), ("hbm_budget", C.c_double), ("pairs", C.c_int32),
+                ("rule", C.c_int32), ("ratio", C.c_double)]
 
 
 class fb_plan_opts(C.Structure):

@@ -172,9 +172,13 @@ class SliceResult:
         return self.Y[:, : self.m_found]
 
 
+# quadrature rules of the contour integral (fb_feast_opts.rule)
+_RULES = {"gauss": 0, "trapezoid": 1}
+
+
 def feast_band_slice(B, lo, hi, Y, m_expected=None, n_nodes=8, tol=1e-10, max_iter=20,
                      precision=0, ir_tol=1e-12, ir_max=4, batched=True, hbm_budget=0.0,
-                     pairs=0, stream=None):
+                     pairs=0, rule="gauss", ratio=1.0, stream=None):
     """FEAST on the slices [lo_i, hi_i) of B from the start blocks Y[i]
     ((n, m0_i) column-major device tensors in the dtype of B; overwritten with
     the Ritz vectors).  Returns one SliceResult per slice."""
@@ -201,7 +205,7 @@ def feast_band_slice(B, lo, hi, Y, m_expected=None, n_nodes=8, tol=1e-10, max_it
     its = np.zeros(ns, np.int32)
     inf = np.zeros(ns, np.int32)
     o = N.fb_feast_opts(n_nodes, tol, max_iter, precision, ir_tol, ir_max, 1 if batched else 0,
-                        float(hbm_budget), int(pairs))
+                        float(hbm_budget), int(pairs), _RULES[rule], float(ratio))
     bs = B.struct()
     L = N.lib()
     sh = C.c_void_p(_stream_handle(stream))
@@ -302,14 +306,16 @@ class FeastFilter:
     (workspace allocated once; each call factors and solves everything)."""
 
     def __init__(self, B, lo, hi, m, n_nodes=8, precision=0, ir_tol=1e-10, ir_max=4,
-                 batched=True, with_resid=False, hbm_budget=0.0, pairs=0, device="cuda"):
+                 batched=True, with_resid=False, hbm_budget=0.0, pairs=0, rule="gauss",
+                 ratio=1.0, device="cuda"):
         self.B = _as_band(B)
         self.lo = np.ascontiguousarray(np.asarray(lo, np.float64).ravel())
         self.hi = np.ascontiguousarray(np.asarray(hi, np.float64).ravel())
         self.m = np.ascontiguousarray(np.asarray(m, np.int32).ravel())
         self.ns = len(self.lo)
         self.o = N.fb_feast_opts(n_nodes, 1e-10, 1, precision, ir_tol, ir_max,
-                                 1 if batched else 0, float(hbm_budget), int(pairs))
+                                 1 if batched else 0, float(hbm_budget), int(pairs),
+                                 _RULES[rule], float(ratio))
         self.with_resid = with_resid
         self.bs = self.B.struct()
         self.resid = np.zeros(self.ns, np.float64)

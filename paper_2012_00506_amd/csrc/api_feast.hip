@@ -58,19 +58,27 @@ void gauss_legendre(int k, std::vector<double>& x, std::vector<double>& w) {
   }
 }
 
-// Half-circle contour through the slice ends: z_j = c + r e^{i theta_j},
-// w_j = (omega_j / 4) r e^{i theta_j}, theta_j = (pi/2)(1 - x_j).
-void contour(double lo, double hi, int k, std::vector<c128>& z, std::vector<c128>& w) {
+// Nodes and weights on the upper half of the contour through the slice ends,
+// z(t) = c + r (cos t + i rho sin t) (rho = 1: the circle), for
+// P = (1/(2 pi i)) \oint (zI - B)^{-1} dz with the lower half by conjugation:
+// w_j = (dt_j / (2 pi)) z'(t_j) / i = (dt_j / (2 pi)) r (rho cos t_j + i sin t_j).
+// rule 0: Gauss-Legendre in t on [0, pi], t_j = (pi/2)(1 - x_j),
+// dt_j = (pi/2) omega_j, so w_j = (omega_j / 4) r (rho cos t_j + i sin t_j);
+// rule 1: midpoint angles t_j = pi (j + 1/2) / k, dt_j = pi / k.
+void contour(double lo, double hi, int k, int rule, double ratio, std::vector<c128>& z,
+             std::vector<c128>& w) {
+  const double rho = ratio > 0.0 ? ratio : 1.0;
   std::vector<double> x, om;
-  gauss_legendre(k, x, om);
+  if (rule == 0) gauss_legendre(k, x, om);
   double c = 0.5 * (lo + hi), r = 0.5 * (hi - lo);
   z.resize(k);
   w.resize(k);
   for (int j = 0; j < k; ++j) {
-    double th = 0.5 * M_PI * (1.0 - x[j]);
-    c128 e = mk(cos(th), sin(th));
-    z[j] = mk(c + r * e.x, r * e.y);
-    w[j] = mk(0.25 * om[j] * r * e.x, 0.25 * om[j] * r * e.y);
+    const double th = rule == 0 ? 0.5 * M_PI * (1.0 - x[j]) : M_PI * (j + 0.5) / k;
+    const double f = rule == 0 ? 0.25 * om[j] : 0.5 / k;  // dt_j / (2 pi)
+    const double ct = cos(th), st = sin(th);
+    z[j] = mk(c + r * ct, r * rho * st);
+    w[j] = mk(f * r * rho * ct, f * r * st);
   }
 }
 
@@ -317,7 +325,7 @@ int feast_wave(const Band& bd, int nslice, const double* lo, const double* hi, c
   std::vector<double> zh(2 * nsys);
   for (int i = 0; i < nslice; ++i) {
     std::vector<c128> z, w;
-    contour(lo[i], hi[i], ne, z, w);
+    contour(lo[i], hi[i], ne, o->rule, o->ratio, z, w);
     for (int j = 0; j < ne; ++j) {
       zsys[i * ne + j] = z[j];
       wsys[i * ne + j] = w[j];
@@ -363,7 +371,14 @@ int feast_wave(const Band& bd, int nslice, const double* lo, const double* hi, c
                              Xp.data(), P, acc_dev, zsys, wsys, cplx, o->batched != 0, ir,
                              o->ir_tol, o->ir_max, ir, rb, sys_res, sys_pass, nullptr, st));
     }
-    // ---- orthonormalise: Q^H Q = V s V^H, keep s > 1e-14 max s, Q' = Q V s^{-1/2}
+    // ---- orthonormalise: Q^H Q = V s V^H, Q' = Q V s^{-1/2} over s > 1e-24 max s,
+    // columns then scaled to unit norm (the Jacobi solver is accurate to
+    // eps max s in absolute terms, so the smallest s, and the scales
+    // s^{-1/2}, are not); the rank decision, s > 1e-14 max s, is taken in
+    // the second pass on the well-scaled Q'.  Truncating at 1e-14 here already
+    // drops the filtered block's directions below 1e-7 of the largest, and
+    // with them the last digits of the wanted eigenvectors (residuals stall
+    // near 1e-8 under sharp filters).
     std::vector<JacobiJob> jj;
     for (int i : act) {
       int m = m0[i];
@@ -383,7 +398,7 @@ int feast_wave(const Band& bd, int nslice, const double* lo, const double* hi, c
       jj.push_back(J);
     }
     FB_TRY(reduced_eig(jj, jj_dev, ew, 60, 1e-14, st));
-    for (int i : act) FB_TRY(gram_keep(sb[i].s, m0[i], 1e-14, sb[i].idx, sb[i].scale, sb[i].kept, st));
+    for (int i : act) FB_TRY(gram_keep(sb[i].s, m0[i], 1e-24, sb[i].idx, sb[i].scale, sb[i].kept, st));
     for (int i : act) FB_HIP(hipMemcpyAsync(&kept[i], sb[i].kept, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     FB_HIP(hipStreamSynchronize(st));
     std::vector<int> prev_kept(kept);
@@ -394,6 +409,7 @@ int feast_wave(const Band& bd, int nslice, const double* lo, const double* hi, c
       // V' = W[:, idx] diag(scale) (m x k) into V; Q' = Q V' into X
       FB_TRY(gather_cols(sb[i].W, m, false, sb[i].V, m, m, k, sb[i].idx, sb[i].scale, st));
       FB_TRY(zgemm(st, false, (int)n, k, m, sb[i].Q, n, sb[i].V, m, sb[i].X, n));
+      FB_TRY(unit_columns(sb[i].X, n, n, k, st));
       // second pass: Q'^H Q' = I + E with E growing with the spread of s;
       // orthonormalising Q' once more makes the basis orthonormal to
       // rounding, which the eigen-residual floor needs
@@ -601,6 +617,7 @@ extern "C" int feast_band_slice(const fb_band* B, int32_t nslice, const double* 
   if (!o) return -14;
   if (!lwork) return -16;
   if (o->n_nodes < 1 || o->n_nodes > 64 || !(o->tol > 0) || o->max_iter < 1) return -14;
+  if ((o->rule != 0 && o->rule != 1) || !(o->ratio >= 0) || !isfinite(o->ratio)) return -14;
   if (o->precision != 0 && o->precision != 1) return -14;
   if (o->precision == 1 && (!(o->ir_tol > 0) || o->ir_max < 0)) return -14;
   for (int i = 0; i < nslice; ++i) {
@@ -682,7 +699,7 @@ int filter_impl(const fb_band* B, int nslice, const double* lo, const double* hi
   std::vector<double> zh(2 * nsys);
   for (int i = 0; i < nslice; ++i) {
     std::vector<c128> z, w;
-    contour(lo[i], hi[i], ne, z, w);
+    contour(lo[i], hi[i], ne, o->rule, o->ratio, z, w);
     for (int j = 0; j < ne; ++j) {
       zsys[i * ne + j] = z[j];
       wsys[i * ne + j] = w[j];
@@ -736,6 +753,7 @@ extern "C" int feast_filter(const fb_band* B, int32_t nslice, const double* lo, 
   if (!o) return -12;
   if (!lwork) return -14;
   if (o->n_nodes < 1 || o->n_nodes > 64) return -12;
+  if ((o->rule != 0 && o->rule != 1) || !(o->ratio >= 0) || !isfinite(o->ratio)) return -12;
   if (o->precision != 0 && o->precision != 1) return -12;
   if (o->precision == 1 && (!(o->ir_tol > 0) || o->ir_max < 0)) return -12;
   for (int i = 0; i < nslice; ++i) {

@@ -72,6 +72,8 @@ size_t eig_work_bytes(const std::vector<int>& ms);
 void carve_eig_work(struct Arena& ar, const std::vector<int>& ms, EigWork& w);
 int reduced_eig(std::vector<JacobiJob> jobs, JacobiJob* jobs_dev, const EigWork& w,
                 int max_sweeps, double tol, hipStream_t st);
+// columns of X (n x k, leading dimension ldx) scaled to unit 2-norm
+int unit_columns(c128* X, int64_t n, int64_t ldx, int k, hipStream_t st);
 int gram_keep(const double* s, int m, double drop, int32_t* idx, double* scale, int32_t* kept,
               hipStream_t st);
 

@@ -422,6 +422,33 @@ __global__ void k_gram_keep(const double* __restrict__ s, int m, double drop,
   *kept = k;
 }
 
+// every column of the n x k block X scaled to unit 2-norm (a zero column
+// stays zero): one workgroup per column
+__global__ void __launch_bounds__(256)
+k_unit_columns(c128* __restrict__ X, int64_t n, int64_t ldx) {
+  __shared__ double red[4];
+  c128* x = X + (int64_t)blockIdx.x * ldx;
+  double ss = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) ss += cabs2(gld(x + i));
+  for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ss;
+  __syncthreads();
+  const double tot = red[0] + red[1] + red[2] + red[3];
+  if (!(tot > 0.0)) return;
+  const double sc = 1.0 / sqrt(tot);
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    c128 v = gld(x + i);
+    gst(x + i, mk(v.x * sc, v.y * sc));
+  }
+}
+
+int unit_columns(c128* X, int64_t n, int64_t ldx, int k, hipStream_t st) {
+  if (k <= 0) return 0;
+  k_unit_columns<<<k, 256, 0, st>>>(X, n, ldx);
+  FB_HIP(hipGetLastError());
+  return 0;
+}
+
 int gram_keep(const double* s, int m, double drop, int32_t* idx, double* scale, int32_t* kept,
               hipStream_t st) {
   k_gram_keep<<<1, 64, 0, st>>>(s, m, drop, idx, scale, kept);

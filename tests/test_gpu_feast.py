@@ -191,3 +191,40 @@ def test_feast_waves_equal_one_wave(fb):
         assert res["one"][i].info == 0
         assert np.array_equal(res["one"][i].evals, res["waves"][i].evals)
         assert torch.equal(res["one"][i].Y, res["waves"][i].Y)
+
+
+@pytest.mark.parametrize("rule,ratio,nodes", [("gauss", 0.5, 8), ("trapezoid", 1.0, 8),
+                                              ("trapezoid", 0.6, 12), ("gauss", 1.0, 16)])
+def test_feast_contour_variants_against_oracle(fb, rule, ratio, nodes):
+    """Other contours and rules (an ellipse through the slice ends, the
+    midpoint rule, 16 nodes): the same bars as the default half circle."""
+    print(f"feast contour {rule} ratio={ratio} nodes={nodes}", flush=True)
+    n = 300
+    ab = synth.band_matrix(n, 6, 12, True, -8, 8)
+    lam_all = np.linalg.eigvalsh(oband.dense_from_band(ab))
+    lo, hi = -1.3, 2.1
+    ref = lam_all[(lam_all >= lo) & (lam_all < hi)]
+    Yh, Y = start_block(fb, n, m0_rule(len(ref)), 13, True)
+    ora = ofeast.feast_slice(ab, lo, hi, Yh, n_nodes=nodes, rule=rule, ratio=ratio)
+    [r] = fb.feast_band_slice(ab, [lo], [hi], [Y], n_nodes=nodes, rule=rule, ratio=ratio)
+    print(f"  iters gpu {r.iters} oracle {ora.iters}", flush=True)
+    check_slice(r, ab, lo, hi, ref, ora)
+
+
+@pytest.mark.parametrize("rule,ratio", [("trapezoid", 0.6), ("gauss", 2.0)])
+def test_filter_contour_variants_against_oracle(fb, rule, ratio):
+    """feast_filter with another contour: Q against the oracle's node sum
+    (FP64 solves: kappa n eps)."""
+    from oracle import bandlu as olu
+    from oracle import quadrature as oq
+    n, b = 500, 7
+    ab = synth.band_matrix(n, b, 62, True, -12, 12)
+    lo, hi = -3.0, 1.5
+    Yh = synth.rhs_block(n, 21, 77, True)
+    r = fb.feast_filter(ab, [lo], [hi], [fb.to_colmajor(Yh)], n_nodes=10, rule=rule, ratio=ratio)
+    assert r.status == 0
+    z, w = oq.contour(lo, hi, 10, rule, ratio)
+    F = [olu.shifted_band_lu(ab, zj) for zj in z]
+    Qr = ofeast.filter_apply(ab, F, w, Yh)
+    err = np.linalg.norm(r.Q[0].cpu().numpy() - Qr) / np.linalg.norm(Qr)
+    assert err <= 1e-11, err
