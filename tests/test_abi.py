@@ -138,3 +138,29 @@ def test_slice_plan_prev_argument_errors_and_query(L):
     assert call(c=None) == -6
     assert call(lwp=None) == -10
     assert call() == 0 and lw.value > 0
+
+
+def test_feast_filter_contour_options_checked(L):
+    from paper_2012_00506_amd import _native as N
+    n = 100
+    bs = _band(n=n, b=4)
+    lo = (C.c_double * 1)(-1.0)
+    hi = (C.c_double * 1)(1.0)
+    m = (C.c_int32 * 1)(5)
+    Y = (C.c_void_p * 1)(1)
+    Q = (C.c_void_p * 1)(2)
+    ld = (C.c_int64 * 1)(n)
+    lw = C.c_size_t(0)
+
+    def call(rule=0, ratio=1.0, nodes=8):
+        o = N.fb_feast_opts(nodes, 1e-10, 1, 0, 1e-12, 4, 1, 0.0, 0, rule, ratio)
+        return L.feast_filter(C.byref(bs), 1, lo, hi, m, Y, ld, Q, ld, None, None, C.byref(o),
+                              None, C.byref(lw), None)
+
+    assert call() == 0 and lw.value > 0
+    assert call(rule=1, ratio=0.3, nodes=16) == 0
+    assert call(ratio=0.0) == 0          # 0 stands for the circle
+    assert call(rule=2) == -12
+    assert call(ratio=-0.5) == -12
+    assert call(ratio=float("inf")) == -12
+    assert call(nodes=65) == -12
