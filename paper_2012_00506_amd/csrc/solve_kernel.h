@@ -187,9 +187,10 @@ struct PreT {
 // ---------------------------------------------------------------- MFMA block solve
 // One workgroup per job with one wave per 16 x (16 NC) output tile of a block
 // product ((NB/16) x (T/(16 NC)) waves; a wave with NC > 1 reuses each factor
-// fragment for NC column tiles); LDS holds 3 NB x T blocks.
-template <typename R, int NB, int T, bool PREF, int NC>
-__global__ void __launch_bounds__(NB * 4 * (T / (16 * NC)))
+// fragment for NC column tiles); LDS holds 3 NB x T blocks.  OCC > 1 asks the
+// compiler to fit the registers of OCC waves per SIMD.
+template <typename R, int NB, int T, bool PREF, int NC, int OCC>
+__global__ void __launch_bounds__(NB * 4 * (T / (16 * NC)), OCC)
 k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
              const int16_t* __restrict__ permg, int64_t n, int K,
              const SolveJob* __restrict__ jobs, int njobs) {
@@ -527,41 +528,41 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
 }
 
 
-template <typename R, int NB, int T, bool PREF, int NC>
+template <typename R, int NB, int T, bool PREF, int NC, int OCC>
 int launch_nb(const cx<R>* mats, const cx<R>* matsT, const int16_t* perm, int64_t n, int njobs,
               const SolveJob* jobs_dev, hipStream_t st) {
   const int K = (int)((n + NB - 1) / NB);
   size_t smem = solve_lds_bytes(NB, T, sizeof(cx<R>));
-  (void)hipFuncSetAttribute((const void*)k_band_solve<R, NB, T, PREF, NC>,
+  (void)hipFuncSetAttribute((const void*)k_band_solve<R, NB, T, PREF, NC, OCC>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   (void)hipGetLastError();
   for (int j0 = 0; j0 < njobs; j0 += 1 << 20) {
     int nj = njobs - j0 < (1 << 20) ? njobs - j0 : (1 << 20);
     int grid = 8 * ((nj + 7) / 8);
-    k_band_solve<R, NB, T, PREF, NC><<<grid, NB * 4 * (T / (16 * NC)), smem, st>>>(
+    k_band_solve<R, NB, T, PREF, NC, OCC><<<grid, NB * 4 * (T / (16 * NC)), smem, st>>>(
         mats, matsT, perm, n, K, jobs_dev + j0, nj);
     FB_HIP(hipGetLastError());
   }
   return 0;
 }
 
-template <typename R, int T, bool PREF, int NC>
+template <typename R, int T, bool PREF, int NC, int OCC = 1>
 int launch_t(const cx<R>* mats, const cx<R>* matsT, const int16_t* perm, int64_t n, int nb,
              int njobs, const SolveJob* jobs_dev, hipStream_t st) {
   switch (nb) {
-    case 16: return launch_nb<R, 16, T, PREF, NC>(mats, matsT, perm, n, njobs, jobs_dev, st);
-    case 32: return launch_nb<R, 32, T, PREF, NC>(mats, matsT, perm, n, njobs, jobs_dev, st);
-    case 48: return launch_nb<R, 48, T, PREF, NC>(mats, matsT, perm, n, njobs, jobs_dev, st);
-    case 64: return launch_nb<R, 64, T, PREF, NC>(mats, matsT, perm, n, njobs, jobs_dev, st);
-    case 80: return launch_nb<R, 80, T, PREF, NC>(mats, matsT, perm, n, njobs, jobs_dev, st);
-    case 96: return launch_nb<R, 96, T, PREF, NC>(mats, matsT, perm, n, njobs, jobs_dev, st);
-    case 112: return launch_nb<R, 112, T, PREF, NC>(mats, matsT, perm, n, njobs, jobs_dev, st);
-    case 128: return launch_nb<R, 128, T, PREF, NC>(mats, matsT, perm, n, njobs, jobs_dev, st);
+    case 16: return launch_nb<R, 16, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st);
+    case 32: return launch_nb<R, 32, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st);
+    case 48: return launch_nb<R, 48, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st);
+    case 64: return launch_nb<R, 64, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st);
+    case 80: return launch_nb<R, 80, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st);
+    case 96: return launch_nb<R, 96, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st);
+    case 112: return launch_nb<R, 112, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st);
+    case 128: return launch_nb<R, 128, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st);
     default: return FB_ERR_INTERNAL;
   }
 }
 
-// every (tile width, prefetch, tiles per wave) variant of one precision
+// every (tile width, prefetch, tiles per wave, register cap) variant of one precision
 template <typename R>
 int launch_variant(int variant, const cx<R>* mats, const cx<R>* matsT, const int16_t* perm,
                    int64_t n, int nb, int njobs, const SolveJob* jobs_dev, hipStream_t st) {
@@ -572,6 +573,8 @@ int launch_variant(int variant, const cx<R>* mats, const cx<R>* matsT, const int
     case 3: return launch_t<R, 32, true, 1>(mats, matsT, perm, n, nb, njobs, jobs_dev, st);
     case 4: return launch_t<R, 32, false, 2>(mats, matsT, perm, n, nb, njobs, jobs_dev, st);
     case 5: return launch_t<R, 32, true, 2>(mats, matsT, perm, n, nb, njobs, jobs_dev, st);
+    case 6: return launch_t<R, 16, false, 1, 3>(mats, matsT, perm, n, nb, njobs, jobs_dev, st);
+    case 7: return launch_t<R, 16, true, 1, 3>(mats, matsT, perm, n, nb, njobs, jobs_dev, st);
     default: return FB_ERR_INTERNAL;
   }
 }

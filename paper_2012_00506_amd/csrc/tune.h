@@ -5,12 +5,13 @@
 namespace fb {
 
 // variant v: tile width (16 or 32 right-hand sides), whether the factor
-// fragments of the next block product are prefetched into registers, and
-// how many 16-column tiles one wave computes (1, or 2 for v >= 4)
-constexpr int kNumVariants = 6;
-inline int variant_tile(int v) { return v >= 2 ? 32 : 16; }
+// fragments of the next block product are prefetched into registers, how
+// many 16-column tiles one wave computes (2 for v = 4, 5), and for v = 6, 7
+// (16-column tiles) registers capped for three waves per SIMD
+constexpr int kNumVariants = 8;
+inline int variant_tile(int v) { return (v >= 2 && v < 6) ? 32 : 16; }
 inline bool variant_prefetch(int v) { return (v & 1) != 0; }
-inline int variant_nc(int v) { return v >= 4 ? 2 : 1; }
+inline int variant_nc(int v) { return (v == 4 || v == 5) ? 2 : 1; }
 // dynamic LDS of the block-solve kernel: 2 NB permutation entries and three
 // NB x T blocks of the factors' element type
 inline size_t solve_lds_bytes(int nb, int t, size_t elem) {
