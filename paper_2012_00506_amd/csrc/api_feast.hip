@@ -134,7 +134,6 @@ int filter_apply(const Band& bd, const FactorBufs<R>& f, int ne, const std::vect
                  hipStream_t st) {
   const int64_t n = bd.n;
   const int tile = rb.tile;
-  for (int i : act) FB_TRY(fill_zero(Qc[i], n, m[i], ldqc[i], st));
   const int ndir = cplx ? 2 : 1;
   std::vector<std::pair<int, int>> pairs;
   for (int j = 0; j < ne; ++j)
@@ -184,6 +183,7 @@ int filter_apply(const Band& bd, const FactorBufs<R>& f, int ne, const std::vect
         J.np = np;
         J.m = m[i];
         J.acc_real = cplx ? 0 : 1;
+        J.init = p0 == 0;  // the first pairs of the sum write Q
         for (int p = 0; p < np; ++p) {
           const int j = pairs[p0 + p].first, dir = pairs[p0 + p].second;
           J.X[p] = Xp[(size_t)i * P + p];

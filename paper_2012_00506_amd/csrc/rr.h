@@ -36,7 +36,7 @@ struct AccJob {
   int32_t np;
   int32_t m;
   int32_t acc_real;
-  int32_t pad_;
+  int32_t init;  // 1: Q starts from zero (the first pairs of a sum), not read
 };
 int accumulate_pairs(const AccJob* jobs_dev, int njobs, int64_t n, int max_m, hipStream_t st);
 int gather_cols(const void* src, int64_t lds, bool real_src, c128* dst, int64_t ldd,

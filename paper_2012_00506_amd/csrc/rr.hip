@@ -30,12 +30,13 @@ __global__ void __launch_bounds__(256)
 k_accumulate_pairs(const AccJob* __restrict__ jobs, int64_t n) {
   const AccJob& J = jobs[blockIdx.y];
   const int64_t total = n * J.m;
+  const int np = J.np;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t col = e / n, row = e - col * n;
     c128* q = J.Q + col * J.ldq + row;
-    c128 acc = gld(q);
-    for (int p = 0; p < J.np; ++p) {
+    c128 acc = J.init ? mk(0.0, 0.0) : gld(q);
+    for (int p = 0; p < np; ++p) {
       c128 wv = J.w[p] * gld(J.X[p] + col * J.ldx + row);
       if (J.acc_real)
         acc.x += 2.0 * wv.x;
