@@ -6,8 +6,9 @@
 // rows j..j+b and columns j..j+2b (U widens to bandwidth 2b under row
 // interchanges); it lives in an MR x MC circular window (MR = b+2,
 // MC = 2b+2) indexed by (physical row, column mod MC).  A logical row i
-// maps to a physical row through phys[i mod MR], so a row interchange is
-// an O(1) swap of two table entries.  Row j+b+1 enters during step j into the
+// maps to a physical row through phys[i mod MR] (held as the row's element
+// offset, physical row times MC), so a row interchange is an O(1) swap of
+// two table entries.  Row j+b+1 enters during step j into the
 // physical row freed by row j-1, and its columns j+1 .. j+2b+1 are exactly
 // the window's columns at step j+1.
 //
@@ -134,7 +135,7 @@ k_band_lu(const c128* __restrict__ Bd_, int64_t n, int b, int nb, int K,
 
   // --- init: zero window, load rows 0..b, identity tables, zero block 0 scratch
   for (int e = t; e < MR * MC; e += blockDim.x) W[e] = mk<R>(0, 0);
-  for (int e = t; e < MR; e += blockDim.x) phys[e] = e;
+  for (int e = t; e < MR; e += blockDim.x) phys[e] = e * MC;
   for (int e = t; e < 2 * nb; e += blockDim.x) {
     idx[e] = e;
     lrow[e] = e;
@@ -207,12 +208,12 @@ k_band_lu(const c128* __restrict__ Bd_, int64_t n, int b, int nb, int K,
 #pragma unroll
       for (int q = 0; q < ER; ++q) {
         const int e = t + q * kLuThreads;
-        if (e <= 2 * b) W[(size_t)pr * MC + cslot(1 + e)] = row_entry(cur[q], j, q);
+        if (e <= 2 * b) W[pr + cslot(1 + e)] = row_entry(cur[q], j, q);
       }
     }
     {
       const int cs = cslot(2 * b + 1);
-      for (int r = t; r <= b; r += blockDim.x) W[(size_t)phys[rslot(r)] * MC + cs] = mk<R>(0, 0);
+      for (int r = t; r <= b; r += blockDim.x) W[phys[rslot(r)] + cs] = mk<R>(0, 0);
     }
     if (j + 1 < npad) fetch_row(nxt, j + 1);
     const int par = k & 1;
@@ -233,7 +234,7 @@ k_band_lu(const c128* __restrict__ Bd_, int64_t n, int b, int nb, int K,
       R best = (R)0;
       int bi = 0x7fffffff;
       for (int r = t; r <= nr; r += 64) {
-        cx<R> a = W[(size_t)phys[rslot(r)] * MC + jc];
+        cx<R> a = W[phys[rslot(r)] + jc];
         R v = cabs2(a);
         if (!(v >= (R)0)) v = (R)0;  // a NaN entry is never preferred
         if (bi == 0x7fffffff || v > best) {
@@ -250,14 +251,14 @@ k_band_lu(const c128* __restrict__ Bd_, int64_t n, int b, int nb, int K,
       const int sj = jr, sp = rslot(bi);
       const int physj_old = phys[sj], physp_old = phys[sp];
       const int pw0 = jj + bi;
-      cx<R> piv = W[(size_t)physp_old * MC + jc];
+      cx<R> piv = W[physp_old + jc];
       cx<R> rp = cabs2(piv) > (R)0 ? cinv(piv) : mk<R>(0, 0);
       for (int r = t + 1; r <= nr; r += 64) {
         // after the interchange, window row jj + r holds the old row j when
         // r == bi; its storage row moves with it
         int pr = (r == bi) ? physj_old : phys[rslot(r)];
         int srow = (r == bi) ? lrk[jj] : lrk[jj + r];
-        cx<R> l = W[(size_t)pr * MC + jc] * rp;
+        cx<R> l = W[pr + jc] * rp;
         lvec[r - 1] = l;
         gst(scr + (size_t)jj * 2 * nb + srow, l);
       }
@@ -283,7 +284,7 @@ k_band_lu(const c128* __restrict__ Bd_, int64_t n, int b, int nb, int K,
       for (int e = t; e < 3 * nb; e += blockDim.x) {
         int co = e - jj;  // column offset from j
         cx<R> v = mk<R>(0, 0);
-        if (co >= 0 && co <= nc) v = W[(size_t)prj * MC + cslot(co)];
+        if (co >= 0 && co <= nc) v = W[prj + cslot(co)];
         int which = 2 + e / nb;
         gst(mats + ((size_t)k * 5 + which) * bb + (size_t)(e % nb) * nb + jj, v);
       }
@@ -291,17 +292,35 @@ k_band_lu(const c128* __restrict__ Bd_, int64_t n, int b, int nb, int K,
       // (ucol, ugrp) keeps one column and walks every ugrps-th row
       if (ugrp < ugrps && ucol < nc) {
         const int cs = cslot(ucol + 1);
-        const cx<R> u = W[(size_t)prj * MC + cs];
+        const cx<R> u = W[prj + cs];
         // rows in batches of UB: all loads of a batch before its stores (the
         // rows are distinct physical rows, so nothing aliases)
         constexpr int UB = 8;
         for (int r0 = ugrp; r0 < nr; r0 += UB * ugrps) {
-          size_t a[UB];
+          int a[UB];
           cx<R> v[UB], l[UB];
+          if (r0 + (UB - 1) * ugrps < nr) {
+            // a whole batch in range (every batch but the last few steps'):
+            // no per-row tests
+#pragma unroll
+            for (int q = 0; q < UB; ++q) a[q] = phys[rslot(r0 + q * ugrps + 1)] + cs;
+#pragma unroll
+            for (int q = 0; q < UB; ++q) {
+              v[q] = W[a[q]];
+              l[q] = lvec[r0 + q * ugrps];
+            }
+#pragma unroll
+            for (int q = 0; q < UB; ++q) {
+              v[q].x -= l[q].x * u.x - l[q].y * u.y;
+              v[q].y -= l[q].x * u.y + l[q].y * u.x;
+              W[a[q]] = v[q];
+            }
+            continue;
+          }
 #pragma unroll
           for (int q = 0; q < UB; ++q) {
             const int ro = r0 + q * ugrps;
-            a[q] = ro < nr ? (size_t)phys[rslot(ro + 1)] * MC + cs : 0;
+            a[q] = ro < nr ? phys[rslot(ro + 1)] + cs : 0;
           }
 #pragma unroll
           for (int q = 0; q < UB; ++q) {
