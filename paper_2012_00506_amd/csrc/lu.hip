@@ -184,6 +184,16 @@ k_band_lu(const c128* __restrict__ Bd_, int64_t n, int b, int nb, int K,
     return d > 0 ? mk<R>((R)-v.x, (R)-v.y) : mk<R>((R)-v.x, (R)v.y);
   };
 
+  // this thread's U-row entries e = t + q kLuThreads (e < 3 nb): block
+  // 2 + e / nb, column e % nb, as an element offset within block row k
+  constexpr int UR = 2;  // 3 nb <= 2 kLuThreads for nb <= 128
+  size_t uoff[UR];
+#pragma unroll
+  for (int q = 0; q < UR; ++q) {
+    const int e = t + q * kLuThreads;
+    uoff[q] = (size_t)(2 + e / nb) * bb + (size_t)(e % nb) * nb;
+  }
+
   // update mapping: 2b columns in flight, kLuThreads / 2b row groups
   const int ucols = 2 * b, ugrps = kLuThreads / ucols;
   const int ucol = t % ucols, ugrp = t / ucols;
@@ -281,12 +291,14 @@ k_band_lu(const c128* __restrict__ Bd_, int64_t n, int b, int nb, int K,
     const int prj = phys[jr];
     {
       // U row j: columns k nb .. k nb+3nb-1 of blocks U(k,k), U(k,k+1), U(k,k+2)
-      for (int e = t; e < 3 * nb; e += blockDim.x) {
-        int co = e - jj;  // column offset from j
+#pragma unroll
+      for (int q = 0; q < UR; ++q) {
+        const int e = t + q * kLuThreads;
+        if (e >= 3 * nb) break;
+        const int co = e - jj;  // column offset from j
         cx<R> v = mk<R>(0, 0);
         if (co >= 0 && co <= nc) v = W[prj + cslot(co)];
-        int which = 2 + e / nb;
-        gst(mats + ((size_t)k * 5 + which) * bb + (size_t)(e % nb) * nb + jj, v);
+        gst(mats + (size_t)k * 5 * bb + uoff[q] + jj, v);
       }
       // rank-one update of rows j+1..last, columns j+1..cend: thread
       // (ucol, ugrp) keeps one column and walks every ugrps-th row
@@ -347,22 +359,22 @@ k_band_lu(const c128* __restrict__ Bd_, int64_t n, int b, int nb, int K,
         // (batches of GB elements per thread: all loads of a batch, then
         // its stores)
         constexpr int GB = 8;
-        for (size_t e0 = t; e0 < 2 * bb; e0 += GB * blockDim.x) {
+        const int nbb = 2 * (int)bb;  // 2 nb^2 <= 32768
+        for (int e0 = t; e0 < nbb; e0 += GB * kLuThreads) {
           cx<R> v[GB];
 #pragma unroll
           for (int q = 0; q < GB; ++q) {
-            const size_t e = e0 + (size_t)q * blockDim.x;
-            const size_t ec = e < 2 * bb ? e : 0;
-            const int c = (int)(ec / (2 * nb)), wr = (int)(ec % (2 * nb));
-            v[q] = gld(scr + (size_t)c * 2 * nb + lrk[wr]);
+            const int e = e0 + q * kLuThreads;
+            const int ec = e < nbb ? e : 0;
+            const int c = ec / (2 * nb), wr = ec - c * 2 * nb;
+            v[q] = gld(scr + c * 2 * nb + lrk[wr]);
           }
 #pragma unroll
           for (int q = 0; q < GB; ++q) {
-            const size_t e = e0 + (size_t)q * blockDim.x;
-            if (e >= 2 * bb) continue;
-            const int c = (int)(e / (2 * nb)), wr = (int)(e % (2 * nb));
-            gst(mats + ((size_t)k * 5 + (wr < nb ? 0 : 1)) * bb + (size_t)c * nb +
-                    (wr < nb ? wr : wr - nb),
+            const int e = e0 + q * kLuThreads;
+            if (e >= nbb) continue;
+            const int c = e / (2 * nb), wr = e - c * 2 * nb;
+            gst(mats + ((size_t)k * 5 + (wr < nb ? 0 : 1)) * bb + c * nb + (wr < nb ? wr : wr - nb),
                 v[q]);
           }
         }
