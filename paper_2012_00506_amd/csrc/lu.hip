@@ -31,7 +31,7 @@
 
 namespace fb {
 
-static const int kLuThreads = 256;
+static const int kLuThreads = 512;
 static const size_t kLdsBudget = 160 * 1024;
 
 template <typename R>
