@@ -15,7 +15,7 @@
 
 namespace fb {
 
-static const int kInertiaThreads = 256;
+static const int kInertiaThreads = 512;
 static const size_t kLdsBudget = 160 * 1024;
 
 __device__ __forceinline__ c128 band_entry(const c128* __restrict__ Bd, int64_t n,
