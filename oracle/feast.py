@@ -14,12 +14,13 @@ Readings of points the paper leaves open:
   slice whose residual stays large are spurious (mixtures of eigenvectors
   outside the slice that the unconverged edge of the search subspace
   produces) and are not reported; the exact count is what tells them apart;
-* orthonormalisation (the mass matrix of the standard problem is I):
-  Q is replaced by Q V s^{-1/2} from the eigen-decomposition Q^H Q = V s V^H,
-  dropping directions with s_k <= 1e-14 max(s) (if any are dropped, the
-  next start block keeps the trailing columns of the previous one); the
-  step is applied twice, since one pass leaves Q^H Q - I as large as the
-  rounding error times the spread of s;
+* orthonormalisation (the mass matrix of the standard problem is I): two
+  passes over the eigen-decomposition Q^H Q = V s V^H.  The first forms Q V
+  over every eigenvector and keeps the columns whose norm, measured on the
+  product, exceeds 1e-12 times the largest, each scaled to unit norm; the
+  second replaces that block by Q' V' s'^{-1/2}, dropping directions with
+  s'_k <= 1e-14 max(s') (if any are dropped, the next start block keeps the
+  trailing columns of the previous one);
 * for complex Hermitian B the filter is
   Q = sum_j [w_j (z_j I - B)^{-1} Y + conj(w_j) (z_j I - B)^{-H} Y];
   for real symmetric B with real Y it is Q = sum_j 2 Re[w_j (z_j I - B)^{-1} Y].
@@ -64,35 +65,36 @@ def filter_apply(ab: np.ndarray, factors, w, Y: np.ndarray) -> np.ndarray:
     return Q
 
 
-def _orthonormalise_once(Q: np.ndarray, drop: float, unit_columns: bool = False):
+def _orthonormalise_once(Q: np.ndarray, drop: float):
     G = Q.conj().T @ Q
     G = 0.5 * (G + G.conj().T)
     s, V = np.linalg.eigh(G)
     keep = s > drop * s.max() if s.max() > 0 else np.zeros(len(s), bool)
-    Q1 = (Q @ V[:, keep]) / np.sqrt(s[keep])
-    if unit_columns:
-        nr = np.linalg.norm(Q1, axis=0)
-        Q1 = Q1 / np.where(nr > 0, nr, 1.0)
-    return Q1
+    return (Q @ V[:, keep]) / np.sqrt(s[keep])
 
 
-def orthonormalise(Q: np.ndarray, drop: float = 1e-14, floor: float = 1e-24):
-    """Q V s^{-1/2} over the kept directions of Q^H Q = V s V^H, applied
-    twice: after one pass Q'^H Q' = I + E with E growing with the spread of
-    s (the filtered block is ill-conditioned by design); the second pass
-    brings E to rounding level.  The first pass keeps every direction with
-    s > floor * max(s) and scales each resulting column to unit norm (an
-    eigenvalue solver accurate to eps max(s) in absolute terms, such as a
-    Jacobi method stopped on the off-diagonal norm, leaves the smallest s
-    inaccurate, and with them the scale s^(-1/2)); the rank decision,
-    s > drop * max(s), is taken in the second pass on the well-scaled block.
-    Truncating at drop in the first pass already discards the filtered
-    block's directions below 1e-7 of its largest, and with them the last
-    digits of the wanted eigenvectors: the residuals stall near 1e-8 when
-    the filter damps many directions that far (16 nodes, m0 >= 2m, flat
-    ellipses)."""
-    Q1 = _orthonormalise_once(Q, floor, unit_columns=True)
-    Q2 = _orthonormalise_once(Q1, drop)
+def orthonormalise(Q: np.ndarray, drop: float = 1e-14, floor: float = 1e-12):
+    """Two passes.  The filtered block is ill-conditioned by design: its
+    Gram matrix Q^H Q spans more orders of magnitude than FP64 resolves, so
+    its smallest eigenvalues s_k are rounding noise (often negative) while
+    the directions Q v_k themselves, formed from Q, are still accurate to
+    about eps ||Q|| / ||Q v_k||.  Those directions carry the last digits of
+    the wanted eigenvectors: dropping the ones whose computed s_k is at or
+    below eps max(s) makes the residuals stall (near 1e-10 with 16 nodes
+    from an almost converged block, near 1e-8 when directions below 1e-7 are
+    dropped).  So the first pass takes Q V over every eigenvector, measures
+    each column's norm on the product, keeps the columns above floor times
+    the largest and scales them to unit norm; the second pass
+    orthonormalises that well-scaled block as Q' V' s'^{-1/2} and takes the
+    rank decision, s' > drop max(s'), bringing Q''^H Q'' - I to rounding
+    level."""
+    G = Q.conj().T @ Q
+    G = 0.5 * (G + G.conj().T)
+    _, V = np.linalg.eigh(G)
+    Q1 = Q @ V
+    c = np.linalg.norm(Q1, axis=0)
+    keep = c > floor * c.max() if c.max() > 0 else np.zeros(len(c), bool)
+    Q2 = _orthonormalise_once(Q1[:, keep] / c[keep], drop)
     return Q2, Q2.shape[1]
 
 

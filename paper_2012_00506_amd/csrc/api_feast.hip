@@ -371,14 +371,15 @@ int feast_wave(const Band& bd, int nslice, const double* lo, const double* hi, c
                              Xp.data(), P, acc_dev, zsys, wsys, cplx, o->batched != 0, ir,
                              o->ir_tol, o->ir_max, ir, rb, sys_res, sys_pass, nullptr, st));
     }
-    // ---- orthonormalise: Q^H Q = V s V^H, Q' = Q V s^{-1/2} over s > 1e-24 max s,
-    // columns then scaled to unit norm (the Jacobi solver is accurate to
-    // eps max s in absolute terms, so the smallest s, and the scales
-    // s^{-1/2}, are not); the rank decision, s > 1e-14 max s, is taken in
-    // the second pass on the well-scaled Q'.  Truncating at 1e-14 here already
-    // drops the filtered block's directions below 1e-7 of the largest, and
-    // with them the last digits of the wanted eigenvectors (residuals stall
-    // near 1e-8 under sharp filters).
+    // ---- orthonormalise, pass 1: Q^H Q = V s V^H; Q V over every eigenvector,
+    // each column's norm measured on the product, the columns above 1e-12 of
+    // the largest kept and scaled to unit norm.  The Gram matrix of a filtered
+    // block spans more orders of magnitude than FP64 resolves: its smallest s
+    // are rounding noise (often negative) while the directions Q v formed from
+    // Q are still accurate, and they carry the last digits of the wanted
+    // eigenvectors (dropping those whose computed s is at or below eps max s
+    // stalls the residuals near 1e-10 under a 16-node filter).  The rank
+    // decision, s > 1e-14 max s, is taken in pass 2 on the well-scaled block.
     std::vector<JacobiJob> jj;
     for (int i : act) {
       int m = m0[i];
@@ -398,22 +399,26 @@ int feast_wave(const Band& bd, int nslice, const double* lo, const double* hi, c
       jj.push_back(J);
     }
     FB_TRY(reduced_eig(jj, jj_dev, ew, 60, 1e-14, st));
-    for (int i : act) FB_TRY(gram_keep(sb[i].s, m0[i], 1e-24, sb[i].idx, sb[i].scale, sb[i].kept, st));
+    for (int i : act) {
+      int m = m0[i];
+      // Q V into X; column norms into s
+      FB_TRY(zgemm(st, false, (int)n, m, m, sb[i].Q, n, sb[i].W, m, sb[i].X, n));
+      FB_TRY(col_norm_keep(sb[i].X, n, n, m, 1e-12, sb[i].s, sb[i].idx, sb[i].scale, sb[i].kept,
+                           st));
+    }
     for (int i : act) FB_HIP(hipMemcpyAsync(&kept[i], sb[i].kept, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     FB_HIP(hipStreamSynchronize(st));
     std::vector<int> prev_kept(kept);
     jj.clear();
     for (int i : act) {
-      int m = m0[i], k = kept[i];
+      int k = kept[i];
       if (k <= 0) continue;
-      // V' = W[:, idx] diag(scale) (m x k) into V; Q' = Q V' into X
-      FB_TRY(gather_cols(sb[i].W, m, false, sb[i].V, m, m, k, sb[i].idx, sb[i].scale, st));
-      FB_TRY(zgemm(st, false, (int)n, k, m, sb[i].Q, n, sb[i].V, m, sb[i].X, n));
-      FB_TRY(unit_columns(sb[i].X, n, n, k, st));
-      // second pass: Q'^H Q' = I + E with E growing with the spread of s;
+      // Q' = kept columns of Q V at unit norm, into Q (the filter sum is spent)
+      FB_TRY(gather_cols(sb[i].X, n, false, sb[i].Q, n, n, k, sb[i].idx, sb[i].scale, st));
+      // pass 2: Q'^H Q' = I + E with E growing with the spread of s;
       // orthonormalising Q' once more makes the basis orthonormal to
       // rounding, which the eigen-residual floor needs
-      FB_TRY(zgemm(st, true, k, k, (int)n, sb[i].X, n, sb[i].X, n, sb[i].G, k));
+      FB_TRY(zgemm(st, true, k, k, (int)n, sb[i].Q, n, sb[i].Q, n, sb[i].G, k));
       FB_TRY(hermitize(sb[i].G, k, k, st));
       JacobiJob J{};
       J.m = k;
@@ -440,10 +445,11 @@ int feast_wave(const Band& bd, int nslice, const double* lo, const double* hi, c
     for (int i : act) {
       int k = kept[i];
       if (k <= 0) continue;
-      // Q'' = Q' W2[:, idx] diag(scale) into Q (the filter sum is spent)
+      // Q'' = Q' W2[:, idx] diag(scale) into X, which then trades places with Q
       const int k1 = (int)prev_kept[i];
       FB_TRY(gather_cols(sb[i].W, k1, false, sb[i].V, k1, k1, k, sb[i].idx, sb[i].scale, st));
-      FB_TRY(zgemm(st, false, (int)n, k, k1, sb[i].X, n, sb[i].V, k1, sb[i].Q, n));
+      FB_TRY(zgemm(st, false, (int)n, k, k1, sb[i].Q, n, sb[i].V, k1, sb[i].X, n));
+      std::swap(sb[i].Q, sb[i].X);
       // B Q'' into Y (its trailing columns keep the start vectors)
       FB_TRY(band_matmul(bd, sb[i].Q, n, sb[i].Y, n, k, st));
       // A_q = Q''^H B Q'' (k x k) into G

@@ -72,8 +72,11 @@ size_t eig_work_bytes(const std::vector<int>& ms);
 void carve_eig_work(struct Arena& ar, const std::vector<int>& ms, EigWork& w);
 int reduced_eig(std::vector<JacobiJob> jobs, JacobiJob* jobs_dev, const EigWork& w,
                 int max_sweeps, double tol, hipStream_t st);
-// columns of X (n x k, leading dimension ldx) scaled to unit 2-norm
-int unit_columns(c128* X, int64_t n, int64_t ldx, int k, hipStream_t st);
+// 2-norms of the m columns of X (n x m, leading dimension ldx) into nrm (m
+// doubles); the columns with nrm > thr * max(nrm) listed in idx (ascending)
+// with scale = 1 / nrm, their number in *kept (all device memory)
+int col_norm_keep(const c128* X, int64_t n, int64_t ldx, int m, double thr, double* nrm,
+                  int32_t* idx, double* scale, int32_t* kept, hipStream_t st);
 int gram_keep(const double* s, int m, double drop, int32_t* idx, double* scale, int32_t* kept,
               hipStream_t st);
 

@@ -423,29 +423,42 @@ __global__ void k_gram_keep(const double* __restrict__ s, int m, double drop,
   *kept = k;
 }
 
-// every column of the n x k block X scaled to unit 2-norm (a zero column
-// stays zero): one workgroup per column
+// 2-norm of every column of the n x m block X: one workgroup per column
 __global__ void __launch_bounds__(256)
-k_unit_columns(c128* __restrict__ X, int64_t n, int64_t ldx) {
+k_col_norms(const c128* __restrict__ X, int64_t n, int64_t ldx, double* __restrict__ nrm) {
   __shared__ double red[4];
-  c128* x = X + (int64_t)blockIdx.x * ldx;
+  const c128* x = X + (int64_t)blockIdx.x * ldx;
   double ss = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) ss += cabs2(gld(x + i));
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) ss += cabs2(x[i]);
   for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ss;
   __syncthreads();
-  const double tot = red[0] + red[1] + red[2] + red[3];
-  if (!(tot > 0.0)) return;
-  const double sc = 1.0 / sqrt(tot);
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-    c128 v = gld(x + i);
-    gst(x + i, mk(v.x * sc, v.y * sc));
-  }
+  if (threadIdx.x == 0) nrm[blockIdx.x] = sqrt(red[0] + red[1] + red[2] + red[3]);
 }
 
-int unit_columns(c128* X, int64_t n, int64_t ldx, int k, hipStream_t st) {
-  if (k <= 0) return 0;
-  k_unit_columns<<<k, 256, 0, st>>>(X, n, ldx);
+// keep = nrm > thr * max(nrm): idx lists the kept columns in order, scale = 1 / nrm
+__global__ void k_norm_keep(const double* __restrict__ nrm, int m, double thr,
+                            int32_t* __restrict__ idx, double* __restrict__ scale,
+                            int32_t* __restrict__ kept) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double mx = 0.0;
+  for (int i = 0; i < m; ++i) mx = fmax(mx, nrm[i]);
+  int k = 0;
+  for (int i = 0; i < m; ++i)
+    if (nrm[i] > thr * mx && mx > 0.0) {
+      idx[k] = i;
+      scale[k] = 1.0 / nrm[i];
+      ++k;
+    }
+  *kept = k;
+}
+
+int col_norm_keep(const c128* X, int64_t n, int64_t ldx, int m, double thr, double* nrm,
+                  int32_t* idx, double* scale, int32_t* kept, hipStream_t st) {
+  if (m <= 0) return 0;
+  k_col_norms<<<m, 256, 0, st>>>(X, n, ldx, nrm);
+  FB_HIP(hipGetLastError());
+  k_norm_keep<<<1, 64, 0, st>>>(nrm, m, thr, idx, scale, kept);
   FB_HIP(hipGetLastError());
   return 0;
 }

@@ -209,6 +209,7 @@ def test_feast_contour_variants_against_oracle(fb, rule, ratio, nodes):
     [r] = fb.feast_band_slice(ab, [lo], [hi], [Y], n_nodes=nodes, rule=rule, ratio=ratio)
     print(f"  iters gpu {r.iters} oracle {ora.iters}", flush=True)
     check_slice(r, ab, lo, hi, ref, ora)
+    assert r.iters <= ora.iters + 1
 
 
 @pytest.mark.parametrize("rule,ratio", [("trapezoid", 0.6), ("gauss", 2.0)])

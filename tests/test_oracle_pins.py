@@ -339,3 +339,25 @@ def test_orthonormalise_ill_conditioned_block():
     # same span as Q: projecting Q onto span(Qo) leaves nothing
     R = Q - Qo @ (Qo.conj().T @ Q)
     assert np.linalg.norm(R) < 1e-12 * np.linalg.norm(Q)
+
+
+def test_orthonormalise_keeps_directions_below_gram_resolution():
+    # singular values down to 3e-9 (Gram eigenvalues down to 1e-17, below
+    # what FP64 resolves in Q^H Q): every direction is kept, the result is
+    # orthonormal, and the smallest singular direction lies in its span
+    rng = np.random.default_rng(11)
+    n, m = 300, 40
+    U, _ = np.linalg.qr(rng.standard_normal((n, m)) + 1j * rng.standard_normal((n, m)))
+    W, _ = np.linalg.qr(rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m)))
+    sv = np.concatenate([np.ones(m - 4), [1e-7, 3e-8, 1e-8, 3e-9]])
+    Q = U @ np.diag(sv) @ W
+    Qo, k = feast.orthonormalise(Q)
+    assert k == m
+    assert np.abs(Qo.conj().T @ Qo - np.eye(k)).max() < 1e-13
+    for j in range(m - 4, m):
+        u = U[:, j]
+        assert np.linalg.norm(u - Qo @ (Qo.conj().T @ u)) < 1e-6
+    # an exactly rank-deficient block: the null directions are dropped
+    Z = np.concatenate([Q[:, :10], Q[:, :10] @ rng.standard_normal((10, 5))], axis=1)
+    _, k2 = feast.orthonormalise(Z)
+    assert k2 == 10
