@@ -46,7 +46,8 @@ def test_ratio_one_is_circle_and_symmetric(rule):
 
 
 @pytest.mark.parametrize("nodes,rule,ratio,m0f", [(16, "gauss", 1.0, 1.5), (8, "gauss", 1.0, 3.0),
-                                                  (12, "trapezoid", 0.3, 1.5)])
+                                                  (12, "trapezoid", 0.3, 1.5),
+                                                  (8, "zolotarev", 0.9, 1.5)])
 def test_sharp_filters_converge(nodes, rule, ratio, m0f):
     """Filters that damp many directions of the block below 1e-7 (16 nodes,
     m0 = 3m, a flat ellipse): FEAST reaches 1e-10 (the rank decision of the
@@ -65,3 +66,68 @@ def test_sharp_filters_converge(nodes, rule, ratio, m0f):
     r = ofeast.feast_slice(ab, lo, hi, Y, n_nodes=nodes, rule=rule, ratio=ratio, max_iter=8)
     assert r.info == 0 and len(r.lam) == m and r.iters <= 4
     assert np.abs(r.lam - lam[(lam >= lo) & (lam < hi)]).max() <= 1e-12 * oband.norm1(ab)
+
+
+@pytest.mark.parametrize("k", [0.3, 0.9, 0.99999])
+def test_elliptic_functions_against_library(k):
+    from scipy.special import ellipj, ellipk
+    assert abs(q.elliptic_k(k) - ellipk(k * k)) <= 1e-14 * ellipk(k * k)
+    for u in (0.05, 0.6, 1.4, 0.99 * ellipk(k * k)):
+        sn, cn, dn = q.jacobi_sn_cn_dn(u, k)
+        ref = ellipj(u, k * k)[:3]
+        # near k = 1 and u = K the small cn is conditioned like eps K / cn
+        np.testing.assert_allclose([sn, cn, dn], ref, rtol=1e-11, atol=1e-14)
+
+
+@pytest.mark.parametrize("m,ell", [(3, 0.05), (6, 1e-2), (8, 1e-3)])
+def test_zolotarev_equioscillates(m, ell):
+    """Z - 1 reaches +-delta with alternating signs at the 2m + 1 points
+    x_j = ell / dn(j K'/(2m); k') of [ell, 1] and stays within delta between
+    them: the alternation property of the best approximation."""
+    c, M, delta, Kp = q.zolotarev_sign(m, ell)
+    kp = np.sqrt(1 - ell * ell)
+
+    def Z(x):
+        num, den = M * x, 1.0
+        for j in range(1, m):
+            num = num * (x * x + c[2 * j - 1])
+        for j in range(1, m + 1):
+            den = den * (x * x + c[2 * j - 2])
+        return num / den
+    # dn(K'; k') = ell gives x = 1 at j = 2m (cos phi_0 / cos(phi_1 - phi_0) is 0/0 there)
+    xs = np.array([ell / q.jacobi_sn_cn_dn(j * Kp / (2 * m), kp)[2] for j in range(2 * m)] + [1.0])
+    assert abs(xs[0] - ell) < 1e-15 and np.all(np.diff(xs) > 0)
+    e = Z(xs) - 1.0
+    np.testing.assert_allclose(np.abs(e), delta, rtol=1e-9, atol=1e-12)
+    assert np.all(np.sign(e[:-1]) == -np.sign(e[1:]))
+    grid = np.geomspace(ell, 1.0, 200001)
+    assert np.abs(Z(grid) - 1.0).max() <= delta * (1 + 1e-9)
+    assert 0 < delta < 1
+
+
+@pytest.mark.parametrize("m,b", [(4, 0.9), (8, 0.95), (6, 0.8)])
+def test_zolotarev_filter_shape(m, b):
+    """The FEAST form of the Zolotarev filter: poles on the circle through
+    the slice ends, the node sum plus the dropped constant equal to
+    (1 + Z(x(t))) / 2, within delta of 1 on |t| <= b and of 0 on |t| >= 1/b."""
+    lo, hi = -1.0, 3.0
+    cc, rr = 1.0, 2.0
+    z, w = q.contour(lo, hi, m, "zolotarev", b)
+    t, wt, finf, (ell, M, c, delta) = q.zolotarev_filter(m, b)
+    assert np.all(z.imag > 0) and np.abs(np.abs(z - cc) - rr).max() < 1e-14
+    tt = np.linspace(-4, 4, 4001)
+    tt = tt[np.abs(np.abs(tt) - 1) > 1e-6]
+    f = q.filter_value(cc + rr * tt, z, w)
+    s = np.sqrt(ell)
+    x = s * (1 + tt) / (1 - tt)
+    num, den = M * x, 1.0
+    for j in range(1, m):
+        num = num * (x * x + c[2 * j - 1])
+    for j in range(1, m + 1):
+        den = den * (x * x + c[2 * j - 2])
+    np.testing.assert_allclose(f + finf, 0.5 * (1 + num / den), rtol=0, atol=1e-13)
+    assert np.abs(f[np.abs(tt) <= b] - 1).max() <= delta * (1 + 1e-9)
+    assert np.abs(f[np.abs(tt) >= 1 / b]).max() <= delta * (1 + 1e-9)
+    assert abs(finf) <= 0.5 * delta * (1 + 1e-9)
+    with pytest.raises(ValueError):
+        q.contour(lo, hi, m, "zolotarev", 1.0)
