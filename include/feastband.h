@@ -124,11 +124,19 @@ typedef struct {
                           eq:integral): 0 Gauss-Legendre in the angle of the
                           upper half, 1 trapezoid (midpoint) rule with 2 n_nodes
                           equispaced angles on the whole curve, of which the
-                          n_nodes on the upper half are used */
-  double ratio;        /* vertical over horizontal semi-axis of the contour
-                          through the slice ends: 1 (or 0) the circle, other
-                          positive values an ellipse
-                          z(t) = c + r (cos t + i ratio sin t) */
+                          n_nodes on the upper half are used, 2 the Zolotarev
+                          rational filter (Section 2.2 names it): the best
+                          uniform rational approximation of sign composed
+                          with a Moebius map of the slice, n_nodes poles on
+                          the upper half of the circle through the slice
+                          ends; within its error delta of 1 on the inner
+                          fraction |lambda - c| <= ratio r and of 0 beyond
+                          r / ratio (c, r: centre and half width) */
+  double ratio;        /* rules 0 and 1: vertical over horizontal semi-axis
+                          of the contour through the slice ends: 1 (or 0) the
+                          circle, other positive values an ellipse
+                          z(t) = c + r (cos t + i ratio sin t); rule 2: the
+                          inner fraction, 0 < ratio < 1 */
 } fb_feast_opts;
 
 /* FEAST on the slices [lo_i, hi_i) of B (Algorithm alg:FEAST, Section 2.2,
@@ -341,6 +349,18 @@ int planner_train_step(void* weights, void* opt_state, int32_t batch, const floa
                        void* work, size_t* lwork, void* stream);
 
 const char* fb_strerror(int code);
+
+/* Nodes z_j and weights w_j, j = 1..k, of the filter
+ * r(x) = sum_j 2 Re[w_j / (z_j - x)] that FEAST applies on the slice
+ * [lo, hi) (Section 2.2, the quadrature of eq:integral), for the rule and
+ * ratio of fb_feast_opts; the lower half of the contour is the conjugate of
+ * the upper.  z and w: caller-owned host arrays of 2k doubles, written as
+ * interleaved (real, imaginary) pairs.  Host only: touches no device.
+ * Returns 0; -1 / -2 for a non-finite lo or hi <= lo; -3 for k outside
+ * 1..64; -4 for an unknown rule; -5 for a ratio the rule does not take;
+ * -6 / -7 for a null z / w. */
+int fb_contour(double lo, double hi, int32_t k, int32_t rule, double ratio, double* z,
+               double* w);
 
 /* Device properties used by the library (for reports): compute units and
  * the device name, written to name (cap bytes). */

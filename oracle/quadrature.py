@@ -68,23 +68,26 @@ def gauss_legendre(k: int):
     return x, w
 
 
-def elliptic_k(k: float) -> float:
+def elliptic_k(k: float, kc: float | None = None) -> float:
     """Complete elliptic integral of the first kind K(k) (modulus k) by the
-    arithmetic-geometric mean: K = pi / (2 AGM(1, sqrt(1 - k^2)))."""
-    a, b = 1.0, np.sqrt(1.0 - k * k)
-    while abs(a - b) > 1e-16 * a:
+    arithmetic-geometric mean: K = pi / (2 AGM(1, k_c)), k_c = sqrt(1 - k^2)
+    (pass k_c when it is known exactly: 1 - k^2 cancels for k near 1)."""
+    a, b = 1.0, np.sqrt(1.0 - k * k) if kc is None else kc
+    for _ in range(64):                # converges quadratically; rounding can
+        if abs(a - b) <= 4e-16 * a:     # leave a and b an ulp apart for good
+            break
         a, b = 0.5 * (a + b), np.sqrt(a * b)
     return np.pi / (2.0 * a)
 
 
-def jacobi_sn_cn_dn(u: float, k: float):
+def jacobi_sn_cn_dn(u: float, k: float, kc: float | None = None):
     """Jacobi elliptic functions sn, cn, dn of argument u and modulus k by the
     descending Landen (AGM) scheme: a_0 = 1, b_0 = sqrt(1 - k^2), c_0 = k;
     a_{i+1} = (a_i + b_i)/2, b_{i+1} = sqrt(a_i b_i), c_{i+1} = (a_i - b_i)/2;
     phi_N = 2^N a_N u, phi_{i-1} = (phi_i + asin(c_i sin(phi_i) / a_i)) / 2;
     sn = sin phi_0, cn = cos phi_0, dn = cos phi_0 / cos(phi_1 - phi_0)."""
-    a, b, c = [1.0], [np.sqrt(1.0 - k * k)], [k]
-    while abs(c[-1]) > 1e-16 * a[-1] and len(a) < 64:
+    a, b, c = [1.0], [np.sqrt(1.0 - k * k) if kc is None else kc], [k]
+    while abs(c[-1]) > 4e-16 * a[-1] and len(a) < 64:
         a.append(0.5 * (a[-1] + b[-1]))
         b.append(np.sqrt(a[-2] * b[-1]))
         c.append(0.5 * (a[-2] - b[-2]))
@@ -104,10 +107,10 @@ def zolotarev_sign(m: int, ell: float):
     Z(x) = M x prod_{j<m}(x^2 + c_{2j}) / prod_{j<=m}(x^2 + c_{2j-1}) and
     max |Z - 1| on [ell, 1] = delta."""
     kp = np.sqrt(1.0 - ell * ell)
-    Kp = elliptic_k(kp)
+    Kp = elliptic_k(kp, ell)
     cj = np.zeros(2 * m)                      # cj[j] = c_j, j = 1..2m-1
     for j in range(1, 2 * m):
-        sn, cn, _ = jacobi_sn_cn_dn(j * Kp / (2 * m), kp)
+        sn, cn, _ = jacobi_sn_cn_dn(j * Kp / (2 * m), kp, ell)
         cj[j] = ell * ell * sn * sn / (cn * cn)
     def zt(x):
         num, den = x, 1.0
@@ -116,7 +119,7 @@ def zolotarev_sign(m: int, ell: float):
         for j in range(1, m + 1):
             den = den * (x * x + cj[2 * j - 1])
         return num / den
-    _, _, dn1 = jacobi_sn_cn_dn(Kp / (2 * m), kp)
+    _, _, dn1 = jacobi_sn_cn_dn(Kp / (2 * m), kp, ell)
     lo_v, hi_v = zt(ell), zt(ell / dn1)        # a minimum and a maximum
     M = 2.0 / (lo_v + hi_v)
     return cj[1:], M, (hi_v - lo_v) / (hi_v + lo_v), Kp

@@ -80,6 +80,7 @@ SIGNATURES = {
     "planner_train_step": (C.c_int, [P, P, C.c_int32, P, P, C.c_float, C.c_int32,
                                      C.POINTER(C.c_float), P, P, PSZ, P]),
     "fb_strerror": (C.c_char_p, [C.c_int]),
+    "fb_contour": (C.c_int, [C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_double, PD, PD]),
     "fb_device_info": (C.c_int, [PI32, C.c_char_p, C.c_int32]),
 }
 

@@ -173,7 +173,18 @@ class SliceResult:
 
 
 # quadrature rules of the contour integral (fb_feast_opts.rule)
-_RULES = {"gauss": 0, "trapezoid": 1}
+_RULES = {"gauss": 0, "trapezoid": 1, "zolotarev": 2}
+
+
+def contour_nodes(lo, hi, k=8, rule="gauss", ratio=1.0):
+    """Upper-half nodes z and weights w (complex arrays of length k) of the
+    filter r(x) = sum_j 2 Re[w_j / (z_j - x)] on [lo, hi); host only."""
+    z = np.zeros(2 * k)
+    w = np.zeros(2 * k)
+    N.check("fb_contour", N.lib().fb_contour(float(lo), float(hi), int(k), _RULES[rule],
+                                              float(ratio), z.ctypes.data_as(N.PD),
+                                              w.ctypes.data_as(N.PD)))
+    return z[0::2] + 1j * z[1::2], w[0::2] + 1j * w[1::2]
 
 
 def feast_band_slice(B, lo, hi, Y, m_expected=None, n_nodes=8, tol=1e-10, max_iter=20,

@@ -58,19 +58,110 @@ void gauss_legendre(int k, std::vector<double>& x, std::vector<double>& w) {
   }
 }
 
+// Descending Landen (arithmetic-geometric mean) chain of modulus k with
+// complementary modulus kc = sqrt(1 - k^2), given separately because 1 - k^2
+// cancels for k near 1: a_0 = 1, b_0 = kc, c_0 = k; a_{i+1} = (a_i + b_i)/2,
+// b_{i+1} = sqrt(a_i b_i), c_{i+1} = (a_i - b_i)/2.  K(k) = pi / (2 a_N).
+struct LandenChain {
+  double a[48], c[48];
+  int n = 0;
+};
+
+static LandenChain landen(double k, double kc) {
+  LandenChain g;
+  g.a[0] = 1.0;
+  g.c[0] = k;
+  double b = kc;
+  while (g.n < 47 && fabs(g.c[g.n]) > 4e-16 * g.a[g.n]) {
+    const double an = g.a[g.n];
+    g.a[g.n + 1] = 0.5 * (an + b);
+    g.c[g.n + 1] = 0.5 * (an - b);
+    b = sqrt(an * b);
+    ++g.n;
+  }
+  return g;
+}
+
+// Jacobi sn, cn, dn of argument u on the chain: phi_N = 2^N a_N u,
+// phi_{i-1} = (phi_i + asin(c_i sin(phi_i) / a_i)) / 2, sn = sin phi_0,
+// cn = cos phi_0, dn = cn / cos(phi_1 - phi_0)
+static void jacobi_sncndn(double u, const LandenChain& g, double* sn, double* cn, double* dn) {
+  double phi = ldexp(g.a[g.n] * u, g.n), phi1 = phi;
+  for (int i = g.n; i >= 1; --i) {
+    phi1 = phi;
+    phi = 0.5 * (phi + asin(g.c[i] * sin(phi) / g.a[i]));
+  }
+  *sn = sin(phi);
+  *cn = cos(phi);
+  *dn = g.n > 0 ? *cn / cos(phi1 - phi) : 1.0;
+}
+
+// Zolotarev filter on the scaled slice t in (-1, 1) with inner fraction b:
+// Z(x) = M x prod_{j<m}(x^2 + c_{2j}) / prod_{j<=m}(x^2 + c_{2j-1}), the best
+// type (2m-1, 2m) approximation of sign(x) on [-1, -l] U [l, 1] with
+// c_j = l^2 sn^2 / cn^2 (j K'/(2m); k'), k' = sqrt(1 - l^2),
+// l = ((1 - b)/(1 + b))^2; M centres the error, whose extrema on [l, 1] are at
+// x = l / dn(j K'/(2m); k').  With x = s (1 + t)/(1 - t), s = sqrt(l), the
+// filter (1 + Z(x(t)))/2 has its poles t_q = (i a - s)/(i a + s),
+// a = sqrt(c_{2q-1}), on the unit circle; its pole part gives
+// w_q = -rho_q s ((s^2 - a^2) - 2 i a s) / (a^2 + s^2)^2 with rho_q the residue
+// of Z at x = i a.  The constant (1 + Z(-s))/2, below half the error, is left
+// out so that the filter keeps the form sum_q 2 Re[w_q / (t_q - t)].
+static void zolotarev_nodes(int m, double b, std::vector<c128>& t, std::vector<c128>& w) {
+  const double l = ((1.0 - b) / (1.0 + b)) * ((1.0 - b) / (1.0 + b));
+  const double s = sqrt(l);
+  const LandenChain g = landen(sqrt((1.0 - l) * (1.0 + l)), l);
+  const double Kp = M_PI / (2.0 * g.a[g.n]);
+  std::vector<double> c(2 * m, 0.0);  // c[1..2m-1]
+  double sn, cn, dn;
+  for (int j = 1; j < 2 * m; ++j) {
+    jacobi_sncndn(j * Kp / (2.0 * m), g, &sn, &cn, &dn);
+    c[j] = l * l * (sn * sn) / (cn * cn);
+  }
+  auto zt = [&](double x) {
+    double num = x, den = 1.0;
+    for (int j = 1; j < m; ++j) num *= x * x + c[2 * j];
+    for (int j = 1; j <= m; ++j) den *= x * x + c[2 * j - 1];
+    return num / den;
+  };
+  jacobi_sncndn(Kp / (2.0 * m), g, &sn, &cn, &dn);
+  const double M = 2.0 / (zt(l) + zt(l / dn));
+  t.resize(m);
+  w.resize(m);
+  for (int q = 1; q <= m; ++q) {
+    const double a2 = c[2 * q - 1], a = sqrt(a2);
+    double num = M, den = 2.0;
+    for (int j = 1; j < m; ++j) num *= c[2 * j] - a2;
+    for (int j = 1; j <= m; ++j)
+      if (j != q) den *= c[2 * j - 1] - a2;
+    const double rho = num / den, d = a2 + l;
+    t[q - 1] = mk((a2 - l) / d, 2.0 * a * s / d);
+    w[q - 1] = mk(-rho * s * (l - a2) / (d * d), 2.0 * rho * l * a / (d * d));
+  }
+}
+
 // Nodes and weights on the upper half of the contour through the slice ends,
 // z(t) = c + r (cos t + i rho sin t) (rho = 1: the circle), for
 // P = (1/(2 pi i)) \oint (zI - B)^{-1} dz with the lower half by conjugation:
 // w_j = (dt_j / (2 pi)) z'(t_j) / i = (dt_j / (2 pi)) r (rho cos t_j + i sin t_j).
 // rule 0: Gauss-Legendre in t on [0, pi], t_j = (pi/2)(1 - x_j),
 // dt_j = (pi/2) omega_j, so w_j = (omega_j / 4) r (rho cos t_j + i sin t_j);
-// rule 1: midpoint angles t_j = pi (j + 1/2) / k, dt_j = pi / k.
+// rule 1: midpoint angles t_j = pi (j + 1/2) / k, dt_j = pi / k;
+// rule 2: the Zolotarev filter with inner fraction ratio, mapped to the slice.
 void contour(double lo, double hi, int k, int rule, double ratio, std::vector<c128>& z,
              std::vector<c128>& w) {
+  double c = 0.5 * (lo + hi), r = 0.5 * (hi - lo);
+  if (rule == 2) {
+    zolotarev_nodes(k, ratio, z, w);
+    for (int j = 0; j < k; ++j) {
+      z[j] = mk(c + r * z[j].x, r * z[j].y);
+      w[j] = mk(r * w[j].x, r * w[j].y);
+    }
+    return;
+  }
   const double rho = ratio > 0.0 ? ratio : 1.0;
   std::vector<double> x, om;
   if (rule == 0) gauss_legendre(k, x, om);
-  double c = 0.5 * (lo + hi), r = 0.5 * (hi - lo);
   z.resize(k);
   w.resize(k);
   for (int j = 0; j < k; ++j) {
@@ -80,6 +171,13 @@ void contour(double lo, double hi, int k, int rule, double ratio, std::vector<c1
     z[j] = mk(c + r * ct, r * rho * st);
     w[j] = mk(f * r * rho * ct, f * r * st);
   }
+}
+
+// rule and ratio as fb_feast_opts takes them
+static bool contour_ok(int rule, double ratio) {
+  if (rule == 0 || rule == 1) return ratio >= 0.0 && isfinite(ratio);
+  if (rule == 2) return ratio > 0.0 && ratio < 1.0;
+  return false;
 }
 
 // ---------------------------------------------------------------- rocBLAS
@@ -623,7 +721,7 @@ extern "C" int feast_band_slice(const fb_band* B, int32_t nslice, const double* 
   if (!o) return -14;
   if (!lwork) return -16;
   if (o->n_nodes < 1 || o->n_nodes > 64 || !(o->tol > 0) || o->max_iter < 1) return -14;
-  if ((o->rule != 0 && o->rule != 1) || !(o->ratio >= 0) || !isfinite(o->ratio)) return -14;
+  if (!contour_ok(o->rule, o->ratio)) return -14;
   if (o->precision != 0 && o->precision != 1) return -14;
   if (o->precision == 1 && (!(o->ir_tol > 0) || o->ir_max < 0)) return -14;
   for (int i = 0; i < nslice; ++i) {
@@ -759,7 +857,7 @@ extern "C" int feast_filter(const fb_band* B, int32_t nslice, const double* lo, 
   if (!o) return -12;
   if (!lwork) return -14;
   if (o->n_nodes < 1 || o->n_nodes > 64) return -12;
-  if ((o->rule != 0 && o->rule != 1) || !(o->ratio >= 0) || !isfinite(o->ratio)) return -12;
+  if (!contour_ok(o->rule, o->ratio)) return -12;
   if (o->precision != 0 && o->precision != 1) return -12;
   if (o->precision == 1 && (!(o->ir_tol > 0) || o->ir_max < 0)) return -12;
   for (int i = 0; i < nslice; ++i) {
@@ -778,4 +876,24 @@ extern "C" int feast_filter(const fb_band* B, int32_t nslice, const double* lo, 
                               st);
   return filter_impl<double>(B, nslice, lo, hi, m, Y, ldy, Q, ldq, resid, passes, o, work, lwork,
                              st);
+}
+
+extern "C" int fb_contour(double lo, double hi, int32_t k, int32_t rule, double ratio, double* z,
+                          double* w) {
+  if (!isfinite(lo)) return -1;
+  if (!isfinite(hi) || !(hi > lo)) return -2;
+  if (k < 1 || k > 64) return -3;
+  if (rule < 0 || rule > 2) return -4;
+  if (!contour_ok(rule, ratio)) return -5;
+  if (!z) return -6;
+  if (!w) return -7;
+  std::vector<c128> zz, ww;
+  contour(lo, hi, k, rule, ratio, zz, ww);
+  for (int j = 0; j < k; ++j) {
+    z[2 * j] = zz[j].x;
+    z[2 * j + 1] = zz[j].y;
+    w[2 * j] = ww[j].x;
+    w[2 * j + 1] = ww[j].y;
+  }
+  return 0;
 }

@@ -160,7 +160,45 @@ def test_feast_filter_contour_options_checked(L):
     assert call() == 0 and lw.value > 0
     assert call(rule=1, ratio=0.3, nodes=16) == 0
     assert call(ratio=0.0) == 0          # 0 stands for the circle
-    assert call(rule=2) == -12
+    assert call(rule=2, ratio=0.9) == 0   # Zolotarev, inner fraction 0.9
+    assert call(rule=2) == -12             # ratio 1 is no inner fraction
+    assert call(rule=3) == -12
     assert call(ratio=-0.5) == -12
     assert call(ratio=float("inf")) == -12
     assert call(nodes=65) == -12
+
+
+@pytest.mark.parametrize("rule,ratio,k", [("gauss", 1.0, 8), ("gauss", 0.4, 16),
+                                          ("trapezoid", 0.6, 12), ("zolotarev", 0.9, 8),
+                                          ("zolotarev", 0.95, 16), ("zolotarev", 0.6, 3)])
+def test_contour_nodes_match_oracle(rule, ratio, k):
+    """The library's nodes and weights (host code, no GPU) against the
+    oracle's for every rule; for the Zolotarev rule this also pins the
+    library's elliptic functions."""
+    from oracle import quadrature as oq
+    from paper_2012_00506_amd.api import contour_nodes
+    lo, hi = -2.5, 4.0
+    z, w = contour_nodes(lo, hi, k, rule, ratio)
+    zo, wo = oq.contour(lo, hi, k, rule, ratio)
+    assert np.abs(z - zo).max() <= 1e-13 * (hi - lo)
+    assert np.abs(w - wo).max() <= 1e-12 * np.abs(wo).max()
+    x = np.linspace(lo - 3, hi + 3, 301)
+    np.testing.assert_allclose(oq.filter_value(x, z, w), oq.filter_value(x, zo, wo),
+                               rtol=0, atol=1e-12)
+
+
+def test_contour_argument_errors(L):
+    from paper_2012_00506_amd import _native as N
+    z = np.zeros(16)
+    w = np.zeros(16)
+    zp, wp = z.ctypes.data_as(N.PD), w.ctypes.data_as(N.PD)
+    assert L.fb_contour(0.0, 1.0, 8, 2, 0.9, zp, wp) == 0
+    assert L.fb_contour(float("nan"), 1.0, 8, 0, 1.0, zp, wp) == -1
+    assert L.fb_contour(1.0, 1.0, 8, 0, 1.0, zp, wp) == -2
+    assert L.fb_contour(0.0, 1.0, 0, 0, 1.0, zp, wp) == -3
+    assert L.fb_contour(0.0, 1.0, 8, 3, 1.0, zp, wp) == -4
+    assert L.fb_contour(0.0, 1.0, 8, 2, 1.0, zp, wp) == -5
+    assert L.fb_contour(0.0, 1.0, 8, 2, 0.0, zp, wp) == -5
+    assert L.fb_contour(0.0, 1.0, 8, 0, -1.0, zp, wp) == -5
+    assert L.fb_contour(0.0, 1.0, 8, 0, 1.0, None, wp) == -6
+    assert L.fb_contour(0.0, 1.0, 8, 0, 1.0, zp, None) == -7

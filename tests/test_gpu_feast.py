@@ -194,10 +194,12 @@ def test_feast_waves_equal_one_wave(fb):
 
 
 @pytest.mark.parametrize("rule,ratio,nodes", [("gauss", 0.5, 8), ("trapezoid", 1.0, 8),
-                                              ("trapezoid", 0.6, 12), ("gauss", 1.0, 16)])
+                                              ("trapezoid", 0.6, 12), ("gauss", 1.0, 16),
+                                              ("zolotarev", 0.9, 8)])
 def test_feast_contour_variants_against_oracle(fb, rule, ratio, nodes):
     """Other contours and rules (an ellipse through the slice ends, the
-    midpoint rule, 16 nodes): the same bars as the default half circle."""
+    midpoint rule, 16 nodes, the Zolotarev filter): the same bars as the
+    default half circle."""
     print(f"feast contour {rule} ratio={ratio} nodes={nodes}", flush=True)
     n = 300
     ab = synth.band_matrix(n, 6, 12, True, -8, 8)
@@ -212,7 +214,7 @@ def test_feast_contour_variants_against_oracle(fb, rule, ratio, nodes):
     assert r.iters <= ora.iters + 1
 
 
-@pytest.mark.parametrize("rule,ratio", [("trapezoid", 0.6), ("gauss", 2.0)])
+@pytest.mark.parametrize("rule,ratio", [("trapezoid", 0.6), ("gauss", 2.0), ("zolotarev", 0.85)])
 def test_filter_contour_variants_against_oracle(fb, rule, ratio):
     """feast_filter with another contour: Q against the oracle's node sum
     (FP64 solves: kappa n eps)."""

@@ -95,7 +95,8 @@ def test_zolotarev_equioscillates(m, ell):
             den = den * (x * x + c[2 * j - 2])
         return num / den
     # dn(K'; k') = ell gives x = 1 at j = 2m (cos phi_0 / cos(phi_1 - phi_0) is 0/0 there)
-    xs = np.array([ell / q.jacobi_sn_cn_dn(j * Kp / (2 * m), kp)[2] for j in range(2 * m)] + [1.0])
+    xs = np.array([ell / q.jacobi_sn_cn_dn(j * Kp / (2 * m), kp, ell)[2]
+                   for j in range(2 * m)] + [1.0])
     assert abs(xs[0] - ell) < 1e-15 and np.all(np.diff(xs) > 0)
     e = Z(xs) - 1.0
     np.testing.assert_allclose(np.abs(e), delta, rtol=1e-9, atol=1e-12)
