@@ -231,3 +231,23 @@ def test_filter_contour_variants_against_oracle(fb, rule, ratio):
     Qr = ofeast.filter_apply(ab, F, w, Yh)
     err = np.linalg.norm(r.Q[0].cpu().numpy() - Qr) / np.linalg.norm(Qr)
     assert err <= 1e-11, err
+
+
+@pytest.mark.parametrize("cplx,precision", [(False, 0), (True, 1), (False, 1)])
+def test_feast_zolotarev_real_and_mixed(fb, cplx, precision):
+    """The Zolotarev rule on a real symmetric band (N solves only) and in the
+    complex64 + FP64 refinement path: the same eigenvalues as the dense
+    solver, and as the oracle run with the same filter."""
+    print(f"zolotarev cplx={cplx} precision={precision}", flush=True)
+    n = 400
+    ab = synth.band_matrix(n, 8, 31, cplx, -6, 6)
+    lam_all = np.linalg.eigvalsh(oband.dense_from_band(ab))
+    lo, hi = -0.9, 1.4
+    ref = lam_all[(lam_all >= lo) & (lam_all < hi)]
+    Yh, Y = start_block(fb, n, m0_rule(len(ref)), 17, cplx)
+    ora = ofeast.feast_slice(ab, lo, hi, Yh, n_nodes=8, rule="zolotarev", ratio=0.9)
+    [r] = fb.feast_band_slice(ab, [lo], [hi], [Y], n_nodes=8, rule="zolotarev", ratio=0.9,
+                              precision=precision)
+    print(f"  m={len(ref)} iters gpu {r.iters} oracle {ora.iters}", flush=True)
+    check_slice(r, ab, lo, hi, ref, ora)
+    assert r.iters <= ora.iters + 1
