@@ -170,7 +170,8 @@ def test_feast_filter_contour_options_checked(L):
 
 @pytest.mark.parametrize("rule,ratio,k", [("gauss", 1.0, 8), ("gauss", 0.4, 16),
                                           ("trapezoid", 0.6, 12), ("zolotarev", 0.9, 8),
-                                          ("zolotarev", 0.95, 16), ("zolotarev", 0.6, 3)])
+                                          ("zolotarev", 0.95, 16), ("zolotarev", 0.6, 3),
+                                          ("zolotarev", 0.5, 1), ("zolotarev", 0.99, 64)])
 def test_contour_nodes_match_oracle(rule, ratio, k):
     """The library's nodes and weights (host code, no GPU) against the
     oracle's for every rule; for the Zolotarev rule this also pins the

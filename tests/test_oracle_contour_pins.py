@@ -79,7 +79,7 @@ def test_elliptic_functions_against_library(k):
         np.testing.assert_allclose([sn, cn, dn], ref, rtol=1e-11, atol=1e-14)
 
 
-@pytest.mark.parametrize("m,ell", [(3, 0.05), (6, 1e-2), (8, 1e-3)])
+@pytest.mark.parametrize("m,ell", [(1, 0.3), (3, 0.05), (6, 1e-2), (8, 1e-3), (16, 1e-3)])
 def test_zolotarev_equioscillates(m, ell):
     """Z - 1 reaches +-delta with alternating signs at the 2m + 1 points
     x_j = ell / dn(j K'/(2m); k') of [ell, 1] and stays within delta between
@@ -102,7 +102,8 @@ def test_zolotarev_equioscillates(m, ell):
     np.testing.assert_allclose(np.abs(e), delta, rtol=1e-9, atol=1e-12)
     assert np.all(np.sign(e[:-1]) == -np.sign(e[1:]))
     grid = np.geomspace(ell, 1.0, 200001)
-    assert np.abs(Z(grid) - 1.0).max() <= delta * (1 + 1e-9)
+    # allowance: rounding of Z near 1 (a product of 4m - 1 factors) and of its coefficients
+    assert np.abs(Z(grid) - 1.0).max() <= delta * (1 + 1e-9) + 1e-12
     assert 0 < delta < 1
 
 
