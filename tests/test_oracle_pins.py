@@ -325,14 +325,14 @@ def test_planner_whole_spectrum_when_gershgorin_is_tight():
 
 
 def test_orthonormalise_ill_conditioned_block():
-    # a block whose Gram matrix spans 12 orders of magnitude, like a filtered
+    # a block whose Gram matrix spans 14 orders of magnitude, like a filtered
     # FEAST block: the result is orthonormal to rounding and spans the kept
     # directions
     rng = np.random.default_rng(5)
     n, m = 400, 60
     U, _ = np.linalg.qr(rng.standard_normal((n, m)) + 1j * rng.standard_normal((n, m)))
     W, _ = np.linalg.qr(rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m)))
-    Q = U @ np.diag(10.0 ** -np.linspace(0, 6, m)) @ W
+    Q = U @ np.diag(10.0 ** -np.linspace(0, 7, m)) @ W
     Qo, k = feast.orthonormalise(Q)
     assert k == m
     assert np.abs(Qo.conj().T @ Qo - np.eye(k)).max() < 1e-13
