@@ -41,6 +41,7 @@ extern "C" {
 #define FB_ERR_NOMEM (-2004)      /* workspace or HBM budget below one unit of work */
 #define FB_ERR_NONFINITE (-2005)  /* NaN or Inf in an input block */
 #define FB_ERR_INTERNAL (-2006)
+#define FB_ERR_TOO_LARGE (-2007)  /* beyond the fixed scratch of band_inertia_noalloc */
 
 /* A band Hermitian matrix in LAPACK lower band storage (the compact band form
  * the paper keeps on every process, Section 3 "Proposed algorithm"):
@@ -66,6 +67,26 @@ typedef struct {
 int band_inertia(const fb_band* B, int32_t nshift, const double* shifts,
                  int32_t* n_neg, int32_t* n_zero, int32_t* n_pos,
                  void* work, size_t* lwork, void* stream);
+
+/* Bytes of the library's fixed device scratch used by band_inertia_noalloc
+ * (one copy per device, held from the library's load until the process
+ * ends). */
+#define FB_NOALLOC_SCRATCH_BYTES (64 << 20)
+
+/* band_inertia for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same counts as band_inertia, computed in a fixed library-owned device
+ * scratch of FB_NOALLOC_SCRATCH_BYTES instead of a caller workspace.  The
+ * call makes no device allocation of any kind.  The problem must fit the
+ * scratch: the internal band copy takes (max(b,1) + 1) * n * 16 bytes plus
+ * about 1 KB per 16 shifts, so n * (b + 1) up to about 4.1e6 entries;
+ * larger problems return FB_ERR_TOO_LARGE with nothing launched.  Argument
+ * errors as band_inertia (-1 band, -2 nshift, -3 shifts, -4 n_neg).  Every
+ * call on a device shares that device's scratch: calls that overlap on one
+ * device (other host threads, other streams) race and must be serialised by
+ * the caller.  Synchronises the stream. */
+int band_inertia_noalloc(const fb_band* B, int32_t nshift, const double* shifts,
+                         int32_t* n_neg, int32_t* n_zero, int32_t* n_pos, void* stream);
 
 /* Options of the shifted band solves. */
 typedef struct {

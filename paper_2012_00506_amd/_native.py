@@ -55,6 +55,7 @@ PSZ = C.POINTER(C.c_size_t)
 # name -> (restype, argtypes); every symbol declared in include/feastband.h
 SIGNATURES = {
     "band_inertia": (C.c_int, [C.POINTER(fb_band), C.c_int32, PD, PI32, PI32, PI32, P, PSZ, P]),
+    "band_inertia_noalloc": (C.c_int, [C.POINTER(fb_band), C.c_int32, PD, PI32, PI32, PI32, P]),
     "band_shifted_solve": (C.c_int, [C.POINTER(fb_band), C.c_int32, PD, PI32, C.POINTER(P), PI64,
                                      C.POINTER(P), C.POINTER(P), PI64, PD, PI32,
                                      C.POINTER(fb_solve_opts), P, PSZ, P]),

@@ -74,6 +74,7 @@ extern "C" const char* fb_strerror(int code) {
     case FB_ERR_NOMEM: return "workspace too small";
     case FB_ERR_NONFINITE: return "NaN or Inf in an input block";
     case FB_ERR_INTERNAL: return "internal error";
+    case FB_ERR_TOO_LARGE: return "the problem exceeds the fixed scratch of the no-allocation entry point";
     default: break;
   }
   if (code <= -1000 && code > -2000) return hipGetErrorString((hipError_t)(-1000 - code));
@@ -108,7 +109,7 @@ extern "C" int band_inertia(const fb_band* B, int32_t nshift, const double* shif
   ar.base = (char*)work;
   ar.cap = *lwork;
   Band bd;
-  FB_TRY(ingest_band(B, bd, ar, st));
+  FB_TRY(ingest_band(B, bd, ar, st, false));
   double* sh = ar.take<double>(std::max(nshift, 1));
   int32_t* cnt = ar.take<int32_t>(3 * (size_t)std::max(nshift, 1));
   size_t scb = inertia_scratch_bytes(bd, nshift);

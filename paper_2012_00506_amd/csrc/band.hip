@@ -125,7 +125,7 @@ __global__ void k_band_blocks(const c128* __restrict__ Bd, int64_t n, int b, int
 
 static const int kStatBlocks = 256;
 
-int ingest_band(const fb_band* B, Band& out, Arena& ar, hipStream_t st) {
+int ingest_band(const fb_band* B, Band& out, Arena& ar, hipStream_t st, bool blocks) {
   // a diagonal matrix is handled as a band of width 1 with a zero sub-diagonal
   out.n = B->n;
   out.b = B->b > 0 ? B->b : 1;
@@ -135,7 +135,7 @@ int ingest_band(const fb_band* B, Band& out, Arena& ar, hipStream_t st) {
   out.stats = ar.take<double>(3);
   out.nb = (out.b + 15) / 16 * 16;
   out.K = (int)((out.n + out.nb - 1) / out.nb);
-  out.Bblk = ar.take<c128>((size_t)out.K * 3 * out.nb * out.nb);
+  out.Bblk = blocks ? ar.take<c128>((size_t)out.K * 3 * out.nb * out.nb) : nullptr;
   double* part = ar.take<double>(3 * kStatBlocks);
   if (ar.base == nullptr) return 0;
   if (!ar.fits()) return FB_ERR_NOMEM;
@@ -149,7 +149,7 @@ int ingest_band(const fb_band* B, Band& out, Arena& ar, hipStream_t st) {
   FB_HIP(hipGetLastError());
   k_band_colstats_final<<<1, 256, 0, st>>>(part, kStatBlocks, out.stats);
   FB_HIP(hipGetLastError());
-  {
+  if (blocks) {
     int64_t tb = (int64_t)out.K * 3 * out.nb * out.nb;
     int g = (int)std::min<int64_t>((tb + 255) / 256, 65536);
     k_band_blocks<<<g, 256, 0, st>>>(out.Bd, out.n, out.b, out.nb, out.K, out.Bblk);

@@ -154,7 +154,8 @@ struct Band {
 };
 
 // Kernels launched from the host side (defined in the .hip files).
-int ingest_band(const fb_band* B, Band& out, Arena& ar, hipStream_t st);
+// blocks = false skips the block-tridiagonal copy (only the FP64 residual reads it)
+int ingest_band(const fb_band* B, Band& out, Arena& ar, hipStream_t st, bool blocks = true);
 int band_stats_host(const Band& bd, double* out3, hipStream_t st);
 
 // inertia for nshift shifts (dev shifts array), counts dev int32 x3

@@ -203,3 +203,22 @@ def test_contour_argument_errors(L):
     assert L.fb_contour(0.0, 1.0, 8, 0, -1.0, zp, wp) == -5
     assert L.fb_contour(0.0, 1.0, 8, 0, 1.0, None, wp) == -6
     assert L.fb_contour(0.0, 1.0, 8, 0, 1.0, zp, None) == -7
+
+
+def test_inertia_noalloc_rejects_before_launch(L):
+    # argument errors and problems beyond the fixed scratch return before any
+    # device work (the band pointer here is never dereferenced)
+    from paper_2012_00506_amd import _native as N
+    sh = (C.c_double * 2)(0.0, 1.0)
+    neg = (C.c_int32 * 2)()
+    bad = _band(n=0)
+    assert L.band_inertia_noalloc(C.byref(bad), 2, sh, neg, None, None, None) == -1
+    bs = _band()
+    assert L.band_inertia_noalloc(C.byref(bs), -1, sh, neg, None, None, None) == -2
+    assert L.band_inertia_noalloc(C.byref(bs), 2, None, neg, None, None, None) == -3
+    assert L.band_inertia_noalloc(C.byref(bs), 2, sh, None, None, None, None) == -4
+    nan = (C.c_double * 2)(0.0, float("nan"))
+    assert L.band_inertia_noalloc(C.byref(bs), 2, nan, neg, None, None, None) == -3
+    big = _band(n=70000, b=64)   # 73 MB band copy > 64 MiB scratch
+    assert L.band_inertia_noalloc(C.byref(big), 2, sh, neg, None, None, None) == -2007
+    assert b"scratch" in L.fb_strerror(-2007)
