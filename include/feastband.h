@@ -193,6 +193,30 @@ int feast_band_slice(const fb_band* B, int32_t nslice, const double* lo,
                      int32_t* info, const fb_feast_opts* o, void* work,
                      size_t* lwork, void* stream);
 
+/* Orthonormalisation and Rayleigh-Ritz of given blocks, the step of
+ * Algorithm alg:FEAST that follows the filter (Section 2.2): for every block
+ * Q_i, an orthonormal basis U_i of span(Q_i), the Ritz values and vectors of
+ * B on it (U_i^H B U_i W = W Lambda, X_i = U_i W, ascending) and their
+ * residuals ||B x - l x||_2 / ||B||_1.  The basis is formed by Cholesky QR
+ * applied twice to the column-equilibrated block (D scales every column to
+ * unit norm: (Q D)^H (Q D) = R1^H R1, Q1 = Q D R1^{-1}, Q1^H Q1 = R2^H R2,
+ * U = Q1 R2^{-1}) while every pivot r_jj^2 of both unit-diagonal Gram
+ * matrices exceeds 1e-12; otherwise by two eigen-decomposition passes of the
+ * Gram matrix that drop directions below 1e-14 of the largest (rank < m_i).
+ *  m      host, nblk: columns of each block (0 allowed, at most 4096)
+ *  Q      host array of dev pointers, n x m_i in the dtype of B, leading
+ *         dimension ldq[i] >= n (not modified)
+ *  X      host array of dev pointers, out: the Ritz vectors in the first
+ *         rank_i columns (dtype of B), leading dimension ldx[i] >= n
+ *  evals, resid  host arrays of dev pointers to m_i doubles (first rank_i)
+ *  rank   host, nblk: dimension of the basis
+ *  path   host, nblk or NULL: 0 Cholesky QR, 1 eigen-decomposition passes
+ * Synchronises the stream. */
+int band_rayleigh_ritz(const fb_band* B, int32_t nblk, const int32_t* m, const void* const* Q,
+                       const int64_t* ldq, void* const* X, const int64_t* ldx,
+                       double* const* evals, double* const* resid, int32_t* rank,
+                       int32_t* path, void* work, size_t* lwork, void* stream);
+
 #define FB_PLAN_EQUAL_WIDTH 0 /* Approach-2 of Section 3.1: equal widths */
 #define FB_PLAN_EQUAL_COUNT 1 /* Approach-1 of Section 3.1: equal counts */
 #define FB_PLAN_LEARNED 2     /* equal counts, search guided by the planner network */

@@ -98,9 +98,62 @@ def orthonormalise(Q: np.ndarray, drop: float = 1e-14, floor: float = 1e-12):
     return Q2, Q2.shape[1]
 
 
-def rayleigh_ritz(ab: np.ndarray, Q: np.ndarray):
-    """Ritz values (ascending) and vectors of B on span(Q)."""
-    Qo, k = orthonormalise(Q)
+def _cholesky_upper(G: np.ndarray, piv_min: float):
+    """Upper R with G = R^H R by the column-oriented Cholesky recurrence
+    (r_jj = sqrt(g_jj - sum_i<j |r_ij|^2), r_jk = (g_jk - sum_i<j conj(r_ij)
+    r_ik) / r_jj); None when a pivot r_jj^2 is not above piv_min (or NaN)."""
+    m = G.shape[0]
+    R = np.zeros_like(G)
+    for j in range(m):
+        d = np.real(G[j, j]) - np.real(np.vdot(R[:j, j], R[:j, j]))
+        if not d > piv_min:
+            return None
+        R[j, j] = np.sqrt(d)
+        R[j, j + 1:] = (G[j, j + 1:] - R[:j, j].conj() @ R[:j, j + 1:]) / R[j, j]
+    return R
+
+
+def orthonormalise_cholqr(Q: np.ndarray, piv_min: float = 1e-12):
+    """Cholesky QR applied twice to the column-equilibrated block, or None
+    when it does not apply.  D scales every column of Q to unit norm (the
+    filtered block's columns differ in norm by the filter's range, which the
+    scaling takes out of the Gram matrix); G = (QD)^H (QD) = R^H R and
+    Q1 = Q D R^{-1}; then Q1^H Q1 = R2^H R2 and Q2 = Q1 R2^{-1}.  The first
+    pass applies while every pivot r_jj^2 of G (a unit-diagonal matrix:
+    r_jj is the sine of the angle between column j and the span of the
+    columns before it) is above piv_min, i.e. the equilibrated Gram matrix
+    has no eigenvalue near 1e-12; the second pass must factor too.  A zero
+    column also rules it out."""
+    c = np.linalg.norm(Q, axis=0)
+    if not (c.size and np.all(c > 0) and np.all(np.isfinite(c))):
+        return None
+    Qd = Q / c
+    G = Qd.conj().T @ Qd
+    G = 0.5 * (G + G.conj().T)
+    R = _cholesky_upper(G, piv_min)
+    if R is None:
+        return None
+    Q1 = Qd @ np.linalg.inv(R)
+    G2 = Q1.conj().T @ Q1
+    G2 = 0.5 * (G2 + G2.conj().T)
+    R2 = _cholesky_upper(G2, piv_min)
+    if R2 is None:
+        return None
+    return Q1 @ np.linalg.inv(R2)
+
+
+def rayleigh_ritz(ab: np.ndarray, Q: np.ndarray, stats: dict | None = None):
+    """Ritz values (ascending) and vectors of B on span(Q).  The basis is
+    orthonormalised by Cholesky QR twice when it applies, else by the two
+    eigen-decomposition passes (rank decision included)."""
+    Qc = orthonormalise_cholqr(Q)
+    if Qc is not None:
+        Qo, k = Qc, Qc.shape[1]
+    else:
+        Qo, k = orthonormalise(Q)
+    if stats is not None:
+        stats["cholqr" if Qc is not None else "eig"] = stats.get(
+            "cholqr" if Qc is not None else "eig", 0) + 1
     Aq = Qo.conj().T @ band_matmul(ab, Qo)
     Aq = 0.5 * (Aq + Aq.conj().T)
     lam, W = np.linalg.eigh(Aq)

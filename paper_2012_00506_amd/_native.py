@@ -68,6 +68,9 @@ SIGNATURES = {
                                   PI32, PI32, PI32, P, PSZ, P]),
     "feast_filter": (C.c_int, [C.POINTER(fb_band), C.c_int32, PD, PD, PI32, C.POINTER(P), PI64,
                                C.POINTER(P), PI64, PD, PI32, C.POINTER(fb_feast_opts), P, PSZ, P]),
+    "band_rayleigh_ritz": (C.c_int, [C.POINTER(fb_band), C.c_int32, PI32, C.POINTER(P), PI64,
+                                     C.POINTER(P), PI64, C.POINTER(P), C.POINTER(P), PI32, PI32, P,
+                                     PSZ, P]),
     "fb_profile_enable": (C.c_int, [C.c_int32]),
     "fb_profile_read": (C.c_int, [C.c_int32, PI64, PD, PD]),
     "fb_autotune": (C.c_int, [C.POINTER(fb_band), C.c_int32, C.c_int32, C.c_int32, C.c_char_p,

@@ -237,6 +237,57 @@ def feast_band_slice(B, lo, hi, Y, m_expected=None, n_nodes=8, tol=1e-10, max_it
     return out
 
 
+@dataclass
+class RitzResult:
+    lam: np.ndarray      # Ritz values, ascending (rank of them)
+    resid: np.ndarray    # ||B x - lam x||_2 / ||B||_1
+    X: torch.Tensor      # (n, m) column-major; the first rank columns are the Ritz vectors
+    rank: int
+    path: int            # 0 Cholesky QR twice, 1 eigen-decomposition passes
+
+
+def rayleigh_ritz(B, Q, stream=None) -> list:
+    """Orthonormalisation and Rayleigh-Ritz of the blocks Q[i] ((n, m_i)
+    column-major device tensors in the dtype of B; not modified)."""
+    B = _as_band(B)
+    want = torch.complex128 if B.complex_ else torch.float64
+    for q in Q:
+        if q.dtype != want or q.stride(0) != 1:
+            raise ValueError(f"blocks must be column-major {want}")
+    ns = len(Q)
+    m = np.array([q.shape[1] for q in Q], np.int32)
+    ldq = np.array([q.stride(1) if q.shape[1] > 1 else B.n for q in Q], np.int64)
+    dev = B.data.device
+    X = [colmajor(B.n, int(mm), want, device=dev) for mm in m]
+    ldx = np.array([B.n] * ns, np.int64)
+    ev = [torch.empty(max(int(mm), 1), dtype=torch.float64, device=dev) for mm in m]
+    rs = [torch.empty(max(int(mm), 1), dtype=torch.float64, device=dev) for mm in m]
+    rank = np.zeros(ns, np.int32)
+    path = np.zeros(ns, np.int32)
+    Qp = (C.c_void_p * ns)(*[q.data_ptr() for q in Q])
+    Xp = (C.c_void_p * ns)(*[x.data_ptr() for x in X])
+    Ep = (C.c_void_p * ns)(*[e.data_ptr() for e in ev])
+    Rp = (C.c_void_p * ns)(*[r.data_ptr() for r in rs])
+    bs = B.struct()
+    L = N.lib()
+    sh = C.c_void_p(_stream_handle(stream))
+    args = (C.byref(bs), ns, m.ctypes.data_as(N.PI32), Qp, ldq.ctypes.data_as(N.PI64), Xp,
+            ldx.ctypes.data_as(N.PI64), Ep, Rp, rank.ctypes.data_as(N.PI32),
+            path.ctypes.data_as(N.PI32))
+    lw = C.c_size_t(0)
+    N.check("band_rayleigh_ritz", L.band_rayleigh_ritz(*args, None, C.byref(lw), sh))
+    ws = _workspace(None, lw, dev)
+    lw2 = C.c_size_t(ws.numel())
+    N.check("band_rayleigh_ritz", L.band_rayleigh_ritz(*args, C.c_void_p(ws.data_ptr()),
+                                                       C.byref(lw2), sh))
+    out = []
+    for i in range(ns):
+        k = int(rank[i])
+        out.append(RitzResult(ev[i][:k].cpu().numpy(), rs[i][:k].cpu().numpy(), X[i], k,
+                              int(path[i])))
+    return out
+
+
 def slice_plan(B, K, mode="equal_count", lo=float("nan"), hi=float("nan"), count_tol=0.05,
                cert_delta=1e-8, max_rounds=60, planner=None, seed=0, nev=0, targets=None,
                stream=None):

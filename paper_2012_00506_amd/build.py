@@ -23,15 +23,20 @@ CFLAGS = [
     "-Wno-unused-command-line-argument", "-Wno-unused-result",
     "-I" + os.path.join(HERE, "..", "include"),
 ]
-LDFLAGS = ["-shared", f"--offload-arch={ARCH}", "-lrocblas"]
+LDFLAGS = ["-shared", f"--offload-arch={ARCH}"]
 
 
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src: str) -> str:
+def _compile(src: str, force: bool = True) -> str:
     obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
+    if not force and os.path.exists(obj):
+        deps = [src] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+        deps.append(os.path.join(HERE, "..", "include", "feastband.h"))
+        if os.path.getmtime(obj) > max(os.path.getmtime(d) for d in deps):
+            return obj
     cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -39,12 +44,14 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile all sources and link the shared library; returns its path."""
+def build(verbose: bool = False, force: bool = True) -> str:
+    """Compile all sources and link the shared library; returns its path.
+    force=False recompiles only sources older than their object files'
+    dependencies (the source, the internal headers and the C ABI header)."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda s: _compile(s, force), srcs))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, *LDFLAGS, *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -57,5 +64,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, force="--incremental" not in sys.argv)
     sys.exit(0)

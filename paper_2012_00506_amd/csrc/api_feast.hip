@@ -1,13 +1,13 @@
 // C ABI: feast_band_slice -- FEAST on band slices (Algorithm alg:FEAST of
 // Section 2.2 with the slice count check of Section 3.2).
 #include <math.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <mutex>
 #include <numeric>
 #include <vector>
 
+#include "chol64.h"
 #include "rr.h"
 #include "solve_job.h"
 #include "prof.h"
@@ -180,41 +180,91 @@ static bool contour_ok(int rule, double ratio) {
   return false;
 }
 
-// ---------------------------------------------------------------- rocBLAS
-static rocblas_handle blas_handle(hipStream_t st) {
-  static std::mutex mu;
-  static rocblas_handle h[64] = {};
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  std::lock_guard<std::mutex> g(mu);
-  if (dev < 0 || dev >= 64) return nullptr;
-  if (!h[dev] && rocblas_create_handle(&h[dev]) != rocblas_status_success) h[dev] = nullptr;
-  if (h[dev]) rocblas_set_stream(h[dev], st);
-  return h[dev];
-}
-
-// C = op(A) op(B), complex128 (plain library GEMM)
-static int zgemm(hipStream_t st, bool ta, int m, int n, int k, const c128* A, int64_t lda,
-                 const c128* B, int64_t ldb, c128* C, int64_t ldc) {
-  if (m <= 0 || n <= 0) return 0;
-  rocblas_handle h = blas_handle(st);
-  if (!h) return FB_ERR_INTERNAL;
-  ProfScope ps(FB_PROF_GEMM, st, 8.0 * (double)m * n * k);
-  rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
-  rocblas_status s = rocblas_zgemm(
-      h, ta ? rocblas_operation_conjugate_transpose : rocblas_operation_none,
-      rocblas_operation_none, m, n, k, &one, (const rocblas_double_complex*)A, (rocblas_int)lda,
-      (const rocblas_double_complex*)B, (rocblas_int)ldb, &zero, (rocblas_double_complex*)C,
-      (rocblas_int)ldc);
-  return s == rocblas_status_success ? 0 : FB_ERR_INTERNAL;
-}
-
 struct SliceBufs {
   c128 *Y, *Q, *X;      // n x m0 each (start block, filter sum, scratch)
   c128 *G, *V, *W;      // m0 x m0
-  double *s, *lam, *res, *scale, *part;
-  int32_t *order, *idx, *kept, *sweeps;
+  c128 *Dinv, *Pb;      // Cholesky: diagonal-block inverses, panel scratch (m0 x 64 each)
+  c128* gpart;          // split partial sums of the long products
+  double *s, *lam, *res, *scale, *part, *cscale;
+  int32_t *order, *idx, *kept, *sweeps, *cinfo;
 };
+
+// Pivots r_jj^2 of the equilibrated Gram matrices at or below this end the
+// Cholesky QR of a slice (the eigen-decomposition passes take over).
+constexpr double kCholPivMin = 1e-12;
+// Most split ranges of a long A^H B product (partial sums kept per slice).
+constexpr int kMaxSplit = 8;
+
+// C = op(A) B descriptors of the orthonormalisation and Rayleigh-Ritz
+// products (all complex128, column-major).
+static GemmProb gp_tn(const c128* A, int64_t lda, const c128* B, int64_t ldb, c128* C,
+                      int64_t ldc, int M, int N, int K, int herm) {
+  GemmProb p{};
+  p.A = A;
+  p.lda = lda;
+  p.B = B;
+  p.ldb = ldb;
+  p.C = C;
+  p.ldc = ldc;
+  p.M = M;
+  p.N = N;
+  p.K = K;
+  p.transa = 1;
+  p.herm = herm;
+  p.alpha = mk(1.0, 0.0);
+  p.ksplit = 1;
+  return p;
+}
+static GemmProb gp_nn(const c128* A, int64_t lda, const c128* B, int64_t ldb, c128* C,
+                      int64_t ldc, int M, int N, int K, int b_upper) {
+  GemmProb p = gp_tn(A, lda, B, ldb, C, ldc, M, N, K, 0);
+  p.transa = 0;
+  p.b_upper = b_upper;
+  return p;
+}
+
+static GemmProb with_part(GemmProb p, c128* part) {
+  p.part = part;
+  return p;
+}
+
+static JacobiJob jacobi_job(const SliceBufs& b, int m, double* w) {
+  JacobiJob J{};
+  J.m = m;
+  J.A = b.G;
+  J.lda = m;
+  J.V = b.V;
+  J.ldv = m;
+  J.W = b.W;
+  J.ldw = m;
+  J.w = w;
+  J.order = b.order;
+  J.sweeps = b.sweeps;
+  return J;
+}
+
+// k_colscale: s_j = 1 / sqrt(Re G_jj); k_equil: G_ij *= s_i s_j (upper
+// triangle).  A zero or non-finite column makes the scaled matrix non-finite,
+// which the Cholesky pivot test then rejects.
+__global__ void k_colscale(const CholProb* __restrict__ probs) {
+  const CholProb P = probs[blockIdx.y];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= P.m) return;
+  const double d = gld(P.G + (int64_t)j * P.ld + j).x;
+  gst(const_cast<double*>(P.rowscale) + j, 1.0 / sqrt(d));
+}
+__global__ void __launch_bounds__(256) k_equil(const CholProb* __restrict__ probs) {
+  const CholProb P = probs[blockIdx.y];
+  const int m = P.m;
+  const int64_t tot = (int64_t)m * m;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e / m), i = (int)(e - (int64_t)j * m);
+    if (i > j) continue;
+    c128* g = P.G + (int64_t)j * P.ld + i;
+    gst(g, (gld(P.rowscale + i) * gld(P.rowscale + j)) * gld(g));
+  }
+}
 
 // Q_i = sum_j w_ij (z_ij - B)^{-1} Y_i (+ conj(w_ij) (z_ij - B)^{-H} Y_i) for
 // the slices in act.  The (node, direction) pairs are taken in order, P of
@@ -229,7 +279,7 @@ int filter_apply(const Band& bd, const FactorBufs<R>& f, int ne, const std::vect
                  const std::vector<c128>& zsys, const std::vector<c128>& wsys, bool cplx,
                  bool batched, bool ir, double ir_tol, int ir_max, bool need_res, RefineBufs& rb,
                  std::vector<double>& sys_res, std::vector<int32_t>& sys_pass, int* unconverged,
-                 hipStream_t st) {
+                 hipStream_t st, const C128Fallback* fb) {
   const int64_t n = bd.n;
   const int tile = rb.tile;
   const int ndir = cplx ? 2 : 1;
@@ -270,7 +320,7 @@ int filter_apply(const Band& bd, const FactorBufs<R>& f, int ne, const std::vect
         }
       }
       FB_TRY(solve_refine<R>(bd, f.mats, f.matsT, f.perm, jobs, zsys, ir, ir_tol, ir_max, need_res, rb,
-                             sys_res, sys_pass, unconverged, st));
+                             sys_res, sys_pass, unconverged, st, fb));
       for (size_t a = 0; a < act.size(); ++a) {
         if (!batched && a != g) continue;
         const int i = act[a];
@@ -328,13 +378,70 @@ struct FeastBufs {
   int tile = 16, P = 1;
   std::vector<c128*> Xp;  // slot * P + pair
   RefineBufs rb;
+  FactorBufs<double> f64fb;       // complex128 fallback factors (precision 1)
+  C128Fallback fb;
+  CholProb* chol_dev = nullptr;  // W descriptors
+  GemmProb* gdev = nullptr;      // gcap descriptors
+  size_t gcap = 0;
+  int kmax = 1;                  // split ranges the partial buffers hold
 };
+
+static int gram_tiles(int m) {
+  const int t = (m + kGemmTile - 1) / kGemmTile;
+  return t * (t + 1) / 2;
+}
+
+// The long products (contraction over the n rows of the basis) of one
+// batch, split so that the batch has about 1024 workgroups.
+template <typename R>
+int run_gram(std::vector<GemmProb>& g, const FeastBufs<R>& fb, hipStream_t st) {
+  if (g.empty()) return 0;
+  long tiles = 0;
+  for (const GemmProb& p : g) tiles += gram_tiles(p.M);
+  const int k = (int)std::max<long>(1, std::min<long>(fb.kmax, (1024 + tiles - 1) / tiles));
+  for (GemmProb& p : g) p.ksplit = p.part ? k : 1;
+  return gemm_batched(g, fb.gdev, st);
+}
+
+static CholProb chol_prob(const SliceBufs& b, int m, c128* T, bool scale) {
+  CholProb c{};
+  c.G = b.G;
+  c.ld = m;
+  c.T = T;
+  c.ldt = m;
+  c.Dinv = b.Dinv;
+  c.P = b.Pb;
+  c.rowscale = scale ? b.cscale : nullptr;
+  c.info = b.cinfo;
+  c.m = m;
+  return c;
+}
+
+template <typename R>
+int equilibrate(const std::vector<CholProb>& cp, const FeastBufs<R>& fb, hipStream_t st) {
+  if (cp.empty()) return 0;
+  int mmax = 1;
+  for (const CholProb& c : cp) mmax = std::max(mmax, c.m);
+  FB_HIP(hipMemcpyAsync(fb.chol_dev, cp.data(), sizeof(CholProb) * cp.size(),
+                        hipMemcpyHostToDevice, st));
+  k_colscale<<<dim3((mmax + 255) / 256, (unsigned)cp.size()), 256, 0, st>>>(fb.chol_dev);
+  FB_HIP(hipGetLastError());
+  const int grid = (int)std::min<int64_t>(((int64_t)mmax * mmax + 255) / 256, 4096);
+  k_equil<<<dim3(grid, (unsigned)cp.size()), 256, 0, st>>>(fb.chol_dev);
+  FB_HIP(hipGetLastError());
+  return 0;
+}
 
 template <typename R>
 void carve_feast(Arena& ar, const Band& bd, int W, int maxm, int ne, bool ir, int P,
                  FeastBufs<R>& fb) {
   const int64_t n = bd.n;
   carve_factors<R>(ar, bd, W * ne, fb.f);
+  if (ir && ne > 0) {
+    fb.fb.cap = fallback_cap(W * ne);
+    carve_factors<double>(ar, bd, fb.fb.cap, fb.f64fb);
+    fb.fb.f = &fb.f64fb;
+  }
   fb.shifts = ar.take<double>(2 * W);
   fb.cnt = ar.take<int32_t>(6 * W);
   size_t iscr = inertia_scratch_bytes(bd, 2 * W);
@@ -358,7 +465,18 @@ void carve_feast(Arena& ar, const Band& bd, int W, int maxm, int ne, bool ir, in
     b.idx = ar.take<int32_t>(m);
     b.kept = ar.take<int32_t>(1);
     b.sweeps = ar.take<int32_t>(1);
+    const size_t nblk = (size_t)(m + kGemmTile - 1) / kGemmTile;
+    b.Dinv = ar.take<c128>(nblk * kGemmTile * kGemmTile);
+    b.Pb = ar.take<c128>((size_t)m * kGemmTile);
+    b.cscale = ar.take<double>(m);
+    b.cinfo = ar.take<int32_t>(1);
   }
+  fb.kmax = std::max(1, std::min(kMaxSplit, (1024 + gram_tiles(m) - 1) / gram_tiles(m)));
+  for (int a = 0; a < W; ++a)
+    fb.sb[a].gpart = fb.kmax > 1 ? ar.take<c128>((size_t)fb.kmax * m * m) : nullptr;
+  fb.chol_dev = ar.take<CholProb>(W);
+  fb.gcap = std::max(chol_gemm_descs(W, m), (size_t)kGemmMaxProbs);
+  fb.gdev = ar.take<GemmProb>(fb.gcap);
   fb.jj_dev = ar.take<JacobiJob>(W);
   carve_eig_work(ar, std::vector<int>(W, maxm), fb.ew);
   fb.perm_dev = ar.take<int32_t>(maxm);
@@ -372,6 +490,165 @@ void carve_feast(Arena& ar, const Band& bd, int W, int maxm, int ne, bool ir, in
     for (int p = 1; p < P; ++p) fb.Xp[(size_t)a * P + p] = ar.take<c128>((size_t)n * m);
   }
   carve_refine(ar, bd, fb.tile, max_jobs * P, ir, ir, fb.rb);
+}
+
+// Orthonormalisation and Rayleigh-Ritz of the filtered blocks of the slots
+// in act (Algorithm alg:FEAST): on entry sb[i].Q holds the n x m0[i] block;
+// on exit sb[i].Q holds the orthonormal basis (kept[i] columns), sb[i].X the
+// Ritz vectors, sb[i].lam the Ritz values (ascending) and sb[i].res their
+// residuals ||B x - lambda x||_2 / ||B||_1; sb[i].Y is scratch (its columns
+// from kept[i] on are left as they were).  path[i]: 0 Cholesky QR twice,
+// 1 the eigen-decomposition passes.
+template <typename R>
+int ortho_rr(const Band& bd, int nslice, const std::vector<int>& act, const int32_t* m0,
+             std::vector<int>& kept, std::vector<int>& path, FeastBufs<R>& fbuf, hipStream_t st) {
+  const int64_t n = bd.n;
+  std::vector<SliceBufs>& sb = fbuf.sb;
+  JacobiJob* jj_dev = fbuf.jj_dev;
+  const EigWork& ew = fbuf.ew;
+  // ---- orthonormalise: Cholesky QR twice on the column-equilibrated block
+  // (D scales every column of Q to unit norm): G = D Q^H Q D = R1^H R1,
+  // Q1 = Q D R1^{-1}; Q1^H Q1 = R2^H R2, Q2 = Q1 R2^{-1}.  It applies when
+  // every pivot r_jj^2 of both factorisations is above kCholPivMin (the
+  // equilibrated Gram matrix has unit diagonal, and r_jj is the sine of the
+  // angle between column j and the columns before it); slices where it
+  // does not fall back to the two eigen-decomposition passes below.
+  std::vector<int> chol_ok(nslice, 0), eig_path;
+  {
+    std::vector<GemmProb> g;
+    for (int i : act)
+      g.push_back(with_part(gp_tn(sb[i].Q, n, sb[i].Q, n, sb[i].G, m0[i], m0[i], m0[i], (int)n, 1),
+                            sb[i].gpart));
+    FB_TRY(run_gram(g, fbuf, st));
+    std::vector<CholProb> cp;
+    for (int i : act) cp.push_back(chol_prob(sb[i], m0[i], sb[i].V, true));
+    FB_TRY(equilibrate(cp, fbuf, st));
+    FB_TRY(chol_inverse(cp, fbuf.chol_dev, fbuf.gdev, fbuf.gcap, kCholPivMin, st));
+    g.clear();  // Q1 = Q (D R1^{-1}) into X
+    for (int i : act) g.push_back(gp_nn(sb[i].Q, n, sb[i].V, m0[i], sb[i].X, n, (int)n, m0[i],
+                                        m0[i], 1));
+    FB_TRY(gemm_batched(g, fbuf.gdev, st));
+    std::vector<int32_t> inf1(nslice, 0);
+    for (int i : act) FB_HIP(hipMemcpyAsync(&inf1[i], sb[i].cinfo, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FB_HIP(hipStreamSynchronize(st));
+    std::vector<int> pass2;
+    for (int i : act) (inf1[i] == 0 ? pass2 : eig_path).push_back(i);
+    g.clear();
+    for (int i : pass2)
+      g.push_back(with_part(gp_tn(sb[i].X, n, sb[i].X, n, sb[i].G, m0[i], m0[i], m0[i], (int)n, 1),
+                            sb[i].gpart));
+    FB_TRY(run_gram(g, fbuf, st));
+    cp.clear();
+    for (int i : pass2) cp.push_back(chol_prob(sb[i], m0[i], sb[i].V, false));
+    FB_TRY(chol_inverse(cp, fbuf.chol_dev, fbuf.gdev, fbuf.gcap, kCholPivMin, st));
+    std::vector<int32_t> inf2(nslice, 0);
+    for (int i : pass2) FB_HIP(hipMemcpyAsync(&inf2[i], sb[i].cinfo, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FB_HIP(hipStreamSynchronize(st));
+    g.clear();  // Q2 = Q1 R2^{-1} into Q (the filter sum is spent)
+    for (int i : pass2) {
+      if (inf2[i] != 0) {
+        eig_path.push_back(i);
+        continue;
+      }
+      chol_ok[i] = 1;
+      kept[i] = m0[i];
+      g.push_back(gp_nn(sb[i].X, n, sb[i].V, m0[i], sb[i].Q, n, (int)n, m0[i], m0[i], 1));
+    }
+    FB_TRY(gemm_batched(g, fbuf.gdev, st));
+  }
+  // ---- fallback, pass 1: Q^H Q = V s V^H; Q V over every eigenvector,
+  // each column's norm measured on the product, the columns above 1e-12 of
+  // the largest kept and scaled to unit norm.  The Gram matrix of a filtered
+  // block spans more orders of magnitude than FP64 resolves: its smallest s
+  // are rounding noise (often negative) while the directions Q v formed from
+  // Q are still accurate, and they carry the last digits of the wanted
+  // eigenvectors (dropping those whose computed s is at or below eps max s
+  // stalls the residuals near 1e-10 under a 16-node filter).  The rank
+  // decision, s > 1e-14 max s, is taken in pass 2 on the well-scaled block.
+  std::sort(eig_path.begin(), eig_path.end());
+  if (!eig_path.empty()) {
+    std::vector<JacobiJob> jj;
+    std::vector<GemmProb> g;
+    for (int i : eig_path) {
+      int m = m0[i];
+      g.push_back(with_part(gp_tn(sb[i].Q, n, sb[i].Q, n, sb[i].G, m, m, m, (int)n, 2), sb[i].gpart));
+      jj.push_back(jacobi_job(sb[i], m, sb[i].s));
+    }
+    FB_TRY(run_gram(g, fbuf, st));
+    FB_TRY(reduced_eig(jj, jj_dev, ew, 60, 1e-14, st));
+    g.clear();
+    for (int i : eig_path)  // Q V into X
+      g.push_back(gp_nn(sb[i].Q, n, sb[i].W, m0[i], sb[i].X, n, (int)n, m0[i], m0[i], 0));
+    FB_TRY(gemm_batched(g, fbuf.gdev, st));
+    for (int i : eig_path)  // column norms into s
+      FB_TRY(col_norm_keep(sb[i].X, n, n, m0[i], 1e-12, sb[i].s, sb[i].idx, sb[i].scale,
+                           sb[i].kept, st));
+    for (int i : eig_path)
+      FB_HIP(hipMemcpyAsync(&kept[i], sb[i].kept, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FB_HIP(hipStreamSynchronize(st));
+    std::vector<int> prev_kept(kept);
+    jj.clear();
+    g.clear();
+    for (int i : eig_path) {
+      int k = kept[i];
+      if (k <= 0) continue;
+      // Q' = kept columns of Q V at unit norm, into Q (the filter sum is spent)
+      FB_TRY(gather_cols(sb[i].X, n, false, sb[i].Q, n, n, k, sb[i].idx, sb[i].scale, st));
+      // pass 2: Q'^H Q' = I + E with E growing with the spread of s;
+      // orthonormalising Q' once more makes the basis orthonormal to
+      // rounding, which the eigen-residual floor needs
+      g.push_back(with_part(gp_tn(sb[i].Q, n, sb[i].Q, n, sb[i].G, k, k, k, (int)n, 2), sb[i].gpart));
+      jj.push_back(jacobi_job(sb[i], k, sb[i].s));
+    }
+    FB_TRY(run_gram(g, fbuf, st));
+    if (!jj.empty()) FB_TRY(reduced_eig(jj, jj_dev, ew, 60, 1e-14, st));
+    for (int i : eig_path)
+      if (kept[i] > 0)
+        FB_TRY(gram_keep(sb[i].s, kept[i], 1e-14, sb[i].idx, sb[i].scale, sb[i].kept, st));
+    for (int i : eig_path)
+      if (kept[i] > 0)
+        FB_HIP(hipMemcpyAsync(&kept[i], sb[i].kept, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FB_HIP(hipStreamSynchronize(st));
+    g.clear();
+    for (int i : eig_path) {
+      int k = kept[i];
+      if (k <= 0) continue;
+      // Q'' = Q' W2[:, idx] diag(scale) into X, which then trades places with Q
+      const int k1 = (int)prev_kept[i];
+      FB_TRY(gather_cols(sb[i].W, k1, false, sb[i].V, k1, k1, k, sb[i].idx, sb[i].scale, st));
+      g.push_back(gp_nn(sb[i].Q, n, sb[i].V, k1, sb[i].X, n, (int)n, k, k1, 0));
+    }
+    FB_TRY(gemm_batched(g, fbuf.gdev, st));
+    for (int i : eig_path)
+      if (kept[i] > 0) std::swap(sb[i].Q, sb[i].X);
+  }
+  // ---- Rayleigh-Ritz: A_q = Q^H B Q, A_q W = W Lambda, X = Q W
+  {
+    std::vector<JacobiJob> jj;
+    std::vector<GemmProb> g;
+    for (int i : act) {
+      int k = kept[i];
+      if (k <= 0) continue;
+      // B Q into Y (its trailing columns keep the start vectors)
+      FB_TRY(band_matmul(bd, sb[i].Q, n, sb[i].Y, n, k, st));
+      g.push_back(with_part(gp_tn(sb[i].Q, n, sb[i].Y, n, sb[i].G, k, k, k, (int)n, 2), sb[i].gpart));
+      jj.push_back(jacobi_job(sb[i], k, sb[i].lam));
+    }
+    FB_TRY(run_gram(g, fbuf, st));
+    if (!jj.empty()) FB_TRY(reduced_eig(jj, jj_dev, ew, 60, 1e-14, st));
+    g.clear();
+    for (int i : act) {  // Ritz vectors X = Q W into X
+      int k = kept[i];
+      if (k > 0) g.push_back(gp_nn(sb[i].Q, n, sb[i].W, k, sb[i].X, n, (int)n, k, k, 0));
+    }
+    FB_TRY(gemm_batched(g, fbuf.gdev, st));
+  }
+  for (int i : act) {
+    path[i] = chol_ok[i] ? 0 : 1;
+    if (kept[i] > 0)
+      FB_TRY(eig_residuals(bd, sb[i].X, n, sb[i].lam, kept[i], sb[i].part, sb[i].res, st));
+  }
+  return 0;
 }
 
 // FEAST on nslice slices that share one wave's workspace.
@@ -435,6 +712,7 @@ int feast_wave(const Band& bd, int nslice, const double* lo, const double* hi, c
 
   // ---- start blocks
   std::vector<int> done(nslice, 0), kept(nslice, 0), good(nslice, 0), inside(nslice, 0);
+  std::vector<int> fellback(nslice, 0);  // a system of the slice fell back to complex128
   std::vector<std::vector<double>> hl(nslice), hr(nslice);
   for (int i = 0; i < nslice; ++i) {
     iters[i] = 0;
@@ -467,112 +745,18 @@ int feast_wave(const Band& bd, int nslice, const double* lo, const double* hi, c
       }
       FB_TRY(filter_apply<R>(bd, f, ne, act, m0, Yc.data(), lds.data(), Qc.data(), lds.data(),
                              Xp.data(), P, acc_dev, zsys, wsys, cplx, o->batched != 0, ir,
-                             o->ir_tol, o->ir_max, ir, rb, sys_res, sys_pass, nullptr, st));
+                             o->ir_tol, o->ir_max, ir, rb, sys_res, sys_pass, nullptr, st,
+                             ir ? &fbuf.fb : nullptr));
+      for (int i : act)
+        for (int j = 0; j < ne; ++j)
+          if (sys_pass[i * ne + j] < 0) fellback[i] = 1;
     }
-    // ---- orthonormalise, pass 1: Q^H Q = V s V^H; Q V over every eigenvector,
-    // each column's norm measured on the product, the columns above 1e-12 of
-    // the largest kept and scaled to unit norm.  The Gram matrix of a filtered
-    // block spans more orders of magnitude than FP64 resolves: its smallest s
-    // are rounding noise (often negative) while the directions Q v formed from
-    // Q are still accurate, and they carry the last digits of the wanted
-    // eigenvectors (dropping those whose computed s is at or below eps max s
-    // stalls the residuals near 1e-10 under a 16-node filter).  The rank
-    // decision, s > 1e-14 max s, is taken in pass 2 on the well-scaled block.
-    std::vector<JacobiJob> jj;
-    for (int i : act) {
-      int m = m0[i];
-      FB_TRY(zgemm(st, true, m, m, (int)n, sb[i].Q, n, sb[i].Q, n, sb[i].G, m));
-      FB_TRY(hermitize(sb[i].G, m, m, st));
-      JacobiJob J{};
-      J.m = m;
-      J.A = sb[i].G;
-      J.lda = m;
-      J.V = sb[i].V;
-      J.ldv = m;
-      J.W = sb[i].W;
-      J.ldw = m;
-      J.w = sb[i].s;
-      J.order = sb[i].order;
-      J.sweeps = sb[i].sweeps;
-      jj.push_back(J);
-    }
-    FB_TRY(reduced_eig(jj, jj_dev, ew, 60, 1e-14, st));
-    for (int i : act) {
-      int m = m0[i];
-      // Q V into X; column norms into s
-      FB_TRY(zgemm(st, false, (int)n, m, m, sb[i].Q, n, sb[i].W, m, sb[i].X, n));
-      FB_TRY(col_norm_keep(sb[i].X, n, n, m, 1e-12, sb[i].s, sb[i].idx, sb[i].scale, sb[i].kept,
-                           st));
-    }
-    for (int i : act) FB_HIP(hipMemcpyAsync(&kept[i], sb[i].kept, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    FB_HIP(hipStreamSynchronize(st));
-    std::vector<int> prev_kept(kept);
-    jj.clear();
-    for (int i : act) {
-      int k = kept[i];
-      if (k <= 0) continue;
-      // Q' = kept columns of Q V at unit norm, into Q (the filter sum is spent)
-      FB_TRY(gather_cols(sb[i].X, n, false, sb[i].Q, n, n, k, sb[i].idx, sb[i].scale, st));
-      // pass 2: Q'^H Q' = I + E with E growing with the spread of s;
-      // orthonormalising Q' once more makes the basis orthonormal to
-      // rounding, which the eigen-residual floor needs
-      FB_TRY(zgemm(st, true, k, k, (int)n, sb[i].Q, n, sb[i].Q, n, sb[i].G, k));
-      FB_TRY(hermitize(sb[i].G, k, k, st));
-      JacobiJob J{};
-      J.m = k;
-      J.A = sb[i].G;
-      J.lda = k;
-      J.V = sb[i].V;
-      J.ldv = k;
-      J.W = sb[i].W;
-      J.ldw = k;
-      J.w = sb[i].s;
-      J.order = sb[i].order;
-      J.sweeps = sb[i].sweeps;
-      jj.push_back(J);
-    }
-    if (!jj.empty()) FB_TRY(reduced_eig(jj, jj_dev, ew, 60, 1e-14, st));
-    for (int i : act)
-      if (kept[i] > 0)
-        FB_TRY(gram_keep(sb[i].s, kept[i], 1e-14, sb[i].idx, sb[i].scale, sb[i].kept, st));
-    for (int i : act)
-      if (kept[i] > 0)
-        FB_HIP(hipMemcpyAsync(&kept[i], sb[i].kept, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    FB_HIP(hipStreamSynchronize(st));
-    jj.clear();
-    for (int i : act) {
-      int k = kept[i];
-      if (k <= 0) continue;
-      // Q'' = Q' W2[:, idx] diag(scale) into X, which then trades places with Q
-      const int k1 = (int)prev_kept[i];
-      FB_TRY(gather_cols(sb[i].W, k1, false, sb[i].V, k1, k1, k, sb[i].idx, sb[i].scale, st));
-      FB_TRY(zgemm(st, false, (int)n, k, k1, sb[i].Q, n, sb[i].V, k1, sb[i].X, n));
-      std::swap(sb[i].Q, sb[i].X);
-      // B Q'' into Y (its trailing columns keep the start vectors)
-      FB_TRY(band_matmul(bd, sb[i].Q, n, sb[i].Y, n, k, st));
-      // A_q = Q''^H B Q'' (k x k) into G
-      FB_TRY(zgemm(st, true, k, k, (int)n, sb[i].Q, n, sb[i].Y, n, sb[i].G, k));
-      FB_TRY(hermitize(sb[i].G, k, k, st));
-      JacobiJob J{};
-      J.m = k;
-      J.A = sb[i].G;
-      J.lda = k;
-      J.V = sb[i].V;
-      J.ldv = k;
-      J.W = sb[i].W;
-      J.ldw = k;
-      J.w = sb[i].lam;
-      J.order = sb[i].order;
-      J.sweeps = sb[i].sweeps;
-      jj.push_back(J);
-    }
-    if (!jj.empty()) FB_TRY(reduced_eig(jj, jj_dev, ew, 60, 1e-14, st));
+    std::vector<int> path(nslice, 0);
+    FB_TRY(ortho_rr<R>(bd, nslice, act, m0, kept, path, fbuf, st));
     for (int i : act) {
       int m = m0[i], k = kept[i];
       if (k <= 0) continue;
-      // Ritz vectors X = Q'' W into X; residuals; X becomes the next start block
-      FB_TRY(zgemm(st, false, (int)n, k, k, sb[i].Q, n, sb[i].W, k, sb[i].X, n));
-      FB_TRY(eig_residuals(bd, sb[i].X, n, sb[i].lam, k, sb[i].part, sb[i].res, st));
+      // X becomes the next start block
       if (k < m)  // rank-deficient filter output: keep the trailing start vectors
         FB_HIP(hipMemcpy2DAsync(sb[i].X + (size_t)k * n, n * sizeof(c128), sb[i].Y + (size_t)k * n,
                                 n * sizeof(c128), n * sizeof(c128), m - k,
@@ -620,7 +804,7 @@ int feast_wave(const Band& bd, int nslice, const double* lo, const double* hi, c
     }
     m_found[i] = good[i];
     if (done[i])
-      info[i] = (k < m) ? 4 : 0;
+      info[i] = fellback[i] ? 3 : (k < m) ? 4 : 0;
     else
       info[i] = (good[i] > mexp[i] || inside[i] < mexp[i]) ? 2 : 1;
     if (info[i] == 1 || info[i] == 2) ++nbad;
@@ -649,6 +833,7 @@ int feast_impl(const fb_band* B, int nslice, const double* lo, const double* hi,
   ar.cap = *lwork;
   Band bd;
   FB_TRY(ingest_band(B, bd, ar, st));
+  double* fpart = ar.take<double>((size_t)kFiniteParts * std::max(nslice, 1));
   const int64_t n = B->n;
   const bool cplx = B->dtype == FB_COMPLEX128;
   int maxm = 1;
@@ -689,6 +874,7 @@ int feast_impl(const fb_band* B, int nslice, const double* lo, const double* hi,
     return 0;
   }
   if (!ar.fits()) return FB_ERR_NOMEM;
+  FB_TRY(check_finite_blocks(nslice, Y, ldy, m0, n, cplx, fpart, st));
   int nbad = 0;
   for (int w0 = 0; w0 < nslice; w0 += W) {
     const int nw = std::min(W, nslice - w0);
@@ -758,11 +944,19 @@ int filter_impl(const fb_band* B, int nslice, const double* lo, const double* hi
   ar.cap = *lwork;
   Band bd;
   FB_TRY(ingest_band(B, bd, ar, st));
+  double* fpart = ar.take<double>((size_t)kFiniteParts * std::max(nslice, 1));
   const int64_t n = B->n;
   const bool cplx = B->dtype == FB_COMPLEX128;
   const int nsys = nslice * ne;
   FactorBufs<R> f;
   carve_factors<R>(ar, bd, nsys, f);
+  FactorBufs<double> f64fb;
+  C128Fallback fbk;
+  if (ir) {
+    fbk.cap = fallback_cap(nsys);
+    carve_factors<double>(ar, bd, fbk.cap, f64fb);
+    fbk.f = &f64fb;
+  }
   std::vector<c128*> Yc(nslice), Qc(nslice);
   std::vector<int64_t> ldyc(nslice), ldqc(nslice);
   for (int i = 0; i < nslice; ++i) {
@@ -799,6 +993,7 @@ int filter_impl(const fb_band* B, int nslice, const double* lo, const double* hi
     return 0;
   }
   if (!ar.fits()) return FB_ERR_NOMEM;
+  FB_TRY(check_finite_blocks(nslice, Y, ldy, m, n, cplx, fpart, st));
   std::vector<c128> zsys(nsys), wsys(nsys);
   std::vector<double> zh(2 * nsys);
   for (int i = 0; i < nslice; ++i) {
@@ -823,7 +1018,8 @@ int filter_impl(const fb_band* B, int nslice, const double* lo, const double* hi
   int unconverged = 0;
   FB_TRY(filter_apply<R>(bd, f, ne, act, m, Yc.data(), ldyc.data(), Qc.data(), ldqc.data(),
                          Xp.data(), P, acc_dev, zsys, wsys, cplx, o->batched != 0, ir, o->ir_tol,
-                         o->ir_max, need_res, rb, sys_res, sys_pass, &unconverged, st));
+                         o->ir_max, need_res, rb, sys_res, sys_pass, &unconverged, st,
+                         ir ? &fbk : nullptr));
   if (!cplx)
     for (int i : act) FB_TRY(store_cols(Qc[i], n, Q[i], ldq[i], true, n, m[i], nullptr, st));
   FB_HIP(hipStreamSynchronize(st));
@@ -894,6 +1090,64 @@ extern "C" int fb_contour(double lo, double hi, int32_t k, int32_t rule, double 
     z[2 * j + 1] = zz[j].y;
     w[2 * j] = ww[j].x;
     w[2 * j + 1] = ww[j].y;
+  }
+  return 0;
+}
+
+extern "C" int band_rayleigh_ritz(const fb_band* B, int32_t nblk, const int32_t* m,
+                                  const void* const* Q, const int64_t* ldq, void* const* X,
+                                  const int64_t* ldx, double* const* evals, double* const* resid,
+                                  int32_t* rank, int32_t* path, void* work, size_t* lwork,
+                                  void* stream) {
+  if (check_band(B)) return -1;
+  if (nblk < 0) return -2;
+  if (nblk > 0 && !m) return -3;
+  if (nblk > 0 && (!Q || !ldq)) return -4;
+  if (nblk > 0 && (!X || !ldx)) return -6;
+  if (nblk > 0 && (!evals || !resid)) return -8;
+  if (nblk > 0 && !rank) return -10;
+  if (!lwork) return -13;
+  int maxm = 1;
+  for (int i = 0; i < nblk; ++i) {
+    if (m[i] < 0 || m[i] > 4096 || m[i] > B->n) return -3;
+    if (m[i] > 0 && (!Q[i] || ldq[i] < B->n)) return -4;
+    if (m[i] > 0 && (!X[i] || ldx[i] < B->n)) return -6;
+    if (m[i] > 0 && (!evals[i] || !resid[i])) return -8;
+    maxm = std::max(maxm, (int)m[i]);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  Arena ar;
+  ar.base = (char*)work;
+  ar.cap = *lwork;
+  Band bd;
+  FB_TRY(ingest_band(B, bd, ar, st, false));
+  FeastBufs<double> fbuf;
+  carve_feast<double>(ar, bd, std::max(nblk, 1), maxm, 0, false, 1, fbuf);
+  if (work == nullptr) {
+    *lwork = ar.used;
+    return 0;
+  }
+  if (!ar.fits()) return FB_ERR_NOMEM;
+  const int64_t n = bd.n;
+  const bool cplx = bd.cplx;
+  std::vector<int> act, kept(nblk, 0), pth(nblk, 0);
+  for (int i = 0; i < nblk; ++i) {
+    if (m[i] <= 0) continue;
+    act.push_back(i);
+    FB_TRY(gather_cols(Q[i], ldq[i], !cplx, fbuf.sb[i].Q, n, n, m[i], nullptr, nullptr, st));
+  }
+  FB_TRY(ortho_rr<double>(bd, nblk, act, m, kept, pth, fbuf, st));
+  for (int i : act) {
+    const int k = kept[i];
+    if (k <= 0) continue;
+    FB_TRY(store_cols(fbuf.sb[i].X, n, X[i], ldx[i], !cplx, n, k, nullptr, st));
+    FB_HIP(hipMemcpyAsync(evals[i], fbuf.sb[i].lam, sizeof(double) * k, hipMemcpyDeviceToDevice, st));
+    FB_HIP(hipMemcpyAsync(resid[i], fbuf.sb[i].res, sizeof(double) * k, hipMemcpyDeviceToDevice, st));
+  }
+  FB_HIP(hipStreamSynchronize(st));
+  for (int i = 0; i < nblk; ++i) {
+    rank[i] = kept[i];
+    if (path) path[i] = pth[i];
   }
   return 0;
 }

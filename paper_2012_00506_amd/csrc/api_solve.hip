@@ -178,7 +178,7 @@ int solve_refine(const Band& bd, const cx<R>* mats, const cx<R>* matsT, const in
                  const std::vector<SolveJob>& jobs, const std::vector<c128>& zsys, bool ir,
                  double ir_tol, int ir_max, bool need_res, RefineBufs& rb,
                  std::vector<double>& sys_res, std::vector<int32_t>& sys_pass, int* unconverged,
-                 hipStream_t st) {
+                 hipStream_t st, const C128Fallback* fb) {
   const int njobs = (int)jobs.size();
   if (njobs == 0) return 0;
   if (njobs > rb.cap_jobs) return FB_ERR_INTERNAL;
@@ -205,6 +205,7 @@ int solve_refine(const Band& bd, const cx<R>* mats, const cx<R>* matsT, const in
     groups.push_back({i, i});
   }
   const int ng = (int)groups.size();
+  std::vector<int> failed;  // systems with a group above ir_tol after ir_max passes
   std::vector<ResJob> rj, ra;
   std::vector<SolveJob> cj;
   std::vector<double> rat;
@@ -257,7 +258,7 @@ int solve_refine(const Band& bd, const cx<R>* mats, const cx<R>* matsT, const in
           active[g] = 0;
           double q = rat[a];
           if (!(q <= sys_res[sys])) sys_res[sys] = q;
-          if (ir && !ok && unconverged) ++*unconverged;
+          if (ir && !ok) failed.push_back(sys);
           continue;
         }
         for (int i = groups[w0 + g].first; i <= groups[w0 + g].second; ++i) {
@@ -280,17 +281,57 @@ int solve_refine(const Band& bd, const cx<R>* mats, const cx<R>* matsT, const in
                                   solve_flops(bd.n, bd.b, ccols), st));
     }
   }
+  std::sort(failed.begin(), failed.end());
+  failed.erase(std::unique(failed.begin(), failed.end()), failed.end());
+  if (!failed.empty() && fb && fb->f && fb->cap > 0 && sizeof(R) == 4) {
+    // factor the failing systems again in complex128 and solve their
+    // columns anew from the right-hand sides, cap systems at a time
+    for (size_t c0 = 0; c0 < failed.size(); c0 += fb->cap) {
+      const size_t nc = std::min(failed.size() - c0, (size_t)fb->cap);
+      std::vector<double> zh(2 * nc);
+      std::vector<c128> zsub(nc);
+      for (size_t q = 0; q < nc; ++q) {
+        zsub[q] = zsys[failed[c0 + q]];
+        zh[2 * q] = zsub[q].x;
+        zh[2 * q + 1] = zsub[q].y;
+      }
+      FB_TRY(factor_systems<double>(bd, (int)nc, zh.data(), *fb->f, st));
+      std::vector<SolveJob> sub;
+      for (const SolveJob& jb : jobs) {
+        auto it = std::find(failed.begin() + c0, failed.begin() + c0 + nc, jb.sys);
+        if (it == failed.begin() + c0 + nc) continue;
+        SolveJob c = jb;
+        c.sys = (int32_t)(it - (failed.begin() + c0));
+        c.mid = c.out;
+        c.ldmid = c.ldout;
+        c.add = 0;
+        sub.push_back(c);
+      }
+      std::vector<double> sres(nc, 0.0);
+      std::vector<int32_t> spass(nc, 0);
+      FB_TRY(solve_refine<double>(bd, fb->f->mats, nullptr, fb->f->perm, sub, zsub, false, 0.0, 0,
+                                  true, rb, sres, spass, nullptr, st));
+      for (size_t q = 0; q < nc; ++q) {
+        const int s = failed[c0 + q];
+        sys_res[s] = sres[q];
+        sys_pass[s] = -1;
+      }
+    }
+  }
+  if (unconverged)
+    for (int s : failed)
+      if (!(sys_res[s] <= ir_tol)) ++*unconverged;
   return 0;
 }
 
 template int solve_refine<float>(const Band&, const c64*, const c64*, const int16_t*,
                                  const std::vector<SolveJob>&, const std::vector<c128>&, bool,
                                  double, int, bool, RefineBufs&, std::vector<double>&,
-                                 std::vector<int32_t>&, int*, hipStream_t);
+                                 std::vector<int32_t>&, int*, hipStream_t, const C128Fallback*);
 template int solve_refine<double>(const Band&, const c128*, const c128*, const int16_t*,
                                   const std::vector<SolveJob>&, const std::vector<c128>&, bool,
                                   double, int, bool, RefineBufs&, std::vector<double>&,
-                                  std::vector<int32_t>&, int*, hipStream_t);
+                                  std::vector<int32_t>&, int*, hipStream_t, const C128Fallback*);
 
 template <typename R>
 int shifted_solve_impl(const fb_band* B, int nsys, const double* z, const int32_t* m,
@@ -303,8 +344,16 @@ int shifted_solve_impl(const fb_band* B, int nsys, const double* z, const int32_
   ar.cap = *lwork;
   Band bd;
   FB_TRY(ingest_band(B, bd, ar, st));
+  double* fpart = ar.take<double>((size_t)kFiniteParts * std::max(nsys, 1));
   FactorBufs<R> f;
   carve_factors<R>(ar, bd, nsys, f);
+  FactorBufs<double> f64fb;
+  C128Fallback fbk;
+  if (ir) {
+    fbk.cap = fallback_cap(nsys);
+    carve_factors<double>(ar, bd, fbk.cap, f64fb);
+    fbk.f = &f64fb;
+  }
 
   // jobs: every (system, direction, tile)
   const int tile = solve_tile<R>(bd.b);
@@ -336,6 +385,7 @@ int shifted_solve_impl(const fb_band* B, int nsys, const double* z, const int32_
     return 0;
   }
   if (!ar.fits()) return FB_ERR_NOMEM;
+  FB_TRY(check_finite_blocks(nsys, Y, ldy, m, bd.n, true, fpart, st));
 
   FB_TRY(factor_systems<R>(bd, nsys, z, f, st));
   std::vector<c128> zsys(nsys);
@@ -344,7 +394,7 @@ int shifted_solve_impl(const fb_band* B, int nsys, const double* z, const int32_
   std::vector<int32_t> sys_pass(nsys, 0);
   int unconverged = 0;
   FB_TRY(solve_refine<R>(bd, f.mats, f.matsT, f.perm, jobs, zsys, ir, o->ir_tol, o->ir_max, need_res, rb,
-                         sys_res, sys_pass, &unconverged, st));
+                         sys_res, sys_pass, &unconverged, st, ir ? &fbk : nullptr));
   FB_HIP(hipStreamSynchronize(st));
   if (resid)
     for (int s = 0; s < nsys; ++s) resid[s] = sys_res[s];

@@ -1,6 +1,7 @@
 // Band ingest: LAPACK lower band (real or complex) -> diagonal-major complex128
 // copy, plus ||B||_1 and the Gershgorin interval.
 #include <algorithm>
+#include <vector>
 
 #include "fb_internal.h"
 
@@ -30,19 +31,25 @@ __global__ void k_band_ingest(const double* __restrict__ ab, int64_t ldab, int c
 
 // Column sums of |B| over the full Hermitian matrix: column j holds the
 // lower entries B(j+d, j) and the upper ones conj(B(j, j-d)).
-// Per block: max colsum, min(a_jj - R_j), max(a_jj + R_j).
+// Per block: max colsum, min(a_jj - R_j), max(a_jj + R_j), and the number of
+// stored entries that are NaN or infinite.
 __global__ void k_band_colstats(const c128* __restrict__ Bd, int64_t n, int b,
                                 double* __restrict__ part) {
-  __shared__ double s0[256], s1[256], s2[256];
-  double mx = 0.0, lo = 1e308, hi = -1e308;
+  __shared__ double s0[256], s1[256], s2[256], s3[256];
+  double mx = 0.0, lo = 1e308, hi = -1e308, bad = 0.0;
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * blockDim.x) {
     double r = 0.0;
     for (int d = 1; d <= b; ++d) {
-      if (j + d < n) r += sqrt(cabs2(Bd[(int64_t)d * n + j]));
+      if (j + d < n) {
+        const c128 v = Bd[(int64_t)d * n + j];
+        r += sqrt(cabs2(v));
+        bad += (isfinite(v.x) && isfinite(v.y)) ? 0.0 : 1.0;
+      }
       if (j - d >= 0) r += sqrt(cabs2(Bd[(int64_t)d * n + j - d]));
     }
     double a = Bd[j].x;
+    bad += isfinite(a) ? 0.0 : 1.0;
     mx = fmax(mx, r + fabs(a));
     lo = fmin(lo, a - r);
     hi = fmax(hi, a + r);
@@ -51,41 +58,47 @@ __global__ void k_band_colstats(const c128* __restrict__ Bd, int64_t n, int b,
   s0[t] = mx;
   s1[t] = lo;
   s2[t] = hi;
+  s3[t] = bad;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
     if (t < s) {
       s0[t] = fmax(s0[t], s0[t + s]);
       s1[t] = fmin(s1[t], s1[t + s]);
       s2[t] = fmax(s2[t], s2[t + s]);
+      s3[t] += s3[t + s];
     }
     __syncthreads();
   }
   if (t == 0) {
-    part[3 * blockIdx.x + 0] = s0[0];
-    part[3 * blockIdx.x + 1] = s1[0];
-    part[3 * blockIdx.x + 2] = s2[0];
+    part[4 * blockIdx.x + 0] = s0[0];
+    part[4 * blockIdx.x + 1] = s1[0];
+    part[4 * blockIdx.x + 2] = s2[0];
+    part[4 * blockIdx.x + 3] = s3[0];
   }
 }
 
 __global__ void k_band_colstats_final(const double* __restrict__ part, int nb,
                                       double* __restrict__ out) {
-  __shared__ double s0[256], s1[256], s2[256];
+  __shared__ double s0[256], s1[256], s2[256], s3[256];
   int t = threadIdx.x;
-  double mx = 0.0, lo = 1e308, hi = -1e308;
+  double mx = 0.0, lo = 1e308, hi = -1e308, bad = 0.0;
   for (int i = t; i < nb; i += blockDim.x) {
-    mx = fmax(mx, part[3 * i]);
-    lo = fmin(lo, part[3 * i + 1]);
-    hi = fmax(hi, part[3 * i + 2]);
+    mx = fmax(mx, part[4 * i]);
+    lo = fmin(lo, part[4 * i + 1]);
+    hi = fmax(hi, part[4 * i + 2]);
+    bad += part[4 * i + 3];
   }
   s0[t] = mx;
   s1[t] = lo;
   s2[t] = hi;
+  s3[t] = bad;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
     if (t < s) {
       s0[t] = fmax(s0[t], s0[t + s]);
       s1[t] = fmin(s1[t], s1[t + s]);
       s2[t] = fmax(s2[t], s2[t + s]);
+      s3[t] += s3[t + s];
     }
     __syncthreads();
   }
@@ -93,6 +106,7 @@ __global__ void k_band_colstats_final(const double* __restrict__ part, int nb,
     out[0] = s0[0];
     out[1] = s1[0];
     out[2] = s2[0];
+    out[3] = s3[0];
   }
 }
 
@@ -132,11 +146,11 @@ int ingest_band(const fb_band* B, Band& out, Arena& ar, hipStream_t st, bool blo
   out.b0 = B->b;
   out.cplx = B->dtype == FB_COMPLEX128;
   out.Bd = ar.take<c128>((size_t)(out.b + 1) * B->n);
-  out.stats = ar.take<double>(3);
+  out.stats = ar.take<double>(4);
   out.nb = (out.b + 15) / 16 * 16;
   out.K = (int)((out.n + out.nb - 1) / out.nb);
   out.Bblk = blocks ? ar.take<c128>((size_t)out.K * 3 * out.nb * out.nb) : nullptr;
-  double* part = ar.take<double>(3 * kStatBlocks);
+  double* part = ar.take<double>(4 * kStatBlocks);
   if (ar.base == nullptr) return 0;
   if (!ar.fits()) return FB_ERR_NOMEM;
   int64_t total = (int64_t)(out.b + 1) * B->n;
@@ -155,6 +169,52 @@ int ingest_band(const fb_band* B, Band& out, Arena& ar, hipStream_t st, bool blo
     k_band_blocks<<<g, 256, 0, st>>>(out.Bd, out.n, out.b, out.nb, out.K, out.Bblk);
     FB_HIP(hipGetLastError());
   }
+  double bad = 0.0;
+  FB_HIP(hipMemcpyAsync(&bad, out.stats + 3, sizeof(double), hipMemcpyDeviceToHost, st));
+  FB_HIP(hipStreamSynchronize(st));
+  if (bad != 0.0) return FB_ERR_NONFINITE;
+  return 0;
+}
+
+// Number of NaN or infinite entries of a column-major block (real or
+// complex), per workgroup into part (gridDim.x doubles).
+__global__ void __launch_bounds__(256)
+k_count_nonfinite(const double* __restrict__ p, int64_t rows, int cols, int64_t ld, int words,
+                  double* __restrict__ part) {
+  __shared__ double red[256];
+  double bad = 0.0;
+  const int64_t tot = rows * cols * words;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e / (rows * words), r = e - c * rows * words;
+    bad += isfinite(p[c * ld * words + r]) ? 0.0 : 1.0;
+  }
+  red[threadIdx.x] = bad;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+int check_finite_blocks(int nblk, const void* const* P, const int64_t* ld, const int32_t* cols,
+                        int64_t rows, bool cplx, double* part_dev, hipStream_t st) {
+  constexpr int G = 64;
+  int used = 0;
+  for (int i = 0; i < nblk; ++i) {
+    if (cols[i] <= 0) continue;
+    k_count_nonfinite<<<G, 256, 0, st>>>((const double*)P[i], rows, cols[i], ld[i],
+                                         cplx ? 2 : 1, part_dev + (size_t)used * G);
+    FB_HIP(hipGetLastError());
+    ++used;
+  }
+  if (!used) return 0;
+  std::vector<double> h((size_t)used * G);
+  FB_HIP(hipMemcpyAsync(h.data(), part_dev, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+  FB_HIP(hipStreamSynchronize(st));
+  for (double v : h)
+    if (v != 0.0) return FB_ERR_NONFINITE;
   return 0;
 }
 

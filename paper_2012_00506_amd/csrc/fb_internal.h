@@ -145,7 +145,7 @@ struct Band {
   int b0;        // declared bandwidth (may be 0)
   bool cplx;
   c128* Bd;      // dev, (b+1) * n
-  double* stats; // dev, 3: ||B||_1, g_lo, g_hi
+  double* stats; // dev, 4: ||B||_1, g_lo, g_hi, count of NaN / Inf entries
   // block-tridiagonal copy with nb x nb blocks (nb = b rounded up to 16):
   // Bblk[(k*3 + s) * nb*nb], s = 0: B(k,k-1), 1: B(k,k), 2: B(k,k+1), column-major
   c128* Bblk;
@@ -154,9 +154,16 @@ struct Band {
 };
 
 // Kernels launched from the host side (defined in the .hip files).
-// blocks = false skips the block-tridiagonal copy (only the FP64 residual reads it)
+// blocks = false skips the block-tridiagonal copy (only the FP64 residual reads
+// it).  Returns FB_ERR_NONFINITE when B holds a NaN or an infinity.
 int ingest_band(const fb_band* B, Band& out, Arena& ar, hipStream_t st, bool blocks = true);
 int band_stats_host(const Band& bd, double* out3, hipStream_t st);
+// FB_ERR_NONFINITE when one of the nblk column-major blocks P[i] (rows x
+// cols[i], leading dimension ld[i] in elements; complex128 or double) holds a
+// NaN or an infinity.  part_dev: 64 doubles per block.  Synchronises.
+int check_finite_blocks(int nblk, const void* const* P, const int64_t* ld, const int32_t* cols,
+                        int64_t rows, bool cplx, double* part_dev, hipStream_t st);
+constexpr int kFiniteParts = 64;
 
 // inertia for nshift shifts (dev shifts array), counts dev int32 x3
 int launch_inertia(const Band& bd, int nshift, const double* shifts_dev,

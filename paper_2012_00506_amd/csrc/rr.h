@@ -55,7 +55,7 @@ int launch_jacobi(int njobs, JacobiJob* jobs_dev, int max_sweeps, double tol, hi
 // Parallel block Jacobi (many workgroups per matrix) for larger matrices:
 // work holds block_jacobi_bytes(m) per job, dv_dev one device descriptor
 // per job (kBjDescBytes), norms_dev 2 doubles per job.  Synchronises.
-constexpr size_t kBjDescBytes = 64;
+constexpr size_t kBjDescBytes = 128;
 size_t block_jacobi_bytes(int m);
 int block_jacobi(const std::vector<JacobiJob>& jobs, const JacobiJob* jobs_dev, char* work,
                  void* dv_dev, double* norms_dev, int max_sweeps, double tol, hipStream_t st);

@@ -92,13 +92,24 @@ struct RefineBufs {
 };
 void carve_refine(Arena& ar, const Band& bd, int tile, int max_jobs, bool ir, bool need_res,
                   RefineBufs& rb);
+
+// Complex128 fallback of the refined complex64 solves: a system whose FP64
+// residual stays above ir_tol after ir_max correction passes is factored
+// again in complex128 (cap systems at a time, in f) and its columns are
+// solved again from the right-hand sides; its sys_pass entry becomes -1.
+struct C128Fallback {
+  FactorBufs<double>* f = nullptr;
+  int cap = 0;
+};
+// systems the fallback factors hold at once
+inline int fallback_cap(int nsys) { return nsys < 2 ? nsys : 2; }
 size_t refine_bytes(const Band& bd, int tile, int max_jobs, bool ir, bool need_res);
 template <typename R>
 int solve_refine(const Band& bd, const cx<R>* mats, const cx<R>* matsT, const int16_t* perm,
                  const std::vector<SolveJob>& jobs, const std::vector<c128>& zsys, bool ir,
                  double ir_tol, int ir_max, bool need_res, RefineBufs& rb,
                  std::vector<double>& sys_res, std::vector<int32_t>& sys_pass, int* unconverged,
-                 hipStream_t st);
+                 hipStream_t st, const C128Fallback* fb = nullptr);
 int check_band(const fb_band* B);
 
 }  // namespace fb

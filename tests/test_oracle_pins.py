@@ -361,3 +361,60 @@ def test_orthonormalise_keeps_directions_below_gram_resolution():
     Z = np.concatenate([Q[:, :10], Q[:, :10] @ rng.standard_normal((10, 5))], axis=1)
     _, k2 = feast.orthonormalise(Z)
     assert k2 == 10
+
+
+def test_cholqr_orthonormal_same_span_and_fallback():
+    # Cholesky QR twice on the column-equilibrated block: orthonormal to
+    # rounding, the same span as Q, and column order kept (the basis is
+    # upper-triangular in Q: U = Q T, so the first j columns of U span the
+    # first j columns of Q); a block whose equilibrated Gram matrix has a
+    # pivot at or below 1e-12 is refused (the eigen passes take over)
+    rng = np.random.default_rng(7)
+    n, m = 500, 50
+    U0, _ = np.linalg.qr(rng.standard_normal((n, m)) + 1j * rng.standard_normal((n, m)))
+    W, _ = np.linalg.qr(rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m)))
+    Q = U0 @ np.diag(10.0 ** -np.linspace(0, 5, m)) @ W
+    Qo = feast.orthonormalise_cholqr(Q)
+    assert Qo is not None
+    assert np.abs(Qo.conj().T @ Qo - np.eye(m)).max() < 1e-14
+    R = Q - Qo @ (Qo.conj().T @ Q)
+    assert np.linalg.norm(R) < 1e-11 * np.linalg.norm(Q)
+    T = np.linalg.lstsq(Q, Qo, rcond=None)[0]
+    assert np.abs(np.tril(T, -1)).max() < 1e-6 * np.abs(T).max()
+    # against Householder QR: same columns up to unit phases
+    Qh, Rh = np.linalg.qr(Q)
+    ph = np.diag(Qh.conj().T @ Qo)
+    assert np.allclose(np.abs(ph), 1.0, atol=1e-8)
+    # a column that repeats an earlier one: refused
+    Z = np.concatenate([Q[:, :10], Q[:, 3:4]], axis=1)
+    assert feast.orthonormalise_cholqr(Z) is None
+    # a zero column: refused
+    Z2 = Q[:, :5].copy()
+    Z2[:, 2] = 0
+    assert feast.orthonormalise_cholqr(Z2) is None
+
+
+def test_rayleigh_ritz_paths_agree():
+    # the Cholesky QR and eigen-decomposition paths give the same Ritz values
+    # on a full-rank block (the basis differs by a unitary, the Ritz values
+    # not), and Rayleigh-Ritz on an invariant subspace returns eigenvalues
+    import synth
+    n = 300
+    ab = synth.band_matrix(n, 6, 9, True, -10, 10)
+    rng = np.random.default_rng(1)
+    Q = rng.standard_normal((n, 40)) + 1j * rng.standard_normal((n, 40))
+    st = {}
+    lam_c, X_c, k_c = feast.rayleigh_ritz(ab, Q, st)
+    assert st == {"cholqr": 1} and k_c == 40
+    Qe, k_e = feast.orthonormalise(Q)
+    A = Qe.conj().T @ band.band_matmul(ab, Qe)
+    lam_e = np.linalg.eigvalsh(0.5 * (A + A.conj().T))
+    assert np.abs(lam_c - lam_e).max() < 1e-12 * band.norm1(ab)
+    lam_all, V = np.linalg.eigh(band.dense_from_band(ab))
+    lam_v, _, _ = feast.rayleigh_ritz(ab, V[:, 100:130] @ W30(rng))
+    assert np.abs(lam_v - lam_all[100:130]).max() < 1e-12 * band.norm1(ab)
+
+
+def W30(rng):
+    W, _ = np.linalg.qr(rng.standard_normal((30, 30)) + 1j * rng.standard_normal((30, 30)))
+    return W @ np.diag(10.0 ** -np.linspace(0, 3, 30))
