@@ -44,6 +44,8 @@ def parse():
     p.add_argument("--workload", default="cplx-n16384-b64")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 path")
+    p.add_argument("--no-e2e", action="store_true",
+                   help="skip the end-to-end FEAST runs (all slices to convergence)")
     p.add_argument("--cpu-cols", type=int, default=256, help="columns in the CPU sample")
     p.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                    help="after the timed region, run one plain device copy of MIB MiB "
@@ -81,32 +83,72 @@ def recorded_traffic(workload: str, precision: int):
     return ent["hbm_bytes_per_launch"]
 
 
-def cpu_baseline(cfg, ab, m0_mean, ncols):
-    """The CPU oracle on a bounded sample: one shifted system of the workload,
-    its band LU and ncols N and H solves, timed on this host.  The per-system
-    throughput is scaled to the workload's columns per system
-    (2 * mean m0): t_sys = t_LU + 2 m0 t_col."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_system(args):
+    """One shifted system of the sample in one worker process: band LU and
+    its N and H solves of the worker's columns (oracle, numpy)."""
+    name, z, col0, ncols = args
     from threadpoolctl import threadpool_limits
-    from oracle import bandlu, quadrature
+    from oracle import bandlu
     import synth
-    lo, hi = cfg.slices[len(cfg.slices) // 2]
-    z, _ = quadrature.contour(lo, hi, 8)
-    Y = synth.rhs_block(cfg.n, ncols, cfg.seed, True)
+    cfg = synth.CONFIGS[name]
+    cfg_ab = cfg.matrix()
+    Y = synth.rhs_block(cfg.n, ncols, cfg.seed, cfg.complex_, col0=col0)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        F = bandlu.shifted_band_lu(ab, z[0])
+        F = bandlu.shifted_band_lu(cfg_ab, z)
         t1 = time.perf_counter()
         bandlu.lu_solve(F, Y)
         bandlu.lu_solve_h(F, Y)
         t2 = time.perf_counter()
-    t_lu = t1 - t0
-    t_col = (t2 - t1) / (2 * ncols)
+    return t1 - t0, t2 - t1
+
+
+def cpu_baseline(cfg, m0_mean, ncols):
+    """The CPU oracle on a bounded sample, on all host cores: one worker
+    process per core, each factoring one shifted system of the workload (the
+    nodes of the middle slice, then of further slices) and solving ncols N
+    and ncols H columns with it.  Throughput = all columns solved / wall time,
+    with each worker's per-system time scaled to the workload's columns per
+    system (2 mean m0): t_sys = t_LU + 2 m0 t_col."""
+    import multiprocessing as mp
+    from oracle import quadrature
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, 16))
+    tasks = []
+    k = len(cfg.slices) // 2
+    while len(tasks) < cores:
+        lo, hi = cfg.slices[k % len(cfg.slices)]
+        z, _ = quadrature.contour(lo, hi, 8)
+        for zj in z:
+            if len(tasks) < cores:
+                tasks.append((cfg.name, complex(zj), 64 * len(tasks), ncols))
+        k += 1
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        times = pool.map(_cpu_system, tasks)
+    wall = time.perf_counter() - t0
     cols_sys = 2.0 * m0_mean
-    value = cols_sys / (t_lu + cols_sys * t_col)
-    return {"value": value, "unit": "RHS-cols/s", "cores": 1, "kind": "oracle",
-            "sample": (f"one shifted system of the workload (n={cfg.n}, b={cfg.b}): oracle band LU "
-                       f"{t_lu:.2f} s + {ncols} N and {ncols} H column solves {t2 - t1:.2f} s on one "
-                       f"core; scaled to {cols_sys:.0f} columns per system")}
+    t_sys = [t_lu + cols_sys * t_sol / (2 * ncols) for t_lu, t_sol in times]
+    value = cores * cols_sys / (sum(t_sys) / len(t_sys))
+    t_lu = sum(t for t, _ in times) / len(times)
+    t_sol = sum(t for _, t in times) / len(times)
+    return {"value": value, "unit": "RHS-cols/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "sample": (f"{cores} shifted systems of the workload (n={cfg.n}, b={cfg.b}), one per "
+                       f"core in parallel processes: oracle band LU {t_lu:.2f} s + {ncols} N and "
+                       f"{ncols} H column solves {t_sol:.2f} s each (mean), {wall:.1f} s wall; "
+                       f"per-system time scaled to {cols_sys:.0f} columns per system")}
 
 
 def run_path(fb, F, Y, Q, steps, warmup, cols_per_step):
@@ -137,6 +179,50 @@ def run_path(fb, F, Y, Q, steps, warmup, cols_per_step):
     return {"ms_per_step": ms_step, "value": cols_per_step / (ms_step / 1e3),
             "max_resid": worst, "ir_passes": passes, "prof": prof,
             "event_ms_per_step": ev0.elapsed_time(ev1) / steps}
+
+
+def band_norm1(ab) -> float:
+    """||B||_1 of the Hermitian band (LAPACK lower storage): the largest
+    column sum of |B(i, j)| over the full matrix."""
+    a = np.abs(np.asarray(ab))
+    b1, n = a.shape
+    col = a[0].copy()
+    for d in range(1, b1):
+        col[: n - d] += a[d, : n - d]   # B(j+d, j) in column j
+        col[d:] += a[d, : n - d]        # conj(B(j, j-d)) in column j
+    return float(col.max())
+
+
+def run_e2e(fb, B, cfg, lo, hi, counts, m0, precision, nrm1):
+    """FEAST on every slice of the workload to convergence, from the seeded
+    start blocks, with the per-class kernel time breakdown."""
+    import torch
+    import synth
+    Y = [synth.rhs_block_device(cfg.n, m, cfg.seed * 1000 + i, cfg.complex_)
+         for i, m in enumerate(m0)]
+    Y = [y.contiguous().t().contiguous().t() if y.stride(0) != 1 else y for y in Y]
+    torch.cuda.synchronize()
+    fb.profile_enable(True)
+    t0 = time.perf_counter()
+    res = fb.feast_band_slice(B, lo, hi, Y, m_expected=counts, precision=precision,
+                              ir_tol=1e-10 if precision else 1e-12)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = fb.profile_read()
+    fb.profile_enable(False)
+    mres = max(float(r.resid[: r.m_found].max()) for r in res if r.m_found)
+    del Y
+    torch.cuda.empty_cache()
+    return {"precision": "c64+f64 refinement" if precision else "f64", "seconds": wall,
+            "iters": [r.iters for r in res], "info": [r.info for r in res],
+            "eigenpairs": int(sum(r.m_found for r in res)),
+            "counts_match": bool(all(r.m_found == int(c) for r, c in zip(res, counts))),
+            "max_resid": mres,
+            # a Ritz value with residual ||B x - l x||_2 = r (||x|| = 1) lies
+            # within r of an eigenvalue of the Hermitian B
+            "eig_err_bound_max": mres * nrm1,
+            "breakdown_ms": {k: round(v[1], 3) for k, v in prof.items() if v[0]},
+            "launches": {k: v[0] for k, v in prof.items() if v[0]}}
 
 
 def roofline(prof, precision, workload):
@@ -207,7 +293,7 @@ def main():
         torch.cuda.empty_cache()
         # the plain FP64 path: one launch sequence per slice, no batching
         F64p = fb.FeastFilter(B, lo, hi, m0, n_nodes=n_nodes, precision=0, batched=False)
-        res["fp64_plain"] = run_path(fb, F64p, Y, Q, 1, 0, cols_per_step)
+        res["fp64_plain"] = run_path(fb, F64p, Y, Q, args.steps, args.warmup, cols_per_step)
         del F64p
         torch.cuda.empty_cache()
 
@@ -255,8 +341,13 @@ def main():
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = {"read": nel * 4, "write": nel * 4}
         del src, dst
+    if not args.no_e2e:
+        del Y, Q
+        torch.cuda.empty_cache()
+        nrm1 = band_norm1(ab)
+        out["e2e"] = [run_e2e(fb, B, cfg, lo, hi, counts, m0, prec, nrm1) for prec in (1, 0)]
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(cfg, ab, float(np.mean(m0)), args.cpu_cols)
+        out["cpu_baseline"] = cpu_baseline(cfg, float(np.mean(m0)), args.cpu_cols)
     print(json.dumps(out), flush=True)
 
 
