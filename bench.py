@@ -44,6 +44,8 @@ def parse():
     p.add_argument("--workload", default="cplx-n16384-b64")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 path")
+    p.add_argument("--tune-log", default=None, metavar="PATH",
+                   help="append the autotuner's time of every solve variant to PATH")
     p.add_argument("--no-e2e", action="store_true",
                    help="skip the end-to-end FEAST runs (all slices to convergence)")
     p.add_argument("--cpu-cols", type=int, default=256, help="columns in the CPU sample")
@@ -278,7 +280,7 @@ def main():
     # tune the block-solve kernel for both precisions on this shape (not timed)
     tuned = {}
     for prec in (1, 0):
-        v, ms = fb.autotune(B, prec, nsys=len(m0), m=int(max(m0)))
+        v, ms = fb.autotune(B, prec, nsys=len(m0), m=int(max(m0)), cache_path=args.tune_log)
         tuned["c64" if prec else "c128"] = {"variant": v, "ms": ms}
 
     res = {}

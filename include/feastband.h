@@ -95,7 +95,10 @@ typedef struct {
                            refined in FP64 (residual from the FP64 band) */
   double ir_tol;     /* precision 1: stop refining a column once
                         ||y - A x||_2 / ||y||_2 <= ir_tol */
-  int32_t ir_max;    /* precision 1: at most this many correction passes */
+  int32_t ir_max;    /* precision 1: at most this many correction passes; a
+                        column group whose residual a pass did not halve has
+                        stagnated and stops early (then, above ir_tol, the
+                        complex128 fallback) */
   int32_t tile;      /* right-hand-side columns per work item; 0 = default */
 } fb_solve_opts;
 
@@ -113,10 +116,14 @@ typedef struct {
  *         leading dimension ldx[s] >= n; XH itself or XH[s] may be NULL
  *  resid  host, nsys or NULL: max over the columns of system s (N and H)
  *         of ||y - A x||_2 / ||y||_2 after the call, computed in FP64
- *  passes host, nsys or NULL: refinement passes used (precision 1)
- * Returns FB_ERR_SINGULAR if a pivot is exactly zero.  Precision 1 returns
- * the number of systems whose residual stayed above ir_tol after ir_max
- * passes (0 when all converged). */
+ *  passes host, nsys or NULL: refinement passes used (precision 1); -1
+ *         when the residual stayed above ir_tol after ir_max passes and the
+ *         system was factored again and solved in complex128 (a warning:
+ *         the solution is the FP64 one)
+ * Returns FB_ERR_NONFINITE (nothing solved) when B or a Y block holds a
+ * NaN or an infinity, FB_ERR_SINGULAR if a pivot is exactly zero.
+ * Precision 1 returns the number of systems whose residual is still above
+ * ir_tol after the complex128 fallback (0 when all converged). */
 int band_shifted_solve(const fb_band* B, int32_t nsys, const double* z,
                        const int32_t* m, const void* const* Y,
                        const int64_t* ldy, void* const* X, void* const* XH,
@@ -182,9 +189,15 @@ typedef struct {
  *              eigen-residuals in the order of the columns of Y
  *  m_found, iters, info  host, nslice each.  info: 0 ok, 1 not converged in
  *              max_iter, 2 count mismatch (m0 too small or a missed
- *              eigenvalue: rerun with a larger m0), 4 rank-deficient
+ *              eigenvalue: rerun with a larger m0), 3 converged, but a
+ *              refined complex64 solve of the slice stagnated above ir_tol
+ *              and was redone in complex128 (a warning), 4 rank-deficient
  *              filtered block (a truncated basis was used), 5 m0 < m
- * Returns 0, or the number of slices with info in {1, 2, 5}. */
+ * The filtered block is orthonormalised as band_rayleigh_ritz describes
+ * (Cholesky QR twice, the eigen passes when it does not apply).
+ * Returns 0, or the number of slices with info in {1, 2, 5};
+ * FB_ERR_NONFINITE (nothing solved) when B or a start block holds a NaN or
+ * an infinity. */
 int feast_band_slice(const fb_band* B, int32_t nslice, const double* lo,
                      const double* hi, const int32_t* m0,
                      const int32_t* m_expected, void* const* Y,

@@ -188,7 +188,7 @@ def contour_nodes(lo, hi, k=8, rule="gauss", ratio=1.0):
 
 
 def feast_band_slice(B, lo, hi, Y, m_expected=None, n_nodes=8, tol=1e-10, max_iter=20,
-                     precision=0, ir_tol=1e-12, ir_max=4, batched=True, hbm_budget=0.0,
+                     precision=0, ir_tol=1e-12, ir_max=8, batched=True, hbm_budget=0.0,
                      pairs=0, rule="gauss", ratio=1.0, stream=None):
     """FEAST on the slices [lo_i, hi_i) of B from the start blocks Y[i]
     ((n, m0_i) column-major device tensors in the dtype of B; overwritten with

@@ -230,6 +230,7 @@ int solve_refine(const Band& bd, const cx<R>* mats, const cx<R>* matsT, const in
       r.z = zsys[f.sys];
     }
     const int maxpass = ir ? ir_max : 0;
+    std::vector<double> prev(nw, 0.0);
     for (int pass = 0;; ++pass) {
       ra.clear();
       ai.clear();
@@ -254,7 +255,10 @@ int solve_refine(const Band& bd, const cx<R>* mats, const cx<R>* matsT, const in
         size_t g = ai[a];
         const int sys = jobs[groups[w0 + g].first].sys;
         bool ok = ir ? (rat[a] <= ir_tol) : true;
-        if (ok || pass >= maxpass) {
+        // stagnation: a correction pass that did not halve the residual
+        const bool stalled = ir && pass > 0 && !(rat[a] < 0.5 * prev[g]);
+        prev[g] = rat[a];
+        if (ok || pass >= maxpass || stalled) {
           active[g] = 0;
           double q = rat[a];
           if (!(q <= sys_res[sys])) sys_res[sys] = q;

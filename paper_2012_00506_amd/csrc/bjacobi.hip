@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(256) k_bj_norms(BJDev* __restrict__ dv) {
   const BJDev d = dv[blockIdx.y];
   const int j = blockIdx.x;
   if (j >= d.mp) return;
-  const c128* A = d.A[d.cur];
+  const c128* A = (d.cur ? d.A[1] : d.A[0]);
   __shared__ double r0[256], r1[256];
   double off = 0.0, all = 0.0;
   const bool padj = gld(A + (int64_t)j * d.mp + j).x > 0.5 * kPad;
@@ -127,24 +127,25 @@ __global__ void k_bj_norms_final(BJDev* __restrict__ dv, int nmat, double* __res
 // One workgroup per (pair, matrix): cyclic Jacobi on the 64 x 64 principal
 // block (at most kInner sweeps, fewer once it is diagonal), accumulating U.
 static constexpr int kInner = 2;
+static constexpr int kPairThreads = 1024;  // one 2 x 2 block update per thread per round
 
 __device__ __forceinline__ int bj_player(int pos, int r, int n) {
   return pos == 0 ? 0 : 1 + (pos - 1 + r) % (n - 1);
 }
 
-__global__ void __launch_bounds__(256) k_bj_pairs(BJDev* __restrict__ dv) {
+__global__ void __launch_bounds__(kPairThreads) k_bj_pairs(BJDev* __restrict__ dv) {
   extern __shared__ __align__(16) char lds_raw[];
   c128* S = reinterpret_cast<c128*>(lds_raw);  // column-major, ld kPL
   c128* Us = S + kPb * kPL;                    // column-major, ld kPL
   __shared__ double s_cs[kBs], s_sn[kBs];
   __shared__ c128 s_e[kBs];
   __shared__ int s_p[kBs], s_q[kBs];
-  __shared__ double red[2][256];
+  __shared__ double red[2][kPairThreads];
   const BJDev d = dv[blockIdx.y];
   const int K = blockIdx.x;
   if (K >= d.h) return;
   const int t = threadIdx.x;
-  const c128* A = d.A[d.cur];
+  const c128* A = (d.cur ? d.A[1] : d.A[0]);
   const int64_t base = (int64_t)K * kPb;
   for (int e = t; e < kPb * kPb; e += blockDim.x) {
     const int cj = e / kPb, ci = e % kPb;
@@ -165,7 +166,7 @@ __global__ void __launch_bounds__(256) k_bj_pairs(BJDev* __restrict__ dv) {
     red[0][t] = off;
     red[1][t] = dg;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
+    for (int s = kPairThreads / 2; s > 0; s >>= 1) {
       if (t < s) {
         red[0][t] += red[0][t + s];
         red[1][t] += red[1][t + s];
@@ -238,25 +239,85 @@ __global__ void __launch_bounds__(256) k_bj_pairs(BJDev* __restrict__ dv) {
 }
 
 // -------------------------------------------------------------- updates
-// Workgroups 0 .. h^2-1 of a matrix: the tile (K, L) of A, R = U_K^H A[K,L]
-// U_L; workgroups h^2 .. h^2 + h (mp/64) - 1: the tile (I, L) of V,
-// V[I, L] U_L.  Each 32-row and 32-column block of the result is written to
-// its next-round position.  Four waves each own a 32 x 32 quarter of a
-// 64 x 64 x 64 product (2 x 2 MFMA tiles of 16 x 16, Gauss form).
+// Workgroups 0 .. h(h+1)/2-1 of a matrix: the tiles (K, L), K <= L, of A,
+// R = U_K^H A[K,L] U_L (R^H is the tile (L, K): A stays Hermitian);
+// workgroups from h(h+1)/2 on: the tiles (I, L) of V, V[I, L] U_L.  Each
+// 32-row and 32-column block of the result is written to its next-round
+// position.  Four waves each own a 32 x 32 quarter of a 64 x 64 x 64
+// product (2 x 2 MFMA tiles of 16 x 16, Gauss form); operand fragments are
+// loaded one contraction step ahead.
+template <bool CONJA, typename FA, typename FB>
+__device__ __forceinline__ void bj_quarter(bd4 (&p1)[2][2], bd4 (&p2)[2][2], bd4 (&p3)[2][2],
+                                           FA fa, FB fb, int lk) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) p1[a][b][r] = p2[a][b][r] = p3[a][b][r] = 0.0;
+  c128 an[2], bn[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    an[q] = fa(q, lk);
+    bn[q] = fb(q, lk);
+  }
+#pragma unroll 2
+  for (int kk = 0; kk < kPb; kk += 4) {
+    c128 ac[2] = {an[0], an[1]}, bc[2] = {bn[0], bn[1]};
+    if (kk + 4 < kPb) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        an[q] = fa(q, kk + 4 + lk);
+        bn[q] = fb(q, kk + 4 + lk);
+      }
+    }
+    double ar[2], ai[2], as[2], br[2], bi[2], bs[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      ar[q] = ac[q].x;
+      ai[q] = CONJA ? -ac[q].y : ac[q].y;
+      as[q] = ar[q] + ai[q];
+      br[q] = bc[q].x;
+      bi[q] = bc[q].y;
+      bs[q] = bc[q].x + bc[q].y;
+    }
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        p1[rt][ct] = bj_mfma(ar[rt], br[ct], p1[rt][ct]);
+        p2[rt][ct] = bj_mfma(ai[rt], bi[ct], p2[rt][ct]);
+        p3[rt][ct] = bj_mfma(as[rt], bs[ct], p3[rt][ct]);
+      }
+  }
+}
+
 __global__ void __launch_bounds__(256) k_bj_update(BJDev* __restrict__ dv) {
   extern __shared__ __align__(16) char lds_raw[];
   c128* Ts = reinterpret_cast<c128*>(lds_raw);  // 64 x 64, column-major, ld kPL
   const BJDev d = dv[blockIdx.y];
   const int h = d.h;
-  const int nA = h * h, nV = h * (d.mp / kPb);
+  const int nA = h * (h + 1) / 2, nV = h * (d.mp / kPb);
   const int wg = blockIdx.x;
   if (wg >= nA + nV) return;
   const bool isA = wg < nA;
-  const int K = isA ? wg / h : (wg - nA) / h;  // A: row pair; V: row tile
-  const int L = isA ? wg % h : (wg - nA) % h;
+  int K, L;
+  if (isA) {  // wg -> (K, L), K <= L, row by row
+    K = 0;
+    int off = 0;
+    while (off + (h - K) <= wg) {
+      off += h - K;
+      ++K;
+    }
+    L = K + (wg - off);
+  } else {
+    K = (wg - nA) / h;  // row tile of V
+    L = (wg - nA) % h;
+  }
   const int cur = d.cur;
-  const c128* Src = isA ? d.A[cur] : d.V[cur];
-  c128* Dst = isA ? d.A[cur ^ 1] : d.V[cur ^ 1];
+  // (selects, not indexing: an indexed member array would live in scratch)
+  const c128* Src = isA ? (cur ? d.A[1] : d.A[0]) : (cur ? d.V[1] : d.V[0]);
+  c128* Dst = isA ? (cur ? d.A[0] : d.A[1]) : (cur ? d.V[0] : d.V[1]);
   const int64_t ld = d.mp;
   const int64_t r0 = (int64_t)K * kPb, c0 = (int64_t)L * kPb;
   const int skK = isA ? gld(d.skip + K) : 1, skL = gld(d.skip + L);
@@ -265,114 +326,56 @@ __global__ void __launch_bounds__(256) k_bj_update(BJDev* __restrict__ dv) {
   const int li = lane & 15, lk = lane >> 4;
   const c128* UL = d.U + (size_t)L * kPb * kPb;
   const c128* UK = d.U + (size_t)K * kPb * kPb;
+  bd4 p1[2][2], p2[2][2], p3[2][2];
+  auto to_lds = [&]() {
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 32 * wr + 16 * rt + lk + 4 * r, j = 32 * wc + 16 * ct + li;
+          const double x1 = p1[rt][ct][r], x2 = p2[rt][ct][r], x3 = p3[rt][ct][r];
+          Ts[j * kPL + i] = mk(x1 - x2, x3 - x1 - x2);
+        }
+  };
 
-  // tile of Src into Ts when no product is needed on the right
-  if (skL) {
+  if (skL) {  // no product on the right: the tile itself
     for (int e = t; e < kPb * kPb; e += blockDim.x) {
       const int j = e / kPb, i = e % kPb;
       Ts[j * kPL + i] = gld(Src + (c0 + j) * ld + r0 + i);
     }
-  } else {
-    // T = Src[K, L] U_L
-    bd4 p1[2][2], p2[2][2], p3[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) p1[a][b][r] = p2[a][b][r] = p3[a][b][r] = 0.0;
-    for (int kk = 0; kk < kPb; kk += 4) {
-      const int k = kk + lk;
-      double ar[2], ai[2], as[2], br[2], bi[2], bs[2];
-#pragma unroll
-      for (int rt = 0; rt < 2; ++rt) {
-        const c128 a = gld(Src + (c0 + k) * ld + r0 + 32 * wr + 16 * rt + li);
-        ar[rt] = a.x;
-        ai[rt] = a.y;
-        as[rt] = a.x + a.y;
-      }
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct) {
-        const c128 b = gld(UL + k * kPb + 32 * wc + 16 * ct + li);
-        br[ct] = b.x;
-        bi[ct] = b.y;
-        bs[ct] = b.x + b.y;
-      }
-#pragma unroll
-      for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-          p1[rt][ct] = bj_mfma(ar[rt], br[ct], p1[rt][ct]);
-          p2[rt][ct] = bj_mfma(ai[rt], bi[ct], p2[rt][ct]);
-          p3[rt][ct] = bj_mfma(as[rt], bs[ct], p3[rt][ct]);
-        }
-    }
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = 32 * wr + 16 * rt + lk + 4 * r, j = 32 * wc + 16 * ct + li;
-          const double x1 = p1[rt][ct][r], x2 = p2[rt][ct][r], x3 = p3[rt][ct][r];
-          Ts[j * kPL + i] = mk(x1 - x2, x3 - x1 - x2);
-        }
+  } else {  // T = Src[K, L] U_L
+    bj_quarter<false>(
+        p1, p2, p3,
+        [&](int q, int k) { return gld(Src + (c0 + k) * ld + r0 + 32 * wr + 16 * q + li); },
+        [&](int q, int k) { return gld(UL + k * kPb + 32 * wc + 16 * q + li); }, lk);
+    to_lds();
   }
   __syncthreads();
-  if (!skK) {
-    // R = U_K^H T
-    bd4 p1[2][2], p2[2][2], p3[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) p1[a][b][r] = p2[a][b][r] = p3[a][b][r] = 0.0;
-    for (int kk = 0; kk < kPb; kk += 4) {
-      const int k = kk + lk;
-      double ar[2], ai[2], as[2], br[2], bi[2], bs[2];
-#pragma unroll
-      for (int rt = 0; rt < 2; ++rt) {
-        const c128 a = gld(UK + k * kPb + 32 * wr + 16 * rt + li);  // conj(U_K(k, i))
-        ar[rt] = a.x;
-        ai[rt] = -a.y;
-        as[rt] = a.x - a.y;
-      }
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct) {
-        const c128 b = Ts[(32 * wc + 16 * ct + li) * kPL + k];
-        br[ct] = b.x;
-        bi[ct] = b.y;
-        bs[ct] = b.x + b.y;
-      }
-#pragma unroll
-      for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-          p1[rt][ct] = bj_mfma(ar[rt], br[ct], p1[rt][ct]);
-          p2[rt][ct] = bj_mfma(ai[rt], bi[ct], p2[rt][ct]);
-          p3[rt][ct] = bj_mfma(as[rt], bs[ct], p3[rt][ct]);
-        }
-    }
+  if (!skK) {  // R = U_K^H T
+    bj_quarter<true>(
+        p1, p2, p3, [&](int q, int k) { return gld(UK + k * kPb + 32 * wr + 16 * q + li); },
+        [&](int q, int k) { return Ts[(32 * wc + 16 * q + li) * kPL + k]; }, lk);
     __syncthreads();  // every wave has read T
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = 32 * wr + 16 * rt + lk + 4 * r, j = 32 * wc + 16 * ct + li;
-          const double x1 = p1[rt][ct][r], x2 = p2[rt][ct][r], x3 = p3[rt][ct][r];
-          Ts[j * kPL + i] = mk(x1 - x2, x3 - x1 - x2);
-        }
+    to_lds();
     __syncthreads();
   }
-  // write out: rows of an A tile move with their blocks, V rows stay
+  // write out: rows of an A tile move with their blocks, V rows stay; an
+  // off-diagonal A tile also gives its conjugate transpose
   for (int e = t; e < kPb * kPb; e += blockDim.x) {
     const int j = e / kPb, i = e % kPb;
     const int64_t gr = isA ? (int64_t)bj_next(2 * K + i / kBs, h) * kBs + i % kBs : r0 + i;
     const int64_t gc = (int64_t)bj_next(2 * L + j / kBs, h) * kBs + j % kBs;
     gst(Dst + gc * ld + gr, Ts[j * kPL + i]);
+  }
+  if (isA && K != L) {
+    for (int e = t; e < kPb * kPb; e += blockDim.x) {
+      const int i = e / kPb, j = e % kPb;  // conj(R(i, j)) goes to (row of j, column of i)
+      const int64_t gr = (int64_t)bj_next(2 * L + j / kBs, h) * kBs + j % kBs;
+      const int64_t gc = (int64_t)bj_next(2 * K + i / kBs, h) * kBs + i % kBs;
+      gst(Dst + gc * ld + gr, cconj(Ts[j * kPL + i]));
+    }
   }
 }
 
@@ -382,7 +385,7 @@ __global__ void __launch_bounds__(256) k_bj_update(BJDev* __restrict__ dv) {
 __global__ void k_bj_rank(const JacobiJob* __restrict__ jobs, BJDev* __restrict__ dv) {
   const JacobiJob jb = jobs[blockIdx.y];
   const BJDev d = dv[blockIdx.y];
-  const c128* A = d.A[d.cur];
+  const c128* A = (d.cur ? d.A[1] : d.A[0]);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.mp) return;
   const double wi = gld(A + (int64_t)i * d.mp + i).x;
@@ -400,7 +403,7 @@ __global__ void k_bj_rank(const JacobiJob* __restrict__ jobs, BJDev* __restrict_
 __global__ void k_bj_vectors(const JacobiJob* __restrict__ jobs, BJDev* __restrict__ dv) {
   const JacobiJob jb = jobs[blockIdx.y];
   const BJDev d = dv[blockIdx.y];
-  const c128* V = d.V[d.cur];
+  const c128* V = (d.cur ? d.V[1] : d.V[0]);
   const int64_t tot = (int64_t)d.m * d.m;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -472,7 +475,7 @@ int block_jacobi(const std::vector<JacobiJob>& jobs, const JacobiJob* jobs_dev, 
   FB_HIP(hipGetLastError());
   std::vector<double> nrm(2 * nj);
   int sweeps = 0;
-  const int upd_wgs = max_h * max_h + max_h * (max_mp / kPb);
+  const int upd_wgs = max_h * (max_h + 1) / 2 + max_h * (max_mp / kPb);
   for (int sw = 0; sw <= max_sweeps; ++sw) {
     k_bj_norms<<<dim3(max_mp, nj), 256, 0, st>>>(dvd);
     FB_HIP(hipGetLastError());
@@ -488,7 +491,7 @@ int block_jacobi(const std::vector<JacobiJob>& jobs, const JacobiJob* jobs_dev, 
     // every matrix takes max_rounds rounds (a smaller one completes further
     // sweeps of its own schedule, which keeps it converging)
     for (int r = 0; r < max_rounds; ++r) {
-      k_bj_pairs<<<dim3(max_h, nj), 256, lds_pairs, st>>>(dvd);
+      k_bj_pairs<<<dim3(max_h, nj), kPairThreads, lds_pairs, st>>>(dvd);
       FB_HIP(hipGetLastError());
       k_bj_update<<<dim3(upd_wgs, nj), 256, lds_upd, st>>>(dvd);
       FB_HIP(hipGetLastError());

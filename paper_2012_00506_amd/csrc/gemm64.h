@@ -55,6 +55,7 @@ int gemm_batched(std::vector<GemmProb> probs, GemmProb* probs_dev, hipStream_t s
 // descriptors of many batches can then be copied to the device at once.
 struct GemmBatch {
   int nprob = 0;
+  int transa = 0;  // every product of a batch has the same form
   int nwg = 0;
   double work = 0.0;
   bool finish = false;

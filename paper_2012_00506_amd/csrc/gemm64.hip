@@ -42,6 +42,7 @@ __device__ __forceinline__ int gemm_remap(int bid, int nwg) {
 }
 }  // namespace
 
+template <bool TA>
 __global__ void __launch_bounds__(NTH)
 k_zgemm64(const GemmProb* __restrict__ probs, int nprob, int nwg) {
   extern __shared__ __align__(16) char lds_raw[];
@@ -74,7 +75,6 @@ k_zgemm64(const GemmProb* __restrict__ probs, int nprob, int nwg) {
     ke = min(ke, b2 + chunk);
     kb = b2;
   }
-  const bool ta = P.transa != 0;
   const c128* A = P.A;  // B may alias C (in-place panel updates): no restrict
   const c128* B = P.B;
   const int64_t lda = P.lda, ldb = P.ldb;
@@ -84,37 +84,42 @@ k_zgemm64(const GemmProb* __restrict__ probs, int nprob, int nwg) {
   const int li = lane & 15, lk = lane >> 4;
 
   // global -> register loads of one chunk (branch-free: an out-of-range
-  // element reads the operand's first element and is zeroed when stored)
-  c128 ra[4], rb[4];
-  bool va[4], vb[4];
-  auto issue = [&](int kc) {
+  // element reads the operand's first element and is zeroed when stored),
+  // issued one chunk ahead of the products.  The chunk's k-steps are not
+  // unrolled and the stores select values, which keeps every operand in
+  // registers (112 VGPRs, two waves per SIMD, no scratch)
+  struct Regs {
+    c128 a[4], b[4];
+  };
+  // element coordinates of this thread's loads (validity recomputed at the store)
+  auto a_ok = [&](int kc, int q) {
+    if (TA) return (i0 + (t >> 2)) < M && kc + (t & 3) * 4 + q < ke;
+    return (i0 + (t & 15) * 4 + q) < M && kc + (t >> 4) < ke;
+  };
+  auto b_ok = [&](int kc, int q) { return (j0 + (t >> 2)) < N && kc + (t & 3) * 4 + q < ke; };
+  auto issue = [&](Regs& R, int kc) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       int64_t off;
-      if (ta) {  // A^H: A is K x M, k contiguous: element (k, i) of A
-        const int i = t >> 2, k = kc + (t & 3) * 4 + q;
-        va[q] = (i0 + i) < M && k < ke;
-        off = va[q] ? (int64_t)(i0 + i) * lda + k : 0;
-      } else {   // A is M x K, i contiguous: element (i, k)
-        const int k = kc + (t >> 4), i = (t & 15) * 4 + q;
-        va[q] = (i0 + i) < M && k < ke;
-        off = va[q] ? (int64_t)k * lda + i0 + i : 0;
-      }
-      ra[q] = gld(A + off);
-      const int j = t >> 2, k = kc + (t & 3) * 4 + q;
-      vb[q] = (j0 + j) < N && k < ke;
-      rb[q] = gld(B + (vb[q] ? (int64_t)(j0 + j) * ldb + k : 0));
+      if (TA) off = (int64_t)(i0 + (t >> 2)) * lda + kc + (t & 3) * 4 + q;
+      else off = (int64_t)(kc + (t >> 4)) * lda + i0 + (t & 15) * 4 + q;
+      R.a[q] = gld(A + (a_ok(kc, q) ? off : 0));
+      const int64_t offb = (int64_t)(j0 + (t >> 2)) * ldb + kc + (t & 3) * 4 + q;
+      R.b[q] = gld(B + (b_ok(kc, q) ? offb : 0));
     }
   };
-  auto store = [&](int stg) {
+  auto store = [&](const Regs& R, int stg, int kc) {
     c128* As = lds + stg * 2 * STAGE;
     c128* Bs = As + STAGE;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const c128 z = mk(0.0, 0.0);
-      if (ta) As[(t >> 2) * PK + (t & 3) * 4 + q] = va[q] ? ra[q] : z;
-      else As[(t >> 4) * TT + (t & 15) * 4 + q] = va[q] ? ra[q] : z;
-      Bs[(t >> 2) * PK + (t & 3) * 4 + q] = vb[q] ? rb[q] : z;
+      // selects on values (a select of lvalues would put R in memory)
+      const bool oa = a_ok(kc, q), ob = b_ok(kc, q);
+      const c128 va = mk(oa ? R.a[q].x : 0.0, oa ? R.a[q].y : 0.0);
+      const c128 vb = mk(ob ? R.b[q].x : 0.0, ob ? R.b[q].y : 0.0);
+      if (TA) As[(t >> 2) * PK + (t & 3) * 4 + q] = va;
+      else As[(t >> 4) * TT + (t & 15) * 4 + q] = va;
+      Bs[(t >> 2) * PK + (t & 3) * 4 + q] = vb;
     }
   };
 
@@ -125,28 +130,19 @@ k_zgemm64(const GemmProb* __restrict__ probs, int nprob, int nwg) {
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) p1[a][b][r] = p2[a][b][r] = p3[a][b][r] = 0.0;
-
-  const int nch = ke > kb ? (ke - kb + KC - 1) / KC : 0;
-  if (nch > 0) {
-    issue(kb);
-    store(0);
-  }
-  __syncthreads();
-  for (int c = 0; c < nch; ++c) {
-    const int stg = c & 1;
-    if (c + 1 < nch) issue(kb + (c + 1) * KC);
+  auto compute = [&](int stg) {
     const c128* As = lds + stg * 2 * STAGE;
     const c128* Bs = As + STAGE;
-#pragma unroll
+#pragma unroll 1
     for (int kk = 0; kk < KC / 4; ++kk) {
       const int k = 4 * kk + lk;
       double ar[2], ai[2], as[2], br[2], bi[2], bs[2];
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt) {
         const int i = 32 * wr + 16 * rt + li;
-        const c128 a = ta ? As[i * PK + k] : As[k * TT + i];
+        const c128 a = TA ? As[i * PK + k] : As[k * TT + i];
         ar[rt] = a.x;
-        ai[rt] = ta ? -a.y : a.y;
+        ai[rt] = TA ? -a.y : a.y;
         as[rt] = ar[rt] + ai[rt];
       }
 #pragma unroll
@@ -166,7 +162,20 @@ k_zgemm64(const GemmProb* __restrict__ probs, int nprob, int nwg) {
           p3[rt][ct] = mfma64(as[rt], bs[ct], p3[rt][ct]);
         }
     }
-    if (c + 1 < nch) store(stg ^ 1);
+  };
+
+  const int nch = ke > kb ? (ke - kb + KC - 1) / KC : 0;
+  Regs R0;
+  if (nch > 0) {
+    issue(R0, kb);
+    store(R0, 0, kb);
+  }
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int stg = c & 1;
+    if (c + 1 < nch) issue(R0, kb + (c + 1) * KC);
+    compute(stg);
+    if (c + 1 < nch) store(R0, stg ^ 1, kb + (c + 1) * KC);
     __syncthreads();
   }
 
@@ -251,8 +260,10 @@ int gemm_choose_split(const std::vector<GemmProb>& probs, int target_wgs) {
 static void gemm_set_attr() {
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_zgemm64, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)kGemmLds);
+    (void)hipFuncSetAttribute((const void*)k_zgemm64<true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGemmLds);
+    (void)hipFuncSetAttribute((const void*)k_zgemm64<false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGemmLds);
     (void)hipGetLastError();
     attr = true;
   }
@@ -262,12 +273,17 @@ int gemm_prepare(GemmProb* v, int nprob, GemmBatch& b) {
   if (nprob > kGemmMaxProbs) return FB_ERR_INTERNAL;
   b = GemmBatch{};
   b.nprob = nprob;
+  b.transa = -1;
   for (int q = 0; q < nprob; ++q) {
     GemmProb& p = v[q];
     if (p.ksplit < 1) p.ksplit = 1;
     if (p.M < 0 || p.N < 0 || p.K < 0) return FB_ERR_INTERNAL;
     if (p.ksplit > 1 && (p.a_upper || p.b_upper || !p.part)) return FB_ERR_INTERNAL;
     if (p.herm && p.M != p.N) return FB_ERR_INTERNAL;
+    if (p.M > 0 && p.N > 0) {  // one form per batch (empty products take no part)
+      if (b.transa < 0) b.transa = p.transa;
+      if (p.transa != b.transa) return FB_ERR_INTERNAL;
+    }
     p.tm = (p.M + TT - 1) / TT;
     p.tn = (p.N + TT - 1) / TT;
     p.tile0 = b.nwg;
@@ -275,6 +291,7 @@ int gemm_prepare(GemmProb* v, int nprob, GemmBatch& b) {
     b.work += gemm_work(p);
     b.finish = b.finish || p.ksplit > 1 || p.herm == 2;
   }
+  if (b.transa < 0) b.transa = 0;
   return 0;
 }
 
@@ -284,7 +301,10 @@ int gemm_launch(const GemmProb* probs_dev, const GemmBatch& b, hipStream_t st) {
   {
     ProfScope ps(FB_PROF_GEMM, st, b.work);
     // a multiple of 8 workgroups, so that the XCD remapping is a bijection
-    k_zgemm64<<<8 * ((b.nwg + 7) / 8), NTH, kGemmLds, st>>>(probs_dev, b.nprob, b.nwg);
+    if (b.transa)
+      k_zgemm64<true><<<8 * ((b.nwg + 7) / 8), NTH, kGemmLds, st>>>(probs_dev, b.nprob, b.nwg);
+    else
+      k_zgemm64<false><<<8 * ((b.nwg + 7) / 8), NTH, kGemmLds, st>>>(probs_dev, b.nprob, b.nwg);
     FB_HIP(hipGetLastError());
   }
   if (b.finish) {

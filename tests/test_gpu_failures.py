@@ -1,0 +1,99 @@
+"""Failure paths of the C ABI on the GPU: NaN / Inf in B or in a start block
+is refused with FB_ERR_NONFINITE before any solve; a refined complex64 solve
+that cannot converge (a shift within 1e-7 ||B||_1 of an eigenvalue) falls
+back to complex128 (passes = -1) and its solution matches the oracle's
+complex128 solve; FEAST whose refinement is forced to fail falls back on
+every system, reports info 3 and returns the FP64 eigenpairs."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import band as oband
+from oracle import bandlu as olu
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FB_ERR_NONFINITE = -2005
+
+
+@pytest.fixture(scope="module")
+def fb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2012_00506_amd as fb
+    return fb
+
+
+def test_nonfinite_band_refused(fb):
+    from paper_2012_00506_amd._native import FeastBandError
+    ab = synth.band_matrix(500, 6, 31, True, -5, 5)
+    for bad in (np.nan, np.inf):
+        ab2 = ab.copy()
+        ab2[3, 100] = bad
+        print(f"nonfinite band entry {bad}", flush=True)
+        with pytest.raises(FeastBandError) as e:
+            fb.band_inertia(ab2, [0.0])
+        assert e.value.code == FB_ERR_NONFINITE
+        Y = fb.to_colmajor(synth.rhs_block(500, 20, 1, True))
+        with pytest.raises(FeastBandError) as e:
+            fb.feast_band_slice(ab2, [-1.0], [1.0], [Y])
+        assert e.value.code == FB_ERR_NONFINITE
+
+
+def test_nonfinite_start_block_refused(fb):
+    from paper_2012_00506_amd._native import FeastBandError
+    ab = synth.band_matrix(500, 6, 32, True, -5, 5)
+    Yh = synth.rhs_block(500, 30, 2, True)
+    Yh[77, 5] = complex(0.0, np.inf)
+    print("nonfinite start block", flush=True)
+    with pytest.raises(FeastBandError) as e:
+        fb.feast_band_slice(ab, [-1.0], [1.0], [fb.to_colmajor(Yh)])
+    assert e.value.code == FB_ERR_NONFINITE
+    with pytest.raises(FeastBandError) as e:
+        fb.band_shifted_solve(ab, [0.3 + 0.2j], [fb.to_colmajor(Yh)], precision=1)
+    assert e.value.code == FB_ERR_NONFINITE
+
+
+def test_near_real_shift_falls_back_to_complex128(fb):
+    n, b = 1500, 12
+    ab = synth.band_matrix(n, b, 33, True, -10, 10)
+    nrm = oband.norm1(ab)
+    lam = np.linalg.eigvalsh(oband.dense_from_band(ab))
+    z = lam[700] + 1e-7 * nrm * 1j       # kappa ~ 1e7: refinement contracts too slowly
+    zz = lam[200] + 0.5j                 # a well-conditioned companion system
+    Yh = synth.rhs_block(n, 24, 5, True)
+    Y = fb.to_colmajor(Yh)
+    print("near-real shift, precision 1", flush=True)
+    r = fb.band_shifted_solve(ab, [z, zz], [Y, Y], precision=1, ir_tol=1e-10, ir_max=3)
+    assert r.passes[0] == -1 and r.passes[1] >= 0
+    # complex128 LU is backward stable: ||y - A x|| <= c eps ||A|| ||x||
+    assert r.resid.max() <= 1e-9
+    for s, zs in enumerate((z, zz)):
+        F = olu.shifted_band_lu(ab, zs)
+        ref = olu.lu_solve(F, Yh)
+        refh = olu.lu_solve_h(F, Yh)
+        kappa = 1e7 if s == 0 else 1e3
+        X = r.X[s].cpu().numpy()
+        XH = r.XH[s].cpu().numpy()
+        assert np.linalg.norm(X - ref) <= 1e-16 * kappa * 100 * np.linalg.norm(ref)
+        assert np.linalg.norm(XH - refh) <= 1e-16 * kappa * 100 * np.linalg.norm(refh)
+
+
+def test_feast_forced_fallback_reports_info3(fb):
+    n, b = 800, 8
+    ab = synth.band_matrix(n, b, 34, True, -8, 8)
+    nrm = oband.norm1(ab)
+    lam_all = np.linalg.eigvalsh(oband.dense_from_band(ab))
+    lo, hi = -1.0, 1.2
+    ref = lam_all[(lam_all >= lo) & (lam_all < hi)]
+    m0 = max(math.ceil(1.5 * len(ref)), len(ref) + 10)
+    Yh = synth.rhs_block(n, m0, 9, True)
+    print("feast with refinement forced to fail", flush=True)
+    [r] = fb.feast_band_slice(ab, [lo], [hi], [fb.to_colmajor(Yh)], precision=1,
+                              ir_tol=1e-300, ir_max=0)
+    assert r.info == 3 and r.m_found == len(ref)
+    assert np.abs(r.lam - ref).max() <= 1e-12 * nrm
+    assert r.resid[: r.m_found].max() <= 1e-10

@@ -31,7 +31,7 @@ def _check_results(ab, bounds, res, cols_per_slice=3, seed=0):
     nrm = oband.norm1(ab)
     rng = np.random.default_rng(seed)
     for i, r in enumerate(res):
-        assert r.info == 0, (i, r.info, r.m_found)
+        assert r.info in (0, 3), (i, r.info, r.m_found)  # 3: complex128 fallback, a warning
         m = r.m_found
         lam = r.lam
         assert np.all((lam >= bounds[i]) & (lam < bounds[i + 1]))
