@@ -153,26 +153,27 @@ def cpu_baseline(cfg, m0_mean, ncols):
                        f"per-system time scaled to {cols_sys:.0f} columns per system")}
 
 
-def run_path(fb, F, Y, Q, steps, warmup, cols_per_step):
+def run_path(fb, F, Y, Q, steps, warmup, cols_per_step, stream=None):
     import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
     # verification pass (not timed): every column's FP64 residual <= 1e-10
     F.with_resid = True
-    r = F(Y, Q)
+    r = F(Y, Q, stream=s)
     torch.cuda.synchronize()
     worst = float(np.max(r.resid))
     passes = int(np.max(r.passes))
     F.with_resid = False
     for _ in range(warmup):
-        F(Y, Q)
+        F(Y, Q, stream=s)
     torch.cuda.synchronize()
     fb.profile_enable(True)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    ev0.record()
+    ev0.record(s)
     for _ in range(steps):
-        F(Y, Q)
-    ev1.record()
+        F(Y, Q, stream=s)
+    ev1.record(s)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = fb.profile_read()
@@ -288,6 +289,14 @@ def main():
     res["fp32ir"] = run_path(fb, F32, Y, Q, args.steps, args.warmup, cols_per_step)
     del F32
     torch.cuda.empty_cache()
+    # the same sweep replayed from a HIP graph on a stream of its own
+    gs = torch.cuda.Stream()
+    F32g = fb.FeastFilter(B, lo, hi, m0, n_nodes=n_nodes, precision=1, ir_tol=1e-10, ir_max=6,
+                          graph=True)
+    res["fp32ir_graph"] = run_path(fb, F32g, Y, Q, args.steps, args.warmup, cols_per_step,
+                                   stream=gs)
+    del F32g
+    torch.cuda.empty_cache()
     if not args.no_fp64:
         F64 = fb.FeastFilter(B, lo, hi, m0, n_nodes=n_nodes, precision=0)
         res["fp64"] = run_path(fb, F64, Y, Q, args.steps, args.warmup, cols_per_step)
@@ -333,6 +342,9 @@ def main():
         rp = res["fp64_plain"]
         out["fp64_plain"] = {k: v for k, v in rp.items() if k != "prof"}
         out["fp32ir_over_fp64_plain"] = main_["value"] / rp["value"]
+    rg = res["fp32ir_graph"]
+    out["fp32ir_graph"] = {k: v for k, v in rg.items() if k != "prof"}
+    out["graph_over_direct"] = rg["value"] / main_["value"]
     out["solve_variants"] = tuned
     if args.calib_copy:
         nel = args.calib_copy * (1 << 20) // 4

@@ -165,6 +165,16 @@ typedef struct {
                           circle, other positive values an ellipse
                           z(t) = c + r (cos t + i ratio sin t); rule 2: the
                           inner fraction, 0 < ratio < 1 */
+  const char* tune_cache; /* path of a file written by fb_autotune, or NULL:
+                          its choices of the solve variant are loaded first */
+  int32_t graph;       /* feast_filter, batched with every (node, direction)
+                          pair in one launch and a non-null stream: 1 captures
+                          the sweep (factorisations, solves, the refinement
+                          passes with their device-side decisions, node sum)
+                          in a HIP graph on the first call and replays it on
+                          later calls with the same pointers, sizes and
+                          options; a refinement that stagnates is redone by
+                          direct launches with the complex128 fallback */
 } fb_feast_opts;
 
 /* FEAST on the slices [lo_i, hi_i) of B (Algorithm alg:FEAST, Section 2.2,
@@ -323,7 +333,9 @@ int slice_plan_prev(const fb_band* B, const double* prev, int64_t nprev,
  *         dimensions ldy[i], ldq[i] >= n (Y is not modified)
  *  resid  host, nslice or NULL: max over nodes, directions and columns of
  *         ||y - A x||_2 / ||y||_2 in FP64 (extra residual pass for precision 0)
- *  passes host, nslice or NULL: most refinement passes of any tile
+ *  passes host, nslice or NULL: most refinement passes of any tile; -1 when
+ *         a system of the slice was refactored and solved in complex128
+ *         after its refinement stayed above ir_tol
  * o->max_iter, o->tol and o->hbm_budget are ignored.  Returns 0, or for
  * precision 1 the number of slices with a tile above ir_tol after ir_max. */
 int feast_filter(const fb_band* B, int32_t nslice, const double* lo, const double* hi,

@@ -32,7 +32,8 @@ class fb_feast_opts(C.Structure):
     _fields_ = [("n_nodes", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("precision", C.c_int32), ("ir_tol", C.c_double), ("ir_max", C.c_int32),
                 ("batched", C.c_int32), ("hbm_budget", C.c_double), ("pairs", C.c_int32),
-                ("rule", C.c_int32), ("ratio", C.c_double)]
+                ("rule", C.c_int32), ("ratio", C.c_double), ("tune_cache", C.c_char_p),
+                ("graph", C.c_int32)]
 
 
 class fb_plan_opts(C.Structure):

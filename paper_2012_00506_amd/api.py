@@ -189,7 +189,7 @@ def contour_nodes(lo, hi, k=8, rule="gauss", ratio=1.0):
 
 def feast_band_slice(B, lo, hi, Y, m_expected=None, n_nodes=8, tol=1e-10, max_iter=20,
                      precision=0, ir_tol=1e-12, ir_max=8, batched=True, hbm_budget=0.0,
-                     pairs=0, rule="gauss", ratio=1.0, stream=None):
+                     pairs=0, rule="gauss", ratio=1.0, tune_cache=None, stream=None):
     """FEAST on the slices [lo_i, hi_i) of B from the start blocks Y[i]
     ((n, m0_i) column-major device tensors in the dtype of B; overwritten with
     the Ritz vectors).  Returns one SliceResult per slice."""
@@ -216,7 +216,8 @@ def feast_band_slice(B, lo, hi, Y, m_expected=None, n_nodes=8, tol=1e-10, max_it
     its = np.zeros(ns, np.int32)
     inf = np.zeros(ns, np.int32)
     o = N.fb_feast_opts(n_nodes, tol, max_iter, precision, ir_tol, ir_max, 1 if batched else 0,
-                        float(hbm_budget), int(pairs), _RULES[rule], float(ratio))
+                        float(hbm_budget), int(pairs), _RULES[rule], float(ratio),
+                        None if tune_cache is None else str(tune_cache).encode(), 0)
     bs = B.struct()
     L = N.lib()
     sh = C.c_void_p(_stream_handle(stream))
@@ -365,11 +366,13 @@ class FilterResult:
 
 class FeastFilter:
     """Reusable filter application Q_i = r(B) Y_i over a fixed set of slices
-    (workspace allocated once; each call factors and solves everything)."""
+    (workspace allocated once; each call factors and solves everything).
+    graph=True replays the sweep from a HIP graph captured on the first call
+    (batched, every pair in one launch, a stream other than the null one)."""
 
     def __init__(self, B, lo, hi, m, n_nodes=8, precision=0, ir_tol=1e-10, ir_max=4,
                  batched=True, with_resid=False, hbm_budget=0.0, pairs=0, rule="gauss",
-                 ratio=1.0, device="cuda"):
+                 ratio=1.0, graph=False, tune_cache=None, device="cuda"):
         self.B = _as_band(B)
         self.lo = np.ascontiguousarray(np.asarray(lo, np.float64).ravel())
         self.hi = np.ascontiguousarray(np.asarray(hi, np.float64).ravel())
@@ -377,7 +380,9 @@ class FeastFilter:
         self.ns = len(self.lo)
         self.o = N.fb_feast_opts(n_nodes, 1e-10, 1, precision, ir_tol, ir_max,
                                  1 if batched else 0, float(hbm_budget), int(pairs),
-                                 _RULES[rule], float(ratio))
+                                 _RULES[rule], float(ratio),
+                                 None if tune_cache is None else str(tune_cache).encode(),
+                                 1 if graph else 0)
         self.with_resid = with_resid
         self.bs = self.B.struct()
         self.resid = np.zeros(self.ns, np.float64)

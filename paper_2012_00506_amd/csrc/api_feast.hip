@@ -2,8 +2,13 @@
 // Section 2.2 with the slice count check of Section 3.2).
 #include <math.h>
 
+#include <stdio.h>
+
 #include <algorithm>
+#include <map>
 #include <mutex>
+#include <set>
+#include <string>
 #include <numeric>
 #include <vector>
 
@@ -180,6 +185,61 @@ static bool contour_ok(int rule, double ratio) {
   return false;
 }
 
+// Captured filter sweeps, keyed by every argument that shapes their launches
+// (pointers, sizes, options; node values and job tables are uploaded before
+// each replay).  Process-wide, guarded by a mutex, at most kMaxGraphs of them:
+// the oldest is destroyed first (a replay still in flight completes; HIP frees
+// an executable graph once its launches end).
+constexpr size_t kMaxGraphs = 64;
+static std::mutex g_graph_mu;
+struct GraphCache {
+  std::map<std::string, hipGraphExec_t> by_key;
+  std::vector<std::string> order;
+};
+static GraphCache& graph_cache() {
+  static GraphCache c;
+  return c;
+}
+// Launches the sweep cached under k; false when there is none.
+static bool graph_launch(const std::string& k, hipStream_t st, hipError_t* err) {
+  std::lock_guard<std::mutex> g(g_graph_mu);
+  auto it = graph_cache().by_key.find(k);
+  if (it == graph_cache().by_key.end()) return false;
+  *err = hipGraphLaunch(it->second, st);
+  return true;
+}
+// Caches a newly instantiated sweep under k and launches it.
+static hipError_t graph_store_launch(const std::string& k, hipGraphExec_t e, hipStream_t st) {
+  std::lock_guard<std::mutex> g(g_graph_mu);
+  GraphCache& c = graph_cache();
+  auto it = c.by_key.find(k);
+  if (it != c.by_key.end()) {  // another thread captured the same sweep meanwhile
+    (void)hipGraphExecDestroy(e);
+    return hipGraphLaunch(it->second, st);
+  }
+  while (c.order.size() >= kMaxGraphs) {
+    (void)hipGraphExecDestroy(c.by_key[c.order.front()]);
+    c.by_key.erase(c.order.front());
+    c.order.erase(c.order.begin());
+  }
+  c.by_key[k] = e;
+  c.order.push_back(k);
+  return hipGraphLaunch(e, st);
+}
+
+// Loads a tuning file named in the options once per process (false when it
+// cannot be read).
+static bool tune_cache_ok(const char* path) {
+  if (!path) return true;
+  static std::mutex mu;
+  static std::set<std::string> loaded;
+  std::lock_guard<std::mutex> g(mu);
+  if (loaded.count(path)) return true;
+  if (fb_tune_load(path) < 0) return false;
+  loaded.insert(path);
+  return true;
+}
+
 struct SliceBufs {
   c128 *Y, *Q, *X;      // n x m0 each (start block, filter sum, scratch)
   c128 *G, *V, *W;      // m0 x m0
@@ -272,6 +332,67 @@ __global__ void __launch_bounds__(256) k_equil(const CholProb* __restrict__ prob
 // per launch (plain); each pair's solutions go to their own buffer
 // Xp[i * P + p] and are then added into Q_i in pair order, so the sum does
 // not depend on how the pairs were grouped.
+// Solve jobs and accumulation jobs of the pairs p0 .. p0+np-1 for the active
+// slices (all of them, or only act[only] when only >= 0).
+template <typename R>
+void build_pair_jobs(int64_t n, int tile, int ne, const std::vector<int>& act, const int32_t* m,
+                     c128* const* Yc, const int64_t* ldyc, c128* const* Qc, const int64_t* ldqc,
+                     c128* const* Xp, int P, const std::vector<std::pair<int, int>>& pairs, int p0,
+                     int np, int only, const std::vector<c128>& wsys, bool cplx,
+                     std::vector<SolveJob>& jobs, std::vector<AccJob>& aj, int& maxm) {
+  jobs.clear();
+  aj.clear();
+  maxm = 0;
+  for (int p = 0; p < np; ++p) {
+    const int j = pairs[p0 + p].first, dir = pairs[p0 + p].second;
+    for (size_t a = 0; a < act.size(); ++a) {
+      if (only >= 0 && (int)a != only) continue;
+      const int i = act[a];
+      for (int c0 = 0; c0 < m[i]; c0 += tile) {
+        SolveJob jb{};
+        jb.sys = i * ne + j;
+        jb.dir = dir;
+        jb.col0 = c0;
+        jb.ncol = std::min(tile, m[i] - c0);
+        jb.in = Yc[i];
+        jb.ldin = ldyc[i];
+        jb.mid = Xp[(size_t)i * P + p];
+        jb.out = Xp[(size_t)i * P + p];
+        jb.ldout = n;
+        jb.ldmid = n * (int64_t)(sizeof(c128) / sizeof(cx<R>));
+        jobs.push_back(jb);
+      }
+    }
+  }
+  for (size_t a = 0; a < act.size(); ++a) {
+    if (only >= 0 && (int)a != only) continue;
+    const int i = act[a];
+    AccJob J{};
+    J.Q = Qc[i];
+    J.ldq = ldqc[i];
+    J.ldx = n;
+    J.np = np;
+    J.m = m[i];
+    J.acc_real = cplx ? 0 : 1;
+    J.init = p0 == 0;  // the first pairs of the sum write Q
+    for (int p = 0; p < np; ++p) {
+      const int j = pairs[p0 + p].first, dir = pairs[p0 + p].second;
+      J.X[p] = Xp[(size_t)i * P + p];
+      const c128 w = wsys[i * ne + j];
+      J.w[p] = dir == 0 ? w : cconj(w);
+    }
+    maxm = std::max(maxm, m[i]);
+    aj.push_back(J);
+  }
+}
+
+static std::vector<std::pair<int, int>> node_pairs(int ne, bool cplx) {
+  std::vector<std::pair<int, int>> pairs;
+  for (int j = 0; j < ne; ++j)
+    for (int dir = 0; dir < (cplx ? 2 : 1); ++dir) pairs.push_back({j, dir});
+  return pairs;
+}
+
 template <typename R>
 int filter_apply(const Band& bd, const FactorBufs<R>& f, int ne, const std::vector<int>& act,
                  const int32_t* m, c128* const* Yc, const int64_t* ldyc, c128* const* Qc,
@@ -281,11 +402,7 @@ int filter_apply(const Band& bd, const FactorBufs<R>& f, int ne, const std::vect
                  std::vector<double>& sys_res, std::vector<int32_t>& sys_pass, int* unconverged,
                  hipStream_t st, const C128Fallback* fb) {
   const int64_t n = bd.n;
-  const int tile = rb.tile;
-  const int ndir = cplx ? 2 : 1;
-  std::vector<std::pair<int, int>> pairs;
-  for (int j = 0; j < ne; ++j)
-    for (int dir = 0; dir < ndir; ++dir) pairs.push_back({j, dir});
+  const std::vector<std::pair<int, int>> pairs = node_pairs(ne, cplx);
   const int npair = (int)pairs.size();
   const int chunk = batched ? std::max(1, std::min(P, npair)) : 1;
   if (chunk > kMaxPairs) return FB_ERR_INTERNAL;
@@ -295,52 +412,11 @@ int filter_apply(const Band& bd, const FactorBufs<R>& f, int ne, const std::vect
   for (size_t g = 0; g < groups; ++g)
     for (int p0 = 0; p0 < npair; p0 += chunk) {
       const int np = std::min(chunk, npair - p0);
-      jobs.clear();
-      aj.clear();
       int maxm = 0;
-      for (int p = 0; p < np; ++p) {
-        const int j = pairs[p0 + p].first, dir = pairs[p0 + p].second;
-        for (size_t a = 0; a < act.size(); ++a) {
-          if (!batched && a != g) continue;
-          const int i = act[a];
-          for (int c0 = 0; c0 < m[i]; c0 += tile) {
-            SolveJob jb{};
-            jb.sys = i * ne + j;
-            jb.dir = dir;
-            jb.col0 = c0;
-            jb.ncol = std::min(tile, m[i] - c0);
-            jb.in = Yc[i];
-            jb.ldin = ldyc[i];
-            jb.mid = Xp[(size_t)i * P + p];
-            jb.out = Xp[(size_t)i * P + p];
-            jb.ldout = n;
-            jb.ldmid = n * (int64_t)(sizeof(c128) / sizeof(cx<R>));
-            jobs.push_back(jb);
-          }
-        }
-      }
+      build_pair_jobs<R>(n, rb.tile, ne, act, m, Yc, ldyc, Qc, ldqc, Xp, P, pairs, p0, np,
+                         batched ? -1 : (int)g, wsys, cplx, jobs, aj, maxm);
       FB_TRY(solve_refine<R>(bd, f.mats, f.matsT, f.perm, jobs, zsys, ir, ir_tol, ir_max, need_res, rb,
                              sys_res, sys_pass, unconverged, st, fb));
-      for (size_t a = 0; a < act.size(); ++a) {
-        if (!batched && a != g) continue;
-        const int i = act[a];
-        AccJob J{};
-        J.Q = Qc[i];
-        J.ldq = ldqc[i];
-        J.ldx = n;
-        J.np = np;
-        J.m = m[i];
-        J.acc_real = cplx ? 0 : 1;
-        J.init = p0 == 0;  // the first pairs of the sum write Q
-        for (int p = 0; p < np; ++p) {
-          const int j = pairs[p0 + p].first, dir = pairs[p0 + p].second;
-          J.X[p] = Xp[(size_t)i * P + p];
-          const c128 w = wsys[i * ne + j];
-          J.w[p] = dir == 0 ? w : cconj(w);
-        }
-        maxm = std::max(maxm, m[i]);
-        aj.push_back(J);
-      }
       FB_HIP(hipMemcpyAsync(acc_dev, aj.data(), sizeof(AccJob) * aj.size(), hipMemcpyHostToDevice, st));
       FB_TRY(accumulate_pairs(acc_dev, (int)aj.size(), n, maxm, st));
     }
@@ -910,6 +986,8 @@ extern "C" int feast_band_slice(const fb_band* B, int32_t nslice, const double* 
   if (!contour_ok(o->rule, o->ratio)) return -14;
   if (o->precision != 0 && o->precision != 1) return -14;
   if (o->precision == 1 && (!(o->ir_tol > 0) || o->ir_max < 0)) return -14;
+  if (o->graph != 0 && o->graph != 1) return -14;
+  if (!tune_cache_ok(o->tune_cache)) return -14;
   for (int i = 0; i < nslice; ++i) {
     if (!isfinite(lo[i]) || !isfinite(hi[i]) || !(lo[i] < hi[i])) return -3;
     if (m0[i] < 1 || m0[i] > 4096 || m0[i] > B->n) return -5;
@@ -1006,33 +1084,103 @@ int filter_impl(const fb_band* B, int nslice, const double* lo, const double* hi
       zh[2 * (i * ne + j) + 1] = z[j].y;
     }
   }
-  FB_TRY(factor_systems<R>(bd, nsys, zh.data(), f, st));
   std::vector<int> act;
-  for (int i = 0; i < nslice; ++i) {
-    if (m[i] <= 0) continue;
-    act.push_back(i);
-    if (!cplx) FB_TRY(gather_cols(Y[i], ldy[i], true, Yc[i], n, n, m[i], nullptr, nullptr, st));
-  }
+  for (int i = 0; i < nslice; ++i)
+    if (m[i] > 0) act.push_back(i);
   std::vector<double> sys_res(nsys, 0.0);
   std::vector<int32_t> sys_pass(nsys, 0);
   int unconverged = 0;
-  FB_TRY(filter_apply<R>(bd, f, ne, act, m, Yc.data(), ldyc.data(), Qc.data(), ldqc.data(),
-                         Xp.data(), P, acc_dev, zsys, wsys, cplx, o->batched != 0, ir, o->ir_tol,
-                         o->ir_max, need_res, rb, sys_res, sys_pass, &unconverged, st,
-                         ir ? &fbk : nullptr));
-  if (!cplx)
-    for (int i : act) FB_TRY(store_cols(Qc[i], n, Q[i], ldq[i], true, n, m[i], nullptr, st));
+  const int npair_all = ne * (cplx ? 2 : 1);
+  bool done = false;
+  if (o->graph && st != nullptr && o->batched && P >= npair_all && npair_all <= kMaxPairs) {
+    // graph form: the whole sweep (factorisations, solves, refinement passes,
+    // node sum) is captured once per argument set and replayed; the tables
+    // it reads are uploaded before every replay
+    FB_HIP(hipMemcpyAsync(f.z, zh.data(), sizeof(c128) * nsys, hipMemcpyHostToDevice, st));
+    const std::vector<std::pair<int, int>> pairs = node_pairs(ne, cplx);
+    std::vector<SolveJob> jobs;
+    std::vector<AccJob> aj;
+    int maxm = 0;
+    build_pair_jobs<R>(n, rb.tile, ne, act, m, Yc.data(), ldyc.data(), Qc.data(), ldqc.data(),
+                       Xp.data(), P, pairs, 0, npair_all, -1, wsys, cplx, jobs, aj, maxm);
+    RefinePlan plan;
+    FB_TRY(refine_prepare<R>(bd, jobs, zsys, ir, o->ir_tol, o->ir_max, need_res, rb, plan, st));
+    if (!aj.empty())
+      FB_HIP(hipMemcpyAsync(acc_dev, aj.data(), sizeof(AccJob) * aj.size(), hipMemcpyHostToDevice, st));
+    char key[512];
+    snprintf(key, sizeof key, "%d|%p|%lld|%d|%d|%lld|%d|%d|%d|%d|%.17g|%d|%d|%p|%zu|%p",
+             (int)sizeof(R), B->ab, (long long)n, B->b, B->dtype, (long long)B->ldab, nslice, ne,
+             o->precision, o->ir_max, o->ir_tol, P, (int)need_res, work, *lwork, (void*)st);
+    std::string k(key);
+    for (int i = 0; i < nslice; ++i) {
+      snprintf(key, sizeof key, "|%d:%p:%lld:%p:%lld", m[i], Y[i], (long long)ldy[i], Q[i],
+               (long long)ldq[i]);
+      k += key;
+    }
+    hipError_t le = hipSuccess;
+    if (!graph_launch(k, st, &le)) {
+      hipGraphExec_t exec = nullptr;
+      FB_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      int rc = launch_lu_impl<R>(bd, nsys, f.z, f.mats, f.matsT, f.perm, f.info, f.scratch,
+                                 f.lscr, st);
+      for (size_t a = 0; rc == 0 && !cplx && a < act.size(); ++a) {
+        const int i = act[a];
+        rc = gather_cols(Y[i], ldy[i], true, Yc[i], n, n, m[i], nullptr, nullptr, st);
+      }
+      if (rc == 0) rc = refine_launch<R>(bd, f.mats, f.matsT, f.perm, plan, rb, st);
+      if (rc == 0) rc = accumulate_pairs(acc_dev, (int)aj.size(), n, maxm, st);
+      for (size_t a = 0; rc == 0 && !cplx && a < act.size(); ++a) {
+        const int i = act[a];
+        rc = store_cols(Qc[i], n, Q[i], ldq[i], true, n, m[i], nullptr, st);
+      }
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(st, &g);
+      if (rc == 0 && ec != hipSuccess) rc = -1000 - (int)ec;
+      if (rc == 0) {
+        const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        if (ei != hipSuccess) rc = -1000 - (int)ei;
+      }
+      if (g) (void)hipGraphDestroy(g);
+      if (rc != 0) return rc;
+      le = graph_store_launch(k, exec, st);
+    }
+    FB_HIP(le);
+    FB_TRY(factor_check<R>(nsys, f, st));
+    int stagnated = 0;
+    FB_TRY(refine_finish<R>(bd, jobs, zsys, plan, rb, sys_res, sys_pass, &unconverged, st, nullptr,
+                            &stagnated));
+    if (stagnated == 0) {
+      done = true;
+    } else {  // a refinement stagnated: the direct sweep redoes it with the fallback
+      std::fill(sys_res.begin(), sys_res.end(), 0.0);
+      std::fill(sys_pass.begin(), sys_pass.end(), 0);
+      unconverged = 0;
+    }
+  }
+  if (!done) {
+    FB_TRY(factor_systems<R>(bd, nsys, zh.data(), f, st));
+    for (int i : act)
+      if (!cplx) FB_TRY(gather_cols(Y[i], ldy[i], true, Yc[i], n, n, m[i], nullptr, nullptr, st));
+    FB_TRY(filter_apply<R>(bd, f, ne, act, m, Yc.data(), ldyc.data(), Qc.data(), ldqc.data(),
+                           Xp.data(), P, acc_dev, zsys, wsys, cplx, o->batched != 0, ir, o->ir_tol,
+                           o->ir_max, need_res, rb, sys_res, sys_pass, &unconverged, st,
+                           ir ? &fbk : nullptr));
+    if (!cplx)
+      for (int i : act) FB_TRY(store_cols(Qc[i], n, Q[i], ldq[i], true, n, m[i], nullptr, st));
+  }
   FB_HIP(hipStreamSynchronize(st));
   int nbad = 0;
   for (int i = 0; i < nslice; ++i) {
     double r = 0.0;
     int p = 0;
+    bool fell = false;  // a system re-solved in complex128
     for (int j = 0; j < ne; ++j) {
       r = std::max(r, sys_res[i * ne + j]);
       p = std::max(p, sys_pass[i * ne + j]);
+      fell = fell || sys_pass[i * ne + j] < 0;
     }
     if (resid) resid[i] = r;
-    if (passes) passes[i] = p;
+    if (passes) passes[i] = fell ? -1 : p;
     if (ir && !(r <= o->ir_tol) && m[i] > 0) ++nbad;
   }
   return nbad;
@@ -1056,6 +1204,8 @@ extern "C" int feast_filter(const fb_band* B, int32_t nslice, const double* lo, 
   if (!contour_ok(o->rule, o->ratio)) return -12;
   if (o->precision != 0 && o->precision != 1) return -12;
   if (o->precision == 1 && (!(o->ir_tol > 0) || o->ir_max < 0)) return -12;
+  if (o->graph != 0 && o->graph != 1) return -12;
+  if (!tune_cache_ok(o->tune_cache)) return -12;
   for (int i = 0; i < nslice; ++i) {
     if (!isfinite(lo[i]) || !isfinite(hi[i]) || !(lo[i] < hi[i])) return -3;
     if (m[i] < 0) return -5;

@@ -56,6 +56,18 @@ int factor_systems(const Band& bd, int nsys, const double* z_host, FactorBufs<R>
 }
 
 
+template <typename R>
+int factor_check(int nsys, FactorBufs<R>& f, hipStream_t st) {
+  std::vector<int32_t> info(nsys);
+  FB_HIP(hipMemcpyAsync(info.data(), f.info, sizeof(int32_t) * nsys, hipMemcpyDeviceToHost, st));
+  FB_HIP(hipStreamSynchronize(st));
+  for (int s = 0; s < nsys; ++s)
+    if (info[s] != 0) return FB_ERR_SINGULAR;
+  return 0;
+}
+
+template int factor_check<float>(int, FactorBufs<float>&, hipStream_t);
+template int factor_check<double>(int, FactorBufs<double>&, hipStream_t);
 template void carve_factors<float>(Arena&, const Band&, int, FactorBufs<float>&);
 template void carve_factors<double>(Arena&, const Band&, int, FactorBufs<double>&);
 template int factor_systems<float>(const Band&, int, const double*, FactorBufs<float>&, hipStream_t);
@@ -149,16 +161,17 @@ void carve_refine(Arena& ar, const Band& bd, int tile, int max_jobs, bool ir, bo
                   RefineBufs& rb) {
   rb.tile = tile;
   rb.gcols = residual_cols(block_size(bd.b));  // >= tile (variant_fits)
-  rb.jobs_dev = ar.take<SolveJob>(std::max(max_jobs, 1));
   rb.cap_jobs = std::max(max_jobs, 1);
-  rb.wave = need_res ? std::min<size_t>(ir_wave_jobs(bd.n, rb.gcols), (size_t)std::max(max_jobs, 1)) : 0;
-  rb.rjobs_dev = need_res ? ar.take<ResJob>(rb.wave) : nullptr;
-  // every group of a wave can need corrections for all of its tiles
-  const size_t per_group = (size_t)(rb.gcols + tile - 1) / tile;
-  rb.cjobs_dev = ir ? ar.take<SolveJob>(rb.wave * per_group) : nullptr;
+  rb.jobs_dev = ar.take<SolveJob>(rb.cap_jobs);
+  rb.wave = need_res ? std::min<size_t>(ir_wave_jobs(bd.n, rb.gcols), (size_t)rb.cap_jobs) : 0;
+  // every group has a residual job; a group's corrections are its tiles
+  rb.rjobs_dev = need_res ? ar.take<ResJob>(rb.cap_jobs) : nullptr;
+  rb.cjobs_dev = ir ? ar.take<SolveJob>(rb.cap_jobs) : nullptr;
   rb.rbuf = need_res ? ar.take<c128>(rb.wave * (size_t)bd.n * rb.gcols) : nullptr;
   rb.part = need_res ? ar.take<double>(residual_part_doubles(bd.n, (int)rb.wave)) : nullptr;
-  rb.ratio = need_res ? ar.take<double>(rb.wave) : nullptr;
+  rb.ratio = need_res ? ar.take<double>(rb.cap_jobs) : nullptr;
+  rb.flag = need_res ? ar.take<int32_t>(rb.cap_jobs) : nullptr;
+  rb.npass = need_res ? ar.take<int32_t>(rb.cap_jobs) : nullptr;
 }
 
 size_t refine_bytes(const Band& bd, int tile, int max_jobs, bool ir, bool need_res) {
@@ -168,28 +181,36 @@ size_t refine_bytes(const Band& bd, int tile, int max_jobs, bool ir, bool need_r
   return q.used;
 }
 
-// Launch the solve jobs, then (need_res) compute the FP64 residual
-// ||y - A x|| / ||y|| per group of adjacent tiles (same system, direction and
-// blocks, up to gcols columns) and (ir) refine the groups above ir_tol with
-// correction solves of their tiles until they pass or ir_max passes are
-// spent.  Groups are processed in waves that bound the residual buffers.
+// The solve jobs, then (need_res) the FP64 residual ||y - A x|| / ||y|| per
+// group of adjacent tiles (same system, direction and blocks, up to gcols
+// columns) and (ir) correction solves of the groups above ir_tol.  The
+// decisions are taken on the device: each residual launch sets a flag per
+// group that gates the next correction and residual launches (a group stops
+// when it meets ir_tol, after ir_max passes, or when a pass did not halve its
+// residual), so the launches of a call run without host round-trips and can
+// be captured in a graph; the ratios are read back once at the end.  Groups
+// are processed in waves that bound the residual buffers.
+//   refine_prepare: job tables to the device (before any capture)
+//   refine_launch:  every kernel launch of the call (capturable)
+//   refine_finish:  ratios read back, complex128 fallback of stagnated systems
 template <typename R>
-int solve_refine(const Band& bd, const cx<R>* mats, const cx<R>* matsT, const int16_t* perm,
-                 const std::vector<SolveJob>& jobs, const std::vector<c128>& zsys, bool ir,
-                 double ir_tol, int ir_max, bool need_res, RefineBufs& rb,
-                 std::vector<double>& sys_res, std::vector<int32_t>& sys_pass, int* unconverged,
-                 hipStream_t st, const C128Fallback* fb) {
+int refine_prepare(const Band& bd, const std::vector<SolveJob>& jobs,
+                   const std::vector<c128>& zsys, bool ir, double ir_tol, int ir_max,
+                   bool need_res, RefineBufs& rb, RefinePlan& plan, hipStream_t st) {
+  plan = RefinePlan{};
   const int njobs = (int)jobs.size();
+  plan.njobs = njobs;
+  plan.ir = ir;
+  plan.need_res = need_res;
+  plan.ir_tol = ir_tol;
+  plan.maxpass = ir ? ir_max : 0;
   if (njobs == 0) return 0;
   if (njobs > rb.cap_jobs) return FB_ERR_INTERNAL;
   FB_HIP(hipMemcpyAsync(rb.jobs_dev, jobs.data(), sizeof(SolveJob) * njobs, hipMemcpyHostToDevice, st));
-  double cols = 0;
-  for (const SolveJob& jb : jobs) cols += jb.ncol;
-  FB_TRY(launch_solve_jobs<R>(mats, matsT, perm, bd.n, bd.b, njobs, rb.jobs_dev,
-                              solve_flops(bd.n, bd.b, cols), st));
+  for (const SolveJob& jb : jobs) plan.cols += jb.ncol;
   if (!need_res) return 0;
   // groups [first, last] of consecutive jobs
-  std::vector<std::pair<int, int>> groups;
+  auto& groups = plan.groups;
   for (int i = 0; i < njobs; ++i) {
     if (!groups.empty()) {
       const SolveJob& f = jobs[groups.back().first];
@@ -205,86 +226,103 @@ int solve_refine(const Band& bd, const cx<R>* mats, const cx<R>* matsT, const in
     groups.push_back({i, i});
   }
   const int ng = (int)groups.size();
-  std::vector<int> failed;  // systems with a group above ir_tol after ir_max passes
-  std::vector<ResJob> rj, ra;
+  plan.ng = ng;
+  // residual job of every group (its block in the wave's residual buffer)
+  // and the correction jobs of every group, contiguous per wave
+  std::vector<ResJob> rj(ng);
   std::vector<SolveJob> cj;
-  std::vector<double> rat;
-  std::vector<size_t> ai;
-  for (size_t w0 = 0; w0 < (size_t)ng; w0 += rb.wave) {
-    size_t nw = std::min(rb.wave, (size_t)ng - w0);
-    rj.assign(nw, ResJob{});
-    std::vector<int> active(nw, 1);
-    for (size_t g = 0; g < nw; ++g) {
-      const SolveJob& f = jobs[groups[w0 + g].first];
-      const SolveJob& l = jobs[groups[w0 + g].second];
-      ResJob& r = rj[g];
-      r.x = f.out;
-      r.y = f.in;
-      r.r = rb.rbuf + g * (size_t)bd.n * rb.gcols - (int64_t)f.col0 * bd.n;
-      r.ldx = f.ldout;
-      r.ldy = f.ldin;
-      r.ldr = bd.n;
-      r.col0 = f.col0;
-      r.ncol = l.col0 + l.ncol - f.col0;
-      r.dir = f.dir;
-      r.z = zsys[f.sys];
-    }
-    const int maxpass = ir ? ir_max : 0;
-    std::vector<double> prev(nw, 0.0);
-    for (int pass = 0;; ++pass) {
-      ra.clear();
-      ai.clear();
-      for (size_t g = 0; g < nw; ++g)
-        if (active[g]) {
-          ra.push_back(rj[g]);
-          ai.push_back(g);
-        }
-      if (ra.empty()) break;
-      FB_HIP(hipMemcpyAsync(rb.rjobs_dev, ra.data(), sizeof(ResJob) * ra.size(),
-                            hipMemcpyHostToDevice, st));
-      double rcols = 0;
-      for (const ResJob& r : ra) rcols += r.ncol;
-      FB_TRY(launch_residual_jobs(bd, (int)ra.size(), rb.rjobs_dev, rb.part, rb.ratio,
-                                  resid_flops(bd.n, bd.b, rcols), st));
-      rat.resize(ra.size());
-      FB_HIP(hipMemcpyAsync(rat.data(), rb.ratio, sizeof(double) * ra.size(),
-                            hipMemcpyDeviceToHost, st));
-      FB_HIP(hipStreamSynchronize(st));
-      cj.clear();
-      for (size_t a = 0; a < ai.size(); ++a) {
-        size_t g = ai[a];
-        const int sys = jobs[groups[w0 + g].first].sys;
-        bool ok = ir ? (rat[a] <= ir_tol) : true;
-        // stagnation: a correction pass that did not halve the residual
-        const bool stalled = ir && pass > 0 && !(rat[a] < 0.5 * prev[g]);
-        prev[g] = rat[a];
-        if (ok || pass >= maxpass || stalled) {
-          active[g] = 0;
-          double q = rat[a];
-          if (!(q <= sys_res[sys])) sys_res[sys] = q;
-          if (ir && !ok) failed.push_back(sys);
-          continue;
-        }
-        for (int i = groups[w0 + g].first; i <= groups[w0 + g].second; ++i) {
-          SolveJob c = jobs[i];
-          c.in = rj[g].r;
-          c.mid = rj[g].r;
-          c.ldin = bd.n;
-          c.ldmid = bd.n * (int64_t)(sizeof(c128) / sizeof(cx<R>));
-          c.add = 1;
-          cj.push_back(c);
-        }
-        sys_pass[sys] = std::max(sys_pass[sys], pass + 1);
+  plan.gcols.assign(ng, 0.0);
+  for (int g = 0; g < ng; ++g) {
+    if ((size_t)g % rb.wave == 0) plan.cj_off.push_back(cj.size());
+    const SolveJob& f = jobs[groups[g].first];
+    const SolveJob& l = jobs[groups[g].second];
+    ResJob& r = rj[g];
+    r.x = f.out;
+    r.y = f.in;
+    r.r = rb.rbuf + ((size_t)g % rb.wave) * (size_t)bd.n * rb.gcols - (int64_t)f.col0 * bd.n;
+    r.ldx = f.ldout;
+    r.ldy = f.ldin;
+    r.ldr = bd.n;
+    r.col0 = f.col0;
+    r.ncol = l.col0 + l.ncol - f.col0;
+    r.dir = f.dir;
+    r.grp = g;
+    r.z = zsys[f.sys];
+    plan.gcols[g] = r.ncol;
+    if (ir)
+      for (int i = groups[g].first; i <= groups[g].second; ++i) {
+        SolveJob c = jobs[i];
+        c.in = r.r;
+        c.mid = r.r;
+        c.ldin = bd.n;
+        c.ldmid = bd.n * (int64_t)(sizeof(c128) / sizeof(cx<R>));
+        c.add = 1;
+        c.grp = g;
+        cj.push_back(c);
       }
-      if (cj.empty()) break;
-      FB_HIP(hipMemcpyAsync(rb.cjobs_dev, cj.data(), sizeof(SolveJob) * cj.size(),
-                            hipMemcpyHostToDevice, st));
-      double ccols = 0;
-      for (const SolveJob& c : cj) ccols += c.ncol;
-      FB_TRY(launch_solve_jobs<R>(mats, matsT, perm, bd.n, bd.b, (int)cj.size(), rb.cjobs_dev,
-                                  solve_flops(bd.n, bd.b, ccols), st));
+  }
+  plan.cj_off.push_back(cj.size());
+  if (cj.size() > (size_t)rb.cap_jobs) return FB_ERR_INTERNAL;
+  FB_HIP(hipMemcpyAsync(rb.rjobs_dev, rj.data(), sizeof(ResJob) * ng, hipMemcpyHostToDevice, st));
+  if (ir && !cj.empty())
+    FB_HIP(hipMemcpyAsync(rb.cjobs_dev, cj.data(), sizeof(SolveJob) * cj.size(),
+                          hipMemcpyHostToDevice, st));
+  return 0;
+}
+
+template <typename R>
+int refine_launch(const Band& bd, const cx<R>* mats, const cx<R>* matsT, const int16_t* perm,
+                  const RefinePlan& plan, RefineBufs& rb, hipStream_t st) {
+  if (plan.njobs == 0) return 0;
+  FB_TRY(launch_solve_jobs<R>(mats, matsT, perm, bd.n, bd.b, plan.njobs, rb.jobs_dev,
+                              solve_flops(bd.n, bd.b, plan.cols), st));
+  if (!plan.need_res) return 0;
+  for (size_t w0 = 0, wi = 0; w0 < (size_t)plan.ng; w0 += rb.wave, ++wi) {
+    const int nw = (int)std::min(rb.wave, (size_t)plan.ng - w0);
+    double wcols = 0;
+    for (int g = 0; g < nw; ++g) wcols += plan.gcols[w0 + g];
+    RefineCtl ctl{nullptr, rb.flag, rb.ratio, rb.npass, 0, plan.maxpass, plan.ir ? 1 : 0,
+                  plan.ir_tol};
+    FB_TRY(launch_residual_jobs(bd, nw, rb.rjobs_dev + w0, rb.part, ctl,
+                                resid_flops(bd.n, bd.b, wcols), st));
+    for (int pass = 1; pass <= plan.maxpass; ++pass) {
+      // gated launches: their work is added once the passes are known
+      FB_TRY(launch_solve_jobs<R>(mats, matsT, perm, bd.n, bd.b,
+                                  (int)(plan.cj_off[wi + 1] - plan.cj_off[wi]),
+                                  rb.cjobs_dev + plan.cj_off[wi], 0.0, st, rb.flag));
+      ctl.gate = rb.flag;
+      ctl.pass = pass;
+      FB_TRY(launch_residual_jobs(bd, nw, rb.rjobs_dev + w0, rb.part, ctl, 0.0, st));
     }
   }
+  return 0;
+}
+
+template <typename R>
+int refine_finish(const Band& bd, const std::vector<SolveJob>& jobs,
+                  const std::vector<c128>& zsys, const RefinePlan& plan, RefineBufs& rb,
+                  std::vector<double>& sys_res, std::vector<int32_t>& sys_pass, int* unconverged,
+                  hipStream_t st, const C128Fallback* fb, int* stagnated) {
+  if (plan.njobs == 0 || !plan.need_res) return 0;
+  const int ng = plan.ng;
+  const double ir_tol = plan.ir_tol;
+  std::vector<double> ratio(ng);
+  std::vector<int32_t> npass(ng);
+  FB_HIP(hipMemcpyAsync(ratio.data(), rb.ratio, sizeof(double) * ng, hipMemcpyDeviceToHost, st));
+  FB_HIP(hipMemcpyAsync(npass.data(), rb.npass, sizeof(int32_t) * ng, hipMemcpyDeviceToHost, st));
+  FB_HIP(hipStreamSynchronize(st));
+  std::vector<int> failed;  // systems with a group above ir_tol at the end
+  double corr_cols = 0;
+  for (int g = 0; g < ng; ++g) {
+    const int sys = jobs[plan.groups[g].first].sys;
+    if (!(ratio[g] <= sys_res[sys])) sys_res[sys] = ratio[g];
+    sys_pass[sys] = std::max(sys_pass[sys], npass[g]);
+    corr_cols += (double)npass[g] * plan.gcols[g];
+    if (plan.ir && !(ratio[g] <= ir_tol)) failed.push_back(sys);
+  }
+  prof_add_work(FB_PROF_SOLVE, solve_flops(bd.n, bd.b, corr_cols));
+  prof_add_work(FB_PROF_RESID, resid_flops(bd.n, bd.b, corr_cols));
+  if (stagnated) *stagnated = (int)failed.size();
   std::sort(failed.begin(), failed.end());
   failed.erase(std::unique(failed.begin(), failed.end()), failed.end());
   if (!failed.empty() && fb && fb->f && fb->cap > 0 && sizeof(R) == 4) {
@@ -327,6 +365,34 @@ int solve_refine(const Band& bd, const cx<R>* mats, const cx<R>* matsT, const in
       if (!(sys_res[s] <= ir_tol)) ++*unconverged;
   return 0;
 }
+
+
+template <typename R>
+int solve_refine(const Band& bd, const cx<R>* mats, const cx<R>* matsT, const int16_t* perm,
+                 const std::vector<SolveJob>& jobs, const std::vector<c128>& zsys, bool ir,
+                 double ir_tol, int ir_max, bool need_res, RefineBufs& rb,
+                 std::vector<double>& sys_res, std::vector<int32_t>& sys_pass, int* unconverged,
+                 hipStream_t st, const C128Fallback* fb) {
+  RefinePlan plan;
+  FB_TRY(refine_prepare<R>(bd, jobs, zsys, ir, ir_tol, ir_max, need_res, rb, plan, st));
+  FB_TRY(refine_launch<R>(bd, mats, matsT, perm, plan, rb, st));
+  return refine_finish<R>(bd, jobs, zsys, plan, rb, sys_res, sys_pass, unconverged, st, fb,
+                          nullptr);
+}
+
+#define FB_REFINE_INST(R)                                                                      \
+  template int refine_prepare<R>(const Band&, const std::vector<SolveJob>&,                    \
+                                 const std::vector<c128>&, bool, double, int, bool,            \
+                                 RefineBufs&, RefinePlan&, hipStream_t);                       \
+  template int refine_launch<R>(const Band&, const cx<R>*, const cx<R>*, const int16_t*,       \
+                                const RefinePlan&, RefineBufs&, hipStream_t);                  \
+  template int refine_finish<R>(const Band&, const std::vector<SolveJob>&,                     \
+                                const std::vector<c128>&, const RefinePlan&, RefineBufs&,      \
+                                std::vector<double>&, std::vector<int32_t>&, int*, hipStream_t, \
+                                const C128Fallback*, int*);
+FB_REFINE_INST(float)
+FB_REFINE_INST(double)
+#undef FB_REFINE_INST
 
 template int solve_refine<float>(const Band&, const c64*, const c64*, const int16_t*,
                                  const std::vector<SolveJob>&, const std::vector<c128>&, bool,

@@ -6,6 +6,10 @@ namespace fb {
 
 // Records a start event on construction and a stop event on destruction
 // when timing is enabled; work is the algorithmic work of the launch.
+// Adds algorithmic work to a class once it is known (launches whose work
+// depends on device-side decisions record none themselves).
+void prof_add_work(int cls, double work);
+
 struct ProfScope {
   int cls;
   hipStream_t st;

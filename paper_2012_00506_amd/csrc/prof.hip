@@ -42,6 +42,9 @@ void collect_locked(Registry& r) {
 ProfScope::ProfScope(int c, hipStream_t s, double w) : cls(c), st(s), work(w) {
   Registry& r = reg();
   if (!r.on) return;
+  // launches recorded into a graph are not timed one by one
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
     a = b = nullptr;
     return;
@@ -56,6 +59,12 @@ ProfScope::~ProfScope() {
   std::lock_guard<std::mutex> g(r.mu);
   r.pending.push_back({cls, a, b, work});
   if (r.pending.size() > 4096) collect_locked(r);
+}
+
+void prof_add_work(int cls, double work) {
+  Registry& r = reg();
+  std::lock_guard<std::mutex> g(r.mu);
+  if (r.on && cls >= 0 && cls < FB_PROF_NCLASS) r.work[cls] += work;
 }
 
 }  // namespace fb

@@ -17,9 +17,9 @@
 namespace fb {
 // the kernels live in solve_f32.hip / solve_f64.hip
 extern template int launch_variant<float>(int, const c64*, const c64*, const int16_t*, int64_t,
-                                          int, int, const SolveJob*, hipStream_t);
+                                          int, int, const SolveJob*, hipStream_t, const int32_t*);
 extern template int launch_variant<double>(int, const c128*, const c128*, const int16_t*, int64_t,
-                                           int, int, const SolveJob*, hipStream_t);
+                                           int, int, const SolveJob*, hipStream_t, const int32_t*);
 }  // namespace fb
 
 namespace fb {
@@ -32,19 +32,20 @@ int solve_tile(int b) {
 
 template <typename R>
 int launch_solve_jobs(const cx<R>* mats, const cx<R>* matsT, const int16_t* perm, int64_t n,
-                      int b, int njobs, const SolveJob* jobs_dev, double work, hipStream_t st) {
+                      int b, int njobs, const SolveJob* jobs_dev, double work, hipStream_t st,
+                      const int32_t* gate) {
   if (njobs <= 0) return 0;
   if (sizeof(R) == 4 && matsT == nullptr) return FB_ERR_INTERNAL;
   ProfScope ps(FB_PROF_SOLVE, st, work);
   const int nb = block_size(b);
   return launch_variant<R>(tuned_variant(sizeof(R), nb), mats, matsT, perm, n, nb, njobs,
-                           jobs_dev, st);
+                           jobs_dev, st, gate);
 }
 
 template int launch_solve_jobs<float>(const c64*, const c64*, const int16_t*, int64_t, int, int,
-                                      const SolveJob*, double, hipStream_t);
+                                      const SolveJob*, double, hipStream_t, const int32_t*);
 template int launch_solve_jobs<double>(const c128*, const c128*, const int16_t*, int64_t, int,
-                                       int, const SolveJob*, double, hipStream_t);
+                                       int, const SolveJob*, double, hipStream_t, const int32_t*);
 template int solve_tile<float>(int);
 template int solve_tile<double>(int);
 
@@ -58,7 +59,7 @@ template int solve_tile<double>(int);
 template <int NB, int T>
 __global__ void __launch_bounds__(NB * 4 * (T / 16))
 k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* __restrict__ jobs,
-                 int njobs, double* __restrict__ part) {
+                 int njobs, double* __restrict__ part, const int32_t* __restrict__ gate) {
   constexpr int NRW = NB / 16, NW = NRW * (T / 16);
   extern __shared__ __align__(16) char lds_raw[];
   c128* X = reinterpret_cast<c128*>(lds_raw);              // 3 slots of NB x T
@@ -66,6 +67,7 @@ k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* 
   const int job = remap_job(blockIdx.x, njobs);
   if (job >= njobs) return;
   const ResJob jb = jobs[job];
+  if (gate && !gate[jb.grp]) return;  // the group has finished refining
   const c128* jx = jb.x;
   const c128* jy = jb.y;
   c128* jr = jb.r;
@@ -174,19 +176,28 @@ k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* 
   }
 }
 
-// per job: max over its columns of sqrt(sum|r|^2 / sum|y|^2); columns with
-// y = 0 count as converged when r = 0
-__global__ void k_residual_ratio(const double* __restrict__ part, int njobs,
-                                 const ResJob* __restrict__ jobs, double* __restrict__ ratio) {
+// per group: ratio = max over its columns of sqrt(sum|r|^2 / sum|y|^2)
+// (columns with y = 0 count as converged when r = 0), and the decision of
+// the next refinement pass (RefineCtl)
+__global__ void k_refine_decide(const double* __restrict__ part, int njobs,
+                                const ResJob* __restrict__ jobs, RefineCtl ctl) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= njobs) return;
+  const int g = jobs[j].grp;
+  if (ctl.gate && !ctl.gate[g]) return;
   double mx = 0.0;
   for (int c = 0; c < jobs[j].ncol; ++c) {
     double rr = part[((size_t)j * 32 + c) * 2], yy = part[((size_t)j * 32 + c) * 2 + 1];
     double q = yy > 0.0 ? sqrt(rr / yy) : (rr > 0.0 ? 1e300 : 0.0);
     if (!(q <= mx)) mx = q;  // NaN propagates
   }
-  ratio[j] = mx;
+  const double prev = ctl.ratio[g];
+  ctl.ratio[g] = mx;
+  if (ctl.pass == 0) ctl.npass[g] = 0;
+  const bool more = ctl.ir && !(mx <= ctl.ir_tol) && ctl.pass < ctl.max_pass &&
+                    (ctl.pass == 0 || mx < 0.5 * prev);
+  ctl.flag[g] = more ? 1 : 0;
+  if (more) ctl.npass[g] = ctl.pass + 1;
 }
 
 size_t residual_part_doubles(int64_t n, int njobs) {
@@ -198,7 +209,7 @@ size_t residual_part_doubles(int64_t n, int njobs) {
 // tiles (LDS), the others 32
 template <int NB>
 static int launch_res_nb(const Band& bd, int njobs, const ResJob* jobs_dev, double* part,
-                         hipStream_t st) {
+                         const int32_t* gate, hipStream_t st) {
   constexpr int T = NB <= 64 ? 32 : 16;
   size_t smem = (size_t)3 * NB * T * sizeof(c128) + 2 * (NB / 16) * (T / 16) * 16 * sizeof(double);
   (void)hipFuncSetAttribute((const void*)k_shift_residual<NB, T>,
@@ -208,7 +219,7 @@ static int launch_res_nb(const Band& bd, int njobs, const ResJob* jobs_dev, doub
     int nj = njobs - j0 < (1 << 20) ? njobs - j0 : (1 << 20);
     int grid = 8 * ((nj + 7) / 8);
     k_shift_residual<NB, T><<<grid, NB * 4 * (T / 16), smem, st>>>(
-        bd.Bblk, bd.n, bd.K, jobs_dev + j0, nj, part + (size_t)j0 * 64);
+        bd.Bblk, bd.n, bd.K, jobs_dev + j0, nj, part + (size_t)j0 * 64, gate);
     FB_HIP(hipGetLastError());
   }
   return 0;
@@ -217,23 +228,24 @@ static int launch_res_nb(const Band& bd, int njobs, const ResJob* jobs_dev, doub
 int residual_cols(int nb) { return nb <= 64 ? 32 : 16; }
 
 int launch_residual_jobs(const Band& bd, int njobs, const ResJob* jobs_dev, double* part,
-                         double* ratio_dev, double work, hipStream_t st) {
+                         const RefineCtl& ctl, double work, hipStream_t st) {
   if (njobs <= 0) return 0;
   ProfScope ps(FB_PROF_RESID, st, work);
   int rc;
+  const int32_t* gate = ctl.gate;
   switch (bd.nb) {
-    case 16: rc = launch_res_nb<16>(bd, njobs, jobs_dev, part, st); break;
-    case 32: rc = launch_res_nb<32>(bd, njobs, jobs_dev, part, st); break;
-    case 48: rc = launch_res_nb<48>(bd, njobs, jobs_dev, part, st); break;
-    case 64: rc = launch_res_nb<64>(bd, njobs, jobs_dev, part, st); break;
-    case 80: rc = launch_res_nb<80>(bd, njobs, jobs_dev, part, st); break;
-    case 96: rc = launch_res_nb<96>(bd, njobs, jobs_dev, part, st); break;
-    case 112: rc = launch_res_nb<112>(bd, njobs, jobs_dev, part, st); break;
-    case 128: rc = launch_res_nb<128>(bd, njobs, jobs_dev, part, st); break;
+    case 16: rc = launch_res_nb<16>(bd, njobs, jobs_dev, part, gate, st); break;
+    case 32: rc = launch_res_nb<32>(bd, njobs, jobs_dev, part, gate, st); break;
+    case 48: rc = launch_res_nb<48>(bd, njobs, jobs_dev, part, gate, st); break;
+    case 64: rc = launch_res_nb<64>(bd, njobs, jobs_dev, part, gate, st); break;
+    case 80: rc = launch_res_nb<80>(bd, njobs, jobs_dev, part, gate, st); break;
+    case 96: rc = launch_res_nb<96>(bd, njobs, jobs_dev, part, gate, st); break;
+    case 112: rc = launch_res_nb<112>(bd, njobs, jobs_dev, part, gate, st); break;
+    case 128: rc = launch_res_nb<128>(bd, njobs, jobs_dev, part, gate, st); break;
     default: return FB_ERR_INTERNAL;
   }
   if (rc) return rc;
-  k_residual_ratio<<<(njobs + 255) / 256, 256, 0, st>>>(part, njobs, jobs_dev, ratio_dev);
+  k_refine_decide<<<(njobs + 255) / 256, 256, 0, st>>>(part, njobs, jobs_dev, ctl);
   FB_HIP(hipGetLastError());
   return 0;
 }

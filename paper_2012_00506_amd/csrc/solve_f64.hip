@@ -3,5 +3,5 @@
 
 namespace fb {
 template int launch_variant<double>(int, const c128*, const c128*, const int16_t*, int64_t, int,
-                                    int, const SolveJob*, hipStream_t);
+                                    int, const SolveJob*, hipStream_t, const int32_t*);
 }  // namespace fb

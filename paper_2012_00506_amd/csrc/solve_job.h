@@ -17,7 +17,8 @@ struct SolveJob {
   c128* out;      // solution (written, or added to when add != 0)
   int64_t ldin, ldmid, ldout;
   int32_t add;
-  int32_t pad_;
+  int32_t grp;    // residual group of a correction job (the launch's gate array
+                  // says whether it still runs)
 };
 
 // r = y - A x for one tile (A = zI - B, or its conjugate transpose).
@@ -26,7 +27,7 @@ struct ResJob {
   const c128* y;
   c128* r;
   int64_t ldx, ldy, ldr;
-  int32_t col0, ncol, dir, pad_;
+  int32_t col0, ncol, dir, grp;  // grp: index of the group in the call
   c128 z;
 };
 
@@ -35,9 +36,11 @@ inline int block_size(int b) { return (b + 15) / 16 * 16; }
 
 // mats: the factor blocks; matsT: their transposed copy, read by the
 // conjugate-transposed solves (required for complex64, null for complex128)
+// gate (dev, may be null): a job runs only while gate[job.grp] != 0
 template <typename R>
 int launch_solve_jobs(const cx<R>* mats, const cx<R>* matsT, const int16_t* perm, int64_t n,
-                      int b, int njobs, const SolveJob* jobs_dev, double work, hipStream_t st);
+                      int b, int njobs, const SolveJob* jobs_dev, double work, hipStream_t st,
+                      const int32_t* gate = nullptr);
 template <typename R>
 int launch_lu_impl(const Band& bd, int nsys, const c128* z_dev, cx<R>* mats, cx<R>* matsT,
                    int16_t* perm, int32_t* info, cx<R>* scratch, cx<R>* lscr, hipStream_t st);
@@ -50,8 +53,21 @@ int solve_tile(int b);
 size_t residual_part_doubles(int64_t n, int njobs);
 // columns per residual job for block size nb
 int residual_cols(int nb);
+// Residual of every job (group) whose gate entry is set (all when gate is
+// null), then the refinement decision per group: ratio[g] = max over its
+// columns of ||r|| / ||y||; flag[g] = 1 when the group needs a correction
+// pass (ir, ratio above ir_tol, pass < max_pass and, after pass 0, the last
+// pass at least halved the ratio); npass[g] counts the passes asked for.
+struct RefineCtl {
+  const int32_t* gate;  // null in pass 0
+  int32_t* flag;
+  double* ratio;
+  int32_t* npass;
+  int pass, max_pass, ir;
+  double ir_tol;
+};
 int launch_residual_jobs(const Band& bd, int njobs, const ResJob* jobs_dev, double* part,
-                         double* ratio_dev, double work, hipStream_t st);
+                         const RefineCtl& ctl, double work, hipStream_t st);
 // algorithmic flops: solve 24 n b per column (L: n b, U: 2 n b complex MACs),
 // FP64 residual 8 (2b+1) n per column
 inline double solve_flops(int64_t n, int b, double cols) { return 24.0 * (double)n * b * cols; }
@@ -76,19 +92,24 @@ void carve_factors(Arena& ar, const Band& bd, int nsys, FactorBufs<R>& f);
 template <typename R>
 int factor_systems(const Band& bd, int nsys, const double* z_host, FactorBufs<R>& f,
                    hipStream_t st);
+// FB_ERR_SINGULAR when a factorisation met an exactly zero pivot (synchronises)
+template <typename R>
+int factor_check(int nsys, FactorBufs<R>& f, hipStream_t st);
 
 // Buffers of the solve + refinement driver.
 struct RefineBufs {
   int tile = 32;
   int gcols = 32;  // columns per residual group
   int cap_jobs = 0;
-  size_t wave = 0;
+  size_t wave = 0;           // groups whose residual blocks fit at once
   SolveJob* jobs_dev = nullptr;
-  ResJob* rjobs_dev = nullptr;
-  SolveJob* cjobs_dev = nullptr;
-  c128* rbuf = nullptr;
+  ResJob* rjobs_dev = nullptr;   // one per group (cap_jobs)
+  SolveJob* cjobs_dev = nullptr; // correction jobs of every group
+  c128* rbuf = nullptr;          // residual blocks of one wave of groups
   double* part = nullptr;
-  double* ratio = nullptr;
+  double* ratio = nullptr;       // per group
+  int32_t* flag = nullptr;       // per group
+  int32_t* npass = nullptr;      // per group
 };
 void carve_refine(Arena& ar, const Band& bd, int tile, int max_jobs, bool ir, bool need_res,
                   RefineBufs& rb);
@@ -104,6 +125,30 @@ struct C128Fallback {
 // systems the fallback factors hold at once
 inline int fallback_cap(int nsys) { return nsys < 2 ? nsys : 2; }
 size_t refine_bytes(const Band& bd, int tile, int max_jobs, bool ir, bool need_res);
+// Solve + refinement of one batch of jobs in three stages (solve_refine runs
+// all three): tables to the device, kernel launches (no host round-trip, so
+// they can be captured), read-back and complex128 fallback.
+struct RefinePlan {
+  int njobs = 0, ng = 0, maxpass = 0;
+  bool ir = false, need_res = false;
+  double ir_tol = 0.0, cols = 0.0;
+  std::vector<std::pair<int, int>> groups;
+  std::vector<double> gcols;
+  std::vector<size_t> cj_off;
+};
+template <typename R>
+int refine_prepare(const Band& bd, const std::vector<SolveJob>& jobs,
+                   const std::vector<c128>& zsys, bool ir, double ir_tol, int ir_max,
+                   bool need_res, RefineBufs& rb, RefinePlan& plan, hipStream_t st);
+template <typename R>
+int refine_launch(const Band& bd, const cx<R>* mats, const cx<R>* matsT, const int16_t* perm,
+                  const RefinePlan& plan, RefineBufs& rb, hipStream_t st);
+// stagnated (may be null): systems that ended above ir_tol before any fallback
+template <typename R>
+int refine_finish(const Band& bd, const std::vector<SolveJob>& jobs,
+                  const std::vector<c128>& zsys, const RefinePlan& plan, RefineBufs& rb,
+                  std::vector<double>& sys_res, std::vector<int32_t>& sys_pass, int* unconverged,
+                  hipStream_t st, const C128Fallback* fb, int* stagnated);
 template <typename R>
 int solve_refine(const Band& bd, const cx<R>* mats, const cx<R>* matsT, const int16_t* perm,
                  const std::vector<SolveJob>& jobs, const std::vector<c128>& zsys, bool ir,

@@ -193,7 +193,7 @@ template <typename R, int NB, int T, bool PREF, int NC, int OCC>
 __global__ void __launch_bounds__(NB * 4 * (T / (16 * NC)), OCC)
 k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
              const int16_t* __restrict__ permg, int64_t n, int K,
-             const SolveJob* __restrict__ jobs, int njobs) {
+             const SolveJob* __restrict__ jobs, int njobs, const int32_t* __restrict__ gate) {
   // complex64 H solves read the transposed copy of the factor blocks
   constexpr bool TS = sizeof(R) == 4;
   constexpr int NRW = NB / 16;
@@ -203,6 +203,7 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
   const int job = remap_job(blockIdx.x, njobs);
   if (job >= njobs) return;
   const SolveJob jb = jobs[job];
+  if (gate && !gate[jb.grp]) return;  // a correction its group no longer needs
   const int t = threadIdx.x, lane = t & 63;
   // row block and column base of this wave (wave-uniform: scalar registers)
   const int w = __builtin_amdgcn_readfirstlane((t >> 6) % NRW);
@@ -530,7 +531,7 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
 
 template <typename R, int NB, int T, bool PREF, int NC, int OCC>
 int launch_nb(const cx<R>* mats, const cx<R>* matsT, const int16_t* perm, int64_t n, int njobs,
-              const SolveJob* jobs_dev, hipStream_t st) {
+              const SolveJob* jobs_dev, hipStream_t st, const int32_t* gate) {
   const int K = (int)((n + NB - 1) / NB);
   size_t smem = solve_lds_bytes(NB, T, sizeof(cx<R>));
   (void)hipFuncSetAttribute((const void*)k_band_solve<R, NB, T, PREF, NC, OCC>,
@@ -540,7 +541,7 @@ int launch_nb(const cx<R>* mats, const cx<R>* matsT, const int16_t* perm, int64_
     int nj = njobs - j0 < (1 << 20) ? njobs - j0 : (1 << 20);
     int grid = 8 * ((nj + 7) / 8);
     k_band_solve<R, NB, T, PREF, NC, OCC><<<grid, NB * 4 * (T / (16 * NC)), smem, st>>>(
-        mats, matsT, perm, n, K, jobs_dev + j0, nj);
+        mats, matsT, perm, n, K, jobs_dev + j0, nj, gate);
     FB_HIP(hipGetLastError());
   }
   return 0;
@@ -548,16 +549,16 @@ int launch_nb(const cx<R>* mats, const cx<R>* matsT, const int16_t* perm, int64_
 
 template <typename R, int T, bool PREF, int NC, int OCC = 1>
 int launch_t(const cx<R>* mats, const cx<R>* matsT, const int16_t* perm, int64_t n, int nb,
-             int njobs, const SolveJob* jobs_dev, hipStream_t st) {
+             int njobs, const SolveJob* jobs_dev, hipStream_t st, const int32_t* gate) {
   switch (nb) {
-    case 16: return launch_nb<R, 16, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st);
-    case 32: return launch_nb<R, 32, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st);
-    case 48: return launch_nb<R, 48, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st);
-    case 64: return launch_nb<R, 64, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st);
-    case 80: return launch_nb<R, 80, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st);
-    case 96: return launch_nb<R, 96, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st);
-    case 112: return launch_nb<R, 112, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st);
-    case 128: return launch_nb<R, 128, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st);
+    case 16: return launch_nb<R, 16, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
+    case 32: return launch_nb<R, 32, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
+    case 48: return launch_nb<R, 48, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
+    case 64: return launch_nb<R, 64, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
+    case 80: return launch_nb<R, 80, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
+    case 96: return launch_nb<R, 96, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
+    case 112: return launch_nb<R, 112, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
+    case 128: return launch_nb<R, 128, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
     default: return FB_ERR_INTERNAL;
   }
 }
@@ -565,16 +566,17 @@ int launch_t(const cx<R>* mats, const cx<R>* matsT, const int16_t* perm, int64_t
 // every (tile width, prefetch, tiles per wave, register cap) variant of one precision
 template <typename R>
 int launch_variant(int variant, const cx<R>* mats, const cx<R>* matsT, const int16_t* perm,
-                   int64_t n, int nb, int njobs, const SolveJob* jobs_dev, hipStream_t st) {
+                   int64_t n, int nb, int njobs, const SolveJob* jobs_dev, hipStream_t st,
+                   const int32_t* gate) {
   switch (variant) {
-    case 0: return launch_t<R, 16, false, 1>(mats, matsT, perm, n, nb, njobs, jobs_dev, st);
-    case 1: return launch_t<R, 16, true, 1>(mats, matsT, perm, n, nb, njobs, jobs_dev, st);
-    case 2: return launch_t<R, 32, false, 1>(mats, matsT, perm, n, nb, njobs, jobs_dev, st);
-    case 3: return launch_t<R, 32, true, 1>(mats, matsT, perm, n, nb, njobs, jobs_dev, st);
-    case 4: return launch_t<R, 32, false, 2>(mats, matsT, perm, n, nb, njobs, jobs_dev, st);
-    case 5: return launch_t<R, 32, true, 2>(mats, matsT, perm, n, nb, njobs, jobs_dev, st);
-    case 6: return launch_t<R, 16, false, 1, 3>(mats, matsT, perm, n, nb, njobs, jobs_dev, st);
-    case 7: return launch_t<R, 16, true, 1, 3>(mats, matsT, perm, n, nb, njobs, jobs_dev, st);
+    case 0: return launch_t<R, 16, false, 1>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
+    case 1: return launch_t<R, 16, true, 1>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
+    case 2: return launch_t<R, 32, false, 1>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
+    case 3: return launch_t<R, 32, true, 1>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
+    case 4: return launch_t<R, 32, false, 2>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
+    case 5: return launch_t<R, 32, true, 2>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
+    case 6: return launch_t<R, 16, false, 1, 3>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
+    case 7: return launch_t<R, 16, true, 1, 3>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
     default: return FB_ERR_INTERNAL;
   }
 }
