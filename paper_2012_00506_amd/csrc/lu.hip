@@ -18,16 +18,19 @@
 //         interchanges of the block move them, so that P A_panel = Lh U),
 //   Lh21  multipliers of the bottom b rows,
 //   U(k,k), U(k,k+1), U(k,k+2).
-// A second kernel replaces Lh11 and U(k,k) by their inverses, so that the
-// solves are chains of dense b x b products.
+// A second kernel replaces Lh11 and U(k,k) by their inverses and a third
+// Lh21 by M = Lh21 Lh11^{-1}, so that the solves are chains of dense b x b
+// products and a forward step reads its window once (y_top = Lh11^{-1} z_top
+// and carry = z_bot - M z_top are independent products of z_top).
 //
 // Within a block the multipliers are written to a per-system scratch under a
 // storage row that follows each window row through the interchanges (an O(1)
 // swap of two table entries), and gathered into row order once at the end of
 // the block; the entering row of the next step is fetched from B while the
 // current step runs.
-#include "solve_job.h"
 #include "prof.h"
+#include "solve_job.h"
+#include "solve_kernel.h"
 
 namespace fb {
 
@@ -459,6 +462,75 @@ k_block_invert(cx<R>* __restrict__ mats, int b, int nblk) {
     for (int e = t; e < bb; e += blockDim.x) M[e] = A[e];
 }
 
+// M = Lh21 Lh11^{-1} in place of Lh21 (slot 1), one workgroup per block and
+// one wave per 16 rows: a wave holds its rows of Lh21 as MFMA fragments and
+// multiplies them by panels of PW columns of the lower triangular inverse
+// staged in LDS (rows below the panel's first column only).  A wave reads and
+// writes only its own rows of the slot.
+template <typename R, int NB>
+__global__ void __launch_bounds__(NB * 4)
+k_form_m(cx<R>* __restrict__ mats, int nblk) {
+  constexpr int PW = NB < 64 ? NB : 64;
+  constexpr int NC = PW / 16;
+  constexpr int LD = PW + 1;
+  extern __shared__ __align__(16) char lds_raw[];
+  cx<R>* Lp = reinterpret_cast<cx<R>*>(lds_raw);  // NB x LD: Lh11^{-1}(k, p0 + c) at k LD + c
+  const int blk = blockIdx.x;
+  if (blk >= nblk) return;
+  const cx<R>* Li = mats + ((size_t)blk * 5 + 0) * NB * NB;
+  cx<R>* L21 = mats + ((size_t)blk * 5 + 1) * NB * NB;
+  const int t = threadIdx.x, lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  Frag<R, NB> f;
+  frag_load<R, NB, false>(f, L21, w, lane, 0, NB);
+  for (int p0 = 0; p0 < NB; p0 += PW) {
+    __syncthreads();
+    for (int e = t; e < NB * PW; e += NB * 4) {
+      const int k = e % NB, c = e / NB;
+      Lp[k * LD + c] = Li[(size_t)(p0 + c) * NB + k];
+    }
+    __syncthreads();
+    Acc<R, NC> acc;
+    acc.zero();
+    frag_mma<R, NB, NC, false, false>(acc, f, Lp, LD, nullptr, 0, lane, p0, NB);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * w + MF<R>::row(lane, r);
+        const int col = p0 + 16 * c + (lane & 15);
+        gst(L21 + (size_t)col * NB + row, acc.get(c, r));
+      }
+  }
+}
+
+template <typename R, int NB>
+static int launch_form_m_nb(cx<R>* mats, int nblk, hipStream_t st) {
+  constexpr int PW = NB < 64 ? NB : 64;
+  const size_t smem = sizeof(cx<R>) * (size_t)NB * (PW + 1);
+  (void)hipFuncSetAttribute((const void*)k_form_m<R, NB>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
+  (void)hipGetLastError();
+  k_form_m<R, NB><<<nblk, NB * 4, smem, st>>>(mats, nblk);
+  FB_HIP(hipGetLastError());
+  return 0;
+}
+
+template <typename R>
+static int launch_form_m(cx<R>* mats, int nb, int nblk, hipStream_t st) {
+  switch (nb) {
+    case 16: return launch_form_m_nb<R, 16>(mats, nblk, st);
+    case 32: return launch_form_m_nb<R, 32>(mats, nblk, st);
+    case 48: return launch_form_m_nb<R, 48>(mats, nblk, st);
+    case 64: return launch_form_m_nb<R, 64>(mats, nblk, st);
+    case 80: return launch_form_m_nb<R, 80>(mats, nblk, st);
+    case 96: return launch_form_m_nb<R, 96>(mats, nblk, st);
+    case 112: return launch_form_m_nb<R, 112>(mats, nblk, st);
+    case 128: return launch_form_m_nb<R, 128>(mats, nblk, st);
+    default: return FB_ERR_INTERNAL;
+  }
+}
+
 template <typename R>
 static size_t lu_lds_head_bytes(int b) {
   const int nb = block_size(b);
@@ -533,12 +605,14 @@ int launch_lu_impl(const Band& bd, int nsys, const c128* z_dev, cx<R>* mats, cx<
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
   (void)hipGetLastError();
   int nblk = nsys * K;
-  ProfScope ps(FB_PROF_INVERT, st, 8.0 * 2.0 * nblk * (double)nb * nb * nb / 3.0);
+  // inverses (2 nb^3 / 3 complex multiply-adds per block) and M (nb^3 / 2)
+  ProfScope ps(FB_PROF_INVERT, st, 8.0 * nblk * (double)nb * nb * nb * (2.0 / 3.0 + 0.5));
   if (ilds)
     k_block_invert<R, true><<<2 * nblk, 256, ismem, st>>>(mats, nb, nblk);
   else
     k_block_invert<R, false><<<2 * nblk, 256, ismem, st>>>(mats, nb, nblk);
   FB_HIP(hipGetLastError());
+  FB_TRY(launch_form_m<R>(mats, nb, nblk, st));
   if (matsT) {
     k_transpose_blocks<R><<<5 * nblk, 256, 0, st>>>(mats, matsT, nb);
     FB_HIP(hipGetLastError());

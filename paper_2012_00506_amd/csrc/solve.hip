@@ -1,12 +1,13 @@
 // Multi-right-hand-side solves with the block form of the band LU factors.
 //
 // N: x = A^{-1} y.  Forward, block k on the window rows kb .. kb+2b-1:
-//      z = P y_win; y_top = Lh11^{-1} z_top; carry = z_bot - Lh21 y_top
+//      z = P y_win; y_top = Lh11^{-1} z_top; carry = z_bot - M z_top
+//    with M = Lh21 Lh11^{-1} formed once per factorisation.
 //    Backward: x_k = U(k,k)^{-1} (y_k - U(k,k+1) x_{k+1} - U(k,k+2) x_{k+2}).
 // H: x = A^{-H} y.  Forward with U^H:
 //      w_k = U(k,k)^{-H} (y_k - U(k-1,k)^H w_{k-1} - U(k-2,k)^H w_{k-2})
 //    Backward, k descending on the window [w_k ; carry]:
-//      top = Lh11^{-H} (w_k - Lh21^H carry); x_win = P^T [top ; carry]
+//      top = Lh11^{-H} w_k - M^H carry; x_win = P^T [top ; carry]
 //    (rows kb+b .. kb+2b-1 of x_win are final, rows kb .. kb+b-1 carry on).
 // One workgroup per job (system, direction, tile of T columns); the tile's
 // window and carries live in LDS.  Inputs and outputs are complex128; the

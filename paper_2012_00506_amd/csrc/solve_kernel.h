@@ -187,8 +187,12 @@ struct PreT {
 // ---------------------------------------------------------------- MFMA block solve
 // One workgroup per job with one wave per 16 x (16 NC) output tile of a block
 // product ((NB/16) x (T/(16 NC)) waves; a wave with NC > 1 reuses each factor
-// fragment for NC column tiles); LDS holds 3 NB x T blocks.  OCC > 1 asks the
-// compiler to fit the registers of OCC waves per SIMD.
+// fragment for NC column tiles).  LDS holds 3 slots of NB x T (rows padded to
+// T + 1 elements) and the block's permutation with its inverse.  Every tile
+// that enters or leaves global memory goes through an LDS slot with thread
+// e on row e % NB, column e / NB, so that a wave reads or writes whole column
+// runs of 64 rows.  OCC > 1 asks the compiler to fit the registers of OCC
+// waves per SIMD.
 template <typename R, int NB, int T, bool PREF, int NC, int OCC>
 __global__ void __launch_bounds__(NB * 4 * (T / (16 * NC)), OCC)
 k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
@@ -196,19 +200,23 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
              const SolveJob* __restrict__ jobs, int njobs, const int32_t* __restrict__ gate) {
   // complex64 H solves read the transposed copy of the factor blocks
   constexpr bool TS = sizeof(R) == 4;
-  constexpr int NRW = NB / 16;
+  constexpr int LDT = T + 1;    // LDS row of a slot
+  constexpr int SL = NB * LDT;  // one slot
   extern __shared__ __align__(16) char lds_raw[];
-  int* sp = reinterpret_cast<int*>(lds_raw);                        // 2 NB perm entries
-  cx<R>* S = reinterpret_cast<cx<R>*>(lds_raw + ((2 * NB * sizeof(int) + 15) & ~15));
+  int* sp = reinterpret_cast<int*>(lds_raw);  // permutation, 2 NB entries
+  int* si = sp + 2 * NB;                      // its inverse
+  cx<R>* S = reinterpret_cast<cx<R>*>(lds_raw + ((4 * NB * sizeof(int) + 15) & ~15));
   const int job = remap_job(blockIdx.x, njobs);
   if (job >= njobs) return;
   const SolveJob jb = jobs[job];
   if (gate && !gate[jb.grp]) return;  // a correction its group no longer needs
   const int t = threadIdx.x, lane = t & 63;
+  constexpr int NRW = NB / 16;
   // row block and column base of this wave (wave-uniform: scalar registers)
   const int w = __builtin_amdgcn_readfirstlane((t >> 6) % NRW);
   const int cb0 = __builtin_amdgcn_readfirstlane(16 * NC * ((t >> 6) / NRW));
-  const int nthr = NB * 4 * (T / (16 * NC));
+  constexpr int NTHR = NB * 4 * (T / (16 * NC));
+  constexpr int RF = NB * T / NTHR;  // tile elements per thread
   const size_t bb = (size_t)NB * NB;
   const cx<R>* F = mats + (size_t)jb.sys * K * 5 * bb;
   const int16_t* P = permg + (size_t)jb.sys * K * 2 * NB;
@@ -227,76 +235,68 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
   auto conv = [&](auto v, bool ok) -> cx<R> {
     return ok ? mk<R>((R)v.x, (R)v.y) : mk<R>(0, 0);
   };
-  // x into the output (added to it for a correction), a batch at a time:
-  // all loads of the batch first, then the stores
-  auto emit_batch = [&](auto& row, auto& col, auto& v, auto& valid) {
-    constexpr int NQ = sizeof(valid) / sizeof(valid[0]);
-    c128 old[NQ];
-    if (jb.add) {
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) old[q] = gld(gaddr(out, jb.ldout, row[q], col[q]));
-    }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      if (!valid[q] || !okf(row[q], col[q])) continue;
-      c128 x = mk((double)v[q].x, (double)v[q].y);
-      if (jb.add) x = old[q] + x;
-      gst(out + (int64_t)col[q] * jb.ldout + row[q], x);
-    }
-  };
-  constexpr int RE = 4 * NC;
-  auto acc_to_g = [&](const Acc<R, NC>& acc, auto base, int64_t ld, int64_t row0) {
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int64_t row = row0 + 16 * w + MF<R>::row(lane, r);
-        int col = cb0 + 16 * c + (lane & 15);
-        if (row < n && col < ncol)
-          gst(base + (int64_t)col * ld + row, acc.get(c, r));
-      }
-  };
-  auto acc_emit = [&](const Acc<R, NC>& acc, int64_t row0) {
-    int64_t rows[RE];
-    int cols[RE];
-    cx<R> v[RE];
-    bool valid[RE];
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int q = 4 * c + r;
-        rows[q] = row0 + 16 * w + MF<R>::row(lane, r);
-        cols[q] = cb0 + 16 * c + (lane & 15);
-        v[q] = acc.get(c, r);
-        valid[q] = true;
-      }
-    emit_batch(rows, cols, v, valid);
-  };
-  // a whole NB x T block of global rows (row0 ..) into LDS rows (dst)
-  constexpr int NTHR = NB * 4 * (T / (16 * NC));
-  constexpr int RF = NB * T / NTHR;  // elements per thread
-  struct Fill {
+  // tile element q of this thread: row e % NB, column e / NB
+  auto erow = [&](int q) { return (t + q * NTHR) % NB; };
+  auto ecol = [&](int q) { return (t + q * NTHR) / NB; };
+  struct TileC {
     c128 v[RF];
   };
-  auto fill_issue = [&](Fill& f, auto base, int64_t ld, int64_t row0) {
+  struct TileR {
+    cx<R> v[RF];
+  };
+  // global rows row0 .. row0 + NB - 1 of a tile into registers, then LDS
+  auto tile_issue = [&](auto& f, auto base, int64_t ld, int64_t row0) {
+#pragma unroll
+    for (int q = 0; q < RF; ++q) f.v[q] = gld(gaddr(base, ld, row0 + erow(q), ecol(q)));
+  };
+  auto tile_store = [&](const auto& f, cx<R>* dst, int64_t row0) {
+#pragma unroll
+    for (int q = 0; q < RF; ++q)
+      dst[erow(q) * LDT + ecol(q)] = conv(f.v[q], okf(row0 + erow(q), ecol(q)));
+  };
+  // values v[q] of rows row0 + erow(q) into the output (added to it for a
+  // correction): all loads of the old values first, then the stores
+  auto emit_vals = [&](const cx<R>* v, int64_t row0) {
+    c128 old[RF];
+    if (jb.add) {
+#pragma unroll
+      for (int q = 0; q < RF; ++q) old[q] = gld(gaddr(out, jb.ldout, row0 + erow(q), ecol(q)));
+    }
 #pragma unroll
     for (int q = 0; q < RF; ++q) {
-      const int e = t + q * NTHR;
-      f.v[q] = gld(gaddr(base, ld, row0 + e / T, e % T));
+      const int64_t row = row0 + erow(q);
+      if (!okf(row, ecol(q))) continue;
+      c128 x = mk((double)v[q].x, (double)v[q].y);
+      if (jb.add) x = old[q] + x;
+      gst(out + (int64_t)ecol(q) * jb.ldout + row, x);
     }
   };
-  auto fill_store = [&](const Fill& f, cx<R>* dst, int64_t row0) {
+  auto emit_tile = [&](const cx<R>* src, int64_t row0) {
+    cx<R> v[RF];
+#pragma unroll
+    for (int q = 0; q < RF; ++q) v[q] = src[erow(q) * LDT + ecol(q)];
+    emit_vals(v, row0);
+  };
+  auto put_mid = [&](const cx<R>* src, int64_t row0) {
 #pragma unroll
     for (int q = 0; q < RF; ++q) {
-      const int e = t + q * NTHR;
-      dst[e] = conv(f.v[q], okf(row0 + e / T, e % T));
+      const int64_t row = row0 + erow(q);
+      if (okf(row, ecol(q)))
+        gst(mid + (int64_t)ecol(q) * jb.ldmid + row, src[erow(q) * LDT + ecol(q)]);
     }
+  };
+  auto zero_slots = [&](cx<R>* dst, int nslot) {
+    for (int e = t; e < nslot * SL; e += NTHR) dst[e] = mk<R>(0, 0);
+  };
+  // the permutation of block k and its inverse
+  auto perm_put = [&](int e, int v) {
+    sp[e] = v;
+    if ((unsigned)v < (unsigned)(2 * NB)) si[v] = e;
   };
   auto load_perm = [&](int k) {
-    for (int e = t; e < 2 * NB; e += nthr) sp[e] = gld(P + (size_t)k * 2 * NB + e);
+    for (int e = t; e < 2 * NB; e += NTHR) perm_put(e, gld(P + (size_t)k * 2 * NB + e));
   };
-  // the permutation of block k fetched early into registers, stored later
+  // fetched early into registers, stored later
   constexpr int RP = (2 * NB + NTHR - 1) / NTHR;
   struct PermPre {
     int16_t v[RP];
@@ -312,7 +312,7 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
 #pragma unroll
     for (int q = 0; q < RP; ++q) {
       const int e = t + q * NTHR;
-      if (e < 2 * NB) sp[e] = pp.v[q];
+      if (e < 2 * NB) perm_put(e, pp.v[q]);
     }
   };
   const int lo_tri = 16 * w + 16;  // k < lo_tri: lower triangle rows of this wave
@@ -342,21 +342,23 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
   };
   Acc<R, NC> acc;
   Frag<R, NB> fa, fb, fc;
-  PreT<cx<R>, NC> pvm;  // intermediates (backward sweeps)
+  PreT<cx<R>, NC> pvm;  // intermediates (N backward)
   PreT<c128, NC> pvi;   // right-hand sides (H forward)
 
   if (jb.dir == 0) {
     // ---------------------------------------------------------- N forward
-    cx<R>* W = S;                 // window, 2 NB x T
-    cx<R>* Yt = S + 2 * NB * T;   // y_top, NB x T
+    // y_k = Lh11^{-1} z_top and the next window top z_bot - M z_top are both
+    // products of z_top = rows sp[0, NB) of the window
+    cx<R>* W = S;           // window: rows 0 .. 2 NB - 1 (two slots)
+    cx<R>* Yt = S + 2 * SL; // y_k on its way to the intermediate
     {
-      Fill f0, f1;
-      fill_issue(f0, in, jb.ldin, 0);
-      fill_issue(f1, in, jb.ldin, NB);
-      fill_store(f0, W, 0);
-      fill_store(f1, W + NB * T, NB);
+      TileC f0, f1;
+      tile_issue(f0, in, jb.ldin, 0);
+      tile_issue(f1, in, jb.ldin, NB);
+      tile_store(f0, W, 0);
+      tile_store(f1, W + SL, NB);
     }
-    Fill fr;
+    TileC fr;
     load_perm(0);
     if (PREF) frag_load<R, NB, false>(fa, blk(0, 0), w, lane, 0, lo_tri);
     __syncthreads();
@@ -364,28 +366,29 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
       if (PREF) frag_load<R, NB, false>(fb, blk(k, 1), w, lane, 0, NB);
       if (!PREF) frag_load<R, NB, false>(fa, blk(k, 0), w, lane, 0, lo_tri);
       acc.zero();
-      frag_mma<R, NB, NC, false, false>(acc, fa, W, T, sp, cb0, lane, 0, lo_tri);
-      acc_to_lds(acc, Yt, T, nullptr, w, cb0, lane);
-      acc_to_g(acc, mid, jb.ldmid, (int64_t)k * NB);
-      __syncthreads();
-      fill_issue(fr, in, jb.ldin, (int64_t)(k + 2) * NB);  // consumed after the product
+      frag_mma<R, NB, NC, false, false>(acc, fa, W, LDT, sp, cb0, lane, 0, lo_tri);
+      acc_to_lds(acc, Yt, LDT, nullptr, w, cb0, lane);
+      tile_issue(fr, in, jb.ldin, (int64_t)(k + 2) * NB);  // consumed after the product
       PermPre pnext;
       if (k + 1 < K) perm_issue(pnext, k + 1);
       if (PREF && k + 1 < K) frag_load<R, NB, false>(fa, blk(k + 1, 0), w, lane, 0, lo_tri);
       if (!PREF) frag_load<R, NB, false>(fb, blk(k, 1), w, lane, 0, NB);
-      acc_from_lds(acc, W, T, sp + NB, w, cb0, lane);
-      frag_mma<R, NB, NC, false, true>(acc, fb, Yt, T, nullptr, cb0, lane, 0, NB);
+      acc_from_lds(acc, W, LDT, sp + NB, w, cb0, lane);
+      frag_mma<R, NB, NC, false, true>(acc, fb, W, LDT, sp, cb0, lane, 0, NB);
       __syncthreads();
-      acc_to_lds(acc, W, T, nullptr, w, cb0, lane);
-      fill_store(fr, W + NB * T, (int64_t)(k + 2) * NB);
+      acc_to_lds(acc, W, LDT, nullptr, w, cb0, lane);
+      tile_store(fr, W + SL, (int64_t)(k + 2) * NB);
+      put_mid(Yt, (int64_t)k * NB);
       if (k + 1 < K) perm_store(pnext);
       __syncthreads();
     }
     // ---------------------------------------------------------- N backward
+    // x_k = U(k,k)^{-1} v, v = y_k - U(k,k+1) x_{k+1} - U(k,k+2) x_{k+2};
+    // x_{k+1} leaves for the output while step k runs
     cx<R>* X1 = S;
-    cx<R>* X2 = S + NB * T;
-    cx<R>* V = S + 2 * NB * T;
-    for (int e = t; e < 2 * NB * T; e += nthr) S[e] = mk<R>(0, 0);
+    cx<R>* X2 = S + SL;
+    cx<R>* V = S + 2 * SL;
+    zero_slots(S, 2);
     // fa = U(k,k+1), fb = U(k,k+2), fc = U(k,k)^{-1}, pv = y_k: prefetched
     if (PREF) frag_load<R, NB, false>(fc, blk(K - 1, 2), w, lane, up_tri, NB);
     pre_load(pvm, mid, jb.ldmid, K - 1);
@@ -394,9 +397,10 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
       if (!PREF && k + 1 < K) frag_load<R, NB, false>(fa, blk(k, 3), w, lane, 0, NB);
       if (!PREF && k + 2 < K) frag_load<R, NB, false>(fb, blk(k, 4), w, lane, 0, lo_tri);
       pre_to_acc(acc, pvm);
-      if (k + 1 < K) frag_mma<R, NB, NC, false, true>(acc, fa, X1, T, nullptr, cb0, lane, 0, NB);
-      if (k + 2 < K) frag_mma<R, NB, NC, false, true>(acc, fb, X2, T, nullptr, cb0, lane, 0, lo_tri);
-      acc_to_lds(acc, V, T, nullptr, w, cb0, lane);
+      if (k + 1 < K) frag_mma<R, NB, NC, false, true>(acc, fa, X1, LDT, nullptr, cb0, lane, 0, NB);
+      if (k + 2 < K) frag_mma<R, NB, NC, false, true>(acc, fb, X2, LDT, nullptr, cb0, lane, 0, lo_tri);
+      acc_to_lds(acc, V, LDT, nullptr, w, cb0, lane);
+      if (k + 1 < K) emit_tile(X1, (int64_t)(k + 1) * NB);
       __syncthreads();
       if (k > 0) {
         if (PREF && k < K) frag_load<R, NB, false>(fa, blk(k - 1, 3), w, lane, 0, NB);
@@ -405,21 +409,23 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
       }
       if (!PREF) frag_load<R, NB, false>(fc, blk(k, 2), w, lane, up_tri, NB);
       acc.zero();
-      frag_mma<R, NB, NC, false, false>(acc, fc, V, T, nullptr, cb0, lane, up_tri, NB);
+      frag_mma<R, NB, NC, false, false>(acc, fc, V, LDT, nullptr, cb0, lane, up_tri, NB);
       if (PREF && k > 0) frag_load<R, NB, false>(fc, blk(k - 1, 2), w, lane, up_tri, NB);
-      acc_emit(acc, (int64_t)k * NB);
-      acc_to_lds(acc, X2, T, nullptr, w, cb0, lane);
+      acc_to_lds(acc, X2, LDT, nullptr, w, cb0, lane);
       __syncthreads();
       cx<R>* tmp = X1;
       X1 = X2;
       X2 = tmp;
     }
+    emit_tile(X1, 0);
   } else {
     // ---------------------------------------------------------- H forward (U^H)
+    // w_k = U(k,k)^{-H} v, v = y_k - U(k-1,k)^H w_{k-1} - U(k-2,k)^H w_{k-2};
+    // w_{k-1} leaves for the intermediate while step k runs
     cx<R>* W1 = S;
-    cx<R>* W2 = S + NB * T;
-    cx<R>* V = S + 2 * NB * T;
-    for (int e = t; e < 2 * NB * T; e += nthr) S[e] = mk<R>(0, 0);
+    cx<R>* W2 = S + SL;
+    cx<R>* V = S + 2 * SL;
+    zero_slots(S, 2);
     // fa = U(k-1,k)^H, fb = U(k-2,k)^H, fc = U(k,k)^{-H}, pv = y_k
     if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(0, 2), w, lane, 0, lo_tri);
     pre_load(pvi, in, jb.ldin, 0);
@@ -428,9 +434,10 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
       if (!PREF && k >= 1) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k - 1, 3), w, lane, 0, NB);
       if (!PREF && k >= 2) frag_load<R, NB, true, const cx<R>*, TS>(fb, blkh(k - 2, 4), w, lane, up_tri, NB);
       pre_to_acc(acc, pvi);
-      if (k >= 1) frag_mma<R, NB, NC, true, true>(acc, fa, W1, T, nullptr, cb0, lane, 0, NB);
-      if (k >= 2) frag_mma<R, NB, NC, true, true>(acc, fb, W2, T, nullptr, cb0, lane, up_tri, NB);
-      acc_to_lds(acc, V, T, nullptr, w, cb0, lane);
+      if (k >= 1) frag_mma<R, NB, NC, true, true>(acc, fa, W1, LDT, nullptr, cb0, lane, 0, NB);
+      if (k >= 2) frag_mma<R, NB, NC, true, true>(acc, fb, W2, LDT, nullptr, cb0, lane, up_tri, NB);
+      acc_to_lds(acc, V, LDT, nullptr, w, cb0, lane);
+      if (k >= 1) put_mid(W1, (int64_t)(k - 1) * NB);
       __syncthreads();
       if (k + 1 < K) {
         if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k, 3), w, lane, 0, NB);
@@ -439,92 +446,76 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
       }
       if (!PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(k, 2), w, lane, 0, lo_tri);
       acc.zero();
-      frag_mma<R, NB, NC, true, false>(acc, fc, V, T, nullptr, cb0, lane, 0, lo_tri);
+      frag_mma<R, NB, NC, true, false>(acc, fc, V, LDT, nullptr, cb0, lane, 0, lo_tri);
       if (PREF && k + 1 < K) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(k + 1, 2), w, lane, 0, lo_tri);
-      acc_to_g(acc, mid, jb.ldmid, (int64_t)k * NB);
-      acc_to_lds(acc, W2, T, nullptr, w, cb0, lane);
+      acc_to_lds(acc, W2, LDT, nullptr, w, cb0, lane);
       __syncthreads();
       cx<R>* tmp = W1;
       W1 = W2;
       W2 = tmp;
     }
+    put_mid(W1, (int64_t)(K - 1) * NB);
+    __syncthreads();
     // ---------------------------------------------------------- H backward (L^H)
-    // Three rotating blocks: the carry (window bottom), the L^H step's
-    // intermediate and the window top.  The intermediate block is dead once
-    // the window top is formed, so it receives the next carry, and the two
-    // exchange roles for the next step.
-    cx<R>* Vt = S;               // top of the window after the L^H step
-    cx<R>* T1 = S + NB * T;      // intermediate, then the next carry
-    cx<R>* Cb = S + 2 * NB * T;  // carry: window bottom
-    for (int e = t; e < NB * T; e += nthr) Cb[e] = mk<R>(0, 0);
+    // top = Lh11^{-H} w_k - M^H carry from w_k and the carry in LDS; then
+    // x_win = P^T [top ; carry], taken row by row through the inverse
+    // permutation: window row si[d] lands on row d, rows d >= NB leave for the
+    // output and rows d < NB form the next carry in the slot w_k held, and
+    // w_{k-1} goes to the slot of the old carry.
+    cx<R>* Cb = S;           // carry: window bottom
+    cx<R>* Wk = S + SL;      // w_k, then the next carry
+    cx<R>* Vt = S + 2 * SL;  // top of the window after the step
+    zero_slots(Cb, 1);
+    {
+      TileR f0;
+      tile_issue(f0, mid, jb.ldmid, (int64_t)(K - 1) * NB);
+      tile_store(f0, Wk, (int64_t)(K - 1) * NB);
+    }
     load_perm(K - 1);
-    // fa = Lh21^H, fc = (Lh11^{-1})^H, pv = w_k
+    // fa = M^H, fc = (Lh11^{-1})^H
     if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(K - 1, 1), w, lane, 0, NB);
     if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(K - 1, 0), w, lane, up_tri, NB);
-    pre_load(pvm, mid, jb.ldmid, K - 1);
     __syncthreads();
     for (int k = K - 1; k >= 0; --k) {
-      if (!PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k, 1), w, lane, 0, NB);
-      pre_to_acc(acc, pvm);
-      frag_mma<R, NB, NC, true, true>(acc, fa, Cb, T, nullptr, cb0, lane, 0, NB);
-      acc_to_lds(acc, T1, T, nullptr, w, cb0, lane);
-      __syncthreads();
-      PermPre pnext;
-      if (k > 0) {
-        if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k - 1, 1), w, lane, 0, NB);
-        pre_load(pvm, mid, jb.ldmid, k - 1);
-        perm_issue(pnext, k - 1);
-      }
       if (!PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(k, 0), w, lane, up_tri, NB);
       acc.zero();
-      frag_mma<R, NB, NC, true, false>(acc, fc, T1, T, nullptr, cb0, lane, up_tri, NB);
-      if (PREF && k > 0) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(k - 1, 0), w, lane, up_tri, NB);
-      acc_to_lds(acc, Vt, T, nullptr, w, cb0, lane);
+      frag_mma<R, NB, NC, true, false>(acc, fc, Wk, LDT, nullptr, cb0, lane, up_tri, NB);
+      if (!PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k, 1), w, lane, 0, NB);
+      frag_mma<R, NB, NC, true, true>(acc, fa, Cb, LDT, nullptr, cb0, lane, 0, NB);
+      TileR fw;
+      PermPre pnext;
+      if (k > 0) {
+        tile_issue(fw, mid, jb.ldmid, (int64_t)(k - 1) * NB);
+        perm_issue(pnext, k - 1);
+        if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k - 1, 1), w, lane, 0, NB);
+        if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(k - 1, 0), w, lane, up_tri, NB);
+      }
+      acc_to_lds(acc, Vt, LDT, nullptr, w, cb0, lane);
       __syncthreads();
-      // x_win = P^T [top ; carry]: rows that leave the window are emitted,
-      // the others form the next carry in T1
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        int64_t rows[RF];
-        int cols[RF];
-        cx<R> vals[RF];
-        bool valid[RF];
+      {
+        cx<R> carry[RF], leave[RF];
 #pragma unroll
         for (int q = 0; q < RF; ++q) {
-          const int e = t + (h * RF + q) * NTHR;
-          const int i = e / T, col = e % T;
-          const cx<R> v = i < NB ? Vt[i * T + col] : Cb[(i - NB) * T + col];
-          const int d = sp[i];
-          valid[q] = d >= NB;
-          rows[q] = (int64_t)k * NB + d;
-          cols[q] = col;
-          vals[q] = v;
-          if (d < NB) T1[d * T + col] = v;
+          const int r = erow(q), col = ecol(q);
+          const int ic = si[r], il = si[NB + r];
+          carry[q] = ic < NB ? Vt[ic * LDT + col] : Cb[(ic - NB) * LDT + col];
+          leave[q] = il < NB ? Vt[il * LDT + col] : Cb[(il - NB) * LDT + col];
         }
-        emit_batch(rows, cols, vals, valid);
-      }
-      __syncthreads();
-      cx<R>* tmp = Cb;
-      Cb = T1;
-      T1 = tmp;
-      if (k > 0) perm_store(pnext);
-      __syncthreads();
-    }
-    {
-      int64_t rows[RF];
-      int cols[RF];
-      cx<R> vals[RF];
-      bool valid[RF];
 #pragma unroll
-      for (int q = 0; q < RF; ++q) {
-        const int e = t + q * NTHR;
-        valid[q] = true;
-        rows[q] = e / T;
-        cols[q] = e % T;
-        vals[q] = Cb[e];
+        for (int q = 0; q < RF; ++q) Wk[erow(q) * LDT + ecol(q)] = carry[q];
+        emit_vals(leave, (int64_t)k * NB + NB);
       }
-      emit_batch(rows, cols, vals, valid);
+      __syncthreads();
+      if (k > 0) {
+        tile_store(fw, Cb, (int64_t)(k - 1) * NB);
+        perm_store(pnext);
+      }
+      cx<R>* tmp = Cb;
+      Cb = Wk;
+      Wk = tmp;
+      __syncthreads();
     }
+    emit_tile(Cb, 0);
   }
 }
 

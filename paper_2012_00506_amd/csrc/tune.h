@@ -12,10 +12,11 @@ constexpr int kNumVariants = 8;
 inline int variant_tile(int v) { return (v >= 2 && v < 6) ? 32 : 16; }
 inline bool variant_prefetch(int v) { return (v & 1) != 0; }
 inline int variant_nc(int v) { return (v == 4 || v == 5) ? 2 : 1; }
-// dynamic LDS of the block-solve kernel: 2 NB permutation entries and three
-// NB x T blocks of the factors' element type
+// dynamic LDS of the block-solve kernel: the block's permutation and its
+// inverse (2 NB entries each) and three NB x T slots of the factors' element
+// type with rows padded to T + 1
 inline size_t solve_lds_bytes(int nb, int t, size_t elem) {
-  return ((2 * (size_t)nb * sizeof(int) + 15) & ~(size_t)15) + (size_t)3 * nb * t * elem;
+  return ((4 * (size_t)nb * sizeof(int) + 15) & ~(size_t)15) + (size_t)3 * nb * (t + 1) * elem;
 }
 bool variant_fits(size_t rsize, int nb, int v);
 int tuned_variant(size_t rsize, int nb);
