@@ -278,10 +278,12 @@ def main():
     cols_per_step = float(sum(m0) * n_nodes * ndir)
     setup_s = time.perf_counter() - t_setup
 
-    # tune the block-solve kernel for both precisions on this shape (not timed)
+    # tune the block-solve kernel for both precisions on this shape (not timed):
+    # every system of a sweep, enough columns that each variant fills the GPU
+    # several times over as the sweep's launches do
     tuned = {}
     for prec in (1, 0):
-        v, ms = fb.autotune(B, prec, nsys=len(m0), m=int(max(m0)), cache_path=args.tune_log)
+        v, ms = fb.autotune(B, prec, nsys=len(m0) * n_nodes, m=512, cache_path=args.tune_log)
         tuned["c64" if prec else "c128"] = {"variant": v, "ms": ms}
 
     res = {}

@@ -55,16 +55,21 @@ template int solve_tile<double>(int);
 // conj(z) for A^H x = y), with B in block-tridiagonal form:
 // (B x)_k = B(k,k-1) x_{k-1} + B(k,k) x_k + B(k,k+1) x_{k+1}, each an NB x NB
 // by NB x T product on f64 MFMA (three real products per complex one), one
-// wave per 16 x 16 output tile.  x blocks roll through three LDS slots.  Per
-// (job, column): sum |r|^2 and sum |y|^2.
+// wave per 16 x 16 output tile.  x blocks roll through three LDS slots and a
+// fourth holds y_k, then r_k; tiles enter and leave global memory with thread
+// e on row e % NB, column e / NB, so that a wave moves whole column runs.
+// Per (job, column): sum |r|^2 and sum |y|^2.
 template <int NB, int T>
 __global__ void __launch_bounds__(NB * 4 * (T / 16))
 k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* __restrict__ jobs,
                  int njobs, double* __restrict__ part, const int32_t* __restrict__ gate) {
-  constexpr int NRW = NB / 16, NW = NRW * (T / 16);
+  constexpr int LDT = T + 1;    // LDS row of a slot
+  constexpr int SL = NB * LDT;  // one slot
+  constexpr int NTH = NB * 4 * (T / 16);
+  constexpr int RX = NB * T / NTH;  // tile elements per thread
   extern __shared__ __align__(16) char lds_raw[];
-  c128* X = reinterpret_cast<c128*>(lds_raw);              // 3 slots of NB x T
-  double* red = reinterpret_cast<double*>(X + 3 * NB * T);  // 2 x NW x 16
+  c128* X = reinterpret_cast<c128*>(lds_raw);  // 3 slots of x blocks
+  c128* Yr = X + 3 * SL;                       // y_k, overwritten by r_k
   const int job = remap_job(blockIdx.x, njobs);
   if (job >= njobs) return;
   const ResJob jb = jobs[job];
@@ -72,105 +77,95 @@ k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* 
   const c128* jx = jb.x;
   const c128* jy = jb.y;
   c128* jr = jb.r;
-  const c128* Bg = Bblk;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  constexpr int NRW = NB / 16;
   const int w = __builtin_amdgcn_readfirstlane(wv % NRW);
   const int cb0 = __builtin_amdgcn_readfirstlane(16 * (wv / NRW));
-  const int nthr = NB * 4 * (T / 16);
   const int c0 = jb.col0;
   const int nc = jb.ncol;
   const size_t bb = (size_t)NB * NB;
   const c128 zz = jb.dir ? mk(jb.z.x, -jb.z.y) : jb.z;
+  // tile element q of this thread: row e % NB, column e / NB (one column
+  // per wave and q)
+  auto erow = [&](int q) { return (t + q * NTH) % NB; };
+  auto ecol = [&](int q) { return (t + q * NTH) / NB; };
+  auto ok = [&](int k, int q) {
+    const int64_t i = (int64_t)k * NB + erow(q);
+    return k < K && i < n && ecol(q) < nc;
+  };
   // branch-free loads (clamped address, zeroed when stored), issued one
   // block row ahead so that their latency overlaps the products
-  constexpr int NTH = NB * 4 * (T / 16);
-  constexpr int RX = NB * T / NTH;
-  auto xok = [&](int k, int e) {
-    const int64_t i = (int64_t)k * NB + e / T;
-    return k < K && i < n && (e % T) < nc;
-  };
-  auto xaddr = [&](int k, int e) {
-    return jx + (xok(k, e) ? (int64_t)(c0 + e % T) * jb.ldx + (int64_t)k * NB + e / T : 0);
-  };
-  auto xissue = [&](c128* xr, int k) {
+  auto tissue = [&](c128* v, const c128* base, int64_t ld, int k) {
 #pragma unroll
-    for (int q = 0; q < RX; ++q) xr[q] = gld(xaddr(k, t + q * NTH));
+    for (int q = 0; q < RX; ++q)
+      v[q] = gld(base + (ok(k, q) ? (int64_t)(c0 + ecol(q)) * ld + (int64_t)k * NB + erow(q) : 0));
   };
-  auto xstore = [&](const c128* xr, int k, int slot) {
+  auto tstore = [&](const c128* v, c128* dst, int k) {
 #pragma unroll
-    for (int q = 0; q < RX; ++q) {
-      const int e = t + q * NTH;
-      X[slot * NB * T + e] = xok(k, e) ? xr[q] : mk(0.0, 0.0);
-    }
+    for (int q = 0; q < RX; ++q) dst[erow(q) * LDT + ecol(q)] = ok(k, q) ? v[q] : mk(0.0, 0.0);
   };
+  for (int e = t; e < SL; e += NTH) X[2 * SL + e] = mk(0.0, 0.0);  // x_{-1}
+  c128 xr[RX], yv[RX];
+  double rr[RX], yy[RX];
+#pragma unroll
+  for (int q = 0; q < RX; ++q) rr[q] = yy[q] = 0.0;
+  tissue(xr, jx, jb.ldx, 0);
+  tstore(xr, X, 0);
+  tissue(xr, jx, jb.ldx, 1);
+  tissue(yv, jy, jb.ldy, 0);
   const int col = cb0 + (lane & 15);
-  auto yok = [&](int k, int r) {
-    const int64_t i = (int64_t)k * NB + 16 * w + MF<double>::row(lane, r);
-    return i < n && col < nc;
-  };
-  auto yissue = [&](c128* yr, int k) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t i = (int64_t)k * NB + 16 * w + MF<double>::row(lane, r);
-      yr[r] = gld(jy + (yok(k, r) ? (int64_t)(c0 + col) * jb.ldy + i : 0));
-    }
-  };
-  for (int e = t; e < NB * T; e += nthr) X[2 * NB * T + e] = mk(0.0, 0.0);  // x_{-1}
-  c128 xr[RX], yr[4], yn[4];
-  xissue(xr, 0);
-  xstore(xr, 0, 0);
-  xissue(xr, 1);
-  yissue(yr, 0);
-  double rr = 0.0, yy = 0.0;
   for (int k = 0; k < K; ++k) {
-    xstore(xr, k + 1, (k + 1) % 3);
+    tstore(xr, X + ((k + 1) % 3) * SL, k + 1);
+    tstore(yv, Yr, k);
+#pragma unroll
+    for (int q = 0; q < RX; ++q)
+      if (ok(k, q)) yy[q] += cabs2(yv[q]);
     __syncthreads();
-    if (k + 2 <= K) xissue(xr, k + 2);
-    if (k + 1 < K) yissue(yn, k + 1);
-    const c128* Xk = X + (k % 3) * NB * T;
+    if (k + 2 <= K) tissue(xr, jx, jb.ldx, k + 2);
+    if (k + 1 < K) tissue(yv, jy, jb.ldy, k + 1);
+    const c128* Xk = X + (k % 3) * SL;
     // (B x)_k by the three block products, then r = y - zz x + B x
     Acc<double, 1> acc;
     acc.zero();
-    const c128* Bk = Bg + (size_t)k * 3 * bb;
+    const c128* Bk = Bblk + (size_t)k * 3 * bb;
     if (k > 0)
-      wave_prod<double, NB, 1, false, false>(acc, Bk, X + ((k + 2) % 3) * NB * T, T, nullptr, w,
+      wave_prod<double, NB, 1, false, false>(acc, Bk, X + ((k + 2) % 3) * SL, LDT, nullptr, w,
                                              cb0, lane, 16 * w, NB);
-    wave_prod<double, NB, 1, false, false>(acc, Bk + bb, Xk, T, nullptr, w, cb0, lane, 0, NB);
+    wave_prod<double, NB, 1, false, false>(acc, Bk + bb, Xk, LDT, nullptr, w, cb0, lane, 0, NB);
     if (k + 1 < K)
-      wave_prod<double, NB, 1, false, false>(acc, Bk + 2 * bb, X + ((k + 1) % 3) * NB * T, T,
+      wave_prod<double, NB, 1, false, false>(acc, Bk + 2 * bb, X + ((k + 1) % 3) * SL, LDT,
                                              nullptr, w, cb0, lane, 0, 16 * w + 16);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * w + MF<double>::row(lane, r);
-      const int64_t i = (int64_t)k * NB + row;
-      const c128 yv = yok(k, r) ? yr[r] : mk(0.0, 0.0);
-      yy += cabs2(yv);
-      if (i < n && col < nc) {
-        const c128 v = yv - zz * Xk[row * T + col] + acc.get(0, r);
-        gst(jr + (int64_t)(c0 + col) * jb.ldr + i, v);
-        rr += cabs2(v);
-      }
+      c128* p = Yr + row * LDT + col;
+      *p = *p - zz * Xk[row * LDT + col] + acc.get(0, r);
     }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) yr[r] = yn[r];
     __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RX; ++q) {
+      if (!ok(k, q)) continue;
+      const c128 v = Yr[erow(q) * LDT + ecol(q)];
+      gst(jr + (int64_t)(c0 + ecol(q)) * jb.ldr + (int64_t)k * NB + erow(q), v);
+      rr[q] += cabs2(v);
+    }
   }
-  // column sums: lanes l, l+16, l+32, l+48 share a column; then across row waves
-  for (int off = 16; off < 64; off <<= 1) {
-    rr += __shfl_xor(rr, off, 64);
-    yy += __shfl_xor(yy, off, 64);
-  }
-  if (lane < 16) {
-    red[(0 * NW + wv) * 16 + lane] = rr;
-    red[(1 * NW + wv) * 16 + lane] = yy;
+  // column sums in a fixed order: per-element partial sums through LDS (the
+  // x slots are free), then one thread per column adds its NB rows
+  __syncthreads();
+  double* red = reinterpret_cast<double*>(X);  // 2 x T columns x NB rows
+#pragma unroll
+  for (int q = 0; q < RX; ++q) {
+    const int e = t + q * NTH;
+    red[e] = rr[q];
+    red[NB * T + e] = yy[q];
   }
   __syncthreads();
   if (t < T) {
-    const int cw = t / 16, l = t % 16;
     double sr = 0.0, sy = 0.0;
-    for (int q = 0; q < NRW; ++q) {
-      sr += red[(0 * NW + cw * NRW + q) * 16 + l];
-      sy += red[(1 * NW + cw * NRW + q) * 16 + l];
+    for (int i = 0; i < NB; ++i) {
+      sr += red[t * NB + i];
+      sy += red[NB * T + t * NB + i];
     }
     part[((size_t)job * 32 + t) * 2] = sr;
     part[((size_t)job * 32 + t) * 2 + 1] = sy;
@@ -212,7 +207,7 @@ template <int NB>
 static int launch_res_nb(const Band& bd, int njobs, const ResJob* jobs_dev, double* part,
                          const int32_t* gate, hipStream_t st) {
   constexpr int T = NB <= 64 ? 32 : 16;
-  size_t smem = (size_t)3 * NB * T * sizeof(c128) + 2 * (NB / 16) * (T / 16) * 16 * sizeof(double);
+  size_t smem = (size_t)4 * NB * (T + 1) * sizeof(c128);
   (void)hipFuncSetAttribute((const void*)k_shift_residual<NB, T>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   (void)hipGetLastError();
