@@ -323,6 +323,25 @@ int slice_plan_prev(const fb_band* B, const double* prev, int64_t nprev,
                     int32_t* K_out, int32_t* n_inertia, void* work, size_t* lwork,
                     void* stream);
 
+/* Boundary certification for a matrix of a sequence whose slices were placed
+ * on an earlier one (the per-slice validation of Section 3.2 before FEAST
+ * runs on the new matrix): bounds[i] (host, nb ascending doubles, in/out)
+ * is replaced by the first of s = bounds[i] + 2 d k, k = 0, 1, -1, ..., 32,
+ * -32 (d = cert_delta ||B||_1) with n_-(s - d) = n_-(s + d), so that no
+ * eigenvalue lies within d of it.  neg (host, nb) receives n_-(bounds[i]),
+ * counts (host, nb - 1) the exact slice counts neg[i+1] - neg[i], and m0
+ * (host, nb - 1, or NULL) the subspace sizes fb_m0_rule(counts[i]).
+ * n_inertia (host or NULL): inertia evaluations used.  Returns 0,
+ * FB_ERR_CERTIFY when a boundary cannot be certified or two of them meet,
+ * or a negative argument index. */
+int slice_certify(const fb_band* B, int32_t nb, double* bounds, double cert_delta,
+                  int32_t* neg, int32_t* counts, int32_t* m0, int32_t* n_inertia,
+                  void* work, size_t* lwork, void* stream);
+/* Subspace size for a slice of m eigenvalues: max(ceil(1.5 m), m + 10) (the
+ * paper's rule of a margin over the count, Section 3.2, with the 1.5 factor
+ * of the configurations); -1 for m < 0.  Host only. */
+int32_t fb_m0_rule(int32_t m);
+
 /* Filter application only (the shifted solves of one FEAST iteration,
  * Section 2.2, eq:feast_L2 and the quadrature sum Q = sum_j w_j Q^(j)):
  * factor z_j I - B for every node of every slice, solve with Y[i]

@@ -67,6 +67,9 @@ SIGNATURES = {
                              PSZ, P]),
     "slice_plan_prev": (C.c_int, [C.POINTER(fb_band), PD, C.c_int64, C.POINTER(fb_prev_opts), PD,
                                   PI32, PI32, PI32, P, PSZ, P]),
+    "slice_certify": (C.c_int, [C.POINTER(fb_band), C.c_int32, PD, C.c_double, PI32, PI32, PI32,
+                                PI32, P, PSZ, P]),
+    "fb_m0_rule": (C.c_int32, [C.c_int32]),
     "feast_filter": (C.c_int, [C.POINTER(fb_band), C.c_int32, PD, PD, PI32, C.POINTER(P), PI64,
                                C.POINTER(P), PI64, PD, PI32, C.POINTER(fb_feast_opts), P, PSZ, P]),
     "band_rayleigh_ritz": (C.c_int, [C.POINTER(fb_band), C.c_int32, PI32, C.POINTER(P), PI64,

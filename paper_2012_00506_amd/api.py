@@ -11,6 +11,7 @@ vectors are (n, m) tensors in column-major storage (``colmajor``).
 from __future__ import annotations
 
 import ctypes as C
+import math
 from dataclasses import dataclass
 
 import numpy as np
@@ -189,10 +190,17 @@ def contour_nodes(lo, hi, k=8, rule="gauss", ratio=1.0):
 
 def feast_band_slice(B, lo, hi, Y, m_expected=None, n_nodes=8, tol=1e-10, max_iter=20,
                      precision=0, ir_tol=1e-12, ir_max=8, batched=True, hbm_budget=0.0,
-                     pairs=0, rule="gauss", ratio=1.0, tune_cache=None, stream=None):
+                     pairs=0, rule="gauss", ratio=1.0, tune_cache=None, rerun=True,
+                     stream=None):
     """FEAST on the slices [lo_i, hi_i) of B from the start blocks Y[i]
     ((n, m0_i) column-major device tensors in the dtype of B; overwritten with
-    the Ritz vectors).  Returns one SliceResult per slice."""
+    the Ritz vectors).  Returns one SliceResult per slice.
+
+    rerun: a slice that ends with info 2 (count mismatch) or 5 (m0 < m) is
+    run once more (the rerun with more start vectors of Section 3.2) from a
+    new block of m0' = ceil(1.5 max(m, m_found)) + 10 columns: its Ritz
+    vectors first, then seeded random columns.  That slice's SliceResult
+    then refers to the new block, not to Y[i]."""
     B = _as_band(B)
     lo = np.ascontiguousarray(np.asarray(lo, dtype=np.float64).ravel())
     hi = np.ascontiguousarray(np.asarray(hi, dtype=np.float64).ravel())
@@ -235,6 +243,35 @@ def feast_band_slice(B, lo, hi, Y, m_expected=None, n_nodes=8, tol=1e-10, max_it
     for i in range(ns):
         out.append(SliceResult(float(lo[i]), float(hi[i]), int(mf[i]), int(its[i]), int(inf[i]),
                                ev[i].cpu().numpy(), rs[i].cpu().numpy(), Y[i]))
+    redo = [i for i in range(ns) if out[i].info in (2, 5)]
+    if rerun and redo:
+        if mexp is None:
+            edges = np.concatenate([lo[redo], hi[redo]])
+            neg, _, _ = band_inertia(B, edges, stream=stream)
+            m_exact = neg[len(redo):] - neg[:len(redo)]
+        else:
+            m_exact = mexp[redo]
+        Y2 = []
+        for a, i in enumerate(redo):
+            m_new = math.ceil(1.5 * max(int(m_exact[a]), out[i].m_found)) + 10
+            m_new = min(m_new, B.n)
+            keep = min(int(m0[i]), m_new)
+            y = torch.empty((m_new, B.n), dtype=want, device=dev).t()  # column-major
+            y[:, :keep] = Y[i][:, :keep]
+            if m_new > keep:
+                g = torch.Generator(device=dev)
+                g.manual_seed(7919 * (i + 1) + m_new)
+                fill = torch.randn((m_new - keep, B.n), generator=g, device=dev,
+                                   dtype=torch.float64 if not B.complex_ else torch.complex128)
+                y[:, keep:] = fill.t()
+            Y2.append(y)
+        res2 = feast_band_slice(B, lo[redo], hi[redo], Y2, m_expected=np.asarray(m_exact),
+                                n_nodes=n_nodes, tol=tol, max_iter=max_iter,
+                                precision=precision, ir_tol=ir_tol, ir_max=ir_max,
+                                batched=batched, hbm_budget=hbm_budget, pairs=pairs, rule=rule,
+                                ratio=ratio, tune_cache=tune_cache, rerun=False, stream=stream)
+        for a, i in enumerate(redo):
+            out[i] = res2[a]
     return out
 
 
@@ -354,6 +391,35 @@ def slice_plan_prev(B, prev, nev, K, alpha=1e-3, m1=6, cert_delta=1e-8, max_swee
                                                  sh))
     k = int(kout.value)
     return bounds[:k + 1], counts[:k], int(nev_.value)
+
+
+def m0_rule(m: int) -> int:
+    """Subspace size for a slice of m eigenvalues (fb_m0_rule)."""
+    return int(N.lib().fb_m0_rule(int(m)))
+
+
+def slice_certify(B, bounds, cert_delta=1e-8, stream=None):
+    """Certified copies of ``bounds`` on B (slice_certify): returns (bounds,
+    n_-(bounds), exact counts, m0 per slice, inertia evaluations)."""
+    B = _as_band(B)
+    b = np.ascontiguousarray(np.asarray(bounds, np.float64).copy())
+    nb = b.size
+    neg = np.zeros(nb, np.int32)
+    counts = np.zeros(max(nb - 1, 1), np.int32)
+    m0 = np.zeros(max(nb - 1, 1), np.int32)
+    nin = C.c_int32(0)
+    bs = B.struct()
+    L = N.lib()
+    sh = C.c_void_p(_stream_handle(stream))
+    args = (C.byref(bs), nb, b.ctypes.data_as(N.PD), float(cert_delta),
+            neg.ctypes.data_as(N.PI32), counts.ctypes.data_as(N.PI32),
+            m0.ctypes.data_as(N.PI32), C.byref(nin))
+    lw = C.c_size_t(0)
+    N.check("slice_certify", L.slice_certify(*args, None, C.byref(lw), sh))
+    ws = _workspace(None, lw, B.data.device)
+    lw2 = C.c_size_t(ws.numel())
+    N.check("slice_certify", L.slice_certify(*args, C.c_void_p(ws.data_ptr()), C.byref(lw2), sh))
+    return b, neg, counts[:nb - 1], m0[:nb - 1], int(nin.value)
 
 
 @dataclass

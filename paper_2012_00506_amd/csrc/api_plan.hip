@@ -477,3 +477,58 @@ extern "C" int slice_plan_prev(const fb_band* B, const double* prev, int64_t npr
   if (n_inertia) *n_inertia = ir.evals;
   return 0;
 }
+
+extern "C" int32_t fb_m0_rule(int32_t m) {
+  if (m < 0) return -1;
+  const int64_t a = ((int64_t)3 * m + 1) / 2;  // ceil(1.5 m)
+  const int64_t v = std::max<int64_t>(a, (int64_t)m + 10);
+  return v > INT32_MAX ? INT32_MAX : (int32_t)v;
+}
+
+extern "C" int slice_certify(const fb_band* B, int32_t nb, double* bounds, double cert_delta,
+                             int32_t* neg, int32_t* counts, int32_t* m0, int32_t* n_inertia,
+                             void* work, size_t* lwork, void* stream) {
+  if (check_band(B)) return -1;
+  if (nb < 1 || nb > (1 << 20)) return -2;
+  if (!bounds) return -3;
+  for (int i = 0; i < nb; ++i)
+    if (!isfinite(bounds[i]) || (i > 0 && !(bounds[i] > bounds[i - 1]))) return -3;
+  if (!(cert_delta >= 0) || !isfinite(cert_delta)) return -4;
+  if (!neg) return -5;
+  if (nb > 1 && !counts) return -6;
+  if (!lwork) return -10;
+  hipStream_t st = (hipStream_t)stream;
+  Arena ar;
+  ar.base = (char*)work;
+  ar.cap = *lwork;
+  Band bd;
+  FB_TRY(ingest_band(B, bd, ar, st));
+  const int cap = 2 * nb;
+  double* sh = ar.take<double>(cap);
+  int32_t* cnt = ar.take<int32_t>(3 * (size_t)cap);
+  size_t scb = inertia_scratch_bytes(bd, cap);
+  void* scratch = scb ? (void*)ar.take<char>(scb) : nullptr;
+  if (work == nullptr) {
+    *lwork = ar.used;
+    return 0;
+  }
+  if (!ar.fits()) return FB_ERR_NOMEM;
+  double stats[3];
+  FB_TRY(band_stats_host(bd, stats, st));
+  InertiaRunner ir{&bd, sh, cnt, scratch, cap, st};
+  std::vector<double> edges(bounds, bounds + nb);
+  std::vector<int> ng;
+  FB_TRY(certify_all(ir, edges, cert_delta * stats[0], ng));
+  for (int i = 0; i + 1 < nb; ++i)
+    if (!(edges[i + 1] > edges[i])) return FB_ERR_CERTIFY;  // two boundaries met
+  for (int i = 0; i < nb; ++i) {
+    bounds[i] = edges[i];
+    neg[i] = ng[i];
+  }
+  for (int i = 0; i + 1 < nb; ++i) {
+    counts[i] = ng[i + 1] - ng[i];
+    if (m0) m0[i] = fb_m0_rule(counts[i]);
+  }
+  if (n_inertia) *n_inertia = ir.evals;
+  return 0;
+}

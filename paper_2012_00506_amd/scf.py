@@ -32,37 +32,15 @@ from . import api
 
 
 def m0_rule(m: int) -> int:
-    return max(math.ceil(1.5 * m), m + 10)
+    """Subspace size of a slice of m eigenvalues (fb_m0_rule in the library)."""
+    return api.m0_rule(m)
 
 
-def certify(B, bounds, cert_delta=1e-8, max_tries=64):
-    """Certified copies of the boundaries on B and n_-(s) at each (one batched
-    inertia launch per try round)."""
-    B = api._as_band(B)
-    _, g = api.cheb_moments(B, K=0, P=1)
-    delta = cert_delta * g[2]
-    base = np.asarray(bounds, np.float64)
-    out = base.copy()
-    neg = np.zeros(len(base), np.int64)
-    open_ = np.ones(len(base), bool)
-    tries = np.zeros(len(base), np.int64)
-    for _ in range(max_tries + 1):
-        idx = np.nonzero(open_)[0]
-        if len(idx) == 0:
-            return out, neg
-        k = np.where(tries[idx] == 0, 0.0,
-                     np.where(tries[idx] % 2 == 1, (tries[idx] + 1) // 2, -(tries[idx] // 2)))
-        c = base[idx] + 2.0 * delta * k
-        sh = np.empty(2 * len(idx))
-        sh[0::2] = c - delta
-        sh[1::2] = c + delta
-        n_, _, _ = api.band_inertia(B, sh)
-        ok = n_[0::2] == n_[1::2]
-        out[idx[ok]] = c[ok]
-        neg[idx[ok]] = n_[0::2][ok]
-        open_[idx[ok]] = False
-        tries[idx[~ok]] += 1
-    raise RuntimeError("a boundary could not be certified")
+def certify(B, bounds, cert_delta=1e-8):
+    """Certified copies of the boundaries on B and n_-(s) at each
+    (slice_certify in the library)."""
+    b, neg, _, _, _ = api.slice_certify(B, bounds, cert_delta)
+    return b, neg.astype(np.int64)
 
 
 @dataclass
@@ -139,11 +117,11 @@ class SliceSequence:
             bounds, counts, _ = api.slice_plan_prev(B, self.prev_pairs[0], self.replan_nev,
                                                     self.K)
             replanned = True
+            m0 = [m0_rule(int(c)) for c in counts]
         else:
-            bounds, neg = certify(B, self.bounds)
-            counts = np.diff(neg)
+            bounds, _, counts, m0, _ = api.slice_certify(B, self.bounds)
+            m0 = [int(v) for v in m0]
         self.bounds = np.asarray(bounds, np.float64)
-        m0 = [m0_rule(int(c)) for c in counts]
         Y = []
         for i, m in enumerate(m0):
             if replanned and self.warm:

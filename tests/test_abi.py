@@ -140,6 +140,37 @@ def test_slice_plan_prev_argument_errors_and_query(L):
     assert call() == 0 and lw.value > 0
 
 
+def test_slice_certify_argument_errors_and_query(L):
+    from paper_2012_00506_amd import _native as N
+    bs = _band(n=50, b=3)
+    bounds = np.array([-1.0, 0.0, 2.0])
+    neg = np.zeros(3, np.int32)
+    counts = np.zeros(2, np.int32)
+    lw = C.c_size_t(0)
+
+    def call(nb=3, b=bounds, d=1e-8, ng=neg, c=counts, lwp=C.byref(lw)):
+        bp = None if b is None else b.ctypes.data_as(N.PD)
+        return L.slice_certify(C.byref(bs), nb, bp, d, None if ng is None else
+                               ng.ctypes.data_as(N.PI32), None if c is None else
+                               c.ctypes.data_as(N.PI32), None, None, None, lwp, None)
+
+    assert call(nb=0) == -2
+    assert call(b=None) == -3
+    assert call(b=np.array([0.0, -1.0, 2.0])) == -3     # not ascending
+    assert call(b=np.array([0.0, np.nan, 2.0])) == -3
+    assert call(d=-1.0) == -4
+    assert call(ng=None) == -5
+    assert call(c=None) == -6
+    assert call(lwp=None) == -10
+    assert call() == 0 and lw.value > 0
+
+
+@pytest.mark.parametrize("m", [0, 1, 7, 19, 20, 21, 100, 1023])
+def test_m0_rule(L, m):
+    import math
+    assert L.fb_m0_rule(m) == max(math.ceil(1.5 * m), m + 10)
+
+
 def test_feast_filter_contour_options_checked(L):
     from paper_2012_00506_amd import _native as N
     n = 100

@@ -103,8 +103,23 @@ def test_feast_m0_below_count_flagged(fb):
     ab = synth.band_matrix(n, 4, 14, True, -6, 6)
     m = oin.count_in(ab, -2.0, 2.0)
     _, Y = start_block(fb, n, m - 5, 14, True)
-    [r] = fb.feast_band_slice(ab, [-2.0], [2.0], [Y])
+    [r] = fb.feast_band_slice(ab, [-2.0], [2.0], [Y], rerun=False)
     assert r.info == 5 and r.m_found == 0
+
+
+def test_feast_m0_below_count_rerun_once(fb):
+    """info 5 (m0 < m) triggers one rerun with ceil(1.5 m) + 10 columns, whose
+    result matches the dense eigenvalues."""
+    n = 200
+    ab = synth.band_matrix(n, 4, 14, True, -6, 6)
+    lam = np.linalg.eigvalsh(oband.dense_from_band(ab))
+    ref = lam[(lam >= -2.0) & (lam < 2.0)]
+    m = len(ref)
+    _, Y = start_block(fb, n, m - 5, 14, True)
+    [r] = fb.feast_band_slice(ab, [-2.0], [2.0], [Y])
+    assert r.info == 0 and r.m_found == m
+    assert r.Y.shape[1] == math.ceil(1.5 * m) + 10
+    assert np.abs(r.lam - ref).max() <= 1e-12 * oband.norm1(ab)
 
 
 @pytest.mark.parametrize("precision", [0, 1])

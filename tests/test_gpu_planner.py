@@ -291,3 +291,31 @@ def test_slice_plan_prev_parity(fb, n, b, cplx, nev, K):
     assert len(c) == rk <= K
     assert np.array_equal(e, re) and np.array_equal(c, rc) and ne == rne
     assert c.sum() >= nev
+
+
+def test_slice_certify_parity_and_moves(fb):
+    """slice_certify: counts equal the oracle's inertia at the certified
+    boundaries; a boundary placed exactly on an eigenvalue (diagonal B) is
+    moved off it by 2 delta k, the rest stay; m0 follows fb_m0_rule."""
+    n = 300
+    d = np.linspace(-5.0, 5.0, n)
+    ab = np.zeros((3, n), np.complex128)
+    ab[0] = d
+    nrm = oband.norm1(ab)
+    bounds = np.array([-4.0, d[100], 0.01, d[250], 4.9])
+    b2, neg, counts, m0, nin = fb.slice_certify(ab, bounds, cert_delta=1e-8)
+    delta = 1e-8 * nrm
+    assert b2[0] == bounds[0] and b2[2] == bounds[2] and b2[4] == bounds[4]
+    for i in (1, 3):
+        assert b2[i] != bounds[i] and abs(b2[i] - bounds[i]) <= 2 * delta * 32
+        assert np.abs(d - b2[i]).min() > delta
+    neg_o = np.array([oin.inertia(ab, float(s))[0] for s in b2])
+    assert np.array_equal(neg, neg_o)
+    assert np.array_equal(counts, np.diff(neg_o))
+    assert [int(v) for v in m0] == [fb.m0_rule(int(c)) for c in counts]
+    assert nin >= 2 * len(bounds)
+    # a random Hermitian band: certified boundaries keep the oracle's counts
+    ab = synth.band_matrix(700, 9, 61, True, -6, 6)
+    bounds = np.linspace(-5.0, 5.0, 9)
+    b2, neg, counts, _, _ = fb.slice_certify(ab, bounds)
+    assert np.array_equal(neg, [oin.inertia(ab, float(s))[0] for s in b2])
