@@ -30,6 +30,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# workloads whose slices are placed by exact inertia: (slices, lowest
+# eigenvalues covered, slices per filter group -- the factors of one group's
+# systems and its buffers stay well inside the 288 GB of HBM)
+PLANNED = {"cplx-n65536-b128": (64, 25600, 16)}
+# band sections above this order are sampled on the CPU by a leading section
+CPU_SECTION = 8192
+
 PEAK_FP32_MFMA = 157.3e12   # MI355X dense FP32 matrix, flop/s
 PEAK_FP64 = 78.6e12         # MI355X FP64 (vector and matrix), flop/s
 PEAK_HBM = 8.0e12           # bytes/s
@@ -105,7 +112,13 @@ def _cpu_system(args):
     import synth
     cfg = synth.CONFIGS[name]
     cfg_ab = cfg.matrix()
-    Y = synth.rhs_block(cfg.n, ncols, cfg.seed, cfg.complex_, col0=col0)
+    n = cfg.n
+    if n > CPU_SECTION:  # the leading principal section; times scale with n
+        n = CPU_SECTION
+        cfg_ab = cfg_ab[:, :n].copy()
+        for d in range(1, cfg_ab.shape[0]):
+            cfg_ab[d, n - d:] = 0
+    Y = synth.rhs_block(n, ncols, cfg.seed, cfg.complex_, col0=col0)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         F = bandlu.shifted_band_lu(cfg_ab, z)
@@ -113,10 +126,11 @@ def _cpu_system(args):
         bandlu.lu_solve(F, Y)
         bandlu.lu_solve_h(F, Y)
         t2 = time.perf_counter()
-    return t1 - t0, t2 - t1
+    scale = cfg.n / n
+    return (t1 - t0) * scale, (t2 - t1) * scale
 
 
-def cpu_baseline(cfg, m0_mean, ncols):
+def cpu_baseline(cfg, m0_mean, ncols, slices):
     """The CPU oracle on a bounded sample, on all host cores: one worker
     process per core, each factoring one shifted system of the workload (the
     nodes of the middle slice, then of further slices) and solving ncols N
@@ -128,9 +142,9 @@ def cpu_baseline(cfg, m0_mean, ncols):
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     cores = max(1, min(cores, 16))
     tasks = []
-    k = len(cfg.slices) // 2
+    k = len(slices) // 2
     while len(tasks) < cores:
-        lo, hi = cfg.slices[k % len(cfg.slices)]
+        lo, hi = slices[k % len(slices)]
         z, _ = quadrature.contour(lo, hi, 8)
         for zj in z:
             if len(tasks) < cores:
@@ -147,24 +161,35 @@ def cpu_baseline(cfg, m0_mean, ncols):
     t_sol = sum(t for _, t in times) / len(times)
     return {"value": value, "unit": "RHS-cols/s", "cores": cores, "kind": "oracle",
             "cpu_model": cpu_model(), "nproc": os.cpu_count(),
-            "sample": (f"{cores} shifted systems of the workload (n={cfg.n}, b={cfg.b}), one per "
+            "sample": (("" if cfg.n <= CPU_SECTION else
+                        f"leading n={CPU_SECTION} sections (times scaled by {cfg.n // CPU_SECTION}) "
+                        "of ") +
+                       f"{cores} shifted systems of the workload (n={cfg.n}, b={cfg.b}), one per "
                        f"core in parallel processes: oracle band LU {t_lu:.2f} s + {ncols} N and "
                        f"{ncols} H column solves {t_sol:.2f} s each (mean), {wall:.1f} s wall; "
                        f"per-system time scaled to {cols_sys:.0f} columns per system")}
 
 
-def run_path(fb, F, Y, Q, steps, warmup, cols_per_step, stream=None):
+def run_path(fb, groups, steps, warmup, cols_per_step, stream=None):
+    """Time the filter sweep: a step applies every group's filter (F, Y, Q)
+    once, in order."""
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
+
+    def sweep():
+        return [F(Y, Q, stream=s) for F, Y, Q in groups]
+
     # verification pass (not timed): every column's FP64 residual <= 1e-10
-    F.with_resid = True
-    r = F(Y, Q, stream=s)
+    for F, _, _ in groups:
+        F.with_resid = True
+    rs = sweep()
     torch.cuda.synchronize()
-    worst = float(np.max(r.resid))
-    passes = int(np.max(r.passes))
-    F.with_resid = False
+    worst = max(float(np.max(r.resid)) for r in rs)
+    passes = max(int(np.max(r.passes)) for r in rs)
+    for F, _, _ in groups:
+        F.with_resid = False
     for _ in range(warmup):
-        F(Y, Q, stream=s)
+        sweep()
     torch.cuda.synchronize()
     fb.profile_enable(True)
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -172,7 +197,7 @@ def run_path(fb, F, Y, Q, steps, warmup, cols_per_step, stream=None):
     t0 = time.perf_counter()
     ev0.record(s)
     for _ in range(steps):
-        F(Y, Q, stream=s)
+        sweep()
     ev1.record(s)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -236,7 +261,9 @@ def roofline(prof, precision, workload):
     if name == "solve":
         peak = PEAK_FP32_MFMA if precision == 1 else PEAK_FP64
         bound = "mfma"
-    elif name in ("resid", "bandmm", "inertia"):
+    elif name == "resid":   # FP64 MFMA products
+        peak, bound = PEAK_FP64, "mfma"
+    elif name in ("bandmm", "inertia"):
         peak, bound = PEAK_FP64, "alu"
     else:
         peak = PEAK_FP32_MFMA if precision == 1 else PEAK_FP64
@@ -263,12 +290,19 @@ def main():
     t_setup = time.perf_counter()
     ab = cfg.matrix()
     B = fb.DeviceBand.from_band(ab)
-    edges = [cfg.slices[0][0]] + [s[1] for s in cfg.slices]
+    if cfg.slices:
+        slices = list(cfg.slices)
+        group = len(slices)
+    else:  # equal-count slices of the lowest nev eigenvalues, by exact inertia
+        K, nev, group = PLANNED[cfg.name]
+        bounds, _, _ = fb.slice_plan(B, K, "equal_count", nev=nev)
+        slices = [(float(bounds[i]), float(bounds[i + 1])) for i in range(K)]
+    edges = [slices[0][0]] + [s[1] for s in slices]
     neg, _, _ = fb.band_inertia(B, edges)
     counts = np.diff(neg)
     m0 = [max(math.ceil(1.5 * int(c)), int(c) + 10) for c in counts]
-    lo = [s[0] for s in cfg.slices]
-    hi = [s[1] for s in cfg.slices]
+    lo = [s[0] for s in slices]
+    hi = [s[1] for s in slices]
     Y = [synth.rhs_block_device(cfg.n, m, cfg.seed * 1000 + i, cfg.complex_)
          for i, m in enumerate(m0)]
     Y = [y.contiguous().t().contiguous().t() if y.stride(0) != 1 else y for y in Y]
@@ -277,38 +311,53 @@ def main():
     ndir = 2 if cfg.complex_ else 1
     cols_per_step = float(sum(m0) * n_nodes * ndir)
     setup_s = time.perf_counter() - t_setup
+    spans = [(g, min(g + group, len(slices))) for g in range(0, len(slices), group)]
+
+    def groups(**kw):
+        """One filter per group of slices (the whole sweep when it fits),
+        sharing one workspace."""
+        gs = [(fb.FeastFilter(B, lo[a:b], hi[a:b], m0[a:b], n_nodes=n_nodes, **kw), Y[a:b],
+               Q[a:b]) for a, b in spans]
+        need = max(F.workspace_bytes(y, q) for F, y, q in gs)
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+        for F, _, _ in gs:
+            F._ws = ws
+        return gs
 
     # tune the block-solve kernel for both precisions on this shape (not timed):
-    # every system of a sweep, enough columns that each variant fills the GPU
-    # several times over as the sweep's launches do
+    # the systems of a sweep (at most as many as fit beside their buffers),
+    # enough columns that each variant fills the GPU several times over as
+    # the sweep's launches do
     tuned = {}
+    nsys_t, m_t = min(len(m0) * n_nodes, 128), 512
+    if cfg.n > 32768:
+        nsys_t, m_t = 64, 256
     for prec in (1, 0):
-        v, ms = fb.autotune(B, prec, nsys=len(m0) * n_nodes, m=512, cache_path=args.tune_log)
+        v, ms = fb.autotune(B, prec, nsys=nsys_t, m=m_t, cache_path=args.tune_log)
         tuned["c64" if prec else "c128"] = {"variant": v, "ms": ms}
 
     res = {}
-    F32 = fb.FeastFilter(B, lo, hi, m0, n_nodes=n_nodes, precision=1, ir_tol=1e-10, ir_max=6)
-    res["fp32ir"] = run_path(fb, F32, Y, Q, args.steps, args.warmup, cols_per_step)
-    del F32
+    G = groups(precision=1, ir_tol=1e-10, ir_max=6)
+    res["fp32ir"] = run_path(fb, G, args.steps, args.warmup, cols_per_step)
+    del G
     torch.cuda.empty_cache()
-    # the same sweep replayed from a HIP graph on a stream of its own
+    # the same sweep replayed from HIP graphs on a stream of its own
     gs = torch.cuda.Stream()
-    F32g = fb.FeastFilter(B, lo, hi, m0, n_nodes=n_nodes, precision=1, ir_tol=1e-10, ir_max=6,
-                          graph=True)
-    res["fp32ir_graph"] = run_path(fb, F32g, Y, Q, args.steps, args.warmup, cols_per_step,
-                                   stream=gs)
-    del F32g
+    G = groups(precision=1, ir_tol=1e-10, ir_max=6, graph=True)
+    res["fp32ir_graph"] = run_path(fb, G, args.steps, args.warmup, cols_per_step, stream=gs)
+    del G
     torch.cuda.empty_cache()
     if not args.no_fp64:
-        F64 = fb.FeastFilter(B, lo, hi, m0, n_nodes=n_nodes, precision=0)
-        res["fp64"] = run_path(fb, F64, Y, Q, args.steps, args.warmup, cols_per_step)
-        del F64
+        G = groups(precision=0)
+        res["fp64"] = run_path(fb, G, args.steps, args.warmup, cols_per_step)
+        del G
         torch.cuda.empty_cache()
-        # the plain FP64 path: one launch sequence per slice, no batching
-        F64p = fb.FeastFilter(B, lo, hi, m0, n_nodes=n_nodes, precision=0, batched=False)
-        res["fp64_plain"] = run_path(fb, F64p, Y, Q, args.steps, args.warmup, cols_per_step)
-        del F64p
-        torch.cuda.empty_cache()
+        if len(spans) == 1:
+            # the plain FP64 path: one launch sequence per slice, no batching
+            G = groups(precision=0, batched=False)
+            res["fp64_plain"] = run_path(fb, G, args.steps, args.warmup, cols_per_step)
+            del G
+            torch.cuda.empty_cache()
 
     main_ = res["fp32ir"]
     out = {
@@ -325,7 +374,8 @@ def main():
         "dtype": "c64 LU+solves, f64 residual/refinement",
         "data": "synthetic",
         "config": {"workload": cfg.name, "n": cfg.n, "b": cfg.b, "complex": cfg.complex_,
-                   "slices": len(cfg.slices), "nodes": n_nodes, "systems": len(cfg.slices) * n_nodes,
+                   "slices": len(slices), "nodes": n_nodes, "systems": len(slices) * n_nodes,
+                   "slices_per_filter_launch_group": group,
                    "m0": m0, "rhs_cols_per_step": cols_per_step, "ir_tol": 1e-10,
                    "parallelism": "single GPU"},
         "roofline": roofline(main_["prof"], 1, cfg.name),
@@ -341,9 +391,12 @@ def main():
         out["kernels_fp64"] = {k: {"launches": v[0], "ms": v[1], "flop": v[2]}
                                for k, v in r64["prof"].items() if v[0]}
         out["fp32ir_over_fp64"] = main_["value"] / r64["value"]
-        rp = res["fp64_plain"]
-        out["fp64_plain"] = {k: v for k, v in rp.items() if k != "prof"}
-        out["fp32ir_over_fp64_plain"] = main_["value"] / rp["value"]
+        if "fp64_plain" in res:
+            rp = res["fp64_plain"]
+            out["fp64_plain"] = {k: v for k, v in rp.items() if k != "prof"}
+            out["fp32ir_over_fp64_plain"] = main_["value"] / rp["value"]
+        else:
+            out["fp64_plain"] = "not run: the sweep is split into filter groups"
     rg = res["fp32ir_graph"]
     out["fp32ir_graph"] = {k: v for k, v in rg.items() if k != "prof"}
     out["graph_over_direct"] = rg["value"] / main_["value"]
@@ -363,7 +416,7 @@ def main():
         nrm1 = band_norm1(ab)
         out["e2e"] = [run_e2e(fb, B, cfg, lo, hi, counts, m0, prec, nrm1) for prec in (1, 0)]
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(cfg, float(np.mean(m0)), args.cpu_cols)
+        out["cpu_baseline"] = cpu_baseline(cfg, float(np.mean(m0)), args.cpu_cols, slices)
     print(json.dumps(out), flush=True)
 
 

@@ -355,7 +355,8 @@ int32_t fb_m0_rule(int32_t m);
  *  passes host, nslice or NULL: most refinement passes of any tile; -1 when
  *         a system of the slice was refactored and solved in complex128
  *         after its refinement stayed above ir_tol
- * o->max_iter, o->tol and o->hbm_budget are ignored.  Returns 0, or for
+ * o->max_iter and o->tol are ignored; o->hbm_budget and o->pairs set how
+ * many (node, direction) pairs share a launch.  Returns 0, or for
  * precision 1 the number of slices with a tile above ir_tol after ir_max. */
 int feast_filter(const fb_band* B, int32_t nslice, const double* lo, const double* hi,
                  const int32_t* m, const void* const* Y, const int64_t* ldy,

@@ -434,11 +434,13 @@ class FeastFilter:
     """Reusable filter application Q_i = r(B) Y_i over a fixed set of slices
     (workspace allocated once; each call factors and solves everything).
     graph=True replays the sweep from a HIP graph captured on the first call
-    (batched, every pair in one launch, a stream other than the null one)."""
+    (batched, every pair in one launch, a stream other than the null one).
+    workspace: a uint8 device tensor of at least workspace_bytes() bytes that
+    filters run one after another may share."""
 
     def __init__(self, B, lo, hi, m, n_nodes=8, precision=0, ir_tol=1e-10, ir_max=4,
                  batched=True, with_resid=False, hbm_budget=0.0, pairs=0, rule="gauss",
-                 ratio=1.0, graph=False, tune_cache=None, device="cuda"):
+                 ratio=1.0, graph=False, tune_cache=None, workspace=None, device="cuda"):
         self.B = _as_band(B)
         self.lo = np.ascontiguousarray(np.asarray(lo, np.float64).ravel())
         self.hi = np.ascontiguousarray(np.asarray(hi, np.float64).ravel())
@@ -453,7 +455,7 @@ class FeastFilter:
         self.bs = self.B.struct()
         self.resid = np.zeros(self.ns, np.float64)
         self.passes = np.zeros(self.ns, np.int32)
-        self._ws = None
+        self._ws = workspace  # a uint8 device tensor shared with other filters, or None
 
     def _args(self, Y, Q):
         ldy = np.array([y.stride(1) if y.shape[1] > 1 else self.B.n for y in Y], np.int64)
@@ -477,6 +479,8 @@ class FeastFilter:
         if self._ws is None:
             self._ws = torch.empty(max(self.workspace_bytes(Y, Q), 256), dtype=torch.uint8,
                                    device=self.B.data.device)
+        if self._ws.numel() < self.workspace_bytes(Y, Q):
+            raise ValueError("the filter's workspace is smaller than workspace_bytes()")
         lw = C.c_size_t(self._ws.numel())
         rc = N.lib().feast_filter(*self._args(Y, Q), C.c_void_p(self._ws.data_ptr()),
                                   C.byref(lw), C.c_void_p(_stream_handle(stream)))
