@@ -5,7 +5,9 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfeastband.so")
+# FEASTBAND_LIB names another build of the same library (the host-sanitizer
+# build of the C ABI checks); it is never a substitute for the GPU code
+LIB_PATH = os.environ.get("FEASTBAND_LIB") or os.path.join(_HERE, "libfeastband.so")
 
 FB_REAL64 = 1
 FB_COMPLEX128 = 2

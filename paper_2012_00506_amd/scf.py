@@ -21,6 +21,7 @@ search-space size of a slice follows them (m0 = max(ceil(1.5 m), m + 10)).
 """
 from __future__ import annotations
 
+import json
 import math
 import time
 from dataclasses import dataclass, field
@@ -58,18 +59,53 @@ class StepResult:
 class SliceSequence:
     """FEAST on fixed slices of a sequence of matrices with warm starts."""
 
-    def __init__(self, bounds, precision=1, warm=True, seed=0, replan_nev=0, **feast_kw):
+    def __init__(self, bounds, precision=1, warm=True, seed=0, replan_nev=0, log_path=None,
+                 **feast_kw):
         self.bounds = np.asarray(bounds, np.float64)
         self.K = len(self.bounds) - 1
         self.precision = precision
         self.warm = warm
         self.replan_nev = int(replan_nev)
         self.feast_kw = feast_kw
+        self.log_path = log_path  # one JSON line per step when set
         self.prev = None
         self.prev_pairs = None  # (ascending eigenvalues, their vectors) of the last step
         self.gen = torch.Generator(device="cuda")
         self.gen.manual_seed(seed)
         self.step_no = 0
+
+    # ------------------------------------------------------------ checkpoint
+    def save(self, path):
+        """Write the sequence state (boundaries, step number, the last step's
+        start blocks, and with re-partitioning its eigenpairs, the random
+        generator) to an .npz file that ``load`` reads back."""
+        arrays = {"bounds": self.bounds, "step_no": np.int64(self.step_no),
+                  "precision": np.int64(self.precision), "warm": np.int64(self.warm),
+                  "replan_nev": np.int64(self.replan_nev),
+                  "gen_state": self.gen.get_state().numpy()}
+        if self.prev is not None:
+            arrays["n_prev"] = np.int64(len(self.prev))
+            for i, y in enumerate(self.prev):
+                arrays[f"prev_{i}"] = y.cpu().numpy()
+        if self.prev_pairs is not None and self.prev_pairs[1] is not None:
+            arrays["pairs_lam"] = self.prev_pairs[0]
+            arrays["pairs_X"] = self.prev_pairs[1].cpu().numpy()
+        np.savez(path, **arrays)
+
+    @classmethod
+    def load(cls, path, **feast_kw):
+        """A sequence resumed from ``save``: the next ``step`` continues
+        exactly as the saved sequence would have."""
+        z = np.load(path, allow_pickle=False)
+        seq = cls(z["bounds"], precision=int(z["precision"]), warm=bool(z["warm"]),
+                  replan_nev=int(z["replan_nev"]), **feast_kw)
+        seq.step_no = int(z["step_no"])
+        seq.gen.set_state(torch.from_numpy(z["gen_state"].copy()))
+        if "n_prev" in z.files:
+            seq.prev = [torch.from_numpy(z[f"prev_{i}"]).cuda() for i in range(int(z["n_prev"]))]
+        if "pairs_lam" in z.files:
+            seq.prev_pairs = (z["pairs_lam"], torch.from_numpy(z["pairs_X"]).cuda())
+        return seq
 
     def _random(self, n, m, complex_):
         if complex_:
@@ -86,6 +122,34 @@ class SliceSequence:
             return y[:, :m0]
         extra = self._random(n, m0 - y.shape[1], complex_)
         return torch.cat([y, extra], dim=1)
+
+    def _log(self, dt, counts, m0, res):
+        """Append one JSON line: counts, sizes, iterations, info codes, the
+        largest eigen-residual, the orthogonality max |X^H X - I| per slice,
+        and per kernel class its launches, time and achieved FLOP/s."""
+        prof = api.profile_read()
+        api.profile_enable(False)
+        orth = []
+        for r in res:
+            X = r.Y[:, : r.m_found]
+            if r.m_found == 0:
+                orth.append(0.0)
+                continue
+            G = X.conj().t() @ X
+            G -= torch.eye(r.m_found, dtype=G.dtype, device=G.device)
+            orth.append(float(G.abs().max()))
+        rec = {"step": self.step_no + 1, "seconds": dt,
+               "bounds": [float(v) for v in self.bounds],
+               "counts": [int(c) for c in counts], "m0": [int(v) for v in m0],
+               "iters": [r.iters for r in res], "info": [r.info for r in res],
+               "max_resid": max((float(r.resid[:r.m_found].max()) for r in res if r.m_found),
+                                default=0.0),
+               "orthogonality": orth,
+               "kernels": {k: {"launches": v[0], "ms": v[1],
+                               "tflops": (v[2] / v[1] / 1e9) if v[1] > 0 else 0.0}
+                           for k, v in prof.items() if v[0]}}
+        with open(self.log_path, "a") as f:
+            f.write(json.dumps(rec) + "\n")
 
     def _pairs(self, res):
         """Converged in-slice pairs of a step, ascending."""
@@ -129,10 +193,14 @@ class SliceSequence:
             else:
                 y = self._start(i, B.n, m, B.complex_)
             Y.append(y.contiguous().t().contiguous().t())  # column-major copy
+        if self.log_path:
+            api.profile_enable(True)
         res = api.feast_band_slice(B, self.bounds[:-1], self.bounds[1:], Y, m_expected=counts,
                                    precision=self.precision, **self.feast_kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        if self.log_path:
+            self._log(dt, counts, m0, res)
         self.prev = [r.Y for r in res]
         if self.replan_nev > 0:
             self.prev_pairs = self._pairs(res)

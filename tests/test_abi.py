@@ -253,3 +253,20 @@ def test_inertia_noalloc_rejects_before_launch(L):
     big = _band(n=70000, b=64)   # 73 MB band copy > 64 MiB scratch
     assert L.band_inertia_noalloc(C.byref(big), 2, sh, neg, None, None, None) == -2007
     assert b"scratch" in L.fb_strerror(-2007)
+
+
+def test_tune_file_parsing(L, tmp_path):
+    """fb_tune_load reads only well-formed choices and skips the rest (the
+    autotuner's per-variant timing lines, truncated or out-of-range lines)."""
+    p = tmp_path / "tune.jsonl"
+    p.write_text('{"timed": 1, "rsize": 4, "nb": 64, "variant": 0, "ms": 1.0}\n'
+                 '{"rsize": 4, "nb": 64, "variant": 3, "ms": 2.0, "n": 100, "m": 8}\n'
+                 '{"rsize": 8, "nb": 48, "variant": 1}\n'
+                 '{"rsize": 4, "nb": 64, "variant": 99}\n'
+                 '{"rsize": 3, "nb": 64, "variant": 1}\n'
+                 '{"rsize": 4, "nb": 65, "variant": 1}\n'
+                 '{"rsize": 4, "nb"\n'
+                 + "x" * 2000 + "\n")
+    assert L.fb_tune_load(str(p).encode()) == 2
+    assert L.fb_tune_load(str(tmp_path / "missing").encode()) == -1
+    assert L.fb_tune_load(None) == -1

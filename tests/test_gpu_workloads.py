@@ -129,3 +129,36 @@ def test_scf_sequence_repartition(fb):
             assert r.counts[j] == oin.count_in(ab, seq.bounds[j], seq.bounds[j + 1])
         _check_results(ab, seq.bounds, r.results)
         del B
+
+
+def test_scf_checkpoint_resume_and_log(fb, tmp_path):
+    """A sequence saved after its first step and loaded into a new driver
+    takes the second step exactly as the uninterrupted one (same eigenvalues
+    and vectors, bit for bit); the JSONL log has one record per step."""
+    import json
+    from paper_2012_00506_amd.scf import SliceSequence
+    cfg = synth.Config("cplx-n4096-b16-seq", 4096, 16, True, 9, -30.0, 30.0, (),
+                       "small SCF-like sequence")
+    nev, K = 300, 4
+    ab0 = synth.scf_matrix(cfg, 0)
+    bounds, _, _ = fb.slice_plan(ab0, K, "equal_count", nev=nev)
+    log = tmp_path / "run.jsonl"
+    seq = SliceSequence(bounds, precision=1, warm=True, seed=5, log_path=str(log))
+    seq.step(fb.DeviceBand.from_band(ab0))
+    ck = tmp_path / "seq.npz"
+    seq.save(ck)
+    seq2 = SliceSequence.load(ck)
+    ab1 = synth.scf_matrix(cfg, 1)
+    B1 = fb.DeviceBand.from_band(ab1)
+    r1 = seq.step(B1)
+    r2 = seq2.step(B1)
+    assert r1.counts == r2.counts and r1.iters == r2.iters
+    for a, b in zip(r1.results, r2.results):
+        assert np.array_equal(a.lam, b.lam)
+        assert torch.equal(a.Y, b.Y)
+    recs = [json.loads(line) for line in open(log)]
+    assert [r["step"] for r in recs] == [1, 2]
+    for r in recs:
+        assert len(r["counts"]) == K and r["max_resid"] <= 1e-10
+        assert max(r["orthogonality"]) <= 1e-12
+        assert r["kernels"]["solve"]["launches"] > 0 and r["kernels"]["solve"]["tflops"] > 0
