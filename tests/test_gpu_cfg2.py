@@ -112,3 +112,30 @@ def test_cfg2_one_slice_fp64_agrees(setup):
         assert r.resid[: r.m_found].max() <= 1e-10
         out[prec] = r.lam
     assert np.abs(out[0] - out[1]).max() <= 1e-12 * nrm
+
+
+def test_cfg2_interior_slice_zolotarev(setup):
+    """Zolotarev's rational filter (8 nodes, inner fraction 0.9) on the
+    interior slice [-6.25, 0) with m0 = 1.5 m: converges within the
+    iterations of the Gauss rule, in both precisions, to the same eigenvalues
+    (1e-12 ||B||_1)."""
+    fb, cfg, ab, B, edges, counts = setup
+    nrm = oband.norm1(ab)
+    i = 7
+    assert (edges[i], edges[i + 1]) == (-6.25, 0.0)
+    m = int(counts[i])
+    m0 = max(math.ceil(1.5 * m), m + 10)
+    out = {}
+    for rule, ratio, prec in (("gauss", 1.0, 1), ("zolotarev", 0.9, 1), ("zolotarev", 0.9, 0)):
+        Y = [_start(fb, cfg, m0, i)]
+        print(f"interior slice {rule} precision {prec}", flush=True)
+        [r] = fb.feast_band_slice(B, [edges[i]], [edges[i + 1]], Y, m_expected=[m],
+                                  precision=prec, rule=rule, ratio=ratio,
+                                  ir_tol=1e-10 if prec else 1e-12, rerun=False)
+        assert r.info in (0, 3) and r.m_found == m
+        assert r.resid[:m].max() <= 1e-10
+        out[(rule, prec)] = r
+    g = out[("gauss", 1)]
+    for key in (("zolotarev", 1), ("zolotarev", 0)):
+        assert out[key].iters <= g.iters
+        assert np.abs(out[key].lam - g.lam).max() <= 1e-12 * nrm
