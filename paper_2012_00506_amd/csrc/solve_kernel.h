@@ -554,18 +554,22 @@ int launch_t(const cx<R>* mats, const cx<R>* matsT, const int16_t* perm, int64_t
   }
 }
 
-// every (tile width, prefetch, tiles per wave, register cap) variant of one precision
+// every (tile width, prefetch, tiles per wave, register cap) variant of one
+// precision; in complex64, two tiles per wave ask for two waves per SIMD,
+// which without the cap the compiler exceeds with accumulation registers
 template <typename R>
 int launch_variant(int variant, const cx<R>* mats, const cx<R>* matsT, const int16_t* perm,
                    int64_t n, int nb, int njobs, const SolveJob* jobs_dev, hipStream_t st,
                    const int32_t* gate) {
+  // complex128 fragments are twice as wide: capped at two waves they spill
+  constexpr int kOcc2 = sizeof(R) == 4 ? 2 : 1;
   switch (variant) {
     case 0: return launch_t<R, 16, false, 1>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
     case 1: return launch_t<R, 16, true, 1>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
     case 2: return launch_t<R, 32, false, 1>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
     case 3: return launch_t<R, 32, true, 1>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
-    case 4: return launch_t<R, 32, false, 2>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
-    case 5: return launch_t<R, 32, true, 2>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
+    case 4: return launch_t<R, 32, false, 2, kOcc2>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
+    case 5: return launch_t<R, 32, true, 2, kOcc2>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
     case 6: return launch_t<R, 16, false, 1, 3>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
     case 7: return launch_t<R, 16, true, 1, 3>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
     default: return FB_ERR_INTERNAL;

@@ -6,8 +6,9 @@ namespace fb {
 
 // variant v: tile width (16 or 32 right-hand sides), whether the factor
 // fragments of the next block product are prefetched into registers, how
-// many 16-column tiles one wave computes (2 for v = 4, 5), and for v = 6, 7
-// (16-column tiles) registers capped for three waves per SIMD
+// many 16-column tiles one wave computes (2 for v = 4, 5, with registers
+// capped for two waves per SIMD in complex64), and for v = 6, 7 (16-column tiles)
+// registers capped for three waves per SIMD
 constexpr int kNumVariants = 8;
 inline int variant_tile(int v) { return (v >= 2 && v < 6) ? 32 : 16; }
 inline bool variant_prefetch(int v) { return (v & 1) != 0; }
