@@ -177,44 +177,43 @@ int ingest_band(const fb_band* B, Band& out, Arena& ar, hipStream_t st, bool blo
 }
 
 // Number of NaN or infinite entries of a column-major block (real or
-// complex), per workgroup into part (gridDim.x doubles).
+// complex), added to *count: workgroup (x, c) reads a stretch of column c,
+// one contiguous run of rows x words doubles, so the scan runs at HBM rate.
 __global__ void __launch_bounds__(256)
-k_count_nonfinite(const double* __restrict__ p, int64_t rows, int cols, int64_t ld, int words,
-                  double* __restrict__ part) {
-  __shared__ double red[256];
-  double bad = 0.0;
-  const int64_t tot = rows * cols * words;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t c = e / (rows * words), r = e - c * rows * words;
-    bad += isfinite(p[c * ld * words + r]) ? 0.0 : 1.0;
-  }
-  red[threadIdx.x] = bad;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+k_count_nonfinite(const double* __restrict__ p, int64_t rows, int64_t ld, int words,
+                  int32_t* __restrict__ count) {
+  const int64_t len = rows * words;
+  const double* col = p + (int64_t)blockIdx.y * ld * words;
+  int bad = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+       e += (int64_t)gridDim.x * blockDim.x)
+    bad += isfinite(col[e]) ? 0 : 1;
+  for (int off = 32; off > 0; off >>= 1) bad += __shfl_xor(bad, off, 64);
+  if ((threadIdx.x & 63) == 0 && bad) atomicAdd(count, bad);
 }
 
 int check_finite_blocks(int nblk, const void* const* P, const int64_t* ld, const int32_t* cols,
                         int64_t rows, bool cplx, double* part_dev, hipStream_t st) {
-  constexpr int G = 64;
-  int used = 0;
+  if (nblk <= 0) return 0;
+  int32_t* cnt = reinterpret_cast<int32_t*>(part_dev);  // nblk counters
+  FB_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nblk, st));
+  const int words = cplx ? 2 : 1;
+  const int64_t len = rows * words;
+  const int gx = (int)std::min<int64_t>((len + 1023) / 1024, 64);  // about 4 doubles per thread
   for (int i = 0; i < nblk; ++i) {
     if (cols[i] <= 0) continue;
-    k_count_nonfinite<<<G, 256, 0, st>>>((const double*)P[i], rows, cols[i], ld[i],
-                                         cplx ? 2 : 1, part_dev + (size_t)used * G);
-    FB_HIP(hipGetLastError());
-    ++used;
+    for (int c0 = 0; c0 < cols[i]; c0 += 65535) {
+      const int nc = std::min(cols[i] - c0, 65535);
+      k_count_nonfinite<<<dim3(gx, nc), 256, 0, st>>>(
+          (const double*)P[i] + (int64_t)c0 * ld[i] * words, rows, ld[i], words, cnt + i);
+      FB_HIP(hipGetLastError());
+    }
   }
-  if (!used) return 0;
-  std::vector<double> h((size_t)used * G);
-  FB_HIP(hipMemcpyAsync(h.data(), part_dev, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+  std::vector<int32_t> h(nblk);
+  FB_HIP(hipMemcpyAsync(h.data(), cnt, sizeof(int32_t) * nblk, hipMemcpyDeviceToHost, st));
   FB_HIP(hipStreamSynchronize(st));
-  for (double v : h)
-    if (v != 0.0) return FB_ERR_NONFINITE;
+  for (int32_t v : h)
+    if (v != 0) return FB_ERR_NONFINITE;
   return 0;
 }
 

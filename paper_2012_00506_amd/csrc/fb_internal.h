@@ -160,7 +160,8 @@ int ingest_band(const fb_band* B, Band& out, Arena& ar, hipStream_t st, bool blo
 int band_stats_host(const Band& bd, double* out3, hipStream_t st);
 // FB_ERR_NONFINITE when one of the nblk column-major blocks P[i] (rows x
 // cols[i], leading dimension ld[i] in elements; complex128 or double) holds a
-// NaN or an infinity.  part_dev: 64 doubles per block.  Synchronises.
+// NaN or an infinity.  part_dev: scratch of kFiniteParts doubles per block
+// (one int32 counter per block is used).  Synchronises.
 int check_finite_blocks(int nblk, const void* const* P, const int64_t* ld, const int32_t* cols,
                         int64_t rows, bool cplx, double* part_dev, hipStream_t st);
 constexpr int kFiniteParts = 64;
