@@ -58,7 +58,14 @@ template int solve_tile<double>(int);
 // wave per 16 x 16 output tile.  x blocks roll through three LDS slots and a
 // fourth holds y_k, then r_k; tiles enter and leave global memory with thread
 // e on row e % NB, column e / NB, so that a wave moves whole column runs.
-// Per (job, column): sum |r|^2 and sum |y|^2.
+//
+// A wave's share of the three products is a fixed list of 2 NB/16 + 1
+// chunks of 16 B columns (the triangles of B(k,k-1) and B(k,k+1) outside
+// the band are skipped).  Its B fragments are loaded chunk by chunk RD chunks
+// ahead of the MFMAs that use them, across block rows and barriers, so that
+// no product waits for its first fragment.  The blocks B(0,-1) and
+// B(K-1,K) are zero, as are the x slots beyond the ends, so every block row
+// runs the same list.  Per (job, column): sum |r|^2 and sum |y|^2.
 template <int NB, int T>
 __global__ void __launch_bounds__(NB * 4 * (T / 16))
 k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* __restrict__ jobs,
@@ -67,6 +74,11 @@ k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* 
   constexpr int SL = NB * LDT;  // one slot
   constexpr int NTH = NB * 4 * (T / 16);
   constexpr int RX = NB * T / NTH;  // tile elements per thread
+  constexpr int NRW = NB / 16;
+  constexpr int L = 2 * NRW + 1;    // chunks per block row and wave
+  // chunks of fragments in flight: two where the registers hold them
+  // without spilling (checked per block size), else one
+  constexpr int RD = (NB <= 32 || NB == 64) ? 2 : 1;
   extern __shared__ __align__(16) char lds_raw[];
   c128* X = reinterpret_cast<c128*>(lds_raw);  // 3 slots of x blocks
   c128* Yr = X + 3 * SL;                       // y_k, overwritten by r_k
@@ -78,13 +90,29 @@ k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* 
   const c128* jy = jb.y;
   c128* jr = jb.r;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  constexpr int NRW = NB / 16;
   const int w = __builtin_amdgcn_readfirstlane(wv % NRW);
   const int cb0 = __builtin_amdgcn_readfirstlane(16 * (wv / NRW));
   const int c0 = jb.col0;
   const int nc = jb.ncol;
   const size_t bb = (size_t)NB * NB;
   const c128 zz = jb.dir ? mk(jb.z.x, -jb.z.y) : jb.z;
+  const int kq = lane >> 4;
+  const int col = cb0 + (lane & 15);
+  // chunk i of the list: product p (0: B(k,k-1), 1: B(k,k), 2: B(k,k+1))
+  // over B columns 16 ch .. 16 ch + 15
+  const int n0 = NRW - w;  // chunks of product 0
+  auto chunk_p = [&](int i) { return i < n0 ? 0 : (i < n0 + NRW ? 1 : 2); };
+  auto chunk_c = [&](int i) { return i < n0 ? w + i : (i < n0 + NRW ? i - n0 : i - n0 - NRW); };
+  // fragment q of a chunk: B[16 w + lane % 16][16 ch + 4 q + lane / 16]
+  struct Ch {
+    c128 a[4];
+  };
+  const c128* Brow = Bblk + (size_t)(kq * NB + 16 * w + (lane & 15));
+  auto cload = [&](Ch& f, int k, int i) {
+    const c128* A = Brow + ((size_t)k * 3 + chunk_p(i)) * bb + (size_t)(16 * chunk_c(i)) * NB;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) f.a[q] = gld(A + (size_t)(4 * q) * NB);
+  };
   // tile element q of this thread: row e % NB, column e / NB (one column
   // per wave and q)
   auto erow = [&](int q) { return (t + q * NTH) % NB; };
@@ -109,11 +137,13 @@ k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* 
   double rr[RX], yy[RX];
 #pragma unroll
   for (int q = 0; q < RX; ++q) rr[q] = yy[q] = 0.0;
+  Ch carry[RD];
+#pragma unroll
+  for (int i = 0; i < RD; ++i) cload(carry[i], 0, i);
   tissue(xr, jx, jb.ldx, 0);
   tstore(xr, X, 0);
   tissue(xr, jx, jb.ldx, 1);
   tissue(yv, jy, jb.ldy, 0);
-  const int col = cb0 + (lane & 15);
   for (int k = 0; k < K; ++k) {
     tstore(xr, X + ((k + 1) % 3) * SL, k + 1);
     tstore(yv, Yr, k);
@@ -124,17 +154,35 @@ k_shift_residual(const c128* __restrict__ Bblk, int64_t n, int K, const ResJob* 
     if (k + 2 <= K) tissue(xr, jx, jb.ldx, k + 2);
     if (k + 1 < K) tissue(yv, jy, jb.ldy, k + 1);
     const c128* Xk = X + (k % 3) * SL;
-    // (B x)_k by the three block products, then r = y - zz x + B x
+    const c128* Sp[3] = {X + ((k + 2) % 3) * SL, Xk, X + ((k + 1) % 3) * SL};
+    const bool more = k + 1 < K;
+    // (B x)_k over the chunk list, then r = y - zz x + B x
     Acc<double, 1> acc;
     acc.zero();
-    const c128* Bk = Bblk + (size_t)k * 3 * bb;
-    if (k > 0)
-      wave_prod<double, NB, 1, false, false>(acc, Bk, X + ((k + 2) % 3) * SL, LDT, nullptr, w,
-                                             cb0, lane, 16 * w, NB);
-    wave_prod<double, NB, 1, false, false>(acc, Bk + bb, Xk, LDT, nullptr, w, cb0, lane, 0, NB);
-    if (k + 1 < K)
-      wave_prod<double, NB, 1, false, false>(acc, Bk + 2 * bb, X + ((k + 1) % 3) * SL, LDT,
-                                             nullptr, w, cb0, lane, 0, 16 * w + 16);
+    Ch buf[L + RD];
+#pragma unroll
+    for (int i = 0; i < RD; ++i) buf[i] = carry[i];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      if (i + RD < L)
+        cload(buf[i + RD], k, i + RD);
+      else if (more)
+        cload(buf[i + RD], k + 1, i + RD - L);
+      const int p = chunk_p(i), ch = chunk_c(i);
+      const c128* bp = (p == 0 ? Sp[0] : (p == 1 ? Sp[1] : Sp[2])) + (16 * ch + kq) * LDT + col;
+      c128 bv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bv[q] = bp[4 * q * LDT];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double ar = buf[i].a[q].x, ai = buf[i].a[q].y;
+        acc.p1[0] = MF<double>::mma(ar, bv[q].x, acc.p1[0]);
+        acc.p2[0] = MF<double>::mma(ai, bv[q].y, acc.p2[0]);
+        acc.p3[0] = MF<double>::mma(ar + ai, bv[q].x + bv[q].y, acc.p3[0]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RD; ++i) carry[i] = buf[L + i];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * w + MF<double>::row(lane, r);
