@@ -18,10 +18,11 @@
 //         interchanges of the block move them, so that P A_panel = Lh U),
 //   Lh21  multipliers of the bottom b rows,
 //   U(k,k), U(k,k+1), U(k,k+2).
-// A second kernel replaces Lh11 and U(k,k) by their inverses and a third
-// Lh21 by M = Lh21 Lh11^{-1}, so that the solves are chains of dense b x b
-// products and a forward step reads its window once (y_top = Lh11^{-1} z_top
-// and carry = z_bot - M z_top are independent products of z_top).
+// A second kernel replaces Lh11 and U(k,k) by their inverses, a third Lh21
+// by M = Lh21 Lh11^{-1}, and a fourth Lh11^{-1}, U(k,k+1) and U(k,k+2) by
+// Q = U(k,k)^{-1} Lh11^{-1}, G1 = U(k,k)^{-1} U(k,k+1) and
+// G2 = U(k,k)^{-1} U(k,k+2), so that each step of every solve sweep is one
+// set of independent dense b x b products (see solve.hip).
 //
 // Within a block the multipliers are written to a per-system scratch under a
 // storage row that follows each window row through the interchanges (an O(1)
@@ -531,6 +532,96 @@ static int launch_form_m(cx<R>* mats, int nb, int nblk, hipStream_t st) {
   }
 }
 
+// The blocks that let every solve sweep take one product phase per block
+// row, from the inverses (slot 2: U(k,k)^{-1}, slot 0: Lh11^{-1}) and U's
+// off-diagonal blocks:
+//   Q  = U(k,k)^{-1} Lh11^{-1}  in place of Lh11^{-1} (slot 0),
+//   G1 = U(k,k)^{-1} U(k,k+1)   in place of U(k,k+1)  (slot 3),
+//   G2 = U(k,k)^{-1} U(k,k+2)   in place of U(k,k+2)  (slot 4).
+// One workgroup per block and one wave per 16 rows: a wave holds its rows of
+// the upper triangular inverse as MFMA fragments and multiplies them by
+// panels of PW columns of each right operand staged in LDS, with the
+// triangles that vanish in exact arithmetic (below the diagonal of U(k,k)^{-1},
+// above it in Lh11^{-1} and U(k,k+2)) taken as zeros.  A panel is staged
+// before any wave overwrites its columns.  Runs after k_form_m, which reads
+// Lh11^{-1}.
+template <typename R, int NB>
+__global__ void __launch_bounds__(NB * 4)
+k_form_qg(cx<R>* __restrict__ mats, int nblk) {
+  constexpr int PW = NB < 64 ? NB : 64;
+  constexpr int NC = PW / 16;
+  constexpr int LD = PW + 1;
+  extern __shared__ __align__(16) char lds_raw[];
+  cx<R>* Bp = reinterpret_cast<cx<R>*>(lds_raw);  // NB x LD: operand(k, p0 + c) at k LD + c
+  const int blk = blockIdx.x;
+  if (blk >= nblk) return;
+  cx<R>* base = mats + (size_t)blk * 5 * NB * NB;
+  const cx<R>* Ui = base + (size_t)2 * NB * NB;
+  const int t = threadIdx.x, lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  Frag<R, NB> f;
+  frag_load<R, NB, false>(f, Ui, w, lane, 16 * w, NB);
+  {
+    // fragment s holds row 16 w + lane % 16, column 4 s + lane / 16
+    const int i = 16 * w + (lane & 15);
+#pragma unroll
+    for (int s = 0; s < NB / 4; ++s)
+      if (4 * s + (lane >> 4) < i) f.a[s] = mk<R>(0, 0);
+  }
+  for (int which = 0; which < 3; ++which) {
+    cx<R>* O = base + (size_t)(which == 0 ? 0 : which + 2) * NB * NB;
+    const bool lower = which != 1;  // Lh11^{-1} and U(k,k+2)
+    for (int p0 = 0; p0 < NB; p0 += PW) {
+      __syncthreads();
+      for (int e = t; e < NB * PW; e += NB * 4) {
+        const int k = e % NB, c = e / NB;
+        cx<R> v = O[(size_t)(p0 + c) * NB + k];
+        if (lower && k < p0 + c) v = mk<R>(0, 0);
+        Bp[k * LD + c] = v;
+      }
+      __syncthreads();
+      Acc<R, NC> acc;
+      acc.zero();
+      frag_mma<R, NB, NC, false, false>(acc, f, Bp, LD, nullptr, 0, lane, 16 * w, NB);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * w + MF<R>::row(lane, r);
+          const int col = p0 + 16 * c + (lane & 15);
+          gst(O + (size_t)col * NB + row, acc.get(c, r));
+        }
+    }
+  }
+}
+
+template <typename R, int NB>
+static int launch_form_qg_nb(cx<R>* mats, int nblk, hipStream_t st) {
+  constexpr int PW = NB < 64 ? NB : 64;
+  const size_t smem = sizeof(cx<R>) * (size_t)NB * (PW + 1);
+  (void)hipFuncSetAttribute((const void*)k_form_qg<R, NB>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
+  (void)hipGetLastError();
+  k_form_qg<R, NB><<<nblk, NB * 4, smem, st>>>(mats, nblk);
+  FB_HIP(hipGetLastError());
+  return 0;
+}
+
+template <typename R>
+static int launch_form_qg(cx<R>* mats, int nb, int nblk, hipStream_t st) {
+  switch (nb) {
+    case 16: return launch_form_qg_nb<R, 16>(mats, nblk, st);
+    case 32: return launch_form_qg_nb<R, 32>(mats, nblk, st);
+    case 48: return launch_form_qg_nb<R, 48>(mats, nblk, st);
+    case 64: return launch_form_qg_nb<R, 64>(mats, nblk, st);
+    case 80: return launch_form_qg_nb<R, 80>(mats, nblk, st);
+    case 96: return launch_form_qg_nb<R, 96>(mats, nblk, st);
+    case 112: return launch_form_qg_nb<R, 112>(mats, nblk, st);
+    case 128: return launch_form_qg_nb<R, 128>(mats, nblk, st);
+    default: return FB_ERR_INTERNAL;
+  }
+}
+
 template <typename R>
 static size_t lu_lds_head_bytes(int b) {
   const int nb = block_size(b);
@@ -605,14 +696,17 @@ int launch_lu_impl(const Band& bd, int nsys, const c128* z_dev, cx<R>* mats, cx<
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
   (void)hipGetLastError();
   int nblk = nsys * K;
-  // inverses (2 nb^3 / 3 complex multiply-adds per block) and M (nb^3 / 2)
-  ProfScope ps(FB_PROF_INVERT, st, 8.0 * nblk * (double)nb * nb * nb * (2.0 / 3.0 + 0.5));
+  // inverses (2 nb^3 / 3 complex multiply-adds per block), M (nb^3 / 2) and
+  // Q, G1, G2 (nb^3 / 3 + nb^3 / 2 + nb^3 / 3)
+  ProfScope ps(FB_PROF_INVERT, st,
+               8.0 * nblk * (double)nb * nb * nb * (2.0 / 3.0 + 0.5 + 7.0 / 6.0));
   if (ilds)
     k_block_invert<R, true><<<2 * nblk, 256, ismem, st>>>(mats, nb, nblk);
   else
     k_block_invert<R, false><<<2 * nblk, 256, ismem, st>>>(mats, nb, nblk);
   FB_HIP(hipGetLastError());
   FB_TRY(launch_form_m<R>(mats, nb, nblk, st));
+  FB_TRY(launch_form_qg<R>(mats, nb, nblk, st));
   if (matsT) {
     k_transpose_blocks<R><<<5 * nblk, 256, 0, st>>>(mats, matsT, nb);
     FB_HIP(hipGetLastError());

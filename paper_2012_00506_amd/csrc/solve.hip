@@ -1,14 +1,21 @@
 // Multi-right-hand-side solves with the block form of the band LU factors.
+// Every sweep step is one set of independent products of blocks formed once
+// per factorisation (M = Lh21 Lh11^{-1}, Q = U(k,k)^{-1} Lh11^{-1},
+// G1 = U(k,k)^{-1} U(k,k+1), G2 = U(k,k)^{-1} U(k,k+2)), so that a step
+// waits for the previous one only once.
 //
 // N: x = A^{-1} y.  Forward, block k on the window rows kb .. kb+2b-1:
-//      z = P y_win; y_top = Lh11^{-1} z_top; carry = z_bot - M z_top
-//    with M = Lh21 Lh11^{-1} formed once per factorisation.
-//    Backward: x_k = U(k,k)^{-1} (y_k - U(k,k+1) x_{k+1} - U(k,k+2) x_{k+2}).
-// H: x = A^{-H} y.  Forward with U^H:
-//      w_k = U(k,k)^{-H} (y_k - U(k-1,k)^H w_{k-1} - U(k-2,k)^H w_{k-2})
-//    Backward, k descending on the window [w_k ; carry]:
-//      top = Lh11^{-H} w_k - M^H carry; x_win = P^T [top ; carry]
-//    (rows kb+b .. kb+2b-1 of x_win are final, rows kb .. kb+b-1 carry on).
+//      z = P y_win; v_k = Q z_top; carry = z_bot - M z_top
+//    (v_k = U(k,k)^{-1} Lh11^{-1} z_top).
+//    Backward: x_k = v_k - G1 x_{k+1} - G2 x_{k+2}
+//    (= U(k,k)^{-1} (Lh11^{-1} z_top - U(k,k+1) x_{k+1} - U(k,k+2) x_{k+2})).
+// H: x = A^{-H} y.  Forward with U^H, in u_k = U(k,k)^H w_k:
+//      u_k = y_k - G1(k-1)^H u_{k-1} - G2(k-2)^H u_{k-2}
+//    (w_k = U(k,k)^{-H} (y_k - U(k-1,k)^H w_{k-1} - U(k-2,k)^H w_{k-2})).
+//    Backward, k descending on the window [u_k ; carry]:
+//      top = Q^H u_k - M^H carry; x_win = P^T [top ; carry]
+//    (top = Lh11^{-H} w_k - M^H carry; rows kb+b .. kb+2b-1 of x_win are
+//    final, rows kb .. kb+b-1 carry on).
 // One workgroup per job (system, direction, tile of T columns); the tile's
 // window and carries live in LDS.  Inputs and outputs are complex128; the
 // arithmetic is in R (float: complex64 path, double: complex128 path).

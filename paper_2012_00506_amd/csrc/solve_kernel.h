@@ -315,8 +315,6 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
       if (e < 2 * NB) perm_put(e, pp.v[q]);
     }
   };
-  const int lo_tri = 16 * w + 16;  // k < lo_tri: lower triangle rows of this wave
-  const int up_tri = 16 * w;       // k >= up_tri: upper triangle
   auto blk = [&](int k, int slot) { return F + ((size_t)k * 5 + slot) * bb; };
   const cx<R>* FT = TS ? matsT + (size_t)jb.sys * K * 5 * bb : F;
   auto blkh = [&](int k, int slot) { return FT + ((size_t)k * 5 + slot) * bb; };
@@ -347,10 +345,10 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
 
   if (jb.dir == 0) {
     // ---------------------------------------------------------- N forward
-    // y_k = Lh11^{-1} z_top and the next window top z_bot - M z_top are both
+    // v_k = Q z_top and the next window top z_bot - M z_top are both
     // products of z_top = rows sp[0, NB) of the window
     cx<R>* W = S;           // window: rows 0 .. 2 NB - 1 (two slots)
-    cx<R>* Yt = S + 2 * SL; // y_k on its way to the intermediate
+    cx<R>* Yt = S + 2 * SL; // v_k on its way to the intermediate
     {
       TileC f0, f1;
       tile_issue(f0, in, jb.ldin, 0);
@@ -360,18 +358,18 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
     }
     TileC fr;
     load_perm(0);
-    if (PREF) frag_load<R, NB, false>(fa, blk(0, 0), w, lane, 0, lo_tri);
+    if (PREF) frag_load<R, NB, false>(fa, blk(0, 0), w, lane, 0, NB);
     __syncthreads();
     for (int k = 0; k < K; ++k) {
       if (PREF) frag_load<R, NB, false>(fb, blk(k, 1), w, lane, 0, NB);
-      if (!PREF) frag_load<R, NB, false>(fa, blk(k, 0), w, lane, 0, lo_tri);
+      if (!PREF) frag_load<R, NB, false>(fa, blk(k, 0), w, lane, 0, NB);
       acc.zero();
-      frag_mma<R, NB, NC, false, false>(acc, fa, W, LDT, sp, cb0, lane, 0, lo_tri);
+      frag_mma<R, NB, NC, false, false>(acc, fa, W, LDT, sp, cb0, lane, 0, NB);
       acc_to_lds(acc, Yt, LDT, nullptr, w, cb0, lane);
       tile_issue(fr, in, jb.ldin, (int64_t)(k + 2) * NB);  // consumed after the product
       PermPre pnext;
       if (k + 1 < K) perm_issue(pnext, k + 1);
-      if (PREF && k + 1 < K) frag_load<R, NB, false>(fa, blk(k + 1, 0), w, lane, 0, lo_tri);
+      if (PREF && k + 1 < K) frag_load<R, NB, false>(fa, blk(k + 1, 0), w, lane, 0, NB);
       if (!PREF) frag_load<R, NB, false>(fb, blk(k, 1), w, lane, 0, NB);
       acc_from_lds(acc, W, LDT, sp + NB, w, cb0, lane);
       frag_mma<R, NB, NC, false, true>(acc, fb, W, LDT, sp, cb0, lane, 0, NB);
@@ -383,81 +381,70 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
       __syncthreads();
     }
     // ---------------------------------------------------------- N backward
-    // x_k = U(k,k)^{-1} v, v = y_k - U(k,k+1) x_{k+1} - U(k,k+2) x_{k+2};
+    // x_k = v_k - G1 x_{k+1} - G2 x_{k+2}, one set of products per step;
     // x_{k+1} leaves for the output while step k runs
     cx<R>* X1 = S;
     cx<R>* X2 = S + SL;
     cx<R>* V = S + 2 * SL;
     zero_slots(S, 2);
-    // fa = U(k,k+1), fb = U(k,k+2), fc = U(k,k)^{-1}, pv = y_k: prefetched
-    if (PREF) frag_load<R, NB, false>(fc, blk(K - 1, 2), w, lane, up_tri, NB);
+    // fa = G1(k), fb = G2(k), pv = v_k: prefetched (the last step uses
+    // neither block)
     pre_load(pvm, mid, jb.ldmid, K - 1);
     __syncthreads();
     for (int k = K - 1; k >= 0; --k) {
       if (!PREF && k + 1 < K) frag_load<R, NB, false>(fa, blk(k, 3), w, lane, 0, NB);
-      if (!PREF && k + 2 < K) frag_load<R, NB, false>(fb, blk(k, 4), w, lane, 0, lo_tri);
+      if (!PREF && k + 2 < K) frag_load<R, NB, false>(fb, blk(k, 4), w, lane, 0, NB);
       pre_to_acc(acc, pvm);
       if (k + 1 < K) frag_mma<R, NB, NC, false, true>(acc, fa, X1, LDT, nullptr, cb0, lane, 0, NB);
-      if (k + 2 < K) frag_mma<R, NB, NC, false, true>(acc, fb, X2, LDT, nullptr, cb0, lane, 0, lo_tri);
+      if (k + 2 < K) frag_mma<R, NB, NC, false, true>(acc, fb, X2, LDT, nullptr, cb0, lane, 0, NB);
       acc_to_lds(acc, V, LDT, nullptr, w, cb0, lane);
-      if (k + 1 < K) emit_tile(X1, (int64_t)(k + 1) * NB);
-      __syncthreads();
       if (k > 0) {
-        if (PREF && k < K) frag_load<R, NB, false>(fa, blk(k - 1, 3), w, lane, 0, NB);
-        if (PREF && k + 1 < K) frag_load<R, NB, false>(fb, blk(k - 1, 4), w, lane, 0, lo_tri);
+        if (PREF) frag_load<R, NB, false>(fa, blk(k - 1, 3), w, lane, 0, NB);
+        if (PREF && k + 1 < K) frag_load<R, NB, false>(fb, blk(k - 1, 4), w, lane, 0, NB);
         pre_load(pvm, mid, jb.ldmid, k - 1);
       }
-      if (!PREF) frag_load<R, NB, false>(fc, blk(k, 2), w, lane, up_tri, NB);
-      acc.zero();
-      frag_mma<R, NB, NC, false, false>(acc, fc, V, LDT, nullptr, cb0, lane, up_tri, NB);
-      if (PREF && k > 0) frag_load<R, NB, false>(fc, blk(k - 1, 2), w, lane, up_tri, NB);
-      acc_to_lds(acc, X2, LDT, nullptr, w, cb0, lane);
+      if (k + 1 < K) emit_tile(X1, (int64_t)(k + 1) * NB);
       __syncthreads();
-      cx<R>* tmp = X1;
-      X1 = X2;
-      X2 = tmp;
+      cx<R>* tmp = X2;
+      X2 = X1;
+      X1 = V;
+      V = tmp;
     }
     emit_tile(X1, 0);
   } else {
     // ---------------------------------------------------------- H forward (U^H)
-    // w_k = U(k,k)^{-H} v, v = y_k - U(k-1,k)^H w_{k-1} - U(k-2,k)^H w_{k-2};
-    // w_{k-1} leaves for the intermediate while step k runs
+    // u_k = y_k - G1(k-1)^H u_{k-1} - G2(k-2)^H u_{k-2}, one set of products
+    // per step; u_{k-1} leaves for the intermediate while step k runs
     cx<R>* W1 = S;
     cx<R>* W2 = S + SL;
     cx<R>* V = S + 2 * SL;
     zero_slots(S, 2);
-    // fa = U(k-1,k)^H, fb = U(k-2,k)^H, fc = U(k,k)^{-H}, pv = y_k
-    if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(0, 2), w, lane, 0, lo_tri);
+    // fa = G1(k-1)^H, fb = G2(k-2)^H, pv = y_k: prefetched
     pre_load(pvi, in, jb.ldin, 0);
     __syncthreads();
     for (int k = 0; k < K; ++k) {
       if (!PREF && k >= 1) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k - 1, 3), w, lane, 0, NB);
-      if (!PREF && k >= 2) frag_load<R, NB, true, const cx<R>*, TS>(fb, blkh(k - 2, 4), w, lane, up_tri, NB);
+      if (!PREF && k >= 2) frag_load<R, NB, true, const cx<R>*, TS>(fb, blkh(k - 2, 4), w, lane, 0, NB);
       pre_to_acc(acc, pvi);
       if (k >= 1) frag_mma<R, NB, NC, true, true>(acc, fa, W1, LDT, nullptr, cb0, lane, 0, NB);
-      if (k >= 2) frag_mma<R, NB, NC, true, true>(acc, fb, W2, LDT, nullptr, cb0, lane, up_tri, NB);
+      if (k >= 2) frag_mma<R, NB, NC, true, true>(acc, fb, W2, LDT, nullptr, cb0, lane, 0, NB);
       acc_to_lds(acc, V, LDT, nullptr, w, cb0, lane);
-      if (k >= 1) put_mid(W1, (int64_t)(k - 1) * NB);
-      __syncthreads();
       if (k + 1 < K) {
         if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k, 3), w, lane, 0, NB);
-        if (PREF && k >= 1) frag_load<R, NB, true, const cx<R>*, TS>(fb, blkh(k - 1, 4), w, lane, up_tri, NB);
+        if (PREF && k >= 1) frag_load<R, NB, true, const cx<R>*, TS>(fb, blkh(k - 1, 4), w, lane, 0, NB);
         pre_load(pvi, in, jb.ldin, k + 1);
       }
-      if (!PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(k, 2), w, lane, 0, lo_tri);
-      acc.zero();
-      frag_mma<R, NB, NC, true, false>(acc, fc, V, LDT, nullptr, cb0, lane, 0, lo_tri);
-      if (PREF && k + 1 < K) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(k + 1, 2), w, lane, 0, lo_tri);
-      acc_to_lds(acc, W2, LDT, nullptr, w, cb0, lane);
+      if (k >= 1) put_mid(W1, (int64_t)(k - 1) * NB);
       __syncthreads();
-      cx<R>* tmp = W1;
-      W1 = W2;
-      W2 = tmp;
+      cx<R>* tmp = W2;
+      W2 = W1;
+      W1 = V;
+      V = tmp;
     }
     put_mid(W1, (int64_t)(K - 1) * NB);
     __syncthreads();
     // ---------------------------------------------------------- H backward (L^H)
-    // top = Lh11^{-H} w_k - M^H carry from w_k and the carry in LDS; then
+    // top = Q^H u_k - M^H carry from u_k and the carry in LDS; then
     // x_win = P^T [top ; carry], taken row by row through the inverse
     // permutation: window row si[d] lands on row d, rows d >= NB leave for the
     // output and rows d < NB form the next carry in the slot w_k held, and
@@ -472,14 +459,14 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
       tile_store(f0, Wk, (int64_t)(K - 1) * NB);
     }
     load_perm(K - 1);
-    // fa = M^H, fc = (Lh11^{-1})^H
+    // fa = M^H, fc = Q^H
     if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(K - 1, 1), w, lane, 0, NB);
-    if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(K - 1, 0), w, lane, up_tri, NB);
+    if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(K - 1, 0), w, lane, 0, NB);
     __syncthreads();
     for (int k = K - 1; k >= 0; --k) {
-      if (!PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(k, 0), w, lane, up_tri, NB);
+      if (!PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(k, 0), w, lane, 0, NB);
       acc.zero();
-      frag_mma<R, NB, NC, true, false>(acc, fc, Wk, LDT, nullptr, cb0, lane, up_tri, NB);
+      frag_mma<R, NB, NC, true, false>(acc, fc, Wk, LDT, nullptr, cb0, lane, 0, NB);
       if (!PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k, 1), w, lane, 0, NB);
       frag_mma<R, NB, NC, true, true>(acc, fa, Cb, LDT, nullptr, cb0, lane, 0, NB);
       TileR fw;
@@ -488,7 +475,7 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
         tile_issue(fw, mid, jb.ldmid, (int64_t)(k - 1) * NB);
         perm_issue(pnext, k - 1);
         if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k - 1, 1), w, lane, 0, NB);
-        if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(k - 1, 0), w, lane, up_tri, NB);
+        if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(k - 1, 0), w, lane, 0, NB);
       }
       acc_to_lds(acc, Vt, LDT, nullptr, w, cb0, lane);
       __syncthreads();
