@@ -62,7 +62,7 @@ def parse():
     return p.parse_args()
 
 
-# Sources of the block-solve kernel: HBM byte counts recorded under profiles/
+# Sources of the block-solve and residual kernels: HBM byte counts recorded under profiles/
 # are reported as roofline traffic only while these files are unchanged.
 SOLVE_SOURCES = ["solve_kernel.h", "solve_f32.hip", "solve_f64.hip", "solve.hip", "solve_job.h",
                  "fb_internal.h"]
@@ -77,16 +77,18 @@ def solve_source_hash() -> str:
     return h.hexdigest()
 
 
-def recorded_traffic(workload: str, precision: int):
-    """HBM bytes per launch of the block-solve kernel from the committed
-    counter summary of this workload, if taken on the current sources."""
-    path = os.path.join(ROOT, "profiles", f"solve_{workload}_traffic.json")
+def recorded_traffic(workload: str, name: str, precision: int):
+    """HBM bytes per launch of the block-solve (complex64) or FP64 residual
+    kernel from the committed counter summary of this workload, if taken on
+    the current sources."""
+    path = os.path.join(ROOT, "profiles", f"solve-resid_{workload}_traffic.json")
     try:
         with open(path) as fh:
             rec = json.load(fh)
     except OSError:
         return None
-    ent = rec.get("c64" if precision == 1 else "c128")  # only the complex64 kernel is recorded
+    key = {"solve": "solve_c64" if precision == 1 else None, "resid": "resid"}.get(name)
+    ent = rec.get(key) if key else None
     if not ent or rec.get("source_sha256") != solve_source_hash():
         return None
     return ent["hbm_bytes_per_launch"]
@@ -270,7 +272,7 @@ def roofline(prof, precision, workload):
         bound = "mfma"
     return {"kernel": name, "bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12,
             "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": recorded_traffic(workload, precision) if name == "solve" else None,
+            "traffic": recorded_traffic(workload, name, precision),
             "launches": L, "avg_launch_ms": ms / L, "work_per_launch_flop": work / L}
 
 
