@@ -172,6 +172,11 @@ def cpu_baseline(cfg, m0_mean, ncols, slices):
                        f"per-system time scaled to {cols_sys:.0f} columns per system")}
 
 
+def progress(msg: str) -> None:
+    """One line on stderr per finished leg (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def run_path(fb, groups, steps, warmup, cols_per_step, stream=None):
     """Time the filter sweep: a step applies every group's filter (F, Y, Q)
     once, in order."""
@@ -320,9 +325,13 @@ def main():
         sharing one workspace."""
         gs = [(fb.FeastFilter(B, lo[a:b], hi[a:b], m0[a:b], n_nodes=n_nodes, **kw), Y[a:b],
                Q[a:b]) for a, b in spans]
-        for F, _, _ in gs:  # sized for the verification pass, which also keeps residuals
-            F.with_resid = True
-        need = max(F.workspace_bytes(y, q) for F, y, q in gs)
+        # sized for the verification pass (which also keeps residuals) and the
+        # timed passes (without them the waves are planned differently)
+        need = 0
+        for F, y, q in gs:
+            for wr in (False, True):
+                F.with_resid = wr
+                need = max(need, F.workspace_bytes(y, q))
         ws = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
         for F, _, _ in gs:
             F._ws = ws
@@ -339,27 +348,32 @@ def main():
     for prec in (1, 0):
         v, ms = fb.autotune(B, prec, nsys=nsys_t, m=m_t, cache_path=args.tune_log)
         tuned["c64" if prec else "c128"] = {"variant": v, "ms": ms}
+        progress(f"autotune {'c64' if prec else 'c128'}: variant {v}, {ms:.1f} ms")
 
     res = {}
     G = groups(precision=1, ir_tol=1e-10, ir_max=6)
     res["fp32ir"] = run_path(fb, G, args.steps, args.warmup, cols_per_step)
+    progress(f"complex64 + refinement: {res['fp32ir']['ms_per_step']:.1f} ms/step")
     del G
     torch.cuda.empty_cache()
     # the same sweep replayed from HIP graphs on a stream of its own
     gs = torch.cuda.Stream()
     G = groups(precision=1, ir_tol=1e-10, ir_max=6, graph=True)
     res["fp32ir_graph"] = run_path(fb, G, args.steps, args.warmup, cols_per_step, stream=gs)
+    progress(f"complex64 + refinement, graph: {res['fp32ir_graph']['ms_per_step']:.1f} ms/step")
     del G
     torch.cuda.empty_cache()
     if not args.no_fp64:
         G = groups(precision=0)
         res["fp64"] = run_path(fb, G, args.steps, args.warmup, cols_per_step)
+        progress(f"FP64 batched: {res['fp64']['ms_per_step']:.1f} ms/step")
         del G
         torch.cuda.empty_cache()
         if len(spans) == 1:
             # the plain FP64 path: one launch sequence per slice, no batching
             G = groups(precision=0, batched=False)
             res["fp64_plain"] = run_path(fb, G, args.steps, args.warmup, cols_per_step)
+            progress(f"FP64 plain: {res['fp64_plain']['ms_per_step']:.1f} ms/step")
             del G
             torch.cuda.empty_cache()
 
@@ -421,9 +435,13 @@ def main():
         del Y, Q
         torch.cuda.empty_cache()
         nrm1 = band_norm1(ab)
-        out["e2e"] = [run_e2e(fb, B, cfg, lo, hi, counts, m0, prec, nrm1) for prec in (1, 0)]
+        out["e2e"] = []
+        for prec in (1, 0):
+            out["e2e"].append(run_e2e(fb, B, cfg, lo, hi, counts, m0, prec, nrm1))
+            progress(f"end to end {out['e2e'][-1]['precision']}: {out['e2e'][-1]['seconds']:.2f} s")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, float(np.mean(m0)), args.cpu_cols, slices)
+        progress(f"CPU oracle: {out['cpu_baseline']['value']:.0f} RHS-cols/s")
     print(json.dumps(out), flush=True)
 
 
