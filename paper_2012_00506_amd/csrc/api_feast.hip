@@ -514,7 +514,7 @@ void carve_feast(Arena& ar, const Band& bd, int W, int maxm, int ne, bool ir, in
   const int64_t n = bd.n;
   carve_factors<R>(ar, bd, W * ne, fb.f);
   if (ir && ne > 0) {
-    fb.fb.cap = fallback_cap(W * ne);
+    fb.fb.cap = feast_fallback_cap(W * ne);
     carve_factors<double>(ar, bd, fb.fb.cap, fb.f64fb);
     fb.fb.f = &fb.f64fb;
   }
@@ -785,6 +785,7 @@ int feast_wave(const Band& bd, int nslice, const double* lo, const double* hi, c
     }
   }
   FB_TRY(factor_systems<R>(bd, nsys, zh.data(), f, st));
+  fbuf.fb.reset();  // new shifts: no complex128 factors carry over
 
   // ---- start blocks
   std::vector<int> done(nslice, 0), kept(nslice, 0), good(nslice, 0), inside(nslice, 0);

@@ -298,6 +298,75 @@ int refine_launch(const Band& bd, const cx<R>* mats, const cx<R>* matsT, const i
   return 0;
 }
 
+// Columns of the given systems solved anew from the right-hand sides in
+// complex128 with the fallback factors (jobs of other systems are ignored):
+// sys_res gets their FP64 residual ratios, sys_pass -1.
+static int fallback_solve(const Band& bd, const std::vector<SolveJob>& jobs,
+                          const std::vector<int>& systems, const std::vector<c128>& zsys,
+                          RefineBufs& rb, std::vector<double>& sys_res,
+                          std::vector<int32_t>& sys_pass, hipStream_t st, const C128Fallback* fb) {
+  // factors kept from earlier calls are reused; the missing systems are
+  // factored (one launch) into the free slots, and all slots start over when
+  // they do not fit
+  const int nbk = block_size(bd.b);
+  const int K = (int)((bd.n + nbk - 1) / nbk);
+  std::vector<int>& ss = fb->slot_sys;
+  std::vector<int> todo = systems;
+  while (!todo.empty()) {
+    std::vector<int> missing;
+    for (int s : todo)
+      if (std::find(ss.begin(), ss.end(), s) == ss.end()) missing.push_back(s);
+    if (ss.size() + missing.size() > (size_t)fb->cap) {
+      ss.clear();
+      missing.assign(todo.begin(), todo.begin() + std::min(todo.size(), (size_t)fb->cap));
+    }
+    if (!missing.empty()) {
+      const size_t at = ss.size();
+      std::vector<double> zh(2 * missing.size());
+      for (size_t q = 0; q < missing.size(); ++q) {
+        zh[2 * q] = zsys[missing[q]].x;
+        zh[2 * q + 1] = zsys[missing[q]].y;
+      }
+      FactorBufs<double> view = *fb->f;  // slots at .. at + missing - 1
+      view.mats += at * K * 5 * (size_t)nbk * nbk;
+      view.perm += at * K * 2 * (size_t)nbk;
+      view.info += at;
+      view.z += at;
+      FB_TRY(factor_systems<double>(bd, (int)missing.size(), zh.data(), view, st));
+      ss.insert(ss.end(), missing.begin(), missing.end());
+    }
+    std::vector<int> rest;
+    std::vector<SolveJob> sub;
+    for (int s : todo)
+      if (std::find(ss.begin(), ss.end(), s) == ss.end()) rest.push_back(s);
+    for (const SolveJob& jb : jobs) {
+      if (std::find(todo.begin(), todo.end(), jb.sys) == todo.end()) continue;
+      auto it = std::find(ss.begin(), ss.end(), jb.sys);
+      if (it == ss.end()) continue;
+      SolveJob c = jb;
+      c.sys = (int32_t)(it - ss.begin());
+      c.mid = c.out;
+      c.ldmid = c.ldout;
+      c.add = 0;
+      sub.push_back(c);
+    }
+    std::vector<c128> zsub(ss.size());
+    for (size_t q = 0; q < ss.size(); ++q) zsub[q] = zsys[ss[q]];
+    std::vector<double> sres(ss.size(), 0.0);
+    std::vector<int32_t> spass(ss.size(), 0);
+    FB_TRY(solve_refine<double>(bd, fb->f->mats, nullptr, fb->f->perm, sub, zsub, false, 0.0, 0,
+                                true, rb, sres, spass, nullptr, st));
+    for (int s : todo) {
+      auto it = std::find(ss.begin(), ss.end(), s);
+      if (it == ss.end()) continue;
+      sys_res[s] = sres[it - ss.begin()];
+      sys_pass[s] = -1;
+    }
+    todo.swap(rest);
+  }
+  return 0;
+}
+
 template <typename R>
 int refine_finish(const Band& bd, const std::vector<SolveJob>& jobs,
                   const std::vector<c128>& zsys, const RefinePlan& plan, RefineBufs& rb,
@@ -326,39 +395,10 @@ int refine_finish(const Band& bd, const std::vector<SolveJob>& jobs,
   std::sort(failed.begin(), failed.end());
   failed.erase(std::unique(failed.begin(), failed.end()), failed.end());
   if (!failed.empty() && fb && fb->f && fb->cap > 0 && sizeof(R) == 4) {
-    // factor the failing systems again in complex128 and solve their
-    // columns anew from the right-hand sides, cap systems at a time
-    for (size_t c0 = 0; c0 < failed.size(); c0 += fb->cap) {
-      const size_t nc = std::min(failed.size() - c0, (size_t)fb->cap);
-      std::vector<double> zh(2 * nc);
-      std::vector<c128> zsub(nc);
-      for (size_t q = 0; q < nc; ++q) {
-        zsub[q] = zsys[failed[c0 + q]];
-        zh[2 * q] = zsub[q].x;
-        zh[2 * q + 1] = zsub[q].y;
-      }
-      FB_TRY(factor_systems<double>(bd, (int)nc, zh.data(), *fb->f, st));
-      std::vector<SolveJob> sub;
-      for (const SolveJob& jb : jobs) {
-        auto it = std::find(failed.begin() + c0, failed.begin() + c0 + nc, jb.sys);
-        if (it == failed.begin() + c0 + nc) continue;
-        SolveJob c = jb;
-        c.sys = (int32_t)(it - (failed.begin() + c0));
-        c.mid = c.out;
-        c.ldmid = c.ldout;
-        c.add = 0;
-        sub.push_back(c);
-      }
-      std::vector<double> sres(nc, 0.0);
-      std::vector<int32_t> spass(nc, 0);
-      FB_TRY(solve_refine<double>(bd, fb->f->mats, nullptr, fb->f->perm, sub, zsub, false, 0.0, 0,
-                                  true, rb, sres, spass, nullptr, st));
-      for (size_t q = 0; q < nc; ++q) {
-        const int s = failed[c0 + q];
-        sys_res[s] = sres[q];
-        sys_pass[s] = -1;
-      }
-    }
+    FB_TRY(fallback_solve(bd, jobs, failed, zsys, rb, sys_res, sys_pass, st, fb));
+    for (int s : failed)
+      if (std::find(fb->known.begin(), fb->known.end(), s) == fb->known.end())
+        fb->known.push_back(s);
   }
   if (unconverged)
     for (int s : failed)
@@ -373,6 +413,29 @@ int solve_refine(const Band& bd, const cx<R>* mats, const cx<R>* matsT, const in
                  double ir_tol, int ir_max, bool need_res, RefineBufs& rb,
                  std::vector<double>& sys_res, std::vector<int32_t>& sys_pass, int* unconverged,
                  hipStream_t st, const C128Fallback* fb) {
+  if (fb && fb->f && fb->cap > 0 && sizeof(R) == 4 && need_res && !fb->known.empty()) {
+    // systems that fell back in an earlier call go to complex128 at once
+    std::vector<SolveJob> keep;
+    std::vector<int> direct;
+    for (const SolveJob& jb : jobs) {
+      if (std::find(fb->known.begin(), fb->known.end(), jb.sys) == fb->known.end()) {
+        keep.push_back(jb);
+      } else if (std::find(direct.begin(), direct.end(), jb.sys) == direct.end()) {
+        direct.push_back(jb.sys);
+      }
+    }
+    if (!direct.empty()) {
+      FB_TRY(fallback_solve(bd, jobs, direct, zsys, rb, sys_res, sys_pass, st, fb));
+      if (unconverged)
+        for (int s : direct)
+          if (!(sys_res[s] <= ir_tol)) ++*unconverged;
+      RefinePlan plan;
+      FB_TRY(refine_prepare<R>(bd, keep, zsys, ir, ir_tol, ir_max, need_res, rb, plan, st));
+      FB_TRY(refine_launch<R>(bd, mats, matsT, perm, plan, rb, st));
+      return refine_finish<R>(bd, keep, zsys, plan, rb, sys_res, sys_pass, unconverged, st, fb,
+                              nullptr);
+    }
+  }
   RefinePlan plan;
   FB_TRY(refine_prepare<R>(bd, jobs, zsys, ir, ir_tol, ir_max, need_res, rb, plan, st));
   FB_TRY(refine_launch<R>(bd, mats, matsT, perm, plan, rb, st));

@@ -1,5 +1,7 @@
 // Work items of the batched solve and residual launches.
 #pragma once
+#include <algorithm>
+#include <vector>
 #include "fb_internal.h"
 
 namespace fb {
@@ -121,9 +123,22 @@ void carve_refine(Arena& ar, const Band& bd, int tile, int max_jobs, bool ir, bo
 struct C128Fallback {
   FactorBufs<double>* f = nullptr;
   int cap = 0;
+  // the system held in each slot of f, kept between calls with the same
+  // shifts (FEAST iterations of one wave); whoever changes the shifts of the
+  // system indices calls reset()
+  mutable std::vector<int> slot_sys;
+  // systems that fell back in an earlier call with the same shifts: later
+  // calls solve them in complex128 at once
+  mutable std::vector<int> known;
+  void reset() const {
+    slot_sys.clear();
+    known.clear();
+  }
 };
-// systems the fallback factors hold at once
+// systems the fallback factors hold at once: two for one-off solves, a
+// quarter of a FEAST wave's systems, whose factors are kept between iterations
 inline int fallback_cap(int nsys) { return nsys < 2 ? nsys : 2; }
+inline int feast_fallback_cap(int nsys) { return std::min(nsys, std::max(2, nsys / 4)); }
 size_t refine_bytes(const Band& bd, int tile, int max_jobs, bool ir, bool need_res);
 // Solve + refinement of one batch of jobs in three stages (solve_refine runs
 // all three): tables to the device, kernel launches (no host round-trip, so
