@@ -56,6 +56,9 @@ def parse():
     p.add_argument("--no-e2e", action="store_true",
                    help="skip the end-to-end FEAST runs (all slices to convergence)")
     p.add_argument("--cpu-cols", type=int, default=256, help="columns in the CPU sample")
+    p.add_argument("--eig-out", default=None, metavar="PATH",
+                   help="write the end-to-end eigenvalues and residuals of both precisions "
+                        "(.npz)")
     p.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                    help="after the timed region, run one plain device copy of MIB MiB "
                         "(calibrates the HBM byte counters of a profiler run)")
@@ -246,9 +249,12 @@ def run_e2e(fb, B, cfg, lo, hi, counts, m0, precision, nrm1):
     prof = fb.profile_read()
     fb.profile_enable(False)
     mres = max(float(r.resid[: r.m_found].max()) for r in res if r.m_found)
+    lam = np.concatenate([r.lam for r in res])
+    rel = np.concatenate([r.resid[: r.m_found] for r in res])
     del Y
     torch.cuda.empty_cache()
     return {"precision": "c64+f64 refinement" if precision else "f64", "seconds": wall,
+            "per_eigenpair": eigenpair_errors(lam, rel, nrm1), "_lam": lam, "_res": rel,
             "iters": [r.iters for r in res], "info": [r.info for r in res],
             "eigenpairs": int(sum(r.m_found for r in res)),
             "counts_match": bool(all(r.m_found == int(c) for r, c in zip(res, counts))),
@@ -258,6 +264,39 @@ def run_e2e(fb, B, cfg, lo, hi, counts, m0, precision, nrm1):
             "eig_err_bound_max": mres * nrm1,
             "breakdown_ms": {k: round(v[1], 3) for k, v in prof.items() if v[0]},
             "launches": {k: v[0] for k, v in prof.items() if v[0]}}
+
+
+def kato_temple(lam, res_abs):
+    """Per Ritz pair (lam_i, residual r_i = ||B x_i - lam_i x_i||, ||x_i|| = 1)
+    a bound on its distance to an eigenvalue of the Hermitian B: r_i^2 / d_i
+    (Kato-Temple) when the neighbouring Ritz values, widened by their own
+    residuals, leave a gap d_i > r_i on both sides, else r_i.  The outermost
+    pairs of the computed range take r_i (a neighbour beyond it is unknown)."""
+    o = np.argsort(lam)
+    l, r = lam[o], res_abs[o]
+    out = r.copy()
+    for k in range(1, len(l) - 1):
+        d = min(l[k] - l[k - 1] - r[k - 1], l[k + 1] - l[k] - r[k + 1])
+        if d > r[k]:
+            out[k] = min(r[k], r[k] ** 2 / d)
+    b = np.empty_like(out)
+    b[o] = out
+    return b
+
+
+def eigenpair_errors(lam, rel, nrm1):
+    """Per-eigenpair error figures relative to ||B||_1: the residual, the
+    residual bound on the eigenvalue error and the Kato-Temple bound, each as
+    max / 99th percentile / median over the pairs."""
+    kt = kato_temple(lam, rel * nrm1) / nrm1
+
+    def q(v):
+        return {"max": float(np.max(v)), "p99": float(np.percentile(v, 99)),
+                "median": float(np.median(v))}
+    o = np.argsort(lam)
+    inner = kt[o][1:-1] if len(lam) > 2 else kt
+    return {"pairs": int(len(lam)), "resid_rel": q(rel), "eig_err_bound_rel": q(rel),
+            "kato_temple_rel": q(kt), "kato_temple_rel_max_inner": float(np.max(inner))}
 
 
 def roofline(prof, precision, workload):
@@ -439,6 +478,19 @@ def main():
         for prec in (1, 0):
             out["e2e"].append(run_e2e(fb, B, cfg, lo, hi, counts, m0, prec, nrm1))
             progress(f"end to end {out['e2e'][-1]['precision']}: {out['e2e'][-1]['seconds']:.2f} s")
+        lam1, lam0 = out["e2e"][0]["_lam"], out["e2e"][1]["_lam"]
+        if len(lam1) == len(lam0):
+            # the same eigenpairs in both precisions (every count is exact):
+            # per-eigenpair difference of the eigenvalues, relative to ||B||_1
+            d = np.abs(np.sort(lam1) - np.sort(lam0)) / nrm1
+            out["e2e_c64_vs_f64_eig_rel"] = {"max": float(d.max()),
+                                            "p99": float(np.percentile(d, 99)),
+                                            "median": float(np.median(d))}
+        if args.eig_out:
+            np.savez(args.eig_out, lam_c64=lam1, res_c64=out["e2e"][0]["_res"], lam_f64=lam0,
+                     res_f64=out["e2e"][1]["_res"], norm1=nrm1)
+        for e in out["e2e"]:
+            del e["_lam"], e["_res"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, float(np.mean(m0)), args.cpu_cols, slices)
         progress(f"CPU oracle: {out['cpu_baseline']['value']:.0f} RHS-cols/s")
