@@ -175,6 +175,13 @@ typedef struct {
                           later calls with the same pointers, sizes and
                           options; a refinement that stagnates is redone by
                           direct launches with the complex128 fallback */
+  double ir_from;      /* feast_band_slice with precision 1: a slice's
+                          complex64 solves run without refinement (and without
+                          the FP64 residuals) while the m_i-th smallest
+                          eigen-residual of its in-slice Ritz pairs is above
+                          ir_from, for at most 3 iterations, then refined;
+                          the convergence test is on FP64 eigen-residuals
+                          either way.  0 refines from the first iteration */
 } fb_feast_opts;
 
 /* FEAST on the slices [lo_i, hi_i) of B (Algorithm alg:FEAST, Section 2.2,

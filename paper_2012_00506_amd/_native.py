@@ -35,7 +35,7 @@ class fb_feast_opts(C.Structure):
                 ("precision", C.c_int32), ("ir_tol", C.c_double), ("ir_max", C.c_int32),
                 ("batched", C.c_int32), ("hbm_budget", C.c_double), ("pairs", C.c_int32),
                 ("rule", C.c_int32), ("ratio", C.c_double), ("tune_cache", C.c_char_p),
-                ("graph", C.c_int32)]
+                ("graph", C.c_int32), ("ir_from", C.c_double)]
 
 
 class fb_plan_opts(C.Structure):

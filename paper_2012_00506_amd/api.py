@@ -191,7 +191,7 @@ def contour_nodes(lo, hi, k=8, rule="gauss", ratio=1.0):
 def feast_band_slice(B, lo, hi, Y, m_expected=None, n_nodes=8, tol=1e-10, max_iter=20,
                      precision=0, ir_tol=1e-12, ir_max=8, batched=True, hbm_budget=0.0,
                      pairs=0, rule="gauss", ratio=1.0, tune_cache=None, rerun=True,
-                     stream=None):
+                     ir_from=1e-4, stream=None):
     """FEAST on the slices [lo_i, hi_i) of B from the start blocks Y[i]
     ((n, m0_i) column-major device tensors in the dtype of B; overwritten with
     the Ritz vectors).  Returns one SliceResult per slice.
@@ -200,7 +200,11 @@ def feast_band_slice(B, lo, hi, Y, m_expected=None, n_nodes=8, tol=1e-10, max_it
     run once more (the rerun with more start vectors of Section 3.2) from a
     new block of m0' = ceil(1.5 max(m, m_found)) + 10 columns: its Ritz
     vectors first, then seeded random columns.  That slice's SliceResult
-    then refers to the new block, not to Y[i]."""
+    then refers to the new block, not to Y[i].
+
+    ir_from (precision 1): a slice's complex64 solves skip refinement and the
+    FP64 residuals while its eigen-residuals are above ir_from (at most 3
+    iterations); 0 refines from the first iteration."""
     B = _as_band(B)
     lo = np.ascontiguousarray(np.asarray(lo, dtype=np.float64).ravel())
     hi = np.ascontiguousarray(np.asarray(hi, dtype=np.float64).ravel())
@@ -225,7 +229,8 @@ def feast_band_slice(B, lo, hi, Y, m_expected=None, n_nodes=8, tol=1e-10, max_it
     inf = np.zeros(ns, np.int32)
     o = N.fb_feast_opts(n_nodes, tol, max_iter, precision, ir_tol, ir_max, 1 if batched else 0,
                         float(hbm_budget), int(pairs), _RULES[rule], float(ratio),
-                        None if tune_cache is None else str(tune_cache).encode(), 0)
+                        None if tune_cache is None else str(tune_cache).encode(), 0,
+                        float(ir_from))
     bs = B.struct()
     L = N.lib()
     sh = C.c_void_p(_stream_handle(stream))
@@ -269,7 +274,8 @@ def feast_band_slice(B, lo, hi, Y, m_expected=None, n_nodes=8, tol=1e-10, max_it
                                 n_nodes=n_nodes, tol=tol, max_iter=max_iter,
                                 precision=precision, ir_tol=ir_tol, ir_max=ir_max,
                                 batched=batched, hbm_budget=hbm_budget, pairs=pairs, rule=rule,
-                                ratio=ratio, tune_cache=tune_cache, rerun=False, stream=stream)
+                                ratio=ratio, tune_cache=tune_cache, rerun=False, ir_from=ir_from,
+                                stream=stream)
         for a, i in enumerate(redo):
             out[i] = res2[a]
     return out

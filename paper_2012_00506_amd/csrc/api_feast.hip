@@ -806,11 +806,18 @@ int feast_wave(const Band& bd, int nslice, const double* lo, const double* hi, c
   std::vector<double> sys_res(nsys, 0.0);
   std::vector<int32_t> sys_pass(nsys, 0);
   std::vector<SolveJob> jobs;
+  // complex64 solves without refinement while a slice is far from converged
+  // (its eigen-residuals, computed in FP64, decide; at most kCoarseIters
+  // iterations): they move the subspace as far as refined ones there
+  constexpr int kCoarseIters = 3;
+  std::vector<int> coarse(nslice, ir && o->ir_from > 0 ? 1 : 0), ncoarse(nslice, 0);
   for (int it = 1; it <= o->max_iter; ++it) {
     std::vector<int> act;
     for (int i = 0; i < nslice; ++i)
       if (!done[i]) act.push_back(i);
     if (act.empty()) break;
+    std::vector<int> act_c, act_r;
+    for (int i : act) (coarse[i] ? act_c : act_r).push_back(i);
     // ---- filter: Q = sum_j w_j (z_j - B)^{-1} Y (+ conj(w_j)(z_j - B)^{-H} Y)
     {
       std::vector<c128*> Yc(nslice), Qc(nslice);
@@ -820,10 +827,16 @@ int feast_wave(const Band& bd, int nslice, const double* lo, const double* hi, c
         Qc[i] = sb[i].Q;
         Xp[(size_t)i * P] = sb[i].X;  // X and Y trade places every iteration
       }
-      FB_TRY(filter_apply<R>(bd, f, ne, act, m0, Yc.data(), lds.data(), Qc.data(), lds.data(),
-                             Xp.data(), P, acc_dev, zsys, wsys, cplx, o->batched != 0, ir,
-                             o->ir_tol, o->ir_max, ir, rb, sys_res, sys_pass, nullptr, st,
-                             ir ? &fbuf.fb : nullptr));
+      if (!act_c.empty())
+        FB_TRY(filter_apply<R>(bd, f, ne, act_c, m0, Yc.data(), lds.data(), Qc.data(),
+                               lds.data(), Xp.data(), P, acc_dev, zsys, wsys, cplx,
+                               o->batched != 0, false, o->ir_tol, o->ir_max, false, rb, sys_res,
+                               sys_pass, nullptr, st, nullptr));
+      if (!act_r.empty())
+        FB_TRY(filter_apply<R>(bd, f, ne, act_r, m0, Yc.data(), lds.data(), Qc.data(),
+                               lds.data(), Xp.data(), P, acc_dev, zsys, wsys, cplx,
+                               o->batched != 0, ir, o->ir_tol, o->ir_max, ir, rb, sys_res,
+                               sys_pass, nullptr, st, ir ? &fbuf.fb : nullptr));
       for (int i : act)
         for (int j = 0; j < ne; ++j)
           if (sys_pass[i * ne + j] < 0) fellback[i] = 1;
@@ -856,6 +869,17 @@ int feast_wave(const Band& bd, int nslice, const double* lo, const double* hi, c
       good[i] = g;
       inside[i] = in;
       if (g == mexp[i]) done[i] = 1;
+      if (coarse[i] && !done[i]) {
+        // refinement from here on once the m-th smallest in-slice residual
+        // is at ir_from
+        std::vector<double> rin;
+        for (int c = 0; c < k; ++c)
+          if (hl[i][c] >= lo[i] && hl[i][c] < hi[i]) rin.push_back(hr[i][c]);
+        std::sort(rin.begin(), rin.end());
+        const int need = std::max(mexp[i], 1);
+        const bool near = (int)rin.size() >= need && rin[need - 1] <= o->ir_from;
+        if (near || ++ncoarse[i] >= kCoarseIters) coarse[i] = 0;
+      }
     }
   }
 
