@@ -98,6 +98,34 @@ def test_feast_several_slices_batched_equals_unbatched(fb):
         assert torch.equal(res[True][i].Y, res[False][i].Y)
 
 
+@pytest.mark.parametrize("ir_from", [0.0, 1e-4, 1.0])
+def test_feast_coarse_start_iterations(fb, ir_from):
+    """precision 1 with ir_from: unrefined complex64 sweeps while the slices
+    are far from converged (1.0: every slice starts that way, capped at 3
+    iterations), then refined ones.  The result meets the same bars as the
+    refined run from the first iteration, within one more iteration."""
+    print(f"feast coarse start ir_from={ir_from}", flush=True)
+    n = 1500
+    ab = synth.band_matrix(n, 12, 55, True, -10, 10)
+    edges = [-4.0, -1.5, 1.0]
+    lam_all = np.linalg.eigvalsh(oband.dense_from_band(ab))
+    Ys, refs = [], []
+    for i in range(2):
+        ref = lam_all[(lam_all >= edges[i]) & (lam_all < edges[i + 1])]
+        refs.append(ref)
+        Ys.append(start_block(fb, n, m0_rule(len(ref)), 70 + i, True)[1])
+    Y0 = [y.clone() for y in Ys]
+    base = fb.feast_band_slice(ab, edges[:-1], edges[1:], Y0, precision=1, ir_tol=1e-10,
+                               ir_from=0.0)
+    res = fb.feast_band_slice(ab, edges[:-1], edges[1:], Ys, precision=1, ir_tol=1e-10,
+                              ir_from=ir_from)
+    for i in range(2):
+        check_slice(res[i], ab, edges[i], edges[i + 1], refs[i])
+        assert res[i].iters <= base[i].iters + 1
+        if ir_from == 0.0:  # the same run
+            assert np.array_equal(res[i].evals, base[i].evals)
+
+
 def test_feast_m0_below_count_flagged(fb):
     n = 200
     ab = synth.band_matrix(n, 4, 14, True, -6, 6)
