@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import synth
+from kt_bound import kato_temple as _kato_temple
 from oracle import band as oband
 from oracle import inertia as oin
 
@@ -43,21 +44,6 @@ def setup():
 def _start(fb, cfg, m0, i):
     y = synth.rhs_block_device(cfg.n, m0, cfg.seed * 1000 + i, True)
     return y if y.stride(0) == 1 else y.contiguous().t().contiguous().t()
-
-
-def _kato_temple(lam, res_abs, lo, hi):
-    """Upper bounds of |lam_k - lambda| for the eigenvalue lambda nearest to
-    each Ritz value (lam ascending, every eigenvalue in [lo, hi) accounted for
-    by the exact counts, res_abs = ||r_k||_2; the eigenvalues outside lie
-    below lo or at or above hi)."""
-    out = np.full(len(lam), np.inf)
-    for k in range(len(lam)):
-        gaps = [lam[k] - lo if k == 0 else lam[k] - lam[k - 1] - res_abs[k - 1]]
-        gaps.append(hi - lam[k] if k + 1 == len(lam) else lam[k + 1] - lam[k] - res_abs[k + 1])
-        gap = min(gaps) - res_abs[k]
-        if gap > 0:
-            out[k] = res_abs[k] ** 2 / gap
-    return out
 
 
 def test_cfg2_all_slices_mixed_precision(setup):

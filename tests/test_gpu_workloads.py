@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import synth
+from kt_bound import kato_temple
 from oracle import band as oband
 from oracle import inertia as oin
 
@@ -101,6 +102,15 @@ def test_n65536_b128_lowest_slices(fb):
     print(f"feast {ns} slices: {time.time() - t0:.1f} s, iters {[r.iters for r in res]}",
           flush=True)
     _check_results(ab, bounds, res, cols_per_slice=2)
+    # every eigenvalue within 1e-12 ||B||_1 of an exact one: the counts of
+    # [bounds[0], bounds[ns]) are exact, so the Kato-Temple bound applies
+    nrm = oband.norm1(ab)
+    lam = np.concatenate([r.lam for r in res])
+    rab = np.concatenate([r.resid[: r.m_found] for r in res]) * nrm
+    assert np.all(np.diff(lam) >= 0)
+    kt = kato_temple(lam, rab, bounds[0], bounds[ns])
+    print(f"max Kato-Temple bound {kt.max() / nrm:.3e} ||B||_1", flush=True)
+    assert kt.max() <= 1e-12 * nrm
 
 
 def test_scf_sequence_repartition(fb):
