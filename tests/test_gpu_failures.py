@@ -97,3 +97,37 @@ def test_feast_forced_fallback_reports_info3(fb):
     assert r.info == 3 and r.m_found == len(ref)
     assert np.abs(r.lam - ref).max() <= 1e-12 * nrm
     assert r.resid[: r.m_found].max() <= 1e-10
+
+
+@pytest.mark.parametrize("waves", [False, True])
+def test_feast_fallback_every_iteration_several_slices(fb, waves):
+    """Refinement forced to fail from the first iteration on three slices:
+    every system falls back to complex128 in every iteration, through the
+    factors kept between iterations (a quarter of the wave's systems, so
+    slots are reused) and, after the first, straight to complex128.  With
+    waves (one slice per wave: pairs = 1 and a tiny HBM budget) the kept
+    factors are dropped between waves.  The eigenpairs meet the FP64 bars
+    and equal those of the FP64 run to 1e-12 ||B||_1."""
+    n, b = 900, 10
+    ab = synth.band_matrix(n, b, 35, True, -8, 8)
+    nrm = oband.norm1(ab)
+    lam_all = np.linalg.eigvalsh(oband.dense_from_band(ab))
+    edges = [-3.0, -1.0, 0.8, 2.5]
+    refs, Y1, Y0 = [], [], []
+    for i in range(3):
+        ref = lam_all[(lam_all >= edges[i]) & (lam_all < edges[i + 1])]
+        refs.append(ref)
+        Yh = synth.rhs_block(n, max(math.ceil(1.5 * len(ref)), len(ref) + 10), 60 + i, True)
+        Y1.append(fb.to_colmajor(Yh))
+        Y0.append(fb.to_colmajor(Yh))
+    kw = dict(pairs=1, hbm_budget=1.0) if waves else {}
+    print(f"feast fallback every iteration, waves={waves}", flush=True)
+    r1 = fb.feast_band_slice(ab, edges[:-1], edges[1:], Y1, precision=1, ir_tol=1e-300,
+                             ir_max=1, ir_from=0.0, **kw)
+    r0 = fb.feast_band_slice(ab, edges[:-1], edges[1:], Y0, precision=0, **kw)
+    for i in range(3):
+        assert r1[i].info == 3 and r1[i].m_found == len(refs[i])
+        assert r0[i].info == 0 and r0[i].m_found == len(refs[i])
+        assert np.abs(r1[i].lam - refs[i]).max() <= 1e-12 * nrm
+        assert np.abs(r1[i].lam - r0[i].lam).max() <= 1e-12 * nrm
+        assert r1[i].resid[: r1[i].m_found].max() <= 1e-10
