@@ -463,6 +463,150 @@ k_block_invert(cx<R>* __restrict__ mats, int b, int nblk) {
     for (int e = t; e < bb; e += blockDim.x) M[e] = A[e];
 }
 
+// The same inverses by 16 x 16 tiles on MFMA: one workgroup per (system,
+// block, which) and one wave per 16-column tile j of the inverse X, held in
+// LDS (rows padded to 17 elements).  Each wave first inverts its diagonal
+// tile by the column recurrences above (16 lanes), then, after a barrier,
+// runs the substitution down (L) or up (U) its tile column:
+//   L: X(i,j) = -D(i)^{-1} sum_{k=j}^{i-1} L(i,k) X(k,j),   i = j+1 .. T-1
+//   U: X(i,j) = -D(i)^{-1} sum_{k=i+1}^{j} U(i,k) X(k,j),   i = j-1 .. 0
+// with D(i)^{-1} read from the diagonal tile of wave i's column; the sums
+// are products of L or U tiles (fragments read from global memory) with the
+// wave's own column (LDS), in Gauss form.  A wave hands values between its
+// lanes through LDS under a wavefront fence.  All waves finish reading the
+// block before the inverse is written over it.
+template <typename R, int NB>
+__global__ void __launch_bounds__(NB * 4)
+k_block_invert_mfma(cx<R>* __restrict__ mats, int nblk) {
+  constexpr int T = NB / 16;
+  constexpr int LDT = 17;
+  extern __shared__ __align__(16) char lds_raw[];
+  cx<R>* Xs = reinterpret_cast<cx<R>*>(lds_raw);  // T columns of NB x LDT
+  const int g = blockIdx.x;
+  const int blk = g >> 1, which = g & 1;  // 0: Lh11 (slot 0), 1: U(k,k) (slot 2)
+  if (blk >= nblk) return;
+  cx<R>* M = mats + ((size_t)blk * 5 + (which ? 2 : 0)) * NB * NB;
+  const int t = threadIdx.x, lane = t & 63;
+  const int j = __builtin_amdgcn_readfirstlane(t >> 6);  // this wave's tile column
+  cx<R>* X = Xs + (size_t)j * NB * LDT;                  // X(r, c) at r LDT + c
+  auto wfence = [] {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  // the column tile: zero, with the diagonal tile of M at rows 16 j ..
+  for (int e = lane; e < NB * 16; e += 64) {
+    const int r = e % NB, c = e / NB;
+    cx<R> v = mk<R>(0, 0);
+    if (r >= 16 * j && r < 16 * j + 16) v = M[(size_t)(16 * j + c) * NB + r];
+    X[r * LDT + c] = v;
+  }
+  wfence();
+  cx<R>* D = X + 16 * j * LDT;  // D(r, c) at r LDT + c
+  const int r = lane;
+  if (which == 0) {
+    // unit lower: column c below the diagonal = -Dinv22 l (trailing part done)
+    for (int c = 14; c >= 0; --c) {
+      cx<R> acc = mk<R>(0, 0);
+      if (r > c && r < 16) {
+        acc = D[r * LDT + c];
+        for (int q = c + 1; q < r; ++q) cmac(acc, D[r * LDT + q], D[q * LDT + c]);
+      }
+      wfence();
+      if (r > c && r < 16) D[r * LDT + c] = mk<R>(-acc.x, -acc.y);
+      wfence();
+    }
+    if (r < 16) {
+      D[r * LDT + r] = mk<R>((R)1, (R)0);
+      for (int c = r + 1; c < 16; ++c) D[r * LDT + c] = mk<R>(0, 0);
+    }
+  } else {
+    // upper: column c above the diagonal = -Dinv11 u / d_cc (leading part done)
+    for (int c = 0; c < 16; ++c) {
+      const cx<R> d = cinv(D[c * LDT + c]);
+      cx<R> acc = mk<R>(0, 0);
+      if (r < c) {
+        for (int q = r; q < c; ++q) cmac(acc, D[r * LDT + q], D[q * LDT + c]);
+        acc = acc * d;
+      }
+      wfence();
+      if (r < c) D[r * LDT + c] = mk<R>(-acc.x, -acc.y);
+      if (r == c) D[r * LDT + r] = d;
+      wfence();
+    }
+    if (r < 16)
+      for (int c = 0; c < r; ++c) D[r * LDT + c] = mk<R>(0, 0);
+  }
+  __syncthreads();
+  // substitution along the tile column; fragments of the D(i)^{-1} tile:
+  // register s holds D(i)^{-1}(lane % 16, 4 s + lane / 16)
+  auto dinv_frag = [&](Frag<R, 16>& f, int i) {
+    const cx<R>* Di = Xs + (size_t)i * NB * LDT + 16 * i * LDT;
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) f.a[s2] = Di[(lane & 15) * LDT + 4 * s2 + (lane >> 4)];
+  };
+  const int lo = which == 0 ? j + 1 : 0, hi = which == 0 ? T : j;
+  for (int step = 0; step < hi - lo; ++step) {
+    const int i = which == 0 ? lo + step : hi - 1 - step;
+    const int k0 = which == 0 ? 16 * j : 16 * (i + 1);
+    const int k1 = which == 0 ? 16 * i : 16 * (j + 1);
+    Frag<R, NB> f;
+    frag_load<R, NB, false>(f, (const cx<R>*)M, i, lane, k0, k1);
+    Acc<R, 1> acc;
+    acc.zero();
+    frag_mma<R, NB, 1, false, false>(acc, f, X, LDT, nullptr, 0, lane, k0, k1);
+    acc_to_lds(acc, X, LDT, nullptr, i, 0, lane);  // the sum, at rows 16 i ..
+    wfence();
+    Frag<R, 16> fd;
+    dinv_frag(fd, i);
+    Acc<R, 1> acc2;
+    acc2.zero();
+    frag_mma<R, 16, 1, false, true>(acc2, fd, X + 16 * i * LDT, LDT, nullptr, 0, lane, 0, 16);
+    wfence();
+    acc_to_lds(acc2, X, LDT, nullptr, i, 0, lane);
+    wfence();
+  }
+  __syncthreads();  // every wave has read M
+  for (int e = lane; e < NB * 16; e += 64) {
+    const int rr = e % NB, c = e / NB;
+    gst(M + (size_t)(16 * j + c) * NB + rr, X[rr * LDT + c]);
+  }
+}
+
+template <typename R, int NB>
+static int launch_invert_mfma_nb(cx<R>* mats, int nblk, hipStream_t st) {
+  const size_t smem = sizeof(cx<R>) * (size_t)(NB / 16) * NB * 17;
+  if (smem > kLdsBudget) return FB_ERR_INTERNAL;
+  (void)hipFuncSetAttribute((const void*)k_block_invert_mfma<R, NB>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
+  (void)hipGetLastError();
+  k_block_invert_mfma<R, NB><<<2 * nblk, NB * 4, smem, st>>>(mats, nblk);
+  FB_HIP(hipGetLastError());
+  return 0;
+}
+
+// 1: inverted by tiles on MFMA; 0: the tiled form does not fit LDS (the
+// column-recurrence kernel is used)
+template <typename R>
+static int launch_invert_mfma(cx<R>* mats, int nb, int nblk, hipStream_t st, int* done) {
+  *done = 0;
+  if (sizeof(cx<R>) * (size_t)(nb / 16) * nb * 17 > kLdsBudget) return 0;
+  int rc = 0;
+  switch (nb) {
+    case 16: rc = launch_invert_mfma_nb<R, 16>(mats, nblk, st); break;
+    case 32: rc = launch_invert_mfma_nb<R, 32>(mats, nblk, st); break;
+    case 48: rc = launch_invert_mfma_nb<R, 48>(mats, nblk, st); break;
+    case 64: rc = launch_invert_mfma_nb<R, 64>(mats, nblk, st); break;
+    case 80: rc = launch_invert_mfma_nb<R, 80>(mats, nblk, st); break;
+    case 96: rc = launch_invert_mfma_nb<R, 96>(mats, nblk, st); break;
+    case 112: rc = launch_invert_mfma_nb<R, 112>(mats, nblk, st); break;
+    case 128: rc = launch_invert_mfma_nb<R, 128>(mats, nblk, st); break;
+    default: return FB_ERR_INTERNAL;
+  }
+  if (rc == 0) *done = 1;
+  return rc;
+}
+
 // M = Lh21 Lh11^{-1} in place of Lh21 (slot 1), one workgroup per block and
 // one wave per 16 rows: a wave holds its rows of Lh21 as MFMA fragments and
 // multiplies them by panels of PW columns of the lower triangular inverse
@@ -700,11 +844,15 @@ int launch_lu_impl(const Band& bd, int nsys, const c128* z_dev, cx<R>* mats, cx<
   // Q, G1, G2 (nb^3 / 3 + nb^3 / 2 + nb^3 / 3)
   ProfScope ps(FB_PROF_INVERT, st,
                8.0 * nblk * (double)nb * nb * nb * (2.0 / 3.0 + 0.5 + 7.0 / 6.0));
-  if (ilds)
-    k_block_invert<R, true><<<2 * nblk, 256, ismem, st>>>(mats, nb, nblk);
-  else
-    k_block_invert<R, false><<<2 * nblk, 256, ismem, st>>>(mats, nb, nblk);
-  FB_HIP(hipGetLastError());
+  int tiled = 0;
+  FB_TRY(launch_invert_mfma<R>(mats, nb, nblk, st, &tiled));
+  if (!tiled) {
+    if (ilds)
+      k_block_invert<R, true><<<2 * nblk, 256, ismem, st>>>(mats, nb, nblk);
+    else
+      k_block_invert<R, false><<<2 * nblk, 256, ismem, st>>>(mats, nb, nblk);
+    FB_HIP(hipGetLastError());
+  }
   FB_TRY(launch_form_m<R>(mats, nb, nblk, st));
   FB_TRY(launch_form_qg<R>(mats, nb, nblk, st));
   if (matsT) {
