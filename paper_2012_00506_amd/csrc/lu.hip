@@ -630,9 +630,11 @@ k_form_m(cx<R>* __restrict__ mats, int nblk) {
   frag_load<R, NB, false>(f, L21, w, lane, 0, NB);
   for (int p0 = 0; p0 < NB; p0 += PW) {
     __syncthreads();
+    // the last panel of a block that PW does not divide is partial: its
+    // columns beyond the block are zeros and are not written
     for (int e = t; e < NB * PW; e += NB * 4) {
       const int k = e % NB, c = e / NB;
-      Lp[k * LD + c] = Li[(size_t)(p0 + c) * NB + k];
+      Lp[k * LD + c] = p0 + c < NB ? Li[(size_t)(p0 + c) * NB + k] : mk<R>(0, 0);
     }
     __syncthreads();
     Acc<R, NC> acc;
@@ -644,7 +646,7 @@ k_form_m(cx<R>* __restrict__ mats, int nblk) {
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * w + MF<R>::row(lane, r);
         const int col = p0 + 16 * c + (lane & 15);
-        gst(L21 + (size_t)col * NB + row, acc.get(c, r));
+        if (col < NB) gst(L21 + (size_t)col * NB + row, acc.get(c, r));
       }
   }
 }
@@ -719,7 +721,8 @@ k_form_qg(cx<R>* __restrict__ mats, int nblk) {
       __syncthreads();
       for (int e = t; e < NB * PW; e += NB * 4) {
         const int k = e % NB, c = e / NB;
-        cx<R> v = O[(size_t)(p0 + c) * NB + k];
+        // a partial last panel (PW does not divide NB): zeros beyond the block
+        cx<R> v = p0 + c < NB ? O[(size_t)(p0 + c) * NB + k] : mk<R>(0, 0);
         if (lower && k < p0 + c) v = mk<R>(0, 0);
         Bp[k * LD + c] = v;
       }
@@ -733,7 +736,7 @@ k_form_qg(cx<R>* __restrict__ mats, int nblk) {
         for (int r = 0; r < 4; ++r) {
           const int row = 16 * w + MF<R>::row(lane, r);
           const int col = p0 + 16 * c + (lane & 15);
-          gst(O + (size_t)col * NB + row, acc.get(c, r));
+          if (col < NB) gst(O + (size_t)col * NB + row, acc.get(c, r));
         }
     }
   }

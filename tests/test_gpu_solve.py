@@ -104,7 +104,9 @@ def _check_against_oracle(ab, z, Yh, r, tol_x, tol_res, want_h=True, cols=None):
 
 
 CASES = [(1000, 16, True, 70), (700, 64, True, 40), (50, 40, False, 33), (40, 0, True, 5),
-         (333, 1, False, 17), (400, 128, True, 20), (129, 64, False, 1)]
+         (333, 1, False, 17), (400, 128, True, 20), (129, 64, False, 1),
+         # every other block size of the factor blocks (32, 80, 96, 112 rows)
+         (300, 30, True, 24), (350, 70, False, 19), (410, 90, True, 21), (460, 100, True, 18)]
 
 
 @pytest.mark.parametrize("n,b,cplx,m", CASES)
