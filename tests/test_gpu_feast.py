@@ -77,6 +77,21 @@ def test_feast_small_against_oracle(fb, cplx, precision):
     check_slice(r, ab, lo, hi, ref, ora)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_feast_bandwidth_90(fb, precision):
+    """FEAST at b = 90 (factor blocks of 96 rows, which 64-column panels do
+    not divide) against the dense eigenvalues, in both precisions."""
+    print(f"feast b=90 precision={precision}", flush=True)
+    n = 600
+    ab = synth.band_matrix(n, 90, 91, True, -10, 10)
+    lam_all = np.linalg.eigvalsh(oband.dense_from_band(ab))
+    lo, hi = -1.5, 1.0
+    ref = lam_all[(lam_all >= lo) & (lam_all < hi)]
+    _, Y = start_block(fb, n, m0_rule(len(ref)), 91, True)
+    [r] = fb.feast_band_slice(ab, [lo], [hi], [Y], precision=precision)
+    check_slice(r, ab, lo, hi, ref)
+
+
 def test_feast_several_slices_batched_equals_unbatched(fb):
     n = 500
     ab = synth.band_matrix(n, 9, 31, True, -10, 10)

@@ -49,7 +49,8 @@ def certified_shifts(ab, k, seed):
 
 
 @pytest.mark.parametrize("n,b,cplx", [(300, 7, True), (257, 16, False), (97, 64, True),
-                                      (130, 128, True), (40, 0, False), (1, 0, True)])
+                                      (130, 128, True), (40, 0, False), (1, 0, True),
+                                      (150, 33, False), (200, 90, True)])
 def test_inertia_parity(fb, n, b, cplx):
     print(f"inertia n={n} b={b} cplx={cplx}", flush=True)
     ab = synth.band_matrix(n, b, 100 + n, cplx, -10, 10)
