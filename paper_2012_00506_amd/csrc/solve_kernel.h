@@ -184,6 +184,84 @@ struct PreT {
   int k;
 };
 
+// ---------------------------------------------------------------- chunk streaming
+// The streamed form of a step's two block products: chunk ch is columns
+// 16 ch .. 16 ch + 15 of op(A) for the wave's 16 rows (four complex values
+// per lane), loaded RD chunks ahead of the MFMAs that use it, across the two
+// products and into the next step (the carry), so that only RD + 1 chunks
+// live in registers instead of whole fragments.  TR: element (i, k) of op(A)
+// at A[i NB + k] (a conjugate transpose read from the block itself), else at
+// A[k NB + i].
+template <typename R>
+struct Ck {
+  cx<R> a[4];
+};
+
+template <typename R, int NB, bool TR>
+__device__ __forceinline__ void ck_load(Ck<R>& c, const cx<R>* A, int w, int lane, int ch) {
+  const int i = 16 * w + (lane & 15), kq = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int k = 16 * ch + 4 * q + kq;
+    c.a[q] = TR ? A[(size_t)i * NB + k] : A[(size_t)k * NB + i];
+  }
+}
+
+template <typename R, bool CONJT, bool NEG>
+__device__ __forceinline__ void ck_mma(Acc<R, 1>& acc, const Ck<R>& c, const cx<R>* Bl, int ldb,
+                                       const int* rmap, int cb0, int lane, int ch) {
+  const int kq = lane >> 4, j = lane & 15;
+  cx<R> bv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int k = 16 * ch + 4 * q + kq;
+    const int br = rmap ? rmap[k] : k;
+    bv[q] = Bl[(size_t)br * ldb + cb0 + j];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    R ar = c.a[q].x, ai = CONJT ? -c.a[q].y : c.a[q].y;
+    if (NEG) {
+      ar = -ar;
+      ai = -ai;
+    }
+    acc.p1[0] = MF<R>::mma(ar, bv[q].x, acc.p1[0]);
+    acc.p2[0] = MF<R>::mma(ai, bv[q].y, acc.p2[0]);
+    acc.p3[0] = MF<R>::mma(ar + ai, bv[q].x + bv[q].y, acc.p3[0]);
+  }
+}
+
+// acc += op(A0) B0 (NEG0: -=), mid(), acc += op(A1) B1 (NEG1: -=), both over
+// all NB columns; carry holds the first RD chunks of A0 on entry and, when
+// more, of Anext (the next step's A0) on exit (RD <= NB / 16).
+template <typename R, int NB, bool TR, bool CONJT, bool NEG0, bool NEG1, int RD, class Mid>
+__device__ __forceinline__ void stream_step(Acc<R, 1>& acc, Ck<R> (&carry)[RD], const cx<R>* A0,
+                                            const cx<R>* A1, const cx<R>* Anext, bool more,
+                                            const cx<R>* B0, const cx<R>* B1, const int* rm0,
+                                            const int* rm1, int ldb, int cb0, int w, int lane,
+                                            Mid mid) {
+  constexpr int NCH = NB / 16, L = 2 * NCH;
+  static_assert(RD >= 1 && RD <= NCH, "the carry holds chunks of the first product only");
+  Ck<R> buf[L + RD];
+#pragma unroll
+  for (int i = 0; i < RD; ++i) buf[i] = carry[i];
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const int ip = i + RD;
+    if (ip < L)
+      ck_load<R, NB, TR>(buf[ip], ip < NCH ? A0 : A1, w, lane, ip % NCH);
+    else if (more)
+      ck_load<R, NB, TR>(buf[ip], Anext, w, lane, ip - L);
+    if (i == NCH) mid();
+    if (i < NCH)
+      ck_mma<R, CONJT, NEG0>(acc, buf[i], B0, ldb, rm0, cb0, lane, i);
+    else
+      ck_mma<R, CONJT, NEG1>(acc, buf[i], B1, ldb, rm1, cb0, lane, i - NCH);
+  }
+#pragma unroll
+  for (int i = 0; i < RD; ++i) carry[i] = buf[L + i];
+}
+
 // ---------------------------------------------------------------- MFMA block solve
 // One workgroup per job with one wave per 16 x (16 NC) output tile of a block
 // product ((NB/16) x (T/(16 NC)) waves; a wave with NC > 1 reuses each factor
@@ -193,7 +271,7 @@ struct PreT {
 // e on row e % NB, column e / NB, so that a wave reads or writes whole column
 // runs of 64 rows.  OCC > 1 asks the compiler to fit the registers of OCC
 // waves per SIMD.
-template <typename R, int NB, int T, bool PREF, int NC, int OCC>
+template <typename R, int NB, int T, bool PREF, int NC, int OCC, bool STR = false>
 __global__ void __launch_bounds__(NB * 4 * (T / (16 * NC)), OCC)
 k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
              const int16_t* __restrict__ permg, int64_t n, int K,
@@ -343,200 +421,354 @@ k_band_solve(const cx<R>* __restrict__ mats, const cx<R>* __restrict__ matsT,
   PreT<cx<R>, NC> pvm;  // intermediates (N backward)
   PreT<c128, NC> pvi;   // right-hand sides (H forward)
 
-  if (jb.dir == 0) {
-    // ---------------------------------------------------------- N forward
-    // v_k = Q z_top and the next window top z_bot - M z_top are both
-    // products of z_top = rows sp[0, NB) of the window
-    cx<R>* W = S;           // window: rows 0 .. 2 NB - 1 (two slots)
-    cx<R>* Yt = S + 2 * SL; // v_k on its way to the intermediate
-    {
-      TileC f0, f1;
-      tile_issue(f0, in, jb.ldin, 0);
-      tile_issue(f1, in, jb.ldin, NB);
-      tile_store(f0, W, 0);
-      tile_store(f1, W + SL, NB);
-    }
-    TileC fr;
-    load_perm(0);
-    if (PREF) frag_load<R, NB, false>(fa, blk(0, 0), w, lane, 0, NB);
-    __syncthreads();
-    for (int k = 0; k < K; ++k) {
-      if (PREF) frag_load<R, NB, false>(fb, blk(k, 1), w, lane, 0, NB);
-      if (!PREF) frag_load<R, NB, false>(fa, blk(k, 0), w, lane, 0, NB);
-      acc.zero();
-      frag_mma<R, NB, NC, false, false>(acc, fa, W, LDT, sp, cb0, lane, 0, NB);
-      acc_to_lds(acc, Yt, LDT, nullptr, w, cb0, lane);
-      tile_issue(fr, in, jb.ldin, (int64_t)(k + 2) * NB);  // consumed after the product
-      PermPre pnext;
-      if (k + 1 < K) perm_issue(pnext, k + 1);
-      if (PREF && k + 1 < K) frag_load<R, NB, false>(fa, blk(k + 1, 0), w, lane, 0, NB);
-      if (!PREF) frag_load<R, NB, false>(fb, blk(k, 1), w, lane, 0, NB);
-      acc_from_lds(acc, W, LDT, sp + NB, w, cb0, lane);
-      frag_mma<R, NB, NC, false, true>(acc, fb, W, LDT, sp, cb0, lane, 0, NB);
-      __syncthreads();
-      acc_to_lds(acc, W, LDT, nullptr, w, cb0, lane);
-      tile_store(fr, W + SL, (int64_t)(k + 2) * NB);
-      put_mid(Yt, (int64_t)k * NB);
-      if (k + 1 < K) perm_store(pnext);
-      __syncthreads();
-    }
-    // ---------------------------------------------------------- N backward
-    // x_k = v_k - G1 x_{k+1} - G2 x_{k+2}, one set of products per step;
-    // x_{k+1} leaves for the output while step k runs
-    cx<R>* X1 = S;
-    cx<R>* X2 = S + SL;
-    cx<R>* V = S + 2 * SL;
-    zero_slots(S, 2);
-    // fa = G1(k), fb = G2(k), pv = v_k: prefetched (the last step uses
-    // neither block)
-    pre_load(pvm, mid, jb.ldmid, K - 1);
-    __syncthreads();
-    for (int k = K - 1; k >= 0; --k) {
-      if (!PREF && k + 1 < K) frag_load<R, NB, false>(fa, blk(k, 3), w, lane, 0, NB);
-      if (!PREF && k + 2 < K) frag_load<R, NB, false>(fb, blk(k, 4), w, lane, 0, NB);
-      pre_to_acc(acc, pvm);
-      if (k + 1 < K) frag_mma<R, NB, NC, false, true>(acc, fa, X1, LDT, nullptr, cb0, lane, 0, NB);
-      if (k + 2 < K) frag_mma<R, NB, NC, false, true>(acc, fb, X2, LDT, nullptr, cb0, lane, 0, NB);
-      acc_to_lds(acc, V, LDT, nullptr, w, cb0, lane);
-      if (k > 0) {
-        if (PREF) frag_load<R, NB, false>(fa, blk(k - 1, 3), w, lane, 0, NB);
-        if (PREF && k + 1 < K) frag_load<R, NB, false>(fb, blk(k - 1, 4), w, lane, 0, NB);
-        pre_load(pvm, mid, jb.ldmid, k - 1);
-      }
-      if (k + 1 < K) emit_tile(X1, (int64_t)(k + 1) * NB);
-      __syncthreads();
-      cx<R>* tmp = X2;
-      X2 = X1;
-      X1 = V;
-      V = tmp;
-    }
-    emit_tile(X1, 0);
-  } else {
-    // ---------------------------------------------------------- H forward (U^H)
-    // u_k = y_k - G1(k-1)^H u_{k-1} - G2(k-2)^H u_{k-2}, one set of products
-    // per step; u_{k-1} leaves for the intermediate while step k runs
-    cx<R>* W1 = S;
-    cx<R>* W2 = S + SL;
-    cx<R>* V = S + 2 * SL;
-    zero_slots(S, 2);
-    // fa = G1(k-1)^H, fb = G2(k-2)^H, pv = y_k: prefetched
-    pre_load(pvi, in, jb.ldin, 0);
-    __syncthreads();
-    for (int k = 0; k < K; ++k) {
-      if (!PREF && k >= 1) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k - 1, 3), w, lane, 0, NB);
-      if (!PREF && k >= 2) frag_load<R, NB, true, const cx<R>*, TS>(fb, blkh(k - 2, 4), w, lane, 0, NB);
-      pre_to_acc(acc, pvi);
-      if (k >= 1) frag_mma<R, NB, NC, true, true>(acc, fa, W1, LDT, nullptr, cb0, lane, 0, NB);
-      if (k >= 2) frag_mma<R, NB, NC, true, true>(acc, fb, W2, LDT, nullptr, cb0, lane, 0, NB);
-      acc_to_lds(acc, V, LDT, nullptr, w, cb0, lane);
-      if (k + 1 < K) {
-        if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k, 3), w, lane, 0, NB);
-        if (PREF && k >= 1) frag_load<R, NB, true, const cx<R>*, TS>(fb, blkh(k - 1, 4), w, lane, 0, NB);
-        pre_load(pvi, in, jb.ldin, k + 1);
-      }
-      if (k >= 1) put_mid(W1, (int64_t)(k - 1) * NB);
-      __syncthreads();
-      cx<R>* tmp = W2;
-      W2 = W1;
-      W1 = V;
-      V = tmp;
-    }
-    put_mid(W1, (int64_t)(K - 1) * NB);
-    __syncthreads();
-    // ---------------------------------------------------------- H backward (L^H)
-    // top = Q^H u_k - M^H carry from u_k and the carry in LDS; then
-    // x_win = P^T [top ; carry], taken row by row through the inverse
-    // permutation: window row si[d] lands on row d, rows d >= NB leave for the
-    // output and rows d < NB form the next carry in the slot w_k held, and
-    // w_{k-1} goes to the slot of the old carry.
-    cx<R>* Cb = S;           // carry: window bottom
-    cx<R>* Wk = S + SL;      // w_k, then the next carry
-    cx<R>* Vt = S + 2 * SL;  // top of the window after the step
-    zero_slots(Cb, 1);
-    {
-      TileR f0;
-      tile_issue(f0, mid, jb.ldmid, (int64_t)(K - 1) * NB);
-      tile_store(f0, Wk, (int64_t)(K - 1) * NB);
-    }
-    load_perm(K - 1);
-    // fa = M^H, fc = Q^H
-    if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(K - 1, 1), w, lane, 0, NB);
-    if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(K - 1, 0), w, lane, 0, NB);
-    __syncthreads();
-    for (int k = K - 1; k >= 0; --k) {
-      if (!PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(k, 0), w, lane, 0, NB);
-      acc.zero();
-      frag_mma<R, NB, NC, true, false>(acc, fc, Wk, LDT, nullptr, cb0, lane, 0, NB);
-      if (!PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k, 1), w, lane, 0, NB);
-      frag_mma<R, NB, NC, true, true>(acc, fa, Cb, LDT, nullptr, cb0, lane, 0, NB);
-      TileR fw;
-      PermPre pnext;
-      if (k > 0) {
-        tile_issue(fw, mid, jb.ldmid, (int64_t)(k - 1) * NB);
-        perm_issue(pnext, k - 1);
-        if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k - 1, 1), w, lane, 0, NB);
-        if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(k - 1, 0), w, lane, 0, NB);
-      }
-      acc_to_lds(acc, Vt, LDT, nullptr, w, cb0, lane);
-      __syncthreads();
+  if constexpr (STR) {
+    static_assert(NC == 1, "streamed products take one 16-column tile per wave");
+    // chunks in flight: the carry into the next step holds chunks of its
+    // first product only, so at most that product's NB / 16 chunks
+    constexpr int RD = NB >= 32 ? 2 : 1;
+    Ck<R> carry[RD];
+    auto none = [] {};
+    if (jb.dir == 0) {
+      // ------------------------------------------------------- N forward
+      cx<R>* W = S;
+      cx<R>* Yt = S + 2 * SL;
       {
-        cx<R> carry[RF], leave[RF];
+        TileC f0, f1;
+        tile_issue(f0, in, jb.ldin, 0);
+        tile_issue(f1, in, jb.ldin, NB);
+        tile_store(f0, W, 0);
+        tile_store(f1, W + SL, NB);
+      }
+      TileC fr;
+      load_perm(0);
 #pragma unroll
-        for (int q = 0; q < RF; ++q) {
-          const int r = erow(q), col = ecol(q);
-          const int ic = si[r], il = si[NB + r];
-          carry[q] = ic < NB ? Vt[ic * LDT + col] : Cb[(ic - NB) * LDT + col];
-          leave[q] = il < NB ? Vt[il * LDT + col] : Cb[(il - NB) * LDT + col];
+      for (int i = 0; i < RD; ++i) ck_load<R, NB, false>(carry[i], blk(0, 0), w, lane, i);
+      __syncthreads();
+      for (int k = 0; k < K; ++k) {
+        PermPre pnext;
+        acc.zero();
+        const bool more = k + 1 < K;
+        stream_step<R, NB, false, false, false, true, RD>(
+            acc, carry, blk(k, 0), blk(k, 1), blk(more ? k + 1 : k, 0), more, W, W, sp, sp, LDT,
+            cb0, w, lane, [&] {
+              acc_to_lds(acc, Yt, LDT, nullptr, w, cb0, lane);
+              tile_issue(fr, in, jb.ldin, (int64_t)(k + 2) * NB);
+              if (k + 1 < K) perm_issue(pnext, k + 1);
+              acc_from_lds(acc, W, LDT, sp + NB, w, cb0, lane);
+            });
+        __syncthreads();
+        acc_to_lds(acc, W, LDT, nullptr, w, cb0, lane);
+        tile_store(fr, W + SL, (int64_t)(k + 2) * NB);
+        put_mid(Yt, (int64_t)k * NB);
+        if (k + 1 < K) perm_store(pnext);
+        __syncthreads();
+      }
+      // ------------------------------------------------------- N backward
+      // blocks beyond the last (G1(K-1), G2(K-2), G2(K-1)) are zero, as are
+      // the x slots beyond x_{K-1}: every step runs both products
+      cx<R>* X1 = S;
+      cx<R>* X2 = S + SL;
+      cx<R>* V = S + 2 * SL;
+      zero_slots(S, 2);
+      pre_load(pvm, mid, jb.ldmid, K - 1);
+#pragma unroll
+      for (int i = 0; i < RD; ++i) ck_load<R, NB, false>(carry[i], blk(K - 1, 3), w, lane, i);
+      __syncthreads();
+      for (int k = K - 1; k >= 0; --k) {
+        pre_to_acc(acc, pvm);
+        const bool more = k > 0;
+        stream_step<R, NB, false, false, true, true, RD>(
+            acc, carry, blk(k, 3), blk(k, 4), blk(more ? k - 1 : k, 3), more, X1, X2, nullptr,
+            nullptr, LDT, cb0, w, lane, none);
+        acc_to_lds(acc, V, LDT, nullptr, w, cb0, lane);
+        if (k > 0) pre_load(pvm, mid, jb.ldmid, k - 1);
+        if (k + 1 < K) emit_tile(X1, (int64_t)(k + 1) * NB);
+        __syncthreads();
+        cx<R>* tmp = X2;
+        X2 = X1;
+        X1 = V;
+        V = tmp;
+      }
+      emit_tile(X1, 0);
+    } else {
+      // ------------------------------------------------------- H forward
+      // G1(k-1)^H and G2(k-2)^H meet zero slots before the first steps
+      // (block 0 stands in for the missing ones)
+      constexpr bool TRH = !TS;
+      cx<R>* W1 = S;
+      cx<R>* W2 = S + SL;
+      cx<R>* V = S + 2 * SL;
+      zero_slots(S, 2);
+      pre_load(pvi, in, jb.ldin, 0);
+#pragma unroll
+      for (int i = 0; i < RD; ++i) ck_load<R, NB, TRH>(carry[i], blkh(0, 3), w, lane, i);
+      __syncthreads();
+      for (int k = 0; k < K; ++k) {
+        pre_to_acc(acc, pvi);
+        const bool more = k + 1 < K;
+        stream_step<R, NB, TRH, true, true, true, RD>(
+            acc, carry, blkh(k >= 1 ? k - 1 : 0, 3), blkh(k >= 2 ? k - 2 : 0, 4), blkh(k, 3), more,
+            W1, W2, nullptr, nullptr, LDT, cb0, w, lane, none);
+        acc_to_lds(acc, V, LDT, nullptr, w, cb0, lane);
+        if (k >= 1) put_mid(W1, (int64_t)(k - 1) * NB);
+        if (k + 1 < K) pre_load(pvi, in, jb.ldin, k + 1);
+        __syncthreads();
+        cx<R>* tmp = W2;
+        W2 = W1;
+        W1 = V;
+        V = tmp;
+      }
+      put_mid(W1, (int64_t)(K - 1) * NB);
+      __syncthreads();
+      // ------------------------------------------------------- H backward
+      cx<R>* Cb = S;
+      cx<R>* Wk = S + SL;
+      cx<R>* Vt = S + 2 * SL;
+      zero_slots(Cb, 1);
+      {
+        TileR f0;
+        tile_issue(f0, mid, jb.ldmid, (int64_t)(K - 1) * NB);
+        tile_store(f0, Wk, (int64_t)(K - 1) * NB);
+      }
+      load_perm(K - 1);
+#pragma unroll
+      for (int i = 0; i < RD; ++i) ck_load<R, NB, TRH>(carry[i], blkh(K - 1, 0), w, lane, i);
+      __syncthreads();
+      for (int k = K - 1; k >= 0; --k) {
+        acc.zero();
+        const bool more = k > 0;
+        stream_step<R, NB, TRH, true, false, true, RD>(
+            acc, carry, blkh(k, 0), blkh(k, 1), blkh(more ? k - 1 : k, 0), more, Wk, Cb, nullptr,
+            nullptr, LDT, cb0, w, lane, none);
+        TileR fw;
+        PermPre pnext;
+        if (k > 0) {
+          tile_issue(fw, mid, jb.ldmid, (int64_t)(k - 1) * NB);
+          perm_issue(pnext, k - 1);
         }
+        acc_to_lds(acc, Vt, LDT, nullptr, w, cb0, lane);
+        __syncthreads();
+        {
+          cx<R> cv[RF], lv[RF];
 #pragma unroll
-        for (int q = 0; q < RF; ++q) Wk[erow(q) * LDT + ecol(q)] = carry[q];
-        emit_vals(leave, (int64_t)k * NB + NB);
+          for (int q = 0; q < RF; ++q) {
+            const int r = erow(q), col = ecol(q);
+            const int ic = si[r], il = si[NB + r];
+            cv[q] = ic < NB ? Vt[ic * LDT + col] : Cb[(ic - NB) * LDT + col];
+            lv[q] = il < NB ? Vt[il * LDT + col] : Cb[(il - NB) * LDT + col];
+          }
+#pragma unroll
+          for (int q = 0; q < RF; ++q) Wk[erow(q) * LDT + ecol(q)] = cv[q];
+          emit_vals(lv, (int64_t)k * NB + NB);
+        }
+        __syncthreads();
+        if (k > 0) {
+          tile_store(fw, Cb, (int64_t)(k - 1) * NB);
+          perm_store(pnext);
+        }
+        cx<R>* tmp = Cb;
+        Cb = Wk;
+        Wk = tmp;
+        __syncthreads();
       }
-      __syncthreads();
-      if (k > 0) {
-        tile_store(fw, Cb, (int64_t)(k - 1) * NB);
-        perm_store(pnext);
-      }
-      cx<R>* tmp = Cb;
-      Cb = Wk;
-      Wk = tmp;
-      __syncthreads();
+      emit_tile(Cb, 0);
     }
-    emit_tile(Cb, 0);
+  } else {
+    if (jb.dir == 0) {
+      // ---------------------------------------------------------- N forward
+      // v_k = Q z_top and the next window top z_bot - M z_top are both
+      // products of z_top = rows sp[0, NB) of the window
+      cx<R>* W = S;           // window: rows 0 .. 2 NB - 1 (two slots)
+      cx<R>* Yt = S + 2 * SL; // v_k on its way to the intermediate
+      {
+        TileC f0, f1;
+        tile_issue(f0, in, jb.ldin, 0);
+        tile_issue(f1, in, jb.ldin, NB);
+        tile_store(f0, W, 0);
+        tile_store(f1, W + SL, NB);
+      }
+      TileC fr;
+      load_perm(0);
+      if (PREF) frag_load<R, NB, false>(fa, blk(0, 0), w, lane, 0, NB);
+      __syncthreads();
+      for (int k = 0; k < K; ++k) {
+        if (PREF) frag_load<R, NB, false>(fb, blk(k, 1), w, lane, 0, NB);
+        if (!PREF) frag_load<R, NB, false>(fa, blk(k, 0), w, lane, 0, NB);
+        acc.zero();
+        frag_mma<R, NB, NC, false, false>(acc, fa, W, LDT, sp, cb0, lane, 0, NB);
+        acc_to_lds(acc, Yt, LDT, nullptr, w, cb0, lane);
+        tile_issue(fr, in, jb.ldin, (int64_t)(k + 2) * NB);  // consumed after the product
+        PermPre pnext;
+        if (k + 1 < K) perm_issue(pnext, k + 1);
+        if (PREF && k + 1 < K) frag_load<R, NB, false>(fa, blk(k + 1, 0), w, lane, 0, NB);
+        if (!PREF) frag_load<R, NB, false>(fb, blk(k, 1), w, lane, 0, NB);
+        acc_from_lds(acc, W, LDT, sp + NB, w, cb0, lane);
+        frag_mma<R, NB, NC, false, true>(acc, fb, W, LDT, sp, cb0, lane, 0, NB);
+        __syncthreads();
+        acc_to_lds(acc, W, LDT, nullptr, w, cb0, lane);
+        tile_store(fr, W + SL, (int64_t)(k + 2) * NB);
+        put_mid(Yt, (int64_t)k * NB);
+        if (k + 1 < K) perm_store(pnext);
+        __syncthreads();
+      }
+      // ---------------------------------------------------------- N backward
+      // x_k = v_k - G1 x_{k+1} - G2 x_{k+2}, one set of products per step;
+      // x_{k+1} leaves for the output while step k runs
+      cx<R>* X1 = S;
+      cx<R>* X2 = S + SL;
+      cx<R>* V = S + 2 * SL;
+      zero_slots(S, 2);
+      // fa = G1(k), fb = G2(k), pv = v_k: prefetched (the last step uses
+      // neither block)
+      pre_load(pvm, mid, jb.ldmid, K - 1);
+      __syncthreads();
+      for (int k = K - 1; k >= 0; --k) {
+        if (!PREF && k + 1 < K) frag_load<R, NB, false>(fa, blk(k, 3), w, lane, 0, NB);
+        if (!PREF && k + 2 < K) frag_load<R, NB, false>(fb, blk(k, 4), w, lane, 0, NB);
+        pre_to_acc(acc, pvm);
+        if (k + 1 < K) frag_mma<R, NB, NC, false, true>(acc, fa, X1, LDT, nullptr, cb0, lane, 0, NB);
+        if (k + 2 < K) frag_mma<R, NB, NC, false, true>(acc, fb, X2, LDT, nullptr, cb0, lane, 0, NB);
+        acc_to_lds(acc, V, LDT, nullptr, w, cb0, lane);
+        if (k > 0) {
+          if (PREF) frag_load<R, NB, false>(fa, blk(k - 1, 3), w, lane, 0, NB);
+          if (PREF && k + 1 < K) frag_load<R, NB, false>(fb, blk(k - 1, 4), w, lane, 0, NB);
+          pre_load(pvm, mid, jb.ldmid, k - 1);
+        }
+        if (k + 1 < K) emit_tile(X1, (int64_t)(k + 1) * NB);
+        __syncthreads();
+        cx<R>* tmp = X2;
+        X2 = X1;
+        X1 = V;
+        V = tmp;
+      }
+      emit_tile(X1, 0);
+    } else {
+      // ---------------------------------------------------------- H forward (U^H)
+      // u_k = y_k - G1(k-1)^H u_{k-1} - G2(k-2)^H u_{k-2}, one set of products
+      // per step; u_{k-1} leaves for the intermediate while step k runs
+      cx<R>* W1 = S;
+      cx<R>* W2 = S + SL;
+      cx<R>* V = S + 2 * SL;
+      zero_slots(S, 2);
+      // fa = G1(k-1)^H, fb = G2(k-2)^H, pv = y_k: prefetched
+      pre_load(pvi, in, jb.ldin, 0);
+      __syncthreads();
+      for (int k = 0; k < K; ++k) {
+        if (!PREF && k >= 1) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k - 1, 3), w, lane, 0, NB);
+        if (!PREF && k >= 2) frag_load<R, NB, true, const cx<R>*, TS>(fb, blkh(k - 2, 4), w, lane, 0, NB);
+        pre_to_acc(acc, pvi);
+        if (k >= 1) frag_mma<R, NB, NC, true, true>(acc, fa, W1, LDT, nullptr, cb0, lane, 0, NB);
+        if (k >= 2) frag_mma<R, NB, NC, true, true>(acc, fb, W2, LDT, nullptr, cb0, lane, 0, NB);
+        acc_to_lds(acc, V, LDT, nullptr, w, cb0, lane);
+        if (k + 1 < K) {
+          if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k, 3), w, lane, 0, NB);
+          if (PREF && k >= 1) frag_load<R, NB, true, const cx<R>*, TS>(fb, blkh(k - 1, 4), w, lane, 0, NB);
+          pre_load(pvi, in, jb.ldin, k + 1);
+        }
+        if (k >= 1) put_mid(W1, (int64_t)(k - 1) * NB);
+        __syncthreads();
+        cx<R>* tmp = W2;
+        W2 = W1;
+        W1 = V;
+        V = tmp;
+      }
+      put_mid(W1, (int64_t)(K - 1) * NB);
+      __syncthreads();
+      // ---------------------------------------------------------- H backward (L^H)
+      // top = Q^H u_k - M^H carry from u_k and the carry in LDS; then
+      // x_win = P^T [top ; carry], taken row by row through the inverse
+      // permutation: window row si[d] lands on row d, rows d >= NB leave for the
+      // output and rows d < NB form the next carry in the slot w_k held, and
+      // w_{k-1} goes to the slot of the old carry.
+      cx<R>* Cb = S;           // carry: window bottom
+      cx<R>* Wk = S + SL;      // w_k, then the next carry
+      cx<R>* Vt = S + 2 * SL;  // top of the window after the step
+      zero_slots(Cb, 1);
+      {
+        TileR f0;
+        tile_issue(f0, mid, jb.ldmid, (int64_t)(K - 1) * NB);
+        tile_store(f0, Wk, (int64_t)(K - 1) * NB);
+      }
+      load_perm(K - 1);
+      // fa = M^H, fc = Q^H
+      if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(K - 1, 1), w, lane, 0, NB);
+      if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(K - 1, 0), w, lane, 0, NB);
+      __syncthreads();
+      for (int k = K - 1; k >= 0; --k) {
+        if (!PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(k, 0), w, lane, 0, NB);
+        acc.zero();
+        frag_mma<R, NB, NC, true, false>(acc, fc, Wk, LDT, nullptr, cb0, lane, 0, NB);
+        if (!PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k, 1), w, lane, 0, NB);
+        frag_mma<R, NB, NC, true, true>(acc, fa, Cb, LDT, nullptr, cb0, lane, 0, NB);
+        TileR fw;
+        PermPre pnext;
+        if (k > 0) {
+          tile_issue(fw, mid, jb.ldmid, (int64_t)(k - 1) * NB);
+          perm_issue(pnext, k - 1);
+          if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fa, blkh(k - 1, 1), w, lane, 0, NB);
+          if (PREF) frag_load<R, NB, true, const cx<R>*, TS>(fc, blkh(k - 1, 0), w, lane, 0, NB);
+        }
+        acc_to_lds(acc, Vt, LDT, nullptr, w, cb0, lane);
+        __syncthreads();
+        {
+          cx<R> carry[RF], leave[RF];
+  #pragma unroll
+          for (int q = 0; q < RF; ++q) {
+            const int r = erow(q), col = ecol(q);
+            const int ic = si[r], il = si[NB + r];
+            carry[q] = ic < NB ? Vt[ic * LDT + col] : Cb[(ic - NB) * LDT + col];
+            leave[q] = il < NB ? Vt[il * LDT + col] : Cb[(il - NB) * LDT + col];
+          }
+  #pragma unroll
+          for (int q = 0; q < RF; ++q) Wk[erow(q) * LDT + ecol(q)] = carry[q];
+          emit_vals(leave, (int64_t)k * NB + NB);
+        }
+        __syncthreads();
+        if (k > 0) {
+          tile_store(fw, Cb, (int64_t)(k - 1) * NB);
+          perm_store(pnext);
+        }
+        cx<R>* tmp = Cb;
+        Cb = Wk;
+        Wk = tmp;
+        __syncthreads();
+      }
+      emit_tile(Cb, 0);
+    }
   }
 }
 
 
-template <typename R, int NB, int T, bool PREF, int NC, int OCC>
+template <typename R, int NB, int T, bool PREF, int NC, int OCC, bool STR = false>
 int launch_nb(const cx<R>* mats, const cx<R>* matsT, const int16_t* perm, int64_t n, int njobs,
               const SolveJob* jobs_dev, hipStream_t st, const int32_t* gate) {
   const int K = (int)((n + NB - 1) / NB);
   size_t smem = solve_lds_bytes(NB, T, sizeof(cx<R>));
-  (void)hipFuncSetAttribute((const void*)k_band_solve<R, NB, T, PREF, NC, OCC>,
+  (void)hipFuncSetAttribute((const void*)k_band_solve<R, NB, T, PREF, NC, OCC, STR>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   (void)hipGetLastError();
   for (int j0 = 0; j0 < njobs; j0 += 1 << 20) {
     int nj = njobs - j0 < (1 << 20) ? njobs - j0 : (1 << 20);
     int grid = 8 * ((nj + 7) / 8);
-    k_band_solve<R, NB, T, PREF, NC, OCC><<<grid, NB * 4 * (T / (16 * NC)), smem, st>>>(
+    k_band_solve<R, NB, T, PREF, NC, OCC, STR><<<grid, NB * 4 * (T / (16 * NC)), smem, st>>>(
         mats, matsT, perm, n, K, jobs_dev + j0, nj, gate);
     FB_HIP(hipGetLastError());
   }
   return 0;
 }
 
-template <typename R, int T, bool PREF, int NC, int OCC = 1>
+template <typename R, int T, bool PREF, int NC, int OCC = 1, bool STR = false>
 int launch_t(const cx<R>* mats, const cx<R>* matsT, const int16_t* perm, int64_t n, int nb,
              int njobs, const SolveJob* jobs_dev, hipStream_t st, const int32_t* gate) {
   switch (nb) {
-    case 16: return launch_nb<R, 16, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
-    case 32: return launch_nb<R, 32, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
-    case 48: return launch_nb<R, 48, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
-    case 64: return launch_nb<R, 64, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
-    case 80: return launch_nb<R, 80, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
-    case 96: return launch_nb<R, 96, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
-    case 112: return launch_nb<R, 112, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
-    case 128: return launch_nb<R, 128, T, PREF, NC, OCC>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
+    case 16: return launch_nb<R, 16, T, PREF, NC, OCC, STR>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
+    case 32: return launch_nb<R, 32, T, PREF, NC, OCC, STR>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
+    case 48: return launch_nb<R, 48, T, PREF, NC, OCC, STR>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
+    case 64: return launch_nb<R, 64, T, PREF, NC, OCC, STR>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
+    case 80: return launch_nb<R, 80, T, PREF, NC, OCC, STR>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
+    case 96: return launch_nb<R, 96, T, PREF, NC, OCC, STR>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
+    case 112: return launch_nb<R, 112, T, PREF, NC, OCC, STR>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
+    case 128: return launch_nb<R, 128, T, PREF, NC, OCC, STR>(mats, matsT, perm, n, njobs, jobs_dev, st, gate);
     default: return FB_ERR_INTERNAL;
   }
 }
@@ -550,6 +782,8 @@ int launch_variant(int variant, const cx<R>* mats, const cx<R>* matsT, const int
                    const int32_t* gate) {
   // complex128 fragments are twice as wide: capped at two waves they spill
   constexpr int kOcc2 = sizeof(R) == 4 ? 2 : 1;
+  // streamed products (8, 9): fragments no longer fill the registers
+  constexpr int kOccS = 1;
   switch (variant) {
     case 0: return launch_t<R, 16, false, 1>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
     case 1: return launch_t<R, 16, true, 1>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
@@ -559,6 +793,8 @@ int launch_variant(int variant, const cx<R>* mats, const cx<R>* matsT, const int
     case 5: return launch_t<R, 32, true, 2, kOcc2>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
     case 6: return launch_t<R, 16, false, 1, 3>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
     case 7: return launch_t<R, 16, true, 1, 3>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
+    case 8: return launch_t<R, 16, false, 1, kOccS, true>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
+    case 9: return launch_t<R, 32, false, 1, kOccS, true>(mats, matsT, perm, n, nb, njobs, jobs_dev, st, gate);
     default: return FB_ERR_INTERNAL;
   }
 }

@@ -8,9 +8,10 @@ namespace fb {
 // fragments of the next block product are prefetched into registers, how
 // many 16-column tiles one wave computes (2 for v = 4, 5, with registers
 // capped for two waves per SIMD in complex64), and for v = 6, 7 (16-column tiles)
-// registers capped for three waves per SIMD
-constexpr int kNumVariants = 8;
-inline int variant_tile(int v) { return (v >= 2 && v < 6) ? 32 : 16; }
+// registers capped for three waves per SIMD; v = 8, 9 (16- and 32-column
+// tiles) stream their factor fragments chunk by chunk instead
+constexpr int kNumVariants = 10;
+inline int variant_tile(int v) { return ((v >= 2 && v < 6) || v == 9) ? 32 : 16; }
 inline bool variant_prefetch(int v) { return (v & 1) != 0; }
 inline int variant_nc(int v) { return (v == 4 || v == 5) ? 2 : 1; }
 // dynamic LDS of the block-solve kernel: the block's permutation and its
