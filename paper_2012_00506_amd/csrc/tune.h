@@ -14,6 +14,10 @@ constexpr int kNumVariants = 10;
 inline int variant_tile(int v) { return ((v >= 2 && v < 6) || v == 9) ? 32 : 16; }
 inline bool variant_prefetch(int v) { return (v & 1) != 0; }
 inline int variant_nc(int v) { return (v == 4 || v == 5) ? 2 : 1; }
+inline bool variant_streamed(int v) { return v >= 8; }
+// a streamed variant is chosen only when it takes under this fraction of the
+// best other variant's time
+constexpr float kStreamedMargin = 0.97f;
 // dynamic LDS of the block-solve kernel: the block's permutation and its
 // inverse (2 NB entries each) and three NB x T slots of the factors' element
 // type with rows padded to T + 1

@@ -117,13 +117,26 @@ int autotune_impl(const fb_band* B, int nsys, int m, const char* path, int32_t* 
     FB_HIP(hipEventElapsedTime(&ms, e0, e1));
     ms *= 0.5f;
     timed.push_back({v, ms});
-    if (best < 0 || ms < best_ms) {
-      best = v;
-      best_ms = ms;
-    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  // The streamed variants hold one wave per SIMD: on a launch with fewer
+  // workgroups than this full-batch problem (one slice at a time) they hide
+  // less latency, so one wins only by a clear margin over the best of the rest.
+  int best_s = -1;
+  float best_s_ms = 0.f;
+  for (const auto& tv : timed) {
+    int& b = variant_streamed(tv.first) ? best_s : best;
+    float& b_ms = variant_streamed(tv.first) ? best_s_ms : best_ms;
+    if (b < 0 || tv.second < b_ms) {
+      b = tv.first;
+      b_ms = tv.second;
+    }
+  }
+  if (best_s >= 0 && (best < 0 || best_s_ms < kStreamedMargin * best_ms)) {
+    best = best_s;
+    best_ms = best_s_ms;
+  }
   if (best < 0) return FB_ERR_INTERNAL;
   set_tuned_variant(sizeof(R), nb, best);
   if (chosen) *chosen = best;
