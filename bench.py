@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 # workloads whose slices are placed by exact inertia: (slices, lowest
 # eigenvalues covered, slices per filter group -- the factors of one group's
 # systems and its buffers stay well inside the 288 GB of HBM)
-PLANNED = {"cplx-n65536-b128": (64, 25600, 16)}
+PLANNED = {"cplx-n65536-b128": (64, 25600, 32)}
 # band sections above this order are sampled on the CPU by a leading section
 CPU_SECTION = 8192
 
@@ -56,6 +56,8 @@ def parse():
     p.add_argument("--no-e2e", action="store_true",
                    help="skip the end-to-end FEAST runs (all slices to convergence)")
     p.add_argument("--cpu-cols", type=int, default=256, help="columns in the CPU sample")
+    p.add_argument("--group", type=int, default=0, metavar="SLICES",
+                   help="slices per filter group of a planned workload (default: its table entry)")
     p.add_argument("--eig-out", default=None, metavar="PATH",
                    help="write the end-to-end eigenvalues and residuals of both precisions "
                         "(.npz)")
@@ -341,6 +343,8 @@ def main():
         group = len(slices)
     else:  # equal-count slices of the lowest nev eigenvalues, by exact inertia
         K, nev, group = PLANNED[cfg.name]
+        if args.group > 0:
+            group = args.group
         bounds, _, _ = fb.slice_plan(B, K, "equal_count", nev=nev)
         slices = [(float(bounds[i]), float(bounds[i + 1])) for i in range(K)]
     edges = [slices[0][0]] + [s[1] for s in slices]

@@ -108,10 +108,28 @@ __device__ __forceinline__ uint64_t ordered_bits(double v) {
   return (uint64_t)__double_as_longlong(v);
 }
 
+// The elimination window: wholly in LDS, or split at element offset `split`
+// (a whole number of physical rows) with the leading rows in LDS and the rest
+// in the system's global scratch, so that only rows past the split add to
+// the per-step global traffic and the cache footprint.  The split form's
+// accesses are flat ones.
+template <typename R, bool USE_LDS>
+struct LuWindow {
+  cx<R>* l;
+  cx<R>* g;
+  int split;
+  __device__ __forceinline__ cx<R>& operator[](int e) const {
+    if constexpr (USE_LDS)
+      return l[e];
+    else
+      return *(e < split ? l + e : g + e);
+  }
+};
+
 template <typename R, bool USE_LDS>
 __global__ void __launch_bounds__(kLuThreads)
 k_band_lu(const c128* __restrict__ Bd_, int64_t n, int b, int nb, int K,
-          const c128* __restrict__ zs, FactorOut<R> out, cx<R>* __restrict__ gwin) {
+          const c128* __restrict__ zs, FactorOut<R> out, cx<R>* __restrict__ gwin, int wsplit) {
   extern __shared__ __align__(16) char lds_raw[];
   const int MR = b + 2, MC = 2 * b + 2;
   const int s = blockIdx.x;
@@ -127,8 +145,9 @@ k_band_lu(const c128* __restrict__ Bd_, int64_t n, int b, int nb, int K,
   int* lrow = pivp + 4;                   // two storage-row tables (block parity)
   cx<R>* lvec = reinterpret_cast<cx<R>*>(lds_raw + ((sizeof(int) * (MR + 8 * nb + 4) + 15) & ~15));
   // the window's memory is a compile-time choice, so that LDS accesses are
-  // LDS instructions rather than flat ones
-  cx<R>* W = USE_LDS ? lvec + b + 1 : gwin + (size_t)s * MR * MC;
+  // LDS instructions rather than flat ones where the whole window fits
+  const LuWindow<R, USE_LDS> W{lvec + b + 1, USE_LDS ? nullptr : gwin + (size_t)s * MR * MC,
+                               wsplit};
   const c128* Bd = Bd_;
 
   cx<R>* mats = out.mats + (size_t)s * K * 5 * nb * nb;
@@ -780,6 +799,15 @@ static size_t lu_lds_bytes(int b) {
   return lu_lds_head_bytes<R>(b) + sizeof(cx<R>) * (size_t)(b + 2) * (2 * b + 2);
 }
 
+// whole window rows that fit in LDS beside the head when the window does not
+template <typename R>
+static int lu_lds_rows(int b) {
+  const size_t row = sizeof(cx<R>) * (size_t)(2 * b + 2);
+  const size_t head = lu_lds_head_bytes<R>(b);
+  const size_t rows = head < kLdsBudget ? (kLdsBudget - head) / row : 0;
+  return (int)std::min<size_t>(rows, (size_t)b + 2);
+}
+
 template <typename R>
 size_t lu_window_scratch(int b, int nsys) {
   if (lu_lds_bytes<R>(b) <= kLdsBudget) return 0;
@@ -824,16 +852,25 @@ int launch_lu_impl(const Band& bd, int nsys, const c128* z_dev, cx<R>* mats, cx<
   const int K = (int)((bd.n + nb - 1) / nb);
   FactorOut<R> o{mats, perm, info, lscr};
   bool lds = lu_lds_bytes<R>(b) <= kLdsBudget;
-  size_t smem = lds ? lu_lds_bytes<R>(b) : lu_lds_head_bytes<R>(b);
+  // split window: the leading physical rows that fit stay in LDS
+  const int lrows = lds ? b + 2 : lu_lds_rows<R>(b);
+  const int wsplit = lrows * (2 * b + 2);
+  size_t smem = lds ? lu_lds_bytes<R>(b)
+                    : lu_lds_head_bytes<R>(b) + sizeof(cx<R>) * (size_t)wsplit;
+  if (smem > kLdsBudget) return FB_ERR_INTERNAL;
   (void)hipFuncSetAttribute((const void*)k_band_lu<R, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
+  (void)hipFuncSetAttribute((const void*)k_band_lu<R, false>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
   (void)hipGetLastError();
   {
     ProfScope ps(FB_PROF_LU, st, 16.0 * (double)bd.n * b * b * nsys);
     if (lds)
-      k_band_lu<R, true><<<nsys, kLuThreads, smem, st>>>(bd.Bd, bd.n, b, nb, K, z_dev, o, scratch);
+      k_band_lu<R, true><<<nsys, kLuThreads, smem, st>>>(bd.Bd, bd.n, b, nb, K, z_dev, o, scratch,
+                                                         wsplit);
     else
-      k_band_lu<R, false><<<nsys, kLuThreads, smem, st>>>(bd.Bd, bd.n, b, nb, K, z_dev, o, scratch);
+      k_band_lu<R, false><<<nsys, kLuThreads, smem, st>>>(bd.Bd, bd.n, b, nb, K, z_dev, o, scratch,
+                                                          wsplit);
     FB_HIP(hipGetLastError());
   }
   size_t full = sizeof(cx<R>) * ((size_t)nb * nb + nb);
