@@ -484,7 +484,9 @@ k_block_invert(cx<R>* __restrict__ mats, int b, int nblk) {
 
 // The same inverses by 16 x 16 tiles on MFMA: one workgroup per (system,
 // block, which) and one wave per 16-column tile j of the inverse X, held in
-// LDS (rows padded to 17 elements).  Each wave first inverts its diagonal
+// LDS (rows padded to 17 elements) by its rows that can be nonzero only:
+// rows 16 j .. NB-1 of an L tile column, rows 0 .. 16 j + 15 of a U one,
+// T (T + 1) / 2 tiles in all (T = NB / 16).  Each wave first inverts its diagonal
 // tile by the column recurrences above (16 lanes), then, after a barrier,
 // runs the substitution down (L) or up (U) its tile column:
 //   L: X(i,j) = -D(i)^{-1} sum_{k=j}^{i-1} L(i,k) X(k,j),   i = j+1 .. T-1
@@ -500,22 +502,31 @@ k_block_invert_mfma(cx<R>* __restrict__ mats, int nblk) {
   constexpr int T = NB / 16;
   constexpr int LDT = 17;
   extern __shared__ __align__(16) char lds_raw[];
-  cx<R>* Xs = reinterpret_cast<cx<R>*>(lds_raw);  // T columns of NB x LDT
+  cx<R>* Xs = reinterpret_cast<cx<R>*>(lds_raw);  // T (T + 1) / 2 tiles of 16 x LDT
   const int g = blockIdx.x;
   const int blk = g >> 1, which = g & 1;  // 0: Lh11 (slot 0), 1: U(k,k) (slot 2)
   if (blk >= nblk) return;
   cx<R>* M = mats + ((size_t)blk * 5 + (which ? 2 : 0)) * NB * NB;
   const int t = threadIdx.x, lane = t & 63;
   const int j = __builtin_amdgcn_readfirstlane(t >> 6);  // this wave's tile column
-  cx<R>* X = Xs + (size_t)j * NB * LDT;                  // X(r, c) at r LDT + c
+  // tile column i: X(r, c) at r LDT + c for its stored rows r0(i) .. r0(i) + 16 nt(i) - 1
+  // (tiles stored before it: i T - i (i - 1) / 2 for L, i (i + 1) / 2 for U)
+  auto col = [&](int i) -> cx<R>* {
+    const int before = which == 0 ? i * T - i * (i - 1) / 2 : i * (i + 1) / 2;
+    const int r0 = which == 0 ? 16 * i : 0;
+    return Xs + (size_t)(16 * before - r0) * LDT;
+  };
+  cx<R>* X = col(j);
+  const int r0 = which == 0 ? 16 * j : 0;
+  const int nrows = which == 0 ? NB - 16 * j : 16 * j + 16;
   auto wfence = [] {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   };
-  // the column tile: zero, with the diagonal tile of M at rows 16 j ..
-  for (int e = lane; e < NB * 16; e += 64) {
-    const int r = e % NB, c = e / NB;
+  // the column tile's stored rows: zero, with the diagonal tile of M at rows 16 j ..
+  for (int e = lane; e < nrows * 16; e += 64) {
+    const int r = r0 + e % nrows, c = e / nrows;
     cx<R> v = mk<R>(0, 0);
     if (r >= 16 * j && r < 16 * j + 16) v = M[(size_t)(16 * j + c) * NB + r];
     X[r * LDT + c] = v;
@@ -560,7 +571,7 @@ k_block_invert_mfma(cx<R>* __restrict__ mats, int nblk) {
   // substitution along the tile column; fragments of the D(i)^{-1} tile:
   // register s holds D(i)^{-1}(lane % 16, 4 s + lane / 16)
   auto dinv_frag = [&](Frag<R, 16>& f, int i) {
-    const cx<R>* Di = Xs + (size_t)i * NB * LDT + 16 * i * LDT;
+    const cx<R>* Di = col(i) + 16 * i * LDT;
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) f.a[s2] = Di[(lane & 15) * LDT + 4 * s2 + (lane >> 4)];
   };
@@ -588,13 +599,20 @@ k_block_invert_mfma(cx<R>* __restrict__ mats, int nblk) {
   __syncthreads();  // every wave has read M
   for (int e = lane; e < NB * 16; e += 64) {
     const int rr = e % NB, c = e / NB;
-    gst(M + (size_t)(16 * j + c) * NB + rr, X[rr * LDT + c]);
+    const bool stored = rr >= r0 && rr < r0 + nrows;
+    gst(M + (size_t)(16 * j + c) * NB + rr, stored ? X[rr * LDT + c] : mk<R>(0, 0));
   }
+}
+
+template <typename R>
+static size_t invert_mfma_lds_bytes(int nb) {
+  const size_t t = (size_t)nb / 16;
+  return sizeof(cx<R>) * (t * (t + 1) / 2) * 16 * 17;
 }
 
 template <typename R, int NB>
 static int launch_invert_mfma_nb(cx<R>* mats, int nblk, hipStream_t st) {
-  const size_t smem = sizeof(cx<R>) * (size_t)(NB / 16) * NB * 17;
+  const size_t smem = invert_mfma_lds_bytes<R>(NB);
   if (smem > kLdsBudget) return FB_ERR_INTERNAL;
   (void)hipFuncSetAttribute((const void*)k_block_invert_mfma<R, NB>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
@@ -609,7 +627,7 @@ static int launch_invert_mfma_nb(cx<R>* mats, int nblk, hipStream_t st) {
 template <typename R>
 static int launch_invert_mfma(cx<R>* mats, int nb, int nblk, hipStream_t st, int* done) {
   *done = 0;
-  if (sizeof(cx<R>) * (size_t)(nb / 16) * nb * 17 > kLdsBudget) return 0;
+  if (invert_mfma_lds_bytes<R>(nb) > kLdsBudget) return 0;
   int rc = 0;
   switch (nb) {
     case 16: rc = launch_invert_mfma_nb<R, 16>(mats, nblk, st); break;
