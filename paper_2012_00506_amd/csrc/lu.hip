@@ -428,66 +428,15 @@ k_band_lu(const c128* __restrict__ Bd_, int64_t n, int b, int nb, int K,
 }
 
 // In-place inverses of the unit lower Lh11 and the upper U(k,k) of every
-// block: one workgroup per (system, block, which).  Column recurrences on the
-// already inverted part (trailing part for L, leading part for U):
-//   L = [1 0; l L22]:      L^{-1} column j below the diagonal = -L22^{-1} l
-//   U = [U11 u; 0 ujj]:    U^{-1} column j above the diagonal = -U11^{-1} u / ujj
-// The matrix is staged in LDS when it fits, else worked on in place in global
-// memory; only the column being replaced is copied aside.
-template <typename R, bool USE_LDS>
-__global__ void __launch_bounds__(256)
-k_block_invert(cx<R>* __restrict__ mats, int b, int nblk) {
-  extern __shared__ __align__(16) char lds_raw[];
-  const int g = blockIdx.x;
-  const int blk = g >> 1, which = g & 1;  // 0: Lh11 (slot 0), 1: U(k,k) (slot 2)
-  if (blk >= nblk) return;
-  cx<R>* M = mats + ((size_t)blk * 5 + (which ? 2 : 0)) * b * b;
-  cx<R>* xv = reinterpret_cast<cx<R>*>(lds_raw);
-  cx<R>* A = USE_LDS ? xv + b : M;
-  const int t = threadIdx.x;
-  const int bb = b * b;
-  if (USE_LDS) {
-    for (int e = t; e < bb; e += blockDim.x) A[e] = M[e];
-    __syncthreads();
-  }
-  if (which == 0) {
-    for (int j = b - 2; j >= 0; --j) {
-      for (int i = j + 1 + t; i < b; i += blockDim.x) xv[i] = A[j * b + i];
-      __syncthreads();
-      for (int r = j + 1 + t; r < b; r += blockDim.x) {
-        cx<R> acc = xv[r];  // unit diagonal of the inverted trailing block
-        for (int q = j + 1; q < r; ++q) cmac(acc, A[q * b + r], xv[q]);
-        A[j * b + r] = mk<R>(-acc.x, -acc.y);
-      }
-      __syncthreads();
-    }
-    for (int j = t; j < b; j += blockDim.x) A[j * b + j] = mk<R>((R)1, (R)0);
-  } else {
-    for (int j = 0; j < b; ++j) {
-      for (int i = t; i <= j; i += blockDim.x) xv[i] = A[j * b + i];
-      __syncthreads();
-      cx<R> d = cinv(xv[j]);
-      for (int r = t; r < j; r += blockDim.x) {
-        cx<R> acc = mk<R>(0, 0);
-        for (int q = r; q < j; ++q) cmac(acc, A[q * b + r], xv[q]);
-        acc = acc * d;
-        A[j * b + r] = mk<R>(-acc.x, -acc.y);
-      }
-      if (t == 0) A[j * b + j] = d;
-      __syncthreads();
-    }
-  }
-  __syncthreads();
-  if (USE_LDS)
-    for (int e = t; e < bb; e += blockDim.x) M[e] = A[e];
-}
-
-// The same inverses by 16 x 16 tiles on MFMA: one workgroup per (system,
+// block by 16 x 16 tiles on MFMA: one workgroup per (system,
 // block, which) and one wave per 16-column tile j of the inverse X, held in
 // LDS (rows padded to 17 elements) by its rows that can be nonzero only:
 // rows 16 j .. NB-1 of an L tile column, rows 0 .. 16 j + 15 of a U one,
 // T (T + 1) / 2 tiles in all (T = NB / 16).  Each wave first inverts its diagonal
-// tile by the column recurrences above (16 lanes), then, after a barrier,
+// tile by column recurrences on the already inverted part (16 lanes):
+//   L = [1 0; l L22]:      L^{-1} column c below the diagonal = -L22^{-1} l
+//   U = [U11 u; 0 ucc]:    U^{-1} column c above the diagonal = -U11^{-1} u / ucc
+// then, after a barrier,
 // runs the substitution down (L) or up (U) its tile column:
 //   L: X(i,j) = -D(i)^{-1} sum_{k=j}^{i-1} L(i,k) X(k,j),   i = j+1 .. T-1
 //   U: X(i,j) = -D(i)^{-1} sum_{k=i+1}^{j} U(i,k) X(k,j),   i = j-1 .. 0
@@ -622,12 +571,10 @@ static int launch_invert_mfma_nb(cx<R>* mats, int nblk, hipStream_t st) {
   return 0;
 }
 
-// 1: inverted by tiles on MFMA; 0: the tiled form does not fit LDS (the
-// column-recurrence kernel is used)
+// every block size up to 128 fits LDS in both precisions
 template <typename R>
-static int launch_invert_mfma(cx<R>* mats, int nb, int nblk, hipStream_t st, int* done) {
-  *done = 0;
-  if (invert_mfma_lds_bytes<R>(nb) > kLdsBudget) return 0;
+static int launch_invert_mfma(cx<R>* mats, int nb, int nblk, hipStream_t st) {
+  if (invert_mfma_lds_bytes<R>(nb) > kLdsBudget) return FB_ERR_INTERNAL;
   int rc = 0;
   switch (nb) {
     case 16: rc = launch_invert_mfma_nb<R, 16>(mats, nblk, st); break;
@@ -640,7 +587,6 @@ static int launch_invert_mfma(cx<R>* mats, int nb, int nblk, hipStream_t st, int
     case 128: rc = launch_invert_mfma_nb<R, 128>(mats, nblk, st); break;
     default: return FB_ERR_INTERNAL;
   }
-  if (rc == 0) *done = 1;
   return rc;
 }
 
@@ -891,26 +837,12 @@ int launch_lu_impl(const Band& bd, int nsys, const c128* z_dev, cx<R>* mats, cx<
                                                           wsplit);
     FB_HIP(hipGetLastError());
   }
-  size_t full = sizeof(cx<R>) * ((size_t)nb * nb + nb);
-  bool ilds = full <= kLdsBudget;
-  size_t ismem = ilds ? full : sizeof(cx<R>) * (size_t)nb;
-  (void)hipFuncSetAttribute((const void*)k_block_invert<R, true>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
-  (void)hipGetLastError();
   int nblk = nsys * K;
   // inverses (2 nb^3 / 3 complex multiply-adds per block), M (nb^3 / 2) and
   // Q, G1, G2 (nb^3 / 3 + nb^3 / 2 + nb^3 / 3)
   ProfScope ps(FB_PROF_INVERT, st,
                8.0 * nblk * (double)nb * nb * nb * (2.0 / 3.0 + 0.5 + 7.0 / 6.0));
-  int tiled = 0;
-  FB_TRY(launch_invert_mfma<R>(mats, nb, nblk, st, &tiled));
-  if (!tiled) {
-    if (ilds)
-      k_block_invert<R, true><<<2 * nblk, 256, ismem, st>>>(mats, nb, nblk);
-    else
-      k_block_invert<R, false><<<2 * nblk, 256, ismem, st>>>(mats, nb, nblk);
-    FB_HIP(hipGetLastError());
-  }
+  FB_TRY(launch_invert_mfma<R>(mats, nb, nblk, st));
   FB_TRY(launch_form_m<R>(mats, nb, nblk, st));
   FB_TRY(launch_form_qg<R>(mats, nb, nblk, st));
   if (matsT) {
