@@ -276,14 +276,17 @@ typedef struct {
  * Section 3.2).  Every boundary is certified: n_-(s - d) = n_-(s + d) with
  * d = cert_delta * ||B||_1, else it is moved to the first certified point of
  * s + 2 d k, k = 1, -1, 2, -2, ...  Equal count bisects all open boundaries
- * together, one batched inertia launch per round.  LEARNED predicts the
+ * together, one batched inertia launch per round; the bisection that places
+ * hi for nev (or targets) evaluates its next levels (up to 63 midpoints) in
+ * one launch and keeps the points it visits.  LEARNED predicts the
  * eigenvalue distribution from the band features (band_features) with the
  * planner network and searches every boundary by inverting that prediction
  * inside the current bracket, rescaled by the exact counts at its ends (a
  * bracket that did not halve in two rounds is bisected); the final plan is
  * certified and exact whatever the network predicts.
  *  bounds host, K+1 doubles; counts host, K; n_inertia host (may be NULL):
- *  number of shifts factorised.  Synchronises the stream. */
+ *  number of shifts factorised, speculative ones included.  Synchronises
+ *  the stream. */
 int slice_plan(const fb_band* B, const fb_plan_opts* o, double* bounds,
                int32_t* counts, int32_t* n_inertia, void* work, size_t* lwork,
                void* stream);

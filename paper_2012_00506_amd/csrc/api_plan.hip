@@ -175,6 +175,39 @@ extern "C" int slice_plan(const fb_band* B, const fb_plan_opts* o, double* bound
       double a = lo, b = hi;  // n_-(a) <= tcount < ... n_-(b) >= tcount
       int na = n_lo, nb_ = n_hi;
       bool done = false;
+      // One launch evaluates the next `depth` levels of the bisection below
+      // [a, b] (its 2^depth - 1 midpoints, formed as the bisection forms
+      // them), so that the sequential bisection then walks them without a
+      // launch per point; only the points it visits enter `known`, and the
+      // plan is the one a launch per point gives.
+      int depth = 1;
+      while (depth < 6 && (2 << depth) - 1 <= cap) ++depth;
+      std::map<double, int> spec;
+      auto count_at = [&](double c, int& v) -> int {
+        auto it = spec.find(c);
+        if (it == spec.end()) {
+          std::vector<double> tree;
+          std::vector<std::pair<double, double>> lvl = {{a, b}}, nxt;
+          for (int d = 0; d < depth; ++d) {
+            nxt.clear();
+            for (auto& ab2 : lvl) {
+              const double m = 0.5 * (ab2.first + ab2.second);
+              tree.push_back(m);
+              nxt.push_back({ab2.first, m});
+              nxt.push_back({m, ab2.second});
+            }
+            lvl.swap(nxt);
+          }
+          std::vector<int> tv;
+          FB_TRY(ir.run(tree, tv));
+          spec.clear();
+          for (size_t q = 0; q < tree.size(); ++q) spec[tree[q]] = tv[q];
+          it = spec.find(c);
+          if (it == spec.end()) return FB_ERR_INTERNAL;
+        }
+        v = it->second;
+        return 0;
+      };
       for (int round = 0; round < 200 && !done; ++round) {
         double c;
         if (nb_ == tcount) {
@@ -192,18 +225,18 @@ extern "C" int slice_plan(const fb_band* B, const fb_plan_opts* o, double* bound
         } else {
           c = 0.5 * (a + b);
         }
-        std::vector<int> nc;
-        FB_TRY(ir.run({c}, nc));
-        known[c] = nc[0];
-        if (nc[0] > tcount) {
+        int ncv = 0;
+        FB_TRY(count_at(c, ncv));
+        known[c] = ncv;
+        if (ncv > tcount) {
           b = c;
-          nb_ = nc[0];
-        } else if (nc[0] < tcount) {
+          nb_ = ncv;
+        } else if (ncv < tcount) {
           a = c;
-          na = nc[0];
+          na = ncv;
         } else {
           b = c;
-          nb_ = nc[0];
+          nb_ = ncv;
         }
       }
       if (!done) return FB_ERR_CERTIFY;
