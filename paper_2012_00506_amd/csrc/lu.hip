@@ -458,8 +458,9 @@ k_block_invert_mfma(cx<R>* __restrict__ mats, int nblk) {
   cx<R>* M = mats + ((size_t)blk * 5 + (which ? 2 : 0)) * NB * NB;
   const int t = threadIdx.x, lane = t & 63;
   const int j = __builtin_amdgcn_readfirstlane(t >> 6);  // this wave's tile column
-  // tile column i: X(r, c) at r LDT + c for its stored rows r0(i) .. r0(i) + 16 nt(i) - 1
-  // (tiles stored before it: i T - i (i - 1) / 2 for L, i (i + 1) / 2 for U)
+  // tile column i: X(r, c) at r LDT + c for its stored rows (16 i .. NB - 1 for
+  // L, 0 .. 16 i + 15 for U); the tiles stored before it number
+  // i T - i (i - 1) / 2 for L and i (i + 1) / 2 for U
   auto col = [&](int i) -> cx<R>* {
     const int before = which == 0 ? i * T - i * (i - 1) / 2 : i * (i + 1) / 2;
     const int r0 = which == 0 ? 16 * i : 0;
