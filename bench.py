@@ -301,6 +301,19 @@ def eigenpair_errors(lam, rel, nrm1):
             "kato_temple_rel": q(kt), "kato_temple_rel_max_inner": float(np.max(inner))}
 
 
+def bound_via_reference(lam, res_abs, lam_ref, res_ref_abs, nrm1):
+    """Per Ritz value of one run (ascending order), the smaller of its own
+    Kato-Temple bound and |lam - lam_ref| plus the bound of the reference
+    run's Ritz value of the same rank: the reference value lies within its
+    bound of an eigenvalue, so lam lies within the sum of it.  Both runs hold
+    the same eigenpairs (exact counts).  Relative to ||B||_1."""
+    o, oref = np.argsort(lam), np.argsort(lam_ref)
+    own = kato_temple(lam, res_abs)[o]
+    ref = kato_temple(lam_ref, res_ref_abs)[oref]
+    d = np.abs(lam[o] - lam_ref[oref])
+    return np.minimum(own, d + ref) / nrm1
+
+
 def roofline(prof, precision, workload):
     name, (L, ms, work) = max(prof.items(), key=lambda kv: kv[1][1])
     if L == 0 or ms <= 0:
@@ -490,6 +503,10 @@ def main():
             out["e2e_c64_vs_f64_eig_rel"] = {"max": float(d.max()),
                                             "p99": float(np.percentile(d, 99)),
                                             "median": float(np.median(d))}
+            # the complex64 run's eigenvalues certified through the FP64 run's
+            via = bound_via_reference(lam1, out["e2e"][0]["_res"] * nrm1, lam0,
+                                      out["e2e"][1]["_res"] * nrm1, nrm1)
+            out["e2e"][0]["per_eigenpair"]["eig_err_bound_via_f64_rel_max"] = float(via.max())
         if args.eig_out:
             np.savez(args.eig_out, lam_c64=lam1, res_c64=out["e2e"][0]["_res"], lam_f64=lam0,
                      res_f64=out["e2e"][1]["_res"], norm1=nrm1)
